@@ -1,0 +1,194 @@
+/*
+ * fbpq.h -- C ABI of the FBPQ query-time search on AMD Instinct MI355X (gfx950).
+ *
+ * The library answers approximate nearest-neighbour queries over a second-order
+ * inverted multi-index whose points are stored as PQ codes of their
+ * displacement from the cell centroid (Babenko & Lempitsky, "Improving Bilayer
+ * Product Quantization for Billion-Scale Approximate Nearest Neighbors in High
+ * Dimensions"). Given a query q in R^D it forms the candidate list of the
+ * multi-sequence traversal (Section 2.3.3: cells in ascending distance until
+ * L points are collected) and reranks the candidates with the FBPQ distance of
+ * Section 3.1, equations (distance) and (decomposition): work linear in the
+ * code length M per candidate, using query-independent tables of
+ * centroid-by-codeword dot products and squared norms.
+ *
+ * Conventions shared by every entry point
+ *  - Return value: FBPQ_OK (0) or a negative FBPQ_E_* code; no exception and no
+ *    abort crosses the ABI. fbpq_last_error() gives a message for the calling
+ *    thread.
+ *  - Index geometry: D (even), T centroids per half, M PQ subspaces (even,
+ *    D % M == 0), Kc = 256 codewords per subspace. Cell id = i*T + j for the
+ *    half-centroid pair (i, j); subspace k covers coordinates
+ *    [k*D/M, (k+1)*D/M); the first M/2 subspaces lie in the first half.
+ *  - Candidate list: exactly min(L, N) points. Cells are visited in ascending
+ *    (d1[i] + d2[j], a, b), where the half distances are FP64 and a, b are the
+ *    ranks of i, j in the (distance, index) sorted half lists; the last cell
+ *    is cut in storage order. Empty cells are visited and add nothing.
+ *  - Results: row-major [nq][k_max]; row r holds the k[r] smallest candidates
+ *    by (FP32 FBPQ distance, id), ascending; positions past min(k[r], L_eff)
+ *    hold id -1 and distance +inf.
+ *  - Ownership: the caller owns query and result buffers; the library owns
+ *    all device memory behind an index handle. A handle may be used by one
+ *    host thread at a time.
+ *  - Errors on the device (a failed HIP call) poison the handle: later calls
+ *    on it return FBPQ_E_DEVICE.
+ */
+#ifndef FBPQ_H
+#define FBPQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FBPQ_OK 0
+#define FBPQ_E_INVALID (-1)  /* bad argument (null pointer, nq < 0, L < 1, k < 1, k > k_max ...) */
+#define FBPQ_E_IO (-2)       /* index file cannot be opened or read */
+#define FBPQ_E_FORMAT (-3)   /* index file or descriptor is malformed (magic, sizes, CRC, offsets) */
+#define FBPQ_E_OOM (-4)      /* host or device allocation failed */
+#define FBPQ_E_DEVICE (-5)   /* a HIP call failed, or the handle was poisoned by one */
+#define FBPQ_E_STATE (-6)    /* call out of order (e.g. search before fbpq_build_tables) */
+#define FBPQ_E_CAPACITY (-7) /* a query needs more traversal depth than the library supports */
+
+#define FBPQ_KC 256
+#define FBPQ_K_MAX 1024 /* largest k per query */
+
+typedef struct fbpq_index fbpq_index;
+
+/* Host-side description of an index, all pointers to host memory that the
+ * library copies during fbpq_index_create (the caller keeps ownership).
+ *   C1, C2   float  [T][D/2]       half codebooks (Section 2.3.1)
+ *   R        float  [M][Kc][D/M]   displacement codebooks R_1..R_M
+ *   offsets  int64  [T*T + 1]      start of each cell in storage order (Section 2.3.2)
+ *   codes    uint8  [N][M]         PQ code of each stored point
+ *   ids      uint32 [N]            point id of each stored point              */
+typedef struct {
+    int32_t D, T, M, Kc;
+    int64_t N;
+    const float *C1;
+    const float *C2;
+    const float *R;
+    const int64_t *offsets;
+    const uint8_t *codes;
+    const uint32_t *ids;
+} fbpq_index_desc;
+
+typedef struct {
+    int32_t D, T, M, Kc;
+    int64_t N;
+    int64_t table_bytes;  /* centroid-by-codeword dot products: T*M*Kc floats (Section 3.3) */
+    int64_t norm_bytes;   /* squared norms: (2T + M*Kc) floats (Section 3.3) */
+    int64_t device_bytes; /* all device memory currently held by the handle */
+    int32_t tables_ready; /* fbpq_build_tables has run */
+    int32_t device;       /* HIP device ordinal */
+} fbpq_info_t;
+
+/* Upload an index described by host arrays to device `device`. Validates
+ * geometry and offsets (offsets[0] == 0, non-decreasing, offsets[T*T] == N).
+ * On success *out owns the device copy. Errors: INVALID, FORMAT, OOM, DEVICE. */
+int fbpq_index_create(const fbpq_index_desc *desc, int device, fbpq_index **out);
+
+/* Read an index file (layout: 64-byte header "FBPQIDX1", six section records
+ * with CRC-32, then C1, C2, R, offsets, codes, ids), validate it and upload it.
+ * Errors: INVALID, IO, FORMAT (magic, version, sizes, CRC, offsets), OOM, DEVICE. */
+int fbpq_load_index(const char *path, int device, fbpq_index **out);
+
+/* Validate an index file on the host only (no device work). Same checks and
+ * error codes as fbpq_load_index; writes the geometry to *info if non-null. */
+int fbpq_index_file_check(const char *path, fbpq_info_t *info);
+
+/* Build the query-independent tables of equation (decomposition), Section 3.1:
+ *   CR1[i][k][r] = 2 <c1_i|k, R_k(r)>        k <  M/2
+ *   CR2[j][k][r] = 2 <c2_j|k, R_{M/2+k}(r)>  k <  M/2
+ *   nR[k][r]     = ||R_k(r)||^2, nC1[i] = ||c1_i||^2, nC2[j] = ||c2_j||^2
+ * accumulated in FP64 and stored in FP32 (c|k is the k-th D/M slice of the
+ * half centroid). Idempotent. Errors: INVALID, DEVICE. */
+int fbpq_build_tables(fbpq_index *ix);
+
+/* Search nq queries (host memory, float [nq][D]) with one budget L >= 1 and
+ * 1 <= k <= FBPQ_K_MAX; writes host ids [nq][k] and dists [nq][k].
+ * nq == 0 is a no-op. Errors: INVALID, STATE, CAPACITY, OOM, DEVICE. */
+int fbpq_search(fbpq_index *ix, const float *q, int64_t nq, int64_t L, int32_t k,
+                int64_t *ids, float *dists);
+
+/* Same with per-query budgets L[nq] and k[nq] (host arrays), outputs
+ * [nq][k_max] with k[r] <= k_max <= FBPQ_K_MAX. */
+int fbpq_search_uneven(fbpq_index *ix, const float *q, int64_t nq, const int64_t *L,
+                       const int32_t *k, int32_t k_max, int64_t *ids, float *dists);
+
+/* Device-resident form: d_q, d_ids, d_dists are device pointers on the index's
+ * device ([nq][D], [nq][k_max], [nq][k_max]); L and k are HOST arrays of nq
+ * entries. Work is queued on `hip_stream` (a hipStream_t, or null for the
+ * default stream). The call returns after the search has completed on the
+ * stream (it reads a per-query status word back to decide whether deeper
+ * traversal is needed). */
+int fbpq_search_device(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L,
+                       const int32_t *k, int32_t k_max, int64_t *d_ids, float *d_dists,
+                       void *hip_stream);
+
+/* Parity/debug: the visited cells and candidate positions of each query, in
+ * traversal order, produced by the GPU traversal. Host buffers:
+ *   cells [nq][cells_cap][2]  (cell id, points taken from it)
+ *   ncells [nq]
+ *   pos   [nq][pos_cap]       storage positions of the candidates
+ *   npos  [nq]
+ * Errors: INVALID, STATE, CAPACITY (a cap too small), OOM, DEVICE. */
+int fbpq_debug_visit(fbpq_index *ix, const float *q, int64_t nq, int64_t L,
+                     int64_t *cells, int64_t cells_cap, int64_t *ncells,
+                     int64_t *pos, int64_t pos_cap, int64_t *npos);
+
+/* Parity/debug: FP32 FBPQ distance of every candidate of each query, as
+ * (storage position, distance) pairs in an unspecified order. Host buffers
+ * pos [nq][cap], dist [nq][cap], n [nq]. Errors as fbpq_debug_visit. */
+int fbpq_debug_dists(fbpq_index *ix, const float *q, int64_t nq, int64_t L,
+                     int64_t *pos, float *dist, int64_t cap, int64_t *n);
+
+/* Parity/debug: copy the tables of fbpq_build_tables to host buffers
+ * CR1 [T][M/2][Kc], CR2 [T][M/2][Kc], nR [M][Kc], nC1 [T], nC2 [T] (any may be
+ * null). Errors: INVALID, STATE, DEVICE. */
+int fbpq_debug_tables(fbpq_index *ix, float *CR1, float *CR2, float *nR, float *nC1, float *nC2);
+
+/* Parity/debug: the first P entries of both sorted half lists of each query:
+ * keys FP64 [nq][2][P] and centroid indices int32 [nq][2][P]. P <= T. */
+int fbpq_debug_rank(fbpq_index *ix, const float *q, int64_t nq, int32_t P, double *keys,
+                    int32_t *idx);
+
+/* Geometry and memory of an index. Errors: INVALID. */
+int fbpq_info(const fbpq_index *ix, fbpq_info_t *out);
+
+/* Table and norm sizes in bytes for a geometry (host arithmetic only):
+ * T*M*Kc and (2T + M*Kc) FP32 values (Section 3.3). Errors: INVALID. */
+int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int64_t *norm_bytes);
+
+/* Tuning knobs (autotuner and tests). Keys: "prefix" (initial sorted-list
+ * length P), "max_cells" (initial per-query visited-cell capacity), "chunk"
+ * (candidates per scan chunk), "profile" (0/1: time every kernel launch with
+ * HIP events, read with fbpq_profile_read). Errors: INVALID. */
+int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
+
+/* Kernel stages timed by the library's profiler. */
+#define FBPQ_STAGE_HALF_KEYS 0 /* first-layer FP64 half distances */
+#define FBPQ_STAGE_PREFIX 1    /* sorted prefix of each half list */
+#define FBPQ_STAGE_TRAVERSE 2  /* multi-sequence traversal */
+#define FBPQ_STAGE_LAYOUT 3    /* row-major layout of the visited cells */
+#define FBPQ_STAGE_SCAN 4      /* LUT + FBPQ distance scan + top-k */
+#define FBPQ_NUM_STAGES 5
+
+/* Device time per kernel stage, measured with HIP events recorded on the
+ * search stream around every launch while profiling is on (option "profile"
+ * = 1). Writes the accumulated milliseconds and launch count of `stage` and,
+ * if reset != 0, clears that stage's counters. Errors: INVALID. */
+int fbpq_profile_read(fbpq_index *ix, int32_t stage, int32_t reset, double *ms, int64_t *launches);
+
+/* Release the handle and all device memory it holds. Null is a no-op. */
+void fbpq_free_index(fbpq_index *ix);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *fbpq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FBPQ_H */

@@ -1,0 +1,969 @@
+// Host side of libfbpq: the C ABI of include/fbpq.h. Index upload and
+// validation, the index file reader, the table build, and the search
+// pipeline: half keys -> sorted prefixes -> traversal -> layout -> scan+top-k,
+// with a second round for the queries whose traversal needs a longer sorted
+// prefix or more visited cells than the first round provided.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "fbpq.h"
+#include "fbpq_dev.h"
+
+using namespace fbpq;
+
+static constexpr size_t kScanLdsLimit = 76 * 1024;  // two scan workgroups per CU (160 KB LDS)
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace
+
+struct fbpq_index {
+    int device = 0;
+    bool poisoned = false;
+    bool tables = false;
+    DevIndex dv{};
+    hipStream_t stream = nullptr;
+    // owned device allocations
+    float *C1 = nullptr, *C2 = nullptr, *R = nullptr;
+    int64_t *offsets = nullptr;
+    uint8_t *codesA = nullptr, *codesB = nullptr;
+    uint32_t *ids = nullptr;
+    float *CR1 = nullptr, *CR2 = nullptr, *nR = nullptr, *nC1 = nullptr, *nC2 = nullptr;
+    size_t base_bytes = 0, table_bytes = 0;
+    // workspace, grown on demand
+    DevBuf ws[32];
+    void *pinned = nullptr;
+    size_t pinned_cap = 0;
+    // profiler: events recorded around launches while `profile` is on
+    bool profile = false;
+    struct Ev {
+        hipEvent_t a, b;
+        int stage;
+    };
+    std::vector<Ev> ev_live;
+    std::vector<hipEvent_t> ev_pool;
+    double prof_ms[FBPQ_NUM_STAGES] = {0};
+    int64_t prof_n[FBPQ_NUM_STAGES] = {0};
+    // options
+    int32_t prefix = 128;
+    int64_t max_cells = 4096;
+    int32_t chunk = 8192;
+};
+
+namespace {
+
+enum WsSlot {
+    W_Q, W_KEYS, W_LKEY, W_LIDX, W_HDR, W_W, W_ROWNE, W_ROWCAND, W_COLNE, W_COLTOT, W_NECS,
+    W_NECNT, W_NEBEG, W_NECST, W_CMCELL, W_CMPRE, W_L, W_K, W_QLIST, W_FAIL, W_IDS, W_D,
+    W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NSLOTS
+};
+
+#define HCK(ix, expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) {                                                                 \
+            (ix)->poisoned = true;                                                              \
+            return fail(FBPQ_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+        }                                                                                       \
+    } while (0)
+
+int ws_get(fbpq_index *ix, int slot, size_t bytes, void **out)
+{
+    DevBuf &b = ix->ws[slot];
+    if (bytes == 0) bytes = 8;
+    if (b.cap < bytes) {
+        if (b.p) {
+            HCK(ix, hipStreamSynchronize(ix->stream));
+            HCK(ix, hipFree(b.p));
+            b.p = nullptr;
+            b.cap = 0;
+        }
+        const size_t nb = std::max(bytes, b.cap + b.cap / 2);
+        hipError_t e = hipMalloc(&b.p, nb);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            return fail(FBPQ_E_OOM, "device allocation of %zu bytes failed", nb);
+        }
+        b.cap = nb;
+    }
+    *out = b.p;
+    return FBPQ_OK;
+}
+
+int pinned_get(fbpq_index *ix, size_t bytes, void **out)
+{
+    if (ix->pinned_cap < bytes) {
+        if (ix->pinned) {
+            HCK(ix, hipStreamSynchronize(ix->stream));
+            HCK(ix, hipHostFree(ix->pinned));
+            ix->pinned = nullptr;
+            ix->pinned_cap = 0;
+        }
+        const size_t nb = std::max(bytes, (size_t)1 << 16);
+        if (hipHostMalloc(&ix->pinned, nb, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            ix->pinned = nullptr;
+            return fail(FBPQ_E_OOM, "pinned host allocation of %zu bytes failed", nb);
+        }
+        ix->pinned_cap = nb;
+    }
+    *out = ix->pinned;
+    return FBPQ_OK;
+}
+
+hipEvent_t ev_take(fbpq_index *ix)
+{
+    if (!ix->ev_pool.empty()) {
+        hipEvent_t e = ix->ev_pool.back();
+        ix->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Wraps one kernel launch: events before and after it on `st` when profiling.
+template <typename F>
+hipError_t timed(fbpq_index *ix, int stage, hipStream_t st, F &&launch)
+{
+    if (!ix->profile) return launch();
+    hipEvent_t a = ev_take(ix), b = ev_take(ix);
+    if (a) (void)hipEventRecord(a, st);
+    const hipError_t e = launch();
+    if (b) (void)hipEventRecord(b, st);
+    if (a && b) ix->ev_live.push_back({a, b, stage});
+    return e;
+}
+
+// After the stream has been synchronized: fold the recorded intervals into the totals.
+void prof_collect(fbpq_index *ix)
+{
+    for (auto &e : ix->ev_live) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+            ix->prof_ms[e.stage] += ms;
+            ix->prof_n[e.stage] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        ix->ev_pool.push_back(e.a);
+        ix->ev_pool.push_back(e.b);
+    }
+    ix->ev_live.clear();
+}
+
+int check_desc(const fbpq_index_desc *d)
+{
+    if (!d) return fail(FBPQ_E_INVALID, "null descriptor");
+    if (d->D <= 0 || d->D % 2 || d->M <= 0 || d->M % 2 || d->D % d->M)
+        return fail(FBPQ_E_FORMAT, "bad geometry D=%d M=%d (need D, M even and M | D)", d->D, d->M);
+    const int mh = d->M / 2;
+    if (!(mh == 1 || mh == 2 || mh == 4 || mh == 8 || mh == 16))
+        return fail(FBPQ_E_FORMAT, "M=%d not supported (M/2 must be 1, 2, 4, 8 or 16)", d->M);
+    if (d->Kc != FBPQ_KC) return fail(FBPQ_E_FORMAT, "Kc=%d, only 256 is supported", d->Kc);
+    if (d->T <= 0 || d->T > (1 << 20)) return fail(FBPQ_E_FORMAT, "bad T=%d", d->T);
+    if (d->N < 0 || d->N > (int64_t)0xffffffffLL) return fail(FBPQ_E_FORMAT, "bad N=%lld", (long long)d->N);
+    if (d->D > 4096) return fail(FBPQ_E_FORMAT, "D=%d too large", d->D);
+    if (!d->C1 || !d->C2 || !d->R || !d->offsets || (d->N > 0 && (!d->codes || !d->ids)))
+        return fail(FBPQ_E_INVALID, "null array in descriptor");
+    const int64_t C = (int64_t)d->T * d->T;
+    if (d->offsets[0] != 0 || d->offsets[C] != d->N)
+        return fail(FBPQ_E_FORMAT, "offsets must start at 0 and end at N");
+    for (int64_t c = 0; c < C; ++c)
+        if (d->offsets[c + 1] < d->offsets[c])
+            return fail(FBPQ_E_FORMAT, "offsets decrease at cell %lld", (long long)c);
+    return FBPQ_OK;
+}
+
+template <typename T>
+int upload(fbpq_index *ix, T **dst, const void *src, size_t bytes)
+{
+    if (hipMalloc((void **)dst, bytes ? bytes : 8) != hipSuccess) {
+        (void)hipGetLastError();
+        *dst = nullptr;
+        return fail(FBPQ_E_OOM, "device allocation of %zu bytes failed", bytes);
+    }
+    ix->base_bytes += bytes;
+    if (bytes) HCK(ix, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    return FBPQ_OK;
+}
+
+void free_all(fbpq_index *ix)
+{
+    if (!ix) return;
+    (void)hipSetDevice(ix->device);
+    if (ix->stream) (void)hipStreamSynchronize(ix->stream);
+    void *ps[] = {ix->C1, ix->C2, ix->R, ix->offsets, ix->codesA, ix->codesB, ix->ids,
+                  ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    for (auto &b : ix->ws)
+        if (b.p) (void)hipFree(b.p);
+    if (ix->pinned) (void)hipHostFree(ix->pinned);
+    for (auto &e : ix->ev_live) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (auto e : ix->ev_pool) (void)hipEventDestroy(e);
+    if (ix->stream) (void)hipStreamDestroy(ix->stream);
+    delete ix;
+}
+
+int create_impl(const fbpq_index_desc *d, int device, fbpq_index **out)
+{
+    int rc = check_desc(d);
+    if (rc) return rc;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return fail(FBPQ_E_DEVICE, "device %d not available (%d devices)", device, ndev);
+    }
+    fbpq_index *ix = new fbpq_index();
+    ix->device = device;
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&ix->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ix;
+        return fail(FBPQ_E_DEVICE, "cannot initialise device %d", device);
+    }
+    const int64_t T = d->T, h = d->D / 2, C = T * T, N = d->N, M = d->M;
+    rc = upload(ix, &ix->C1, d->C1, sizeof(float) * T * h);
+    if (!rc) rc = upload(ix, &ix->C2, d->C2, sizeof(float) * T * h);
+    if (!rc) rc = upload(ix, &ix->R, d->R, sizeof(float) * M * FBPQ_KC * (d->D / M));
+    if (!rc) rc = upload(ix, &ix->offsets, d->offsets, sizeof(int64_t) * (C + 1));
+    if (!rc) rc = upload(ix, &ix->ids, d->ids, sizeof(uint32_t) * N);
+    if (!rc) {
+        const size_t half = (size_t)N * (M / 2);
+        if (hipMalloc(&ix->codesA, half ? half : 8) != hipSuccess ||
+            hipMalloc(&ix->codesB, half ? half : 8) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = fail(FBPQ_E_OOM, "device allocation of codes failed");
+        } else {
+            ix->base_bytes += 2 * half;
+            // stage AoS codes through a bounded device buffer and split them on the GPU
+            const int64_t step = std::max<int64_t>(1, ((int64_t)64 << 20) / M);
+            void *stage = nullptr;
+            rc = N ? ws_get(ix, W_SPLIT, (size_t)std::min(N, step) * M, &stage) : 0;
+            for (int64_t s = 0; !rc && s < N; s += step) {
+                const int64_t n = std::min(step, N - s);
+                hipError_t e = hipMemcpy(stage, d->codes + s * M, (size_t)n * M, hipMemcpyHostToDevice);
+                if (e == hipSuccess)
+                    e = launch_split_codes((const uint8_t *)stage, n, (int)M, ix->codesA + s * (M / 2),
+                                           ix->codesB + s * (M / 2), ix->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(ix->stream);
+                if (e != hipSuccess) {
+                    ix->poisoned = true;
+                    rc = fail(FBPQ_E_DEVICE, "code upload failed: %s", hipGetErrorString(e));
+                }
+            }
+            if (!rc && ix->ws[W_SPLIT].p) {
+                (void)hipFree(ix->ws[W_SPLIT].p);
+                ix->ws[W_SPLIT] = DevBuf{};
+            }
+        }
+    }
+    if (rc) {
+        free_all(ix);
+        return rc;
+    }
+    DevIndex &v = ix->dv;
+    v.D = d->D;
+    v.T = d->T;
+    v.M = d->M;
+    v.Kc = d->Kc;
+    v.N = N;
+    v.C1 = ix->C1;
+    v.C2 = ix->C2;
+    v.R = ix->R;
+    v.offsets = ix->offsets;
+    v.codesA = ix->codesA;
+    v.codesB = ix->codesB;
+    v.ids = ix->ids;
+    *out = ix;
+    return FBPQ_OK;
+}
+
+// ---- index file -------------------------------------------------------------
+uint32_t crc_table[256];
+bool crc_init = false;
+
+uint32_t crc32_update(uint32_t crc, const unsigned char *p, size_t n)
+{
+    if (!crc_init) {
+        for (uint32_t i = 0; i < 256; ++i) {
+            uint32_t c = i;
+            for (int k = 0; k < 8; ++k) c = (c & 1) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+            crc_table[i] = c;
+        }
+        crc_init = true;
+    }
+    crc = ~crc;
+    for (size_t i = 0; i < n; ++i) crc = crc_table[(crc ^ p[i]) & 255] ^ (crc >> 8);
+    return ~crc;
+}
+
+#pragma pack(push, 1)
+struct FileHdr {
+    char magic[8];
+    uint32_t version, D, T, M, Kc, nsect;
+    uint64_t N;
+    uint8_t reserved[24];
+};
+struct FileSec {
+    uint32_t kind, crc;
+    uint64_t offset, bytes, reserved;
+};
+#pragma pack(pop)
+static_assert(sizeof(FileHdr) == 64, "header layout");
+static_assert(sizeof(FileSec) == 32, "section layout");
+
+struct FileData {
+    FileHdr h;
+    std::vector<float> C1, C2, R;
+    std::vector<int64_t> offsets;
+    std::vector<uint8_t> codes;
+    std::vector<uint32_t> ids;
+};
+
+int read_file(const char *path, FileData *fd, bool keep)
+{
+    if (!path) return fail(FBPQ_E_INVALID, "null path");
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(FBPQ_E_IO, "cannot open %s", path);
+    struct Closer {
+        FILE *f;
+        ~Closer() { fclose(f); }
+    } closer{f};
+    FileHdr &h = fd->h;
+    if (fread(&h, sizeof h, 1, f) != 1) return fail(FBPQ_E_FORMAT, "%s: short header", path);
+    if (memcmp(h.magic, "FBPQIDX1", 8) != 0) return fail(FBPQ_E_FORMAT, "%s: bad magic", path);
+    if (h.version != 1) return fail(FBPQ_E_FORMAT, "%s: unsupported version %u", path, h.version);
+    if (h.nsect != 6) return fail(FBPQ_E_FORMAT, "%s: expected 6 sections", path);
+    if (h.D == 0 || h.D % 2 || h.M == 0 || h.M % 2 || h.D % h.M || h.Kc != FBPQ_KC || h.T == 0 ||
+        h.T > (1u << 20) || h.D > 4096 || h.N > 0xffffffffull)
+        return fail(FBPQ_E_FORMAT, "%s: bad geometry", path);
+    FileSec sec[6];
+    if (fread(sec, sizeof(FileSec), 6, f) != 6) return fail(FBPQ_E_FORMAT, "%s: short section table", path);
+    const uint64_t T = h.T, half = h.D / 2;
+    const uint64_t want[6] = {4 * T * half, 4 * T * half, 4ull * h.M * h.Kc * (h.D / h.M),
+                              8 * (T * T + 1), h.N * h.M, 4 * h.N};
+    void *dst[6] = {nullptr};
+    if (keep) {
+        fd->C1.resize(T * half);
+        fd->C2.resize(T * half);
+        fd->R.resize((size_t)h.M * h.Kc * (h.D / h.M));
+        fd->offsets.resize(T * T + 1);
+        fd->codes.resize(h.N * h.M);
+        fd->ids.resize(h.N);
+        void *d[6] = {fd->C1.data(), fd->C2.data(), fd->R.data(), fd->offsets.data(), fd->codes.data(),
+                      fd->ids.data()};
+        memcpy(dst, d, sizeof d);
+    }
+    std::vector<unsigned char> tmp;
+    std::vector<int64_t> offs_check;
+    for (int s = 0; s < 6; ++s) {
+        const FileSec &r = sec[s];
+        if (r.kind < 1 || r.kind > 6) return fail(FBPQ_E_FORMAT, "%s: bad section kind", path);
+        const int k = (int)r.kind - 1;
+        if (r.bytes != want[k]) return fail(FBPQ_E_FORMAT, "%s: section %d has %llu bytes, want %llu", path,
+                                            k + 1, (unsigned long long)r.bytes, (unsigned long long)want[k]);
+        if (fseeko(f, (off_t)r.offset, SEEK_SET) != 0) return fail(FBPQ_E_FORMAT, "%s: bad section offset", path);
+        unsigned char *p;
+        if (keep) {
+            p = (unsigned char *)dst[k];
+        } else if (k == 3) {
+            offs_check.resize(T * T + 1);
+            p = (unsigned char *)offs_check.data();
+        } else {
+            tmp.resize(std::min<uint64_t>(r.bytes, (uint64_t)1 << 24));
+            p = nullptr;
+        }
+        uint32_t crc = 0;
+        uint64_t left = r.bytes;
+        uint64_t at = 0;
+        while (left) {
+            const size_t n = (size_t)std::min<uint64_t>(left, (uint64_t)1 << 24);
+            unsigned char *q = p ? p + at : tmp.data();
+            if (fread(q, 1, n, f) != n) return fail(FBPQ_E_FORMAT, "%s: truncated section %d", path, k + 1);
+            crc = crc32_update(crc, q, n);
+            left -= n;
+            at += n;
+        }
+        if (crc != r.crc) return fail(FBPQ_E_FORMAT, "%s: CRC mismatch in section %d", path, k + 1);
+    }
+    const int64_t *o = keep ? fd->offsets.data() : offs_check.data();
+    const int64_t C = (int64_t)T * T;
+    if (o[0] != 0 || o[C] != (int64_t)h.N) return fail(FBPQ_E_FORMAT, "%s: offsets must span [0, N]", path);
+    for (int64_t c = 0; c < C; ++c)
+        if (o[c + 1] < o[c]) return fail(FBPQ_E_FORMAT, "%s: offsets decrease at cell %lld", path, (long long)c);
+    return FBPQ_OK;
+}
+
+int check_handle(fbpq_index *ix)
+{
+    if (!ix) return fail(FBPQ_E_INVALID, "null index handle");
+    if (ix->poisoned) return fail(FBPQ_E_DEVICE, "index handle poisoned by an earlier device error");
+    if (hipSetDevice(ix->device) != hipSuccess) {
+        (void)hipGetLastError();
+        ix->poisoned = true;
+        return fail(FBPQ_E_DEVICE, "cannot select device %d", ix->device);
+    }
+    return FBPQ_OK;
+}
+
+// ---- search pipeline ----------------------------------------------------------
+struct DebugOut {
+    // visit mode: traversal only, copy visited cells
+    bool visit = false;
+    int64_t cells_cap = 0;
+    int64_t *cells = nullptr, *ncells = nullptr, *pos = nullptr, *npos = nullptr;
+    int64_t pos_cap = 0;
+    // dist mode: full pipeline, copy per-candidate distances
+    bool dists = false;
+    int64_t *dpos = nullptr;
+    float *dd = nullptr;
+    int64_t dcap = 0;
+    int64_t *dn = nullptr;
+};
+
+#define TRY(x)                   \
+    do {                         \
+        int r_ = (x);            \
+        if (r_) return r_;       \
+    } while (0)
+
+int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, const int32_t *d_qlist,
+              int32_t P, int64_t max_cells, const int64_t *d_L, const int32_t *d_k, int32_t k_max,
+              int64_t *d_ids, float *d_d, hipStream_t st, const float *keys, int32_t *d_fail,
+              const DebugOut *dbg, int64_t *fail_host_count)
+{
+    DevIndex &dv = ix->dv;
+    void *lkey, *lidx, *hdr, *w, *rowne, *rowcand, *colne, *coltot, *necs, *necnt, *nebeg, *necst, *cmcell,
+        *cmpre;
+    TRY(ws_get(ix, W_LKEY, sizeof(double) * nslots * 2 * P, &lkey));
+    TRY(ws_get(ix, W_LIDX, sizeof(int32_t) * nslots * 2 * P, &lidx));
+    TRY(ws_get(ix, W_HDR, sizeof(TravHdr) * nslots, &hdr));
+    TRY(ws_get(ix, W_W, sizeof(int32_t) * nslots * P, &w));
+    TRY(ws_get(ix, W_ROWNE, sizeof(int32_t) * nslots * (P + 1), &rowne));
+    TRY(ws_get(ix, W_ROWCAND, sizeof(int32_t) * nslots * (P + 1), &rowcand));
+    TRY(ws_get(ix, W_COLNE, sizeof(int32_t) * nslots * (P + 1), &colne));
+    TRY(ws_get(ix, W_COLTOT, sizeof(int32_t) * nslots * P, &coltot));
+    TRY(ws_get(ix, W_NECS, sizeof(int32_t) * nslots * max_cells, &necs));
+    TRY(ws_get(ix, W_NECNT, sizeof(int32_t) * nslots * max_cells, &necnt));
+    TRY(ws_get(ix, W_NEBEG, sizeof(int64_t) * nslots * max_cells, &nebeg));
+    TRY(ws_get(ix, W_NECST, sizeof(float) * nslots * max_cells, &necst));
+    TRY(ws_get(ix, W_CMCELL, sizeof(int32_t) * nslots * max_cells, &cmcell));
+    TRY(ws_get(ix, W_CMPRE, sizeof(int32_t) * nslots * max_cells, &cmpre));
+    void *dab = nullptr, *dtake = nullptr, *dbeg = nullptr, *dpos = nullptr, *ddd = nullptr;
+    if (dbg && dbg->visit) {
+        TRY(ws_get(ix, W_DBGAB, sizeof(int32_t) * 2 * nslots * max_cells, &dab));
+        TRY(ws_get(ix, W_DBGTAKE, sizeof(int64_t) * nslots * max_cells, &dtake));
+        TRY(ws_get(ix, W_DBGBEG, sizeof(int64_t) * nslots * max_cells, &dbeg));
+    }
+    if (dbg && dbg->dists) {
+        TRY(ws_get(ix, W_DBGPOS, sizeof(int64_t) * nslots * dbg->dcap, &dpos));
+        TRY(ws_get(ix, W_DBGD, sizeof(float) * nslots * dbg->dcap, &ddd));
+    }
+    HCK(ix, hipMemsetAsync(d_fail, 0, sizeof(int32_t), st));
+    HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_select_prefix(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, st); }));
+    TravArgs ta{};
+    ta.ix = dv;
+    ta.lkey = (const double *)lkey;
+    ta.lidx = (const int32_t *)lidx;
+    ta.P = P;
+    ta.qlist = d_qlist;
+    ta.L = d_L;
+    ta.max_cells = max_cells;
+    ta.hdr = (TravHdr *)hdr;
+    ta.w = (int32_t *)w;
+    ta.fail_count = d_fail;
+    ta.fail_list = d_fail + 1;
+    ta.dbg_ab = (int32_t *)dab;
+    ta.dbg_take = (int64_t *)dtake;
+    ta.dbg_beg = (int64_t *)dbeg;
+    HCK(ix, timed(ix, FBPQ_STAGE_TRAVERSE, st, [&] { return launch_traverse(ta, nslots, st); }));
+    if (!(dbg && dbg->visit)) {
+        LayoutArgs la{};
+        la.ix = dv;
+        la.lkey = (const double *)lkey;
+        la.lidx = (const int32_t *)lidx;
+        la.P = P;
+        la.hdr = (TravHdr *)hdr;
+        la.w = (const int32_t *)w;
+        la.max_cells = max_cells;
+        la.row_ne = (int32_t *)rowne;
+        la.row_cand = (int32_t *)rowcand;
+        la.col_ne = (int32_t *)colne;
+        la.col_tot = (int32_t *)coltot;
+        la.ne_cs = (int32_t *)necs;
+        la.ne_cnt = (int32_t *)necnt;
+        la.ne_beg = (int64_t *)nebeg;
+        la.ne_cst = (float *)necst;
+        la.cm_cell = (int32_t *)cmcell;
+        la.cm_pre = (int32_t *)cmpre;
+        HCK(ix, timed(ix, FBPQ_STAGE_LAYOUT, st, [&] { return launch_layout(la, nslots, st); }));
+        ScanArgs sa{};
+        sa.ix = dv;
+        sa.q = d_q;
+        sa.qlist = d_qlist;
+        sa.k = d_k;
+        sa.k_max = k_max;
+        sa.lidx = (const int32_t *)lidx;
+        sa.P = P;
+        sa.hdr = (const TravHdr *)hdr;
+        sa.max_cells = max_cells;
+        sa.row_ne = (const int32_t *)rowne;
+        sa.row_cand = (const int32_t *)rowcand;
+        sa.col_ne = (const int32_t *)colne;
+        sa.col_tot = (const int32_t *)coltot;
+        sa.ne_cs = (const int32_t *)necs;
+        sa.ne_cnt = (const int32_t *)necnt;
+        sa.ne_beg = (const int64_t *)nebeg;
+        sa.ne_cst = (const float *)necst;
+        sa.cm_cell = (const int32_t *)cmcell;
+        sa.cm_pre = (const int32_t *)cmpre;
+        int chunk = ix->chunk;
+        while (chunk > 256 && scan_lds_bytes(dv.D, dv.M, chunk, k_max, P) > kScanLdsLimit) chunk >>= 1;
+        sa.chunk = chunk;
+        sa.out_ids = d_ids;
+        sa.out_d = d_d;
+        sa.dbg_pos = (int64_t *)dpos;
+        sa.dbg_d = (float *)ddd;
+        sa.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
+        HCK(ix, timed(ix, FBPQ_STAGE_SCAN, st, [&] { return launch_scan(sa, nslots, st); }));
+    }
+    // how many slots need another round
+    // bytes [0, 64) of the pinned buffer hold the failure count; the L/k staging starts at 64
+    void *pin;
+    TRY(pinned_get(ix, 64, &pin));
+    int32_t *hcount = (int32_t *)pin;
+    HCK(ix, hipMemcpyAsync(hcount, d_fail, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (dbg && (dbg->visit || dbg->dists)) {
+        // copy debug outputs of the successful slots to the caller
+        std::vector<TravHdr> hh(nslots);
+        std::vector<int32_t> ql(nslots);
+        HCK(ix, hipMemcpyAsync(hh.data(), hdr, sizeof(TravHdr) * nslots, hipMemcpyDeviceToHost, st));
+        if (d_qlist) HCK(ix, hipMemcpyAsync(ql.data(), d_qlist, sizeof(int32_t) * nslots, hipMemcpyDeviceToHost, st));
+        HCK(ix, hipStreamSynchronize(st));
+        if (!d_qlist)
+            for (int64_t s = 0; s < nslots; ++s) ql[s] = (int32_t)s;
+        if (dbg->visit) {
+            std::vector<int32_t> ab((size_t)2 * nslots * max_cells);
+            std::vector<int64_t> take((size_t)nslots * max_cells), beg((size_t)nslots * max_cells);
+            std::vector<int32_t> li((size_t)nslots * 2 * P);
+            HCK(ix, hipMemcpy(ab.data(), dab, ab.size() * 4, hipMemcpyDeviceToHost));
+            HCK(ix, hipMemcpy(take.data(), dtake, take.size() * 8, hipMemcpyDeviceToHost));
+            HCK(ix, hipMemcpy(beg.data(), dbeg, beg.size() * 8, hipMemcpyDeviceToHost));
+            HCK(ix, hipMemcpy(li.data(), lidx, li.size() * 4, hipMemcpyDeviceToHost));
+            for (int64_t s = 0; s < nslots; ++s) {
+                if (hh[s].status != kStOk) continue;
+                const int64_t q = ql[s];
+                const int64_t nc = hh[s].ncells;
+                if (nc > dbg->cells_cap || hh[s].ncand > dbg->pos_cap)
+                    return fail(FBPQ_E_CAPACITY, "debug buffers too small for query %lld", (long long)q);
+                int64_t np = 0;
+                for (int64_t c = 0; c < nc; ++c) {
+                    const size_t o = (size_t)s * max_cells + c;
+                    const int32_t a = ab[2 * o], b = ab[2 * o + 1];
+                    const int64_t cell = (int64_t)li[(size_t)s * 2 * P + a] * dv.T + li[(size_t)s * 2 * P + P + b];
+                    dbg->cells[(q * dbg->cells_cap + c) * 2] = cell;
+                    dbg->cells[(q * dbg->cells_cap + c) * 2 + 1] = take[o];
+                    for (int64_t t = 0; t < take[o]; ++t) dbg->pos[q * dbg->pos_cap + np++] = beg[o] + t;
+                }
+                dbg->ncells[q] = nc;
+                dbg->npos[q] = np;
+            }
+        }
+        if (dbg->dists) {
+            std::vector<int64_t> pp((size_t)nslots * dbg->dcap);
+            std::vector<float> dd((size_t)nslots * dbg->dcap);
+            HCK(ix, hipMemcpy(pp.data(), dpos, pp.size() * 8, hipMemcpyDeviceToHost));
+            HCK(ix, hipMemcpy(dd.data(), ddd, dd.size() * 4, hipMemcpyDeviceToHost));
+            for (int64_t s = 0; s < nslots; ++s) {
+                if (hh[s].status != kStOk) continue;
+                const int64_t q = ql[s];
+                const int64_t n = hh[s].ncand;
+                if (n > dbg->dcap) return fail(FBPQ_E_CAPACITY, "debug buffers too small");
+                memcpy(dbg->dpos + q * dbg->dcap, pp.data() + s * dbg->dcap, n * 8);
+                memcpy(dbg->dd + q * dbg->dcap, dd.data() + s * dbg->dcap, n * 4);
+                dbg->dn[q] = n;
+            }
+        }
+    }
+    HCK(ix, hipStreamSynchronize(st));
+    prof_collect(ix);
+    *fail_host_count = hcount[0];
+    return FBPQ_OK;
+}
+
+int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
+                int32_t k_max, int64_t *d_ids, float *d_d, hipStream_t st, const DebugOut *dbg)
+{
+    TRY(check_handle(ix));
+    if (!ix->tables) return fail(FBPQ_E_STATE, "fbpq_build_tables has not been called");
+    if (nq < 0) return fail(FBPQ_E_INVALID, "nq < 0");
+    if (nq == 0) return FBPQ_OK;
+    if (nq > 0x7fffffff) return fail(FBPQ_E_INVALID, "nq too large");
+    if (!d_q || !L || !k) return fail(FBPQ_E_INVALID, "null pointer");
+    if (k_max < 1 || k_max > FBPQ_K_MAX) return fail(FBPQ_E_INVALID, "k_max out of range");
+    if (!(dbg && dbg->visit) && (!d_ids || !d_d)) return fail(FBPQ_E_INVALID, "null output");
+    int64_t Lmax = 0;
+    for (int64_t i = 0; i < nq; ++i) {
+        if (L[i] < 1) return fail(FBPQ_E_INVALID, "L[%lld] < 1", (long long)i);
+        if (k[i] < 1 || k[i] > k_max) return fail(FBPQ_E_INVALID, "k[%lld] out of [1, k_max]", (long long)i);
+        Lmax = std::max(Lmax, L[i]);
+    }
+    if (std::min<int64_t>(Lmax, ix->dv.N) > 0x7fffffffLL)
+        return fail(FBPQ_E_CAPACITY, "min(L, N) must stay below 2^31 candidates per query");
+    void *keys, *dL, *dk, *dfail, *pin;
+    TRY(ws_get(ix, W_KEYS, sizeof(float) * nq * 2 * ix->dv.T, &keys));
+    TRY(ws_get(ix, W_L, sizeof(int64_t) * nq, &dL));
+    TRY(ws_get(ix, W_K, sizeof(int32_t) * nq, &dk));
+    TRY(ws_get(ix, W_FAIL, sizeof(int32_t) * (nq + 1), &dfail));
+    TRY(pinned_get(ix, (sizeof(int64_t) + sizeof(int32_t)) * nq + 64, &pin));
+    char *stage = (char *)pin + 64;
+    memcpy(stage, L, sizeof(int64_t) * nq);
+    memcpy(stage + sizeof(int64_t) * nq, k, sizeof(int32_t) * nq);
+    HCK(ix, hipMemcpyAsync(dL, stage, sizeof(int64_t) * nq, hipMemcpyHostToDevice, st));
+    HCK(ix, hipMemcpyAsync(dk, stage + sizeof(int64_t) * nq, sizeof(int32_t) * nq,
+                           hipMemcpyHostToDevice, st));
+    HCK(ix, timed(ix, FBPQ_STAGE_HALF_KEYS, st, [&] { return launch_half_approx(ix->dv, d_q, nq, (float *)keys, st); }));
+
+    const int T = ix->dv.T;
+    int32_t P = std::min<int32_t>(std::max<int32_t>(ix->prefix, 1), T);
+    P = std::min<int32_t>(P, kMaxPrefix);
+    int64_t max_cells = std::max<int64_t>(ix->max_cells, 64);
+    int64_t nslots = nq;
+    const int32_t *qlist = nullptr;
+    std::vector<int32_t> failed;
+    for (int round = 0;; ++round) {
+        int64_t nfail = 0;
+        TRY(run_round(ix, d_q, nq, nslots, qlist, P, max_cells, (const int64_t *)dL, (const int32_t *)dk,
+                      k_max, d_ids, d_d, st, (const float *)keys, (int32_t *)dfail, dbg, &nfail));
+        if (nfail == 0) break;
+        // read the failed queries and their reasons, then grow P and/or the cell capacity
+        failed.resize(nfail);
+        HCK(ix, hipMemcpy(failed.data(), (int32_t *)dfail + 1, sizeof(int32_t) * nfail, hipMemcpyDeviceToHost));
+        std::vector<TravHdr> hh(nslots);
+        void *hdr = ix->ws[W_HDR].p;
+        HCK(ix, hipMemcpy(hh.data(), hdr, sizeof(TravHdr) * nslots, hipMemcpyDeviceToHost));
+        bool need_prefix = false, need_cells = false;
+        for (int64_t s = 0; s < nslots; ++s) {
+            need_prefix |= hh[s].status == kStNeedPrefix;
+            need_cells |= hh[s].status == kStNeedCells;
+        }
+        const int32_t Pcap = std::min<int32_t>(T, kMaxPrefix);
+        if (need_prefix) {
+            if (P >= Pcap)
+                return fail(FBPQ_E_CAPACITY, "a query needs more than %d ranks per half list", Pcap);
+            P = std::min<int32_t>(Pcap, P * 4);
+        }
+        if (need_cells) {
+            const int64_t cap = ((int64_t)1 << 31) / 32;
+            if (max_cells >= cap)
+                return fail(FBPQ_E_CAPACITY, "a query visits more than %lld cells", (long long)cap);
+            // enough cells for the worst failing query at the current density bound
+            max_cells = std::min<int64_t>(cap, max_cells * 8);
+        }
+        void *ql;
+        TRY(ws_get(ix, W_QLIST, sizeof(int32_t) * nfail, &ql));
+        HCK(ix, hipMemcpy(ql, failed.data(), sizeof(int32_t) * nfail, hipMemcpyHostToDevice));
+        qlist = (const int32_t *)ql;
+        nslots = nfail;
+        if (round > 64) return fail(FBPQ_E_CAPACITY, "traversal did not converge");
+    }
+    return FBPQ_OK;
+}
+
+}  // namespace
+
+// ============================== C ABI ========================================
+extern "C" {
+
+const char *fbpq_last_error(void) { return g_err.c_str(); }
+
+int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int64_t *norm_bytes)
+{
+    if (T < 1 || M < 1 || Kc < 1 || !table_bytes || !norm_bytes) return fail(FBPQ_E_INVALID, "bad arguments");
+    *table_bytes = T * M * Kc * (int64_t)sizeof(float);
+    *norm_bytes = (2 * T + M * Kc) * (int64_t)sizeof(float);
+    return FBPQ_OK;
+}
+
+int fbpq_index_create(const fbpq_index_desc *desc, int device, fbpq_index **out)
+{
+    if (!out) return fail(FBPQ_E_INVALID, "null output handle");
+    *out = nullptr;
+    return create_impl(desc, device, out);
+}
+
+int fbpq_index_file_check(const char *path, fbpq_info_t *info)
+{
+    FileData fd;
+    const int rc = read_file(path, &fd, false);
+    if (rc) return rc;
+    if (info) {
+        memset(info, 0, sizeof *info);
+        info->D = (int32_t)fd.h.D;
+        info->T = (int32_t)fd.h.T;
+        info->M = (int32_t)fd.h.M;
+        info->Kc = (int32_t)fd.h.Kc;
+        info->N = (int64_t)fd.h.N;
+        fbpq_table_bytes(info->T, info->M, info->Kc, &info->table_bytes, &info->norm_bytes);
+        info->device = -1;
+    }
+    return FBPQ_OK;
+}
+
+int fbpq_load_index(const char *path, int device, fbpq_index **out)
+{
+    if (!out) return fail(FBPQ_E_INVALID, "null output handle");
+    *out = nullptr;
+    FileData fd;
+    const int rc = read_file(path, &fd, true);
+    if (rc) return rc;
+    fbpq_index_desc d{};
+    d.D = (int32_t)fd.h.D;
+    d.T = (int32_t)fd.h.T;
+    d.M = (int32_t)fd.h.M;
+    d.Kc = (int32_t)fd.h.Kc;
+    d.N = (int64_t)fd.h.N;
+    d.C1 = fd.C1.data();
+    d.C2 = fd.C2.data();
+    d.R = fd.R.data();
+    d.offsets = fd.offsets.data();
+    d.codes = fd.codes.data();
+    d.ids = fd.ids.data();
+    return create_impl(&d, device, out);
+}
+
+int fbpq_build_tables(fbpq_index *ix)
+{
+    TRY(check_handle(ix));
+    if (ix->tables) return FBPQ_OK;
+    const int64_t T = ix->dv.T, M = ix->dv.M;
+    const size_t cr = sizeof(float) * T * (M / 2) * FBPQ_KC;
+    const size_t nr = sizeof(float) * M * FBPQ_KC;
+    if (hipMalloc(&ix->CR1, cr) != hipSuccess || hipMalloc(&ix->CR2, cr) != hipSuccess ||
+        hipMalloc(&ix->nR, nr) != hipSuccess || hipMalloc(&ix->nC1, sizeof(float) * T) != hipSuccess ||
+        hipMalloc(&ix->nC2, sizeof(float) * T) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FBPQ_E_OOM, "table allocation failed");
+    }
+    ix->table_bytes = 2 * cr + nr + 2 * sizeof(float) * T;
+    HCK(ix, launch_tables(ix->dv, ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2, ix->stream));
+    HCK(ix, hipStreamSynchronize(ix->stream));
+    {
+        std::vector<float> n1(T), n2(T);
+        HCK(ix, hipMemcpy(n1.data(), ix->nC1, sizeof(float) * T, hipMemcpyDeviceToHost));
+        HCK(ix, hipMemcpy(n2.data(), ix->nC2, sizeof(float) * T, hipMemcpyDeviceToHost));
+        ix->dv.cmax1 = *std::max_element(n1.begin(), n1.end());
+        ix->dv.cmax2 = *std::max_element(n2.begin(), n2.end());
+    }
+    ix->dv.CR1 = ix->CR1;
+    ix->dv.CR2 = ix->CR2;
+    ix->dv.nR = ix->nR;
+    ix->dv.nC1 = ix->nC1;
+    ix->dv.nC2 = ix->nC2;
+    ix->tables = true;
+    return FBPQ_OK;
+}
+
+int fbpq_search_device(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
+                       int32_t k_max, int64_t *d_ids, float *d_dists, void *hip_stream)
+{
+    return search_impl(ix, d_q, nq, L, k, k_max, d_ids, d_dists, (hipStream_t)hip_stream, nullptr);
+}
+
+static int host_search(fbpq_index *ix, const float *q, int64_t nq, const int64_t *L, const int32_t *k,
+                       int32_t k_max, int64_t *ids, float *dists, const DebugOut *dbg)
+{
+    TRY(check_handle(ix));
+    if (nq < 0) return fail(FBPQ_E_INVALID, "nq < 0");
+    if (nq == 0) return ix->tables ? FBPQ_OK : fail(FBPQ_E_STATE, "fbpq_build_tables has not been called");
+    if (!q) return fail(FBPQ_E_INVALID, "null queries");
+    void *dq, *dids = nullptr, *dd = nullptr;
+    TRY(ws_get(ix, W_Q, sizeof(float) * nq * ix->dv.D, &dq));
+    const bool outputs = !(dbg && dbg->visit);
+    if (outputs) {
+        if (!ids || !dists) return fail(FBPQ_E_INVALID, "null output");
+        TRY(ws_get(ix, W_IDS, sizeof(int64_t) * nq * k_max, &dids));
+        TRY(ws_get(ix, W_D, sizeof(float) * nq * k_max, &dd));
+    }
+    HCK(ix, hipMemcpyAsync(dq, q, sizeof(float) * nq * ix->dv.D, hipMemcpyHostToDevice, ix->stream));
+    TRY(search_impl(ix, (const float *)dq, nq, L, k, k_max, (int64_t *)dids, (float *)dd, ix->stream, dbg));
+    if (outputs) {
+        HCK(ix, hipMemcpyAsync(ids, dids, sizeof(int64_t) * nq * k_max, hipMemcpyDeviceToHost, ix->stream));
+        HCK(ix, hipMemcpyAsync(dists, dd, sizeof(float) * nq * k_max, hipMemcpyDeviceToHost, ix->stream));
+        HCK(ix, hipStreamSynchronize(ix->stream));
+    }
+    return FBPQ_OK;
+}
+
+int fbpq_search_uneven(fbpq_index *ix, const float *q, int64_t nq, const int64_t *L, const int32_t *k,
+                       int32_t k_max, int64_t *ids, float *dists)
+{
+    return host_search(ix, q, nq, L, k, k_max, ids, dists, nullptr);
+}
+
+int fbpq_search(fbpq_index *ix, const float *q, int64_t nq, int64_t L, int32_t k, int64_t *ids, float *dists)
+{
+    if (nq < 0) return fail(FBPQ_E_INVALID, "nq < 0");
+    std::vector<int64_t> Ls((size_t)std::max<int64_t>(nq, 1), L);
+    std::vector<int32_t> ks((size_t)std::max<int64_t>(nq, 1), k);
+    if (k < 1 || k > FBPQ_K_MAX) return fail(FBPQ_E_INVALID, "k out of range");
+    return host_search(ix, q, nq, Ls.data(), ks.data(), k, ids, dists, nullptr);
+}
+
+int fbpq_debug_visit(fbpq_index *ix, const float *q, int64_t nq, int64_t L, int64_t *cells, int64_t cells_cap,
+                     int64_t *ncells, int64_t *pos, int64_t pos_cap, int64_t *npos)
+{
+    if (!cells || !ncells || !pos || !npos || cells_cap < 1 || pos_cap < 1)
+        return fail(FBPQ_E_INVALID, "bad debug buffers");
+    DebugOut dbg;
+    dbg.visit = true;
+    dbg.cells = cells;
+    dbg.cells_cap = cells_cap;
+    dbg.ncells = ncells;
+    dbg.pos = pos;
+    dbg.pos_cap = pos_cap;
+    dbg.npos = npos;
+    std::vector<int64_t> Ls((size_t)std::max<int64_t>(nq, 1), L);
+    std::vector<int32_t> ks((size_t)std::max<int64_t>(nq, 1), 1);
+    return host_search(ix, q, nq, Ls.data(), ks.data(), 1, nullptr, nullptr, &dbg);
+}
+
+int fbpq_debug_dists(fbpq_index *ix, const float *q, int64_t nq, int64_t L, int64_t *pos, float *dist,
+                     int64_t cap, int64_t *n)
+{
+    if (!pos || !dist || !n || cap < 1) return fail(FBPQ_E_INVALID, "bad debug buffers");
+    DebugOut dbg;
+    dbg.dists = true;
+    dbg.dpos = pos;
+    dbg.dd = dist;
+    dbg.dcap = cap;
+    dbg.dn = n;
+    std::vector<int64_t> Ls((size_t)std::max<int64_t>(nq, 1), L);
+    std::vector<int32_t> ks((size_t)std::max<int64_t>(nq, 1), 1);
+    std::vector<int64_t> ids((size_t)std::max<int64_t>(nq, 1));
+    std::vector<float> dd((size_t)std::max<int64_t>(nq, 1));
+    return host_search(ix, q, nq, Ls.data(), ks.data(), 1, ids.data(), dd.data(), &dbg);
+}
+
+int fbpq_debug_tables(fbpq_index *ix, float *CR1, float *CR2, float *nR, float *nC1, float *nC2)
+{
+    TRY(check_handle(ix));
+    if (!ix->tables) return fail(FBPQ_E_STATE, "fbpq_build_tables has not been called");
+    const int64_t T = ix->dv.T, M = ix->dv.M;
+    const size_t cr = sizeof(float) * T * (M / 2) * FBPQ_KC;
+    if (CR1) HCK(ix, hipMemcpy(CR1, ix->CR1, cr, hipMemcpyDeviceToHost));
+    if (CR2) HCK(ix, hipMemcpy(CR2, ix->CR2, cr, hipMemcpyDeviceToHost));
+    if (nR) HCK(ix, hipMemcpy(nR, ix->nR, sizeof(float) * M * FBPQ_KC, hipMemcpyDeviceToHost));
+    if (nC1) HCK(ix, hipMemcpy(nC1, ix->nC1, sizeof(float) * T, hipMemcpyDeviceToHost));
+    if (nC2) HCK(ix, hipMemcpy(nC2, ix->nC2, sizeof(float) * T, hipMemcpyDeviceToHost));
+    return FBPQ_OK;
+}
+
+int fbpq_debug_rank(fbpq_index *ix, const float *q, int64_t nq, int32_t P, double *keys, int32_t *idx)
+{
+    TRY(check_handle(ix));
+    if (nq < 0 || P < 1 || P > ix->dv.T || P > kMaxPrefix || !q || !keys || !idx)
+        return fail(FBPQ_E_INVALID, "bad arguments");
+    if (nq == 0) return FBPQ_OK;
+    if (!ix->tables) return fail(FBPQ_E_STATE, "fbpq_build_tables has not been called");
+    void *dq, *dkeys, *lkey, *lidx;
+    TRY(ws_get(ix, W_Q, sizeof(float) * nq * ix->dv.D, &dq));
+    TRY(ws_get(ix, W_KEYS, sizeof(float) * nq * 2 * ix->dv.T, &dkeys));
+    TRY(ws_get(ix, W_LKEY, sizeof(double) * nq * 2 * P, &lkey));
+    TRY(ws_get(ix, W_LIDX, sizeof(int32_t) * nq * 2 * P, &lidx));
+    HCK(ix, hipMemcpyAsync(dq, q, sizeof(float) * nq * ix->dv.D, hipMemcpyHostToDevice, ix->stream));
+    HCK(ix, launch_half_approx(ix->dv, (const float *)dq, nq, (float *)dkeys, ix->stream));
+    HCK(ix, launch_select_prefix(ix->dv, (const float *)dq, (const float *)dkeys, nq, nullptr, P,
+                                 (double *)lkey, (int32_t *)lidx, ix->stream));
+    HCK(ix, hipMemcpyAsync(keys, lkey, sizeof(double) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
+    HCK(ix, hipMemcpyAsync(idx, lidx, sizeof(int32_t) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
+    HCK(ix, hipStreamSynchronize(ix->stream));
+    return FBPQ_OK;
+}
+
+int fbpq_info(const fbpq_index *ix, fbpq_info_t *out)
+{
+    if (!ix || !out) return fail(FBPQ_E_INVALID, "null argument");
+    memset(out, 0, sizeof *out);
+    out->D = ix->dv.D;
+    out->T = ix->dv.T;
+    out->M = ix->dv.M;
+    out->Kc = ix->dv.Kc;
+    out->N = ix->dv.N;
+    fbpq_table_bytes(out->T, out->M, out->Kc, &out->table_bytes, &out->norm_bytes);
+    size_t ws = 0;
+    for (const auto &b : ix->ws) ws += b.cap;
+    out->device_bytes = (int64_t)(ix->base_bytes + ix->table_bytes + ws);
+    out->tables_ready = ix->tables ? 1 : 0;
+    out->device = ix->device;
+    return FBPQ_OK;
+}
+
+int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
+{
+    if (!ix || !key) return fail(FBPQ_E_INVALID, "null argument");
+    if (!strcmp(key, "prefix")) {
+        if (value < 1 || value > kMaxPrefix) return fail(FBPQ_E_INVALID, "prefix out of [1, %d]", kMaxPrefix);
+        ix->prefix = (int32_t)value;
+    } else if (!strcmp(key, "max_cells")) {
+        if (value < 64 || value > ((int64_t)1 << 26)) return fail(FBPQ_E_INVALID, "max_cells out of range");
+        ix->max_cells = value;
+    } else if (!strcmp(key, "profile")) {
+        ix->profile = value != 0;
+    } else if (!strcmp(key, "chunk")) {
+        if (value < 256 || value > (1 << 16)) return fail(FBPQ_E_INVALID, "chunk out of range");
+        ix->chunk = (int32_t)value;
+    } else {
+        return fail(FBPQ_E_INVALID, "unknown option %s", key);
+    }
+    return FBPQ_OK;
+}
+
+int fbpq_profile_read(fbpq_index *ix, int32_t stage, int32_t reset, double *ms, int64_t *launches)
+{
+    if (!ix || stage < 0 || stage >= FBPQ_NUM_STAGES || !ms || !launches)
+        return fail(FBPQ_E_INVALID, "bad arguments");
+    *ms = ix->prof_ms[stage];
+    *launches = ix->prof_n[stage];
+    if (reset) {
+        ix->prof_ms[stage] = 0;
+        ix->prof_n[stage] = 0;
+    }
+    return FBPQ_OK;
+}
+
+void fbpq_free_index(fbpq_index *ix) { free_all(ix); }
+
+}  // extern "C"

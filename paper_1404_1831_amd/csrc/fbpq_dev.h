@@ -1,0 +1,123 @@
+// Internal definitions shared by the HIP kernels and the host side of libfbpq.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fbpq {
+
+constexpr int kWave = 64;
+constexpr int kKc = 256;
+constexpr int kMaxPrefix = 2048;  // longest sorted half list the traversal tracks
+constexpr int kMaxK = 1024;
+
+// Per-query traversal status written by the traversal kernel.
+enum : int32_t { kStOk = 0, kStNeedPrefix = 1, kStNeedCells = 2 };
+
+// Per-query traversal summary (one record per workspace slot).
+struct TravHdr {
+    int32_t status;
+    int32_t A;        // rows of the visited diagram (ranks a with w[a] > 0)
+    int32_t B;        // columns (= w[0])
+    int32_t cut_a;    // rank pair of the last visited cell
+    int32_t cut_b;
+    int32_t nne;      // nonempty visited cells (set by the layout kernel)
+    int64_t ncells;   // visited cells (= sum of w)
+    int64_t ncand;    // candidates (= min(L, N))
+    int64_t cut_take; // points taken from the last visited cell
+};
+
+// Device view of an index and its tables.
+struct DevIndex {
+    int32_t D, T, M, Kc;
+    int64_t N;
+    const float *C1, *C2, *R;
+    const int64_t *offsets;
+    const uint8_t *codesA;  // [N][M/2] bytes of subspaces 0..M/2-1
+    const uint8_t *codesB;  // [N][M/2] bytes of subspaces M/2..M-1
+    const uint32_t *ids;
+    const float *CR1, *CR2, *nR, *nC1, *nC2;
+    float cmax1, cmax2;  // largest squared half-centroid norm of each half
+};
+
+// Launchers (each defined next to its kernel).
+hipError_t launch_tables(const DevIndex &ix, float *CR1, float *CR2, float *nR, float *nC1,
+                         float *nC2, hipStream_t st);
+
+hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, uint8_t *b,
+                              hipStream_t st);
+
+hipError_t launch_half_approx(const DevIndex &ix, const float *q, int64_t nq, float *ka,
+                              hipStream_t st);
+
+hipError_t launch_select_prefix(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
+                                const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
+                                hipStream_t st);
+
+struct TravArgs {
+    DevIndex ix;
+    const double *lkey;    // [slot][2][P]
+    const int32_t *lidx;   // [slot][2][P]
+    int32_t P;
+    const int32_t *qlist;  // slot -> query (null: identity)
+    const int64_t *L;      // [query]
+    int64_t max_cells;
+    TravHdr *hdr;          // [slot]
+    int32_t *w;            // [slot][P] final row widths
+    int32_t *fail_count;   // number of slots whose status is not kStOk
+    int32_t *fail_list;    // their query ids
+    int32_t *dbg_ab;       // optional [slot][max_cells][2] visited (a, b) in order
+    int64_t *dbg_take;     // optional [slot][max_cells] points taken
+    int64_t *dbg_beg;      // optional [slot][max_cells] storage begin of the cell
+};
+hipError_t launch_traverse(const TravArgs &a, int64_t nslots, hipStream_t st);
+
+struct LayoutArgs {
+    DevIndex ix;
+    const double *lkey;    // [slot][2][P]
+    const int32_t *lidx;   // [slot][2][P]
+    int32_t P;
+    TravHdr *hdr;
+    const int32_t *w;      // [slot][P]
+    int64_t max_cells;
+    int32_t *row_ne;       // [slot][P+1] first compacted cell of each row
+    int32_t *row_cand;     // [slot][P+1] first candidate of each row
+    int32_t *col_ne;       // [slot][P+1] first column-list entry of each column
+    int32_t *col_tot;      // [slot][P] candidates in each column
+    int32_t *ne_cs;        // [slot][max_cells] first candidate of each nonempty cell
+    int32_t *ne_cnt;       // points taken
+    int64_t *ne_beg;       // storage begin
+    float *ne_cst;         // fl32(d1[i] + d2[j])
+    int32_t *cm_cell;      // [slot][max_cells] column lists: compacted cell index
+    int32_t *cm_pre;       // candidates before it in its column
+};
+hipError_t launch_layout(const LayoutArgs &a, int64_t nslots, hipStream_t st);
+
+struct ScanArgs {
+    DevIndex ix;
+    const float *q;        // [query][D]
+    const int32_t *qlist;
+    const int32_t *k;      // [query]
+    int32_t k_max;         // output row stride
+    const int32_t *lidx;
+    int32_t P;
+    const TravHdr *hdr;
+    int64_t max_cells;
+    const int32_t *row_ne, *row_cand, *col_ne, *col_tot;
+    const int32_t *ne_cs, *ne_cnt;
+    const int64_t *ne_beg;
+    const float *ne_cst;
+    const int32_t *cm_cell, *cm_pre;
+    int32_t chunk;         // candidates per LDS chunk
+    int64_t *out_ids;      // [query][k_max]
+    float *out_d;
+    int64_t *dbg_pos;      // optional [slot][dbg_cap]
+    float *dbg_d;
+    int64_t dbg_cap;
+};
+hipError_t launch_scan(const ScanArgs &a, int64_t nslots, hipStream_t st);
+
+size_t scan_lds_bytes(int D, int M, int chunk, int k_max, int P);
+constexpr int kScanCellsLds = 256;  // nonempty cells whose tables the scan keeps in LDS
+
+}  // namespace fbpq

@@ -1,0 +1,479 @@
+// First layer of the search (Section 2.3.3): squared distances from each query
+// half to all T half centroids (equations q1, q2) and the sorted prefix of the
+// closest-centroid list of each half, the input of the multi-sequence
+// traversal.
+//
+// The traversal order is decided by FP64 keys computed in one fixed order:
+// key = sum over t = 0..D/2-1 of e_t^2, e_t = q[t] - c[t] in FP64, one fused
+// multiply-add per coordinate in increasing t; lists are sorted by (key,
+// centroid index). Computing that for all T centroids is FP64-ALU bound, so it
+// is done in two steps:
+//  1. an FP32 matrix-core product gives approximate keys
+//     ka = ||q||^2 + ||c||^2 - 2 <q, c> for every centroid, with an error
+//     below a bound e(q) that holds for any summation order;
+//  2. per (query, half), with kP the P-th smallest approximate key, every
+//     centroid with ka <= kP + 2e can be among the exact P smallest; those
+//     survivors (about P) get their exact FP64 key and are sorted.
+// A query whose survivor set is too large falls back to an exact radix select
+// that recomputes FP64 keys for all centroids.
+#include "fbpq_dev.h"
+
+namespace fbpq {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// ---- step 1: approximate keys on the matrix cores ---------------------------
+// Block tile: 64 queries x 128 centroids of one half, 4 wavefronts; wavefront w
+// owns queries [16w, 16w+16) and all 128 centroids (8 blocks of 16x16). Each
+// v_mfma_f32_16x16x4f32 takes A[i][k] from lane i + 16k and B[k][j] from lane
+// j + 16k and leaves D[4*(lane/16) + r][lane % 16] in accumulator r.
+constexpr int kAQ = 64, kAC = 128, kAS = 68;  // LDS row stride 68 floats: conflict-free reads
+
+__global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q, int64_t nq, int D,
+                                                     const float *__restrict__ C1,
+                                                     const float *__restrict__ C2,
+                                                     const float *__restrict__ nC1,
+                                                     const float *__restrict__ nC2, int T,
+                                                     float *__restrict__ ka)
+{
+    __shared__ __align__(16) float qs[kAQ * kAS];
+    __shared__ __align__(16) float cs[kAC * kAS];
+    __shared__ float qn[kAQ];
+    const int half = blockIdx.z;
+    const int h = D / 2;
+    const float *C = half ? C2 : C1;
+    const float *nC = half ? nC2 : nC1;
+    const int64_t q0 = (int64_t)blockIdx.y * kAQ;
+    const int c0 = blockIdx.x * kAC;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+
+    floatx4 acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float qnorm = 0.f;  // thread tid < 64 accumulates ||q_tid||^2 over the slabs
+
+    for (int t0 = 0; t0 < h; t0 += 64) {
+        const int tn = min(64, h - t0);
+        __syncthreads();
+        for (int e = tid; e < kAQ * 64; e += 256) {
+            const int qq = e >> 6, t = e & 63;
+            const int64_t qi = q0 + qq;
+            qs[qq * kAS + t] = (qi < nq && t < tn) ? Q[qi * D + half * h + t0 + t] : 0.f;
+        }
+        for (int e = tid; e < kAC * 64; e += 256) {
+            const int cc = e >> 6, t = e & 63;
+            const int ci = c0 + cc;
+            cs[cc * kAS + t] = (ci < T && t < tn) ? C[(int64_t)ci * h + t0 + t] : 0.f;
+        }
+        __syncthreads();
+        if (tid < kAQ)
+            for (int t = 0; t < tn; ++t) qnorm = fmaf(qs[tid * kAS + t], qs[tid * kAS + t], qnorm);
+        for (int s = 0; s < 16; ++s) {
+            const float a = qs[(wv * 16 + li) * kAS + 4 * s + lk];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float b = cs[(j * 16 + li) * kAS + 4 * s + lk];
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
+            }
+        }
+    }
+    if (tid < kAQ) qn[tid] = qnorm;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int ci = c0 + j * 16 + li;
+        if (ci >= T) continue;
+        const float nc = nC[ci];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int qq = wv * 16 + 4 * lk + r;
+            const int64_t qi = q0 + qq;
+            if (qi < nq) ka[(qi * 2 + half) * (int64_t)T + ci] = (qn[qq] + nc) - 2.f * acc[j][r];
+        }
+    }
+}
+
+hipError_t launch_half_approx(const DevIndex &ix, const float *q, int64_t nq, float *ka,
+                              hipStream_t st)
+{
+    if (nq == 0) return hipSuccess;
+    dim3 grid((unsigned)((ix.T + kAC - 1) / kAC), (unsigned)((nq + kAQ - 1) / kAQ), 2);
+    hipLaunchKernelGGL(k_half_approx, grid, dim3(256), 0, st, q, nq, ix.D, ix.C1, ix.C2, ix.nC1,
+                       ix.nC2, ix.T, ka);
+    return hipGetLastError();
+}
+
+// ---- step 2: survivors, exact keys, sort -------------------------------------
+constexpr int kSelThreads = 256;
+constexpr int kBins = 1024;
+
+__device__ __forceinline__ uint64_t dkey(double x) { return (uint64_t)__double_as_longlong(x); }
+
+// Exact traversal key of centroid c: FP64, increasing t, one fma per coordinate.
+__device__ __forceinline__ double exact_key(const float *qh, const float *__restrict__ Crow, int h)
+{
+    double acc = 0.0;
+    for (int t = 0; t < h; ++t) {
+        const double e = (double)qh[t] - (double)Crow[t];
+        acc = __builtin_fma(e, e, acc);
+    }
+    return acc;
+}
+
+template <typename V>
+__device__ V block_reduce(V v, V *red, bool is_min)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) {
+        const V u = __shfl_xor(v, o);
+        v = is_min ? (u < v ? u : v) : (u > v ? u : v);
+    }
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    V r = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = is_min ? (red[i] < r ? red[i] : r) : (red[i] > r ? red[i] : r);
+    return r;
+}
+
+__device__ int block_sum(int v, int *red)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    int r = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += red[i];
+    return r;
+}
+
+// Exclusive block scan of one int per thread; *total gets the sum.
+__device__ int block_excl_scan(int v, int *red, int *total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) red[wv] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        if (i < wv) off += red[i];
+        tot += red[i];
+    }
+    *total = tot;
+    return off + x - v;
+}
+
+// Bitonic sort of n (power of two) (key, idx) pairs in LDS, ascending by (key, idx).
+__device__ void bitonic_kv(uint64_t *sk, int32_t *si, int n)
+{
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t ka = sk[lo], kb = sk[hi];
+                const int ia = si[lo], ib = si[hi];
+                const bool gt = ka > kb || (ka == kb && ia > ib);
+                if (gt == up) {
+                    sk[lo] = kb;
+                    sk[hi] = ka;
+                    si[lo] = ib;
+                    si[hi] = ia;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// LDS: qh[h] floats | ka[T] floats (when T <= kApproxLds) | sort keys u64[S] | sort idx i32[S]
+constexpr int kApproxLds = 16384;
+
+__global__ __launch_bounds__(kSelThreads) void k_select_prefix(
+    const float *__restrict__ kapprox, const float *__restrict__ Q, int D,
+    const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, int T,
+    const int32_t *qlist, int P, int S, double *__restrict__ lkey, int32_t *__restrict__ lidx)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t hist[kBins];
+    __shared__ float redf[kSelThreads / 64];
+    __shared__ int redi[kSelThreads / 64];
+    __shared__ uint64_t red64[kSelThreads / 64];
+    __shared__ int s_cnt, s_bin, s_need;
+    const int slot = blockIdx.x, half = blockIdx.y, tid = threadIdx.x;
+    const int h = D / 2;
+    const int64_t qs = qlist ? qlist[slot] : slot;
+    const float *C = half ? C2 : C1;
+    const float cmax = half ? cmax2 : cmax1;
+    const bool lds_ka = T <= kApproxLds;
+    float *qh = reinterpret_cast<float *>(smem);
+    const int hpad = (h + 3) & ~3;
+    float *kal = qh + hpad;
+    uint64_t *sk = reinterpret_cast<uint64_t *>(kal + (lds_ka ? ((T + 1) & ~1) : 0));
+    int32_t *si = reinterpret_cast<int32_t *>(sk + S);
+    const float *kg = kapprox + (qs * 2 + half) * (int64_t)T;
+
+    for (int t = tid; t < h; t += kSelThreads) qh[t] = Q[qs * D + half * h + t];
+    if (lds_ka)
+        for (int i = tid; i < T; i += kSelThreads) kal[i] = kg[i];
+    __syncthreads();
+    const float *kv = lds_ka ? kal : kg;
+
+    // error bound of the approximate keys (any summation order, FP32)
+    double qn = 0.0;
+    for (int t = 0; t < h; ++t) qn += (double)qh[t] * (double)qh[t];
+    const double rn = sqrt(qn) + sqrt((double)cmax) * (1.0 + 1e-6);
+    const float err = (float)(1.25 * (h + 8) * 0x1.0p-23 * rn * rn) + 1e-30f;
+
+    int n_out = 0;
+    bool done = false;
+    if (P >= T) {
+        // every centroid: exact keys and sort
+        for (int i = tid; i < S; i += kSelThreads) {
+            if (i < T) {
+                sk[i] = dkey(exact_key(qh, C + (int64_t)i * h, h));
+                si[i] = i;
+            } else {
+                sk[i] = ~0ull;
+                si[i] = 0x7fffffff;
+            }
+        }
+        __syncthreads();
+        bitonic_kv(sk, si, S);
+        n_out = T;
+        done = true;
+    }
+    if (!done) {
+        // kP: the P-th smallest approximate key, bracketed by value bins
+        float lo = block_reduce(__builtin_huge_valf(), redf, true);
+        {
+            float mn = __builtin_huge_valf(), mx = -__builtin_huge_valf();
+            for (int i = tid; i < T; i += kSelThreads) {
+                const float x = kv[i];
+                mn = x < mn ? x : mn;
+                mx = x > mx ? x : mx;
+            }
+            lo = block_reduce(mn, redf, true);
+            float hi = block_reduce(mx, redf, false);
+            int need = P;
+            float kp = hi;
+            for (int level = 0; level < 3 && hi > lo; ++level) {
+                for (int b = tid; b < kBins; b += kSelThreads) hist[b] = 0;
+                __syncthreads();
+                const float scale = (float)kBins / (hi - lo);
+                for (int i = tid; i < T; i += kSelThreads) {
+                    const float x = kv[i];
+                    if (x >= lo && x <= hi) {
+                        int b = (int)((x - lo) * scale);
+                        b = b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
+                        atomicAdd(&hist[b], 1u);
+                    }
+                }
+                __syncthreads();
+                if (tid < 64) {
+                    constexpr int per = kBins / 64;
+                    uint32_t c[per], sum = 0;
+                    for (int j = 0; j < per; ++j) {
+                        c[j] = hist[tid * per + j];
+                        sum += c[j];
+                    }
+                    uint32_t x = sum;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const uint32_t y = __shfl_up(x, o);
+                        if (tid >= o) x += y;
+                    }
+                    uint32_t before = x - sum;
+                    for (int j = 0; j < per; ++j) {
+                        if (before < (uint32_t)need && before + c[j] >= (uint32_t)need) {
+                            s_bin = tid * per + j;
+                            s_need = need - (int)before;
+                        }
+                        before += c[j];
+                    }
+                }
+                __syncthreads();
+                const int bs = s_bin;
+                need = s_need;
+                // the keys of bin bs bound kP; narrow to that bin
+                float bmn = __builtin_huge_valf(), bmx = -__builtin_huge_valf();
+                for (int i = tid; i < T; i += kSelThreads) {
+                    const float x = kv[i];
+                    if (x >= lo && x <= hi) {
+                        int b = (int)((x - lo) * scale);
+                        b = b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
+                        if (b == bs) {
+                            bmn = x < bmn ? x : bmn;
+                            bmx = x > bmx ? x : bmx;
+                        }
+                    }
+                }
+                const float nlo = block_reduce(bmn, redf, true);
+                const float nhi = block_reduce(bmx, redf, false);
+                kp = nhi;
+                lo = nlo;
+                hi = nhi;
+            }
+            if (!(hi > lo)) kp = hi;
+            // survivors: ka <= kp + 2 err (kp is >= the P-th smallest approximate key)
+            const float thr = kp + 2.f * err;
+            if (tid == 0) s_cnt = 0;
+            __syncthreads();
+            int mine = 0;
+            for (int i = tid; i < T; i += kSelThreads) mine += kv[i] <= thr;
+            const int nsurv = block_sum(mine, redi);
+            if (nsurv <= S) {
+                for (int i = tid; i < T; i += kSelThreads) {
+                    if (kv[i] <= thr) {
+                        const int w = atomicAdd(&s_cnt, 1);
+                        if (w < S) {
+                            sk[w] = dkey(exact_key(qh, C + (int64_t)i * h, h));
+                            si[w] = i;
+                        }
+                    }
+                }
+                __syncthreads();
+                for (int i = nsurv + tid; i < S; i += kSelThreads) {
+                    sk[i] = ~0ull;
+                    si[i] = 0x7fffffff;
+                }
+                __syncthreads();
+                bitonic_kv(sk, si, S);
+                n_out = P;
+                done = true;
+            }
+        }
+    }
+    if (!done) {
+        // exact radix select over recomputed FP64 keys (many near-equal keys)
+        const int per = (T + kSelThreads - 1) / kSelThreads;
+        const int i0 = tid * per, i1 = min(T, i0 + per);
+        uint64_t kmin = ~0ull, kmax = 0;
+        for (int i = i0; i < i1; ++i) {
+            const uint64_t b = dkey(exact_key(qh, C + (int64_t)i * h, h));
+            kmin = b < kmin ? b : kmin;
+            kmax = b > kmax ? b : kmax;
+        }
+        kmin = block_reduce(kmin, red64, true);
+        kmax = block_reduce(kmax, red64, false);
+        uint64_t prefix = 0;
+        int need = P;
+        const uint64_t range = kmax - kmin;
+        const int nb = range ? 64 - __clzll((long long)range) : 0;
+        const int passes = (nb + 7) / 8;
+        for (int p = 0; p < passes; ++p) {
+            const int s = 8 * (passes - 1 - p);
+            for (int b = tid; b < 256; b += kSelThreads) hist[b] = 0;
+            __syncthreads();
+            for (int i = i0; i < i1; ++i) {
+                const uint64_t d = dkey(exact_key(qh, C + (int64_t)i * h, h)) - kmin;
+                const uint64_t hi = (s + 8 >= 64) ? 0 : (d >> (s + 8));
+                if (hi == prefix) atomicAdd(&hist[(d >> s) & 255], 1u);
+            }
+            __syncthreads();
+            if (tid < 64) {
+                uint32_t c[4], sum = 0;
+                for (int j = 0; j < 4; ++j) {
+                    c[j] = hist[tid * 4 + j];
+                    sum += c[j];
+                }
+                uint32_t x = sum;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(x, o);
+                    if (tid >= o) x += y;
+                }
+                uint32_t before = x - sum;
+                for (int j = 0; j < 4; ++j) {
+                    if (before < (uint32_t)need && before + c[j] >= (uint32_t)need) {
+                        s_bin = tid * 4 + j;
+                        s_need = need - (int)before;
+                    }
+                    before += c[j];
+                }
+            }
+            __syncthreads();
+            prefix = (prefix << 8) | (uint64_t)s_bin;
+            need = s_need;
+            __syncthreads();
+        }
+        const uint64_t kstar = kmin + prefix;
+        if (tid == 0) s_cnt = 0;
+        __syncthreads();
+        int my_eq = 0;
+        for (int i = i0; i < i1; ++i) {
+            const uint64_t b = dkey(exact_key(qh, C + (int64_t)i * h, h));
+            if (b < kstar) {
+                const int w = atomicAdd(&s_cnt, 1);
+                if (w < S) {
+                    sk[w] = b;
+                    si[w] = i;
+                }
+            } else if (b == kstar) {
+                ++my_eq;
+            }
+        }
+        int tot_eq;
+        const int eq_before = block_excl_scan(my_eq, redi, &tot_eq);
+        __syncthreads();
+        int ord = eq_before;
+        const int base = P - need;
+        for (int i = i0; i < i1 && ord < need; ++i) {
+            const uint64_t b = dkey(exact_key(qh, C + (int64_t)i * h, h));
+            if (b == kstar && base + ord < S) {
+                sk[base + ord] = b;
+                si[base + ord] = i;
+                ++ord;
+            }
+        }
+        __syncthreads();
+        for (int i = P + tid; i < S; i += kSelThreads) {
+            sk[i] = ~0ull;
+            si[i] = 0x7fffffff;
+        }
+        __syncthreads();
+        bitonic_kv(sk, si, S);
+        n_out = P;
+    }
+    double *ok = lkey + ((int64_t)slot * 2 + half) * P;
+    int32_t *oi = lidx + ((int64_t)slot * 2 + half) * P;
+    for (int i = tid; i < P; i += kSelThreads) {
+        ok[i] = i < n_out ? __longlong_as_double((long long)sk[i]) : __builtin_huge_val();
+        oi[i] = i < n_out ? si[i] : -1;
+    }
+}
+
+int select_sort_size(int P, int T)
+{
+    int S = 1;
+    const int need = P >= T ? T : 2 * P;
+    while (S < need) S <<= 1;
+    return S < 64 ? 64 : S;
+}
+
+size_t select_lds_bytes(int D, int T, int S)
+{
+    const int h = D / 2;
+    const size_t f = (size_t)((h + 3) & ~3) + (T <= kApproxLds ? (size_t)((T + 1) & ~1) : 0);
+    return f * 4 + (size_t)S * (sizeof(uint64_t) + sizeof(int32_t));
+}
+
+hipError_t launch_select_prefix(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
+                                const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
+                                hipStream_t st)
+{
+    if (nslots == 0) return hipSuccess;
+    const int S = select_sort_size(P, ix.T);
+    const size_t lds = select_lds_bytes(ix.D, ix.T, S);
+    hipLaunchKernelGGL(k_select_prefix, dim3((unsigned)nslots, 2), dim3(kSelThreads), lds, st, ka,
+                       q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist, P, S, lkey, lidx);
+    return hipGetLastError();
+}
+
+}  // namespace fbpq

@@ -1,0 +1,97 @@
+// Query-independent tables of the FBPQ distance (Section 3.1, equation
+// decomposition; sizes in Section 3.3). Built once per index.
+//
+//   CR1[i][k][r] = 2 <c1_i|k, R_k(r)>          k < M/2
+//   CR2[j][k][r] = 2 <c2_j|k, R_{M/2+k}(r)>    k < M/2
+//   nR[k][r]     = ||R_k(r)||^2
+//   nC1[i], nC2[j] = squared norms of the half centroids
+//
+// c|k is the k-th D/M slice of a half centroid. Accumulation is FP64, storage
+// FP32. One thread per table entry: the inner loop is D/M long, the whole
+// build is T*Kc*D FMAs, a one-off cost next to any search.
+#include "fbpq_dev.h"
+
+namespace fbpq {
+
+__global__ void k_cross_table(const float *__restrict__ C, const float *__restrict__ R, int T,
+                              int h, int M, int ds, int sub0, float *__restrict__ CR)
+{
+    const int Mh = M / 2;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)T * Mh * kKc;
+    if (e >= total) return;
+    const int r = (int)(e % kKc);
+    const int k = (int)((e / kKc) % Mh);
+    const int64_t i = e / ((int64_t)kKc * Mh);
+    const float *c = C + i * h + (int64_t)k * ds;
+    const float *w = R + ((int64_t)(sub0 + k) * kKc + r) * ds;
+    double acc = 0.0;
+    for (int t = 0; t < ds; ++t) acc += (double)c[t] * (double)w[t];
+    CR[e] = (float)(2.0 * acc);
+}
+
+__global__ void k_norms(const float *__restrict__ R, int M, int ds, const float *__restrict__ C1,
+                        const float *__restrict__ C2, int T, int h, float *__restrict__ nR,
+                        float *__restrict__ nC1, float *__restrict__ nC2)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nr = (int64_t)M * kKc;
+    if (e < nr) {
+        const float *w = R + e * ds;
+        double acc = 0.0;
+        for (int t = 0; t < ds; ++t) acc += (double)w[t] * (double)w[t];
+        nR[e] = (float)acc;
+    } else if (e < nr + 2 * (int64_t)T) {
+        const int64_t i = e - nr;
+        const float *c = i < T ? C1 + i * h : C2 + (i - T) * h;
+        double acc = 0.0;
+        for (int t = 0; t < h; ++t) acc += (double)c[t] * (double)c[t];
+        (i < T ? nC1[i] : nC2[i - T]) = (float)acc;
+    }
+}
+
+hipError_t launch_tables(const DevIndex &ix, float *CR1, float *CR2, float *nR, float *nC1,
+                         float *nC2, hipStream_t st)
+{
+    const int h = ix.D / 2, ds = ix.D / ix.M;
+    const int64_t total = (int64_t)ix.T * (ix.M / 2) * kKc;
+    const int bs = 256;
+    const unsigned grid = (unsigned)((total + bs - 1) / bs);
+    hipLaunchKernelGGL(k_cross_table, dim3(grid), dim3(bs), 0, st, ix.C1, ix.R, ix.T, h, ix.M, ds,
+                       0, CR1);
+    hipLaunchKernelGGL(k_cross_table, dim3(grid), dim3(bs), 0, st, ix.C2, ix.R, ix.T, h, ix.M, ds,
+                       ix.M / 2, CR2);
+    const int64_t nn = (int64_t)ix.M * kKc + 2 * (int64_t)ix.T;
+    hipLaunchKernelGGL(k_norms, dim3((unsigned)((nn + bs - 1) / bs)), dim3(bs), 0, st, ix.R, ix.M,
+                       ds, ix.C1, ix.C2, ix.T, h, nR, nC1, nC2);
+    return hipGetLastError();
+}
+
+}  // namespace fbpq
+
+namespace fbpq {
+
+// Split AoS codes [n][M] into the two half planes [n][M/2] used by the scan.
+__global__ void k_split_codes(const uint8_t *__restrict__ src, int64_t n, int M,
+                              uint8_t *__restrict__ a, uint8_t *__restrict__ b)
+{
+    const int Mh = M / 2;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * M) return;
+    const int64_t p = e / M;
+    const int k = (int)(e % M);
+    if (k < Mh) a[p * Mh + k] = src[e];
+    else b[p * Mh + (k - Mh)] = src[e];
+}
+
+hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, uint8_t *b,
+                              hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t total = n * M;
+    hipLaunchKernelGGL(k_split_codes, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src,
+                       n, M, a, b);
+    return hipGetLastError();
+}
+
+}  // namespace fbpq

@@ -1,0 +1,235 @@
+"""ctypes binding of libfbpq (include/fbpq.h): the same entry points, argument
+marshalling only. Every step of the search runs in the library's HIP kernels.
+
+Arrays are numpy arrays in host memory, or torch tensors on the index's GPU for
+fbpq_search_device (torch provides device memory and the stream). A missing or
+unloadable library raises at import time: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfbpq.so")
+
+FBPQ_OK = 0
+FBPQ_E_INVALID = -1
+FBPQ_E_IO = -2
+FBPQ_E_FORMAT = -3
+FBPQ_E_OOM = -4
+FBPQ_E_DEVICE = -5
+FBPQ_E_STATE = -6
+FBPQ_E_CAPACITY = -7
+FBPQ_KC = 256
+FBPQ_K_MAX = 1024
+
+EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbpq_build_tables",
+           "fbpq_search", "fbpq_search_uneven", "fbpq_search_device", "fbpq_debug_visit",
+           "fbpq_debug_dists", "fbpq_debug_tables", "fbpq_debug_rank", "fbpq_info",
+           "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_free_index",
+           "fbpq_last_error")
+STAGES = ("half_keys", "prefix", "traverse", "layout", "scan")
+
+
+class FbpqError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fbpq error {code}: {msg}")
+        self.code = code
+
+
+class IndexDesc(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("T", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("Kc", ctypes.c_int32), ("N", ctypes.c_int64), ("C1", ctypes.c_void_p),
+                ("C2", ctypes.c_void_p), ("R", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("codes", ctypes.c_void_p), ("ids", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("T", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("Kc", ctypes.c_int32), ("N", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
+                ("norm_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("tables_ready", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built (run paper_1404_1831_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "fbpq_index_create": ([P, ctypes.c_int, P], ctypes.c_int),
+        "fbpq_load_index": ([ctypes.c_char_p, ctypes.c_int, P], ctypes.c_int),
+        "fbpq_index_file_check": ([ctypes.c_char_p, P], ctypes.c_int),
+        "fbpq_build_tables": ([P], ctypes.c_int),
+        "fbpq_search": ([P, P, i64, i64, i32, P, P], ctypes.c_int),
+        "fbpq_search_uneven": ([P, P, i64, P, P, i32, P, P], ctypes.c_int),
+        "fbpq_search_device": ([P, P, i64, P, P, i32, P, P, P], ctypes.c_int),
+        "fbpq_debug_visit": ([P, P, i64, i64, P, i64, P, P, i64, P], ctypes.c_int),
+        "fbpq_debug_dists": ([P, P, i64, i64, P, P, i64, P], ctypes.c_int),
+        "fbpq_debug_tables": ([P, P, P, P, P, P], ctypes.c_int),
+        "fbpq_debug_rank": ([P, P, i64, i32, P, P], ctypes.c_int),
+        "fbpq_info": ([P, P], ctypes.c_int),
+        "fbpq_table_bytes": ([i64, i64, i64, P, P], ctypes.c_int),
+        "fbpq_set_option": ([P, ctypes.c_char_p, i64], ctypes.c_int),
+        "fbpq_profile_read": ([P, i32, i32, P, P], ctypes.c_int),
+        "fbpq_free_index": ([P], None),
+        "fbpq_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int) -> None:
+    if rc != FBPQ_OK:
+        raise FbpqError(rc, lib.fbpq_last_error().decode())
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def fbpq_last_error() -> str:
+    return lib.fbpq_last_error().decode()
+
+
+def fbpq_table_bytes(T: int, M: int, Kc: int = FBPQ_KC):
+    tb, nb = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.fbpq_table_bytes(T, M, Kc, ctypes.byref(tb), ctypes.byref(nb)))
+    return tb.value, nb.value
+
+
+def fbpq_index_file_check(path: str) -> Info:
+    info = Info()
+    _check(lib.fbpq_index_file_check(path.encode(), ctypes.byref(info)))
+    return info
+
+
+def fbpq_index_create(ix, device: int = 0) -> ctypes.c_void_p:
+    """ix: any object with D, T, M, Kc, C1, C2, R, offsets, codes, ids (numpy)."""
+    keep = [np.ascontiguousarray(ix.C1, np.float32), np.ascontiguousarray(ix.C2, np.float32),
+            np.ascontiguousarray(ix.R, np.float32), np.ascontiguousarray(ix.offsets, np.int64),
+            np.ascontiguousarray(ix.codes, np.uint8), np.ascontiguousarray(ix.ids, np.uint32)]
+    d = IndexDesc(ix.D, ix.T, ix.M, ix.Kc, keep[4].shape[0], *[_p(a) for a in keep])
+    h = ctypes.c_void_p()
+    _check(lib.fbpq_index_create(ctypes.byref(d), device, ctypes.byref(h)))
+    return h
+
+
+def fbpq_load_index(path: str, device: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib.fbpq_load_index(path.encode(), device, ctypes.byref(h)))
+    return h
+
+
+def fbpq_build_tables(h) -> None:
+    _check(lib.fbpq_build_tables(h))
+
+
+def fbpq_info(h) -> Info:
+    info = Info()
+    _check(lib.fbpq_info(h, ctypes.byref(info)))
+    return info
+
+
+def fbpq_set_option(h, key: str, value: int) -> None:
+    _check(lib.fbpq_set_option(h, key.encode(), int(value)))
+
+
+def fbpq_profile_read(h, stage: int, reset: bool = False):
+    """(milliseconds, launches) accumulated for a kernel stage while profiling."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib.fbpq_profile_read(h, int(stage), int(reset), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def fbpq_free_index(h) -> None:
+    lib.fbpq_free_index(h)
+
+
+def fbpq_search(h, q: np.ndarray, L: int, k: int):
+    q = np.ascontiguousarray(q, np.float32)
+    nq = q.shape[0]
+    ids = np.empty((nq, k), np.int64)
+    d = np.empty((nq, k), np.float32)
+    _check(lib.fbpq_search(h, _p(q), nq, int(L), int(k), _p(ids), _p(d)))
+    return ids, d
+
+
+def fbpq_search_uneven(h, q: np.ndarray, L, k, k_max: int):
+    q = np.ascontiguousarray(q, np.float32)
+    nq = q.shape[0]
+    L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, np.int64), (nq,)))
+    k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
+    ids = np.empty((nq, k_max), np.int64)
+    d = np.empty((nq, k_max), np.float32)
+    _check(lib.fbpq_search_uneven(h, _p(q), nq, _p(L), _p(k), int(k_max), _p(ids), _p(d)))
+    return ids, d
+
+
+def fbpq_search_device(h, d_q, L: np.ndarray, k: np.ndarray, k_max: int, d_ids, d_dists,
+                       stream=None) -> None:
+    """d_q, d_ids, d_dists: contiguous torch tensors on the index's GPU
+    (float32 [nq, D], int64 [nq, k_max], float32 [nq, k_max]); L, k: host arrays."""
+    nq = d_q.shape[0]
+    assert d_q.is_contiguous() and d_ids.is_contiguous() and d_dists.is_contiguous()
+    L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, np.int64), (nq,)))
+    k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
+    st = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+    _check(lib.fbpq_search_device(h, ctypes.c_void_p(d_q.data_ptr()), nq, _p(L), _p(k), int(k_max),
+                                  ctypes.c_void_p(d_ids.data_ptr()), ctypes.c_void_p(d_dists.data_ptr()),
+                                  st))
+
+
+def fbpq_debug_visit(h, q: np.ndarray, L: int, cells_cap: int, pos_cap: int):
+    """Per query: (cells [n][2] of (cell id, points taken), positions) in visit order."""
+    q = np.ascontiguousarray(q, np.float32)
+    nq = q.shape[0]
+    cells = np.zeros((nq, cells_cap, 2), np.int64)
+    ncells = np.zeros(nq, np.int64)
+    pos = np.zeros((nq, pos_cap), np.int64)
+    npos = np.zeros(nq, np.int64)
+    _check(lib.fbpq_debug_visit(h, _p(q), nq, int(L), _p(cells), cells_cap, _p(ncells), _p(pos),
+                                pos_cap, _p(npos)))
+    return [(cells[r, :ncells[r]], pos[r, :npos[r]]) for r in range(nq)]
+
+
+def fbpq_debug_dists(h, q: np.ndarray, L: int, cap: int):
+    """Per query: (storage positions, FP32 FBPQ distances) of all candidates."""
+    q = np.ascontiguousarray(q, np.float32)
+    nq = q.shape[0]
+    pos = np.zeros((nq, cap), np.int64)
+    d = np.zeros((nq, cap), np.float32)
+    n = np.zeros(nq, np.int64)
+    _check(lib.fbpq_debug_dists(h, _p(q), nq, int(L), _p(pos), _p(d), cap, _p(n)))
+    return [(pos[r, :n[r]], d[r, :n[r]]) for r in range(nq)]
+
+
+def fbpq_debug_tables(h):
+    info = fbpq_info(h)
+    T, M = info.T, info.M
+    CR1 = np.empty((T, M // 2, FBPQ_KC), np.float32)
+    CR2 = np.empty((T, M // 2, FBPQ_KC), np.float32)
+    nR = np.empty((M, FBPQ_KC), np.float32)
+    nC1 = np.empty(T, np.float32)
+    nC2 = np.empty(T, np.float32)
+    _check(lib.fbpq_debug_tables(h, _p(CR1), _p(CR2), _p(nR), _p(nC1), _p(nC2)))
+    return CR1, CR2, nR, nC1, nC2
+
+
+def fbpq_debug_rank(h, q: np.ndarray, P: int):
+    q = np.ascontiguousarray(q, np.float32)
+    nq = q.shape[0]
+    keys = np.empty((nq, 2, P), np.float64)
+    idx = np.empty((nq, 2, P), np.int32)
+    _check(lib.fbpq_debug_rank(h, _p(q), nq, int(P), _p(keys), _p(idx)))
+    return keys, idx

@@ -1,0 +1,115 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+declared in include/fbpq.h, and validates index files without a GPU."""
+
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def fb():
+    lib = os.path.join(ROOT, "paper_1404_1831_amd", "libfbpq.so")
+    if not os.path.exists(lib):
+        from paper_1404_1831_amd.build import build
+        build()
+    from paper_1404_1831_amd import fbpq
+    return fbpq
+
+
+def test_exports_match_header(fb):
+    hdr = open(os.path.join(ROOT, "include", "fbpq.h")).read()
+    declared = set(re.findall(r"\b(fbpq_[a-z_]+)\s*\(", hdr))
+    assert declared == set(fb.EXPORTS)
+    for name in declared:
+        assert hasattr(fb.lib, name)
+
+
+def test_table_bytes_golden(fb):
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "table_memory.json")))
+    tb, nb = fb.fbpq_table_bytes(g["T"], g["M"], g["K"])
+    assert tb == g["dot_product_bytes"]
+    assert nb < g["norm_bytes_below"]
+    assert nb == (2 * g["T"] + g["M"] * g["K"]) * 4
+
+
+def _write(tmp_path, ix, name="ix.bin"):
+    p = str(tmp_path / name)
+    synth.write_index(p, ix)
+    return p
+
+
+def test_index_file_roundtrip_and_check(fb, tmp_path):
+    ix = synth.random_index(N=500, T=8, M=4, D=16, seed=1)
+    p = _write(tmp_path, ix)
+    info = fb.fbpq_index_file_check(p)
+    assert (info.D, info.T, info.M, info.Kc, info.N) == (16, 8, 4, 256, 500)
+    back = synth.read_index(p)
+    for a in ("C1", "C2", "R", "offsets", "codes", "ids"):
+        assert np.array_equal(getattr(back, a), getattr(ix, a))
+
+
+def test_index_file_errors(fb, tmp_path):
+    ix = synth.random_index(N=300, T=4, M=2, D=8, seed=2)
+    p = _write(tmp_path, ix)
+    raw = bytearray(open(p, "rb").read())
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_index_file_check(str(tmp_path / "missing.bin"))
+    assert e.value.code == fb.FBPQ_E_IO
+    bad = bytearray(raw)
+    bad[0:8] = b"NOTFBPQ!"
+    (tmp_path / "magic.bin").write_bytes(bytes(bad))
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_index_file_check(str(tmp_path / "magic.bin"))
+    assert e.value.code == fb.FBPQ_E_FORMAT
+    bad = bytearray(raw)
+    bad[-5] ^= 0xFF  # payload byte of the ids section: CRC must catch it
+    (tmp_path / "crc.bin").write_bytes(bytes(bad))
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_index_file_check(str(tmp_path / "crc.bin"))
+    assert e.value.code == fb.FBPQ_E_FORMAT
+    (tmp_path / "short.bin").write_bytes(bytes(raw[:len(raw) // 2]))
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_index_file_check(str(tmp_path / "short.bin"))
+    assert e.value.code == fb.FBPQ_E_FORMAT
+    # decreasing offsets with valid CRCs
+    ix2 = synth.random_index(N=300, T=4, M=2, D=8, seed=2)
+    ix2.offsets = ix2.offsets.copy()
+    ix2.offsets[3], ix2.offsets[4] = ix2.offsets[4] + 1, ix2.offsets[3]
+    p2 = str(tmp_path / "offs.bin")
+    import zlib
+    # write bypassing Index.check so the bad offsets reach the file
+    arrays = [ix2.C1, ix2.C2, ix2.R, ix2.offsets, ix2.codes, ix2.ids]
+    from synth.indexfile import HDR, SEC, MAGIC, _align
+    pos = _align(HDR.size + SEC.size * 6)
+    recs = []
+    for k, a in enumerate(arrays):
+        a = np.ascontiguousarray(a)
+        recs.append((k + 1, zlib.crc32(a.tobytes()) & 0xFFFFFFFF, pos, a.nbytes, 0))
+        pos = _align(pos + a.nbytes)
+    with open(p2, "wb") as f:
+        f.write(HDR.pack(MAGIC, 1, ix2.D, ix2.T, ix2.M, ix2.Kc, 6, ix2.N, b"\0" * 24))
+        for r in recs:
+            f.write(SEC.pack(*r))
+        for r, a in zip(recs, arrays):
+            f.seek(r[2])
+            np.ascontiguousarray(a).tofile(f)
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_index_file_check(p2)
+    assert e.value.code == fb.FBPQ_E_FORMAT
+    assert "offsets" in str(e.value)
+
+
+def test_invalid_arguments_without_gpu(fb):
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_table_bytes(0, 8, 256)
+    assert e.value.code == fb.FBPQ_E_INVALID
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_set_option(None, "prefix", 4)
+    assert e.value.code == fb.FBPQ_E_INVALID

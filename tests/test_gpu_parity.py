@@ -1,0 +1,304 @@
+"""GPU parity: the HIP search through the C ABI against the FP64 oracle.
+
+Visited-cell lists and candidate positions must be bit-exact, sorted prefixes of
+the half lists bit-exact (FP64 keys and indices), per-candidate distances and
+the top-k within the tolerance of tests/parity.py.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import assert_topk, log, oracle_dists, tol
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fb():
+    from paper_1404_1831_amd import fbpq  # raises if the library is not built
+    return fbpq
+
+
+def _open(fb, ix, **opts):
+    h = fb.fbpq_index_create(ix, 0)
+    fb.fbpq_build_tables(h)
+    for k, v in opts.items():
+        fb.fbpq_set_option(h, k, v)
+    return h
+
+
+@pytest.fixture(scope="module")
+def gmm_small():
+    # 100k SIFT-like points, T=64 per half (4096 cells), M=8: the plain-FBPQ workload
+    means = synth.gmm_means(0)
+    base = synth.sample_points(100000, means, 1)
+    ix = synth.build_index(base, 64, 8)
+    Q = synth.make_queries(100, means, 2)
+    return ix, Q
+
+
+@pytest.fixture(scope="module")
+def gmm_m16():
+    means = synth.gmm_means(0)
+    base = synth.sample_points(60000, means, 1)
+    ix = synth.build_index(base, 128, 16, train_n=10000)
+    Q = synth.make_queries(40, means, 2)
+    return ix, Q
+
+
+def test_tables_match_fp64(fb, gmm_m16):
+    ix, _ = gmm_m16
+    log("tables: T=128 M=16")
+    h = _open(fb, ix)
+    CR1, CR2, nR, nC1, nC2 = fb.fbpq_debug_tables(h)
+    fb.fbpq_free_index(h)
+    C1, C2, R = (a.astype(np.float64) for a in (ix.C1, ix.C2, ix.R))
+    M, ds = ix.M, ix.D // ix.M
+    for k in range(M // 2):
+        ref1 = 2 * C1[:, k * ds:(k + 1) * ds] @ R[k].T
+        ref2 = 2 * C2[:, k * ds:(k + 1) * ds] @ R[M // 2 + k].T
+        np.testing.assert_allclose(CR1[:, k], ref1, rtol=1e-6, atol=1e-6 * np.abs(ref1).max())
+        np.testing.assert_allclose(CR2[:, k], ref2, rtol=1e-6, atol=1e-6 * np.abs(ref2).max())
+    np.testing.assert_allclose(nR, (R * R).sum(2), rtol=1e-6)
+    np.testing.assert_allclose(nC1, (C1 * C1).sum(1), rtol=1e-6)
+    np.testing.assert_allclose(nC2, (C2 * C2).sum(1), rtol=1e-6)
+
+
+@pytest.mark.parametrize("P", [64, 17, 1])
+def test_rank_prefix_bitexact(fb, gmm_small, P):
+    ix, Q = gmm_small
+    log(f"rank prefix: T=64 P={P}")
+    h = _open(fb, ix)
+    keys, idx = fb.fbpq_debug_rank(h, Q[:30], P)
+    fb.fbpq_free_index(h)
+    for r in range(30):
+        d1, d2, u, v = oracle.rank_lists(ix, Q[r])
+        assert np.array_equal(idx[r, 0], u[:P]) and np.array_equal(idx[r, 1], v[:P])
+        assert np.array_equal(keys[r, 0], d1[u[:P]]) and np.array_equal(keys[r, 1], d2[v[:P]])
+
+
+def test_rank_prefix_ties(fb):
+    # integer centroids with many duplicates: equal keys ordered by index
+    ix = synth.random_index(N=2000, T=300, M=4, D=16, seed=3, int_valued=True)
+    ix.C1[100:200] = ix.C1[:100]
+    rng = np.random.default_rng(4)
+    Q = rng.integers(0, 32, (8, 16)).astype(np.float32)
+    log("rank prefix ties: T=300")
+    h = _open(fb, ix)
+    for P in (300, 128, 5):
+        keys, idx = fb.fbpq_debug_rank(h, Q, P)
+        for r in range(8):
+            d1, d2, u, v = oracle.rank_lists(ix, Q[r])
+            assert np.array_equal(idx[r, 0], u[:P]) and np.array_equal(idx[r, 1], v[:P]), P
+            assert np.array_equal(keys[r, 0], d1[u[:P]]) and np.array_equal(keys[r, 1], d2[v[:P]])
+    fb.fbpq_free_index(h)
+
+
+def _check_visit(fb, h, ix, Q, L):
+    got = fb.fbpq_debug_visit(h, Q, L, cells_cap=ix.T * ix.T + 1, pos_cap=max(1, min(L, ix.N)))
+    for r in range(Q.shape[0]):
+        cells, pos = oracle.visit(ix, Q[r], L)
+        gc, gp = got[r]
+        assert np.array_equal(gc, cells), (r, L, gc.shape, cells.shape)
+        assert np.array_equal(gp, pos), (r, L)
+
+
+@pytest.mark.parametrize("L", [10000, 1, 777, 100000, 250000])
+def test_visit_bitexact_gmm(fb, gmm_small, L):
+    ix, Q = gmm_small
+    log(f"visit: N=1e5 T=64 L={L}")
+    h = _open(fb, ix)
+    _check_visit(fb, h, ix, Q[:50], L)
+    fb.fbpq_free_index(h)
+
+
+def test_visit_retries_prefix_and_cells(fb, gmm_small):
+    ix, Q = gmm_small
+    log("visit with prefix=1, max_cells=64 (forced second rounds)")
+    h = _open(fb, ix, prefix=1, max_cells=64)
+    _check_visit(fb, h, ix, Q[:20], 10000)
+    fb.fbpq_free_index(h)
+
+
+@pytest.mark.parametrize("T,seed", [(1, 0), (2, 1), (3, 2), (8, 3), (16, 4), (40, 5)])
+def test_visit_tiny_with_ties_and_empty_cells(fb, T, seed):
+    rng = np.random.default_rng(200 + seed)
+    counts = rng.integers(0, 5, T * T) * (rng.random(T * T) < 0.5)
+    if counts.sum() == 0:
+        counts[0] = 2
+    ix = synth.tiny_index(T, counts, M=2, D=4, seed=seed)
+    Q = rng.integers(0, 6, (6, 4)).astype(np.float32)
+    log(f"visit tiny: T={T} N={ix.N}")
+    h = _open(fb, ix)
+    for L in sorted({1, 2, max(1, ix.N // 2), ix.N, ix.N + 3}):
+        _check_visit(fb, h, ix, Q, L)
+    fb.fbpq_free_index(h)
+
+
+def test_candidate_distances_within_tolerance(fb, gmm_small):
+    ix, Q = gmm_small
+    L = 10000
+    log("per-candidate FBPQ distances: N=1e5 T=64 M=8 L=1e4")
+    h = _open(fb, ix)
+    got = fb.fbpq_debug_dists(h, Q[:20], L, cap=L)
+    fb.fbpq_free_index(h)
+    for r in range(20):
+        pos, d32 = got[r]
+        _, opos = oracle.visit(ix, Q[r], L)
+        assert np.array_equal(np.sort(pos), np.sort(opos))
+        d64 = oracle_dists(ix, Q[r], pos)
+        t = tol(ix, Q[r], pos, d64)
+        err = np.abs(d32.astype(np.float64) - d64)
+        assert np.all(err <= t), (r, float((err / t).max()))
+
+
+def test_candidate_distances_m16_chunked(fb, gmm_m16):
+    ix, Q = gmm_m16
+    L = 5000
+    log("per-candidate distances: T=128 M=16 L=5000 chunk=1024")
+    h = _open(fb, ix, chunk=1024)
+    got = fb.fbpq_debug_dists(h, Q[:10], L, cap=L)
+    fb.fbpq_free_index(h)
+    for r in range(10):
+        pos, d32 = got[r]
+        _, opos = oracle.visit(ix, Q[r], L)
+        assert np.array_equal(np.sort(pos), np.sort(opos))
+        d64 = oracle_dists(ix, Q[r], pos)
+        assert np.all(np.abs(d32 - d64) <= tol(ix, Q[r], pos, d64))
+
+
+def test_search_cfg0_topk(fb, gmm_small):
+    ix, Q = gmm_small
+    L, k = 10000, 10
+    log("search: N=1e5 T=64 M=8 nq=100 L=1e4 k=10")
+    h = _open(fb, ix)
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    g2_ids, g2_d = fb.fbpq_search(h, Q, L, k)
+    fb.fbpq_free_index(h)
+    assert np.array_equal(g_ids, g2_ids) and np.array_equal(g_d, g2_d), "not deterministic"
+    o_ids, o_d, ncand, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+    # recall@10 against exact NN equals the oracle's
+    X = ix.base.astype(np.float64)
+    exact = np.array([np.argmin(((X - q.astype(np.float64)) ** 2).sum(1)) for q in Q])
+    r_gpu = np.mean([exact[i] in g_ids[i] for i in range(len(Q))])
+    r_orc = np.mean([exact[i] in o_ids[i] for i in range(len(Q))])
+    log(f"recall@10 gpu={r_gpu:.3f} oracle={r_orc:.3f}")
+    assert r_gpu == r_orc
+
+
+@pytest.mark.parametrize("chunk", [8192, 512])
+def test_search_m16_k100_chunks(fb, gmm_m16, chunk):
+    ix, Q = gmm_m16
+    L, k = 6000, 100
+    log(f"search: T=128 M=16 L=6000 k=100 chunk={chunk}")
+    h = _open(fb, ix, chunk=chunk)
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
+def test_search_uneven_L_k(fb, gmm_small):
+    ix, Q = gmm_small
+    rng = np.random.default_rng(9)
+    L = rng.integers(1, 30000, Q.shape[0])
+    L[:3] = [1, ix.N, ix.N + 100]
+    k = rng.choice([1, 10, 100], Q.shape[0]).astype(np.int32)
+    log("search uneven L/k: N=1e5 T=64")
+    h = _open(fb, ix)
+    g_ids, g_d = fb.fbpq_search_uneven(h, Q, L, k, 100)
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k, kmax=100)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
+def test_lossless_exact_knn_with_ties(fb):
+    ix = synth.lossless_index(N=5000, T=16, M=4, D=16, seed=7, dup=1000, shuffle_ids=True)
+    rng = np.random.default_rng(5)
+    Q = ix.base[ix.ids[-rng.integers(1, 1000, 12)]] + rng.integers(-1, 2, (12, 16)).astype(np.float32)
+    k = 30
+    log("lossless with duplicates: N=5000 T=16 M=4 L>N")
+    h = _open(fb, ix)
+    g_ids, g_d = fb.fbpq_search(h, Q, ix.N + 1, k)
+    fb.fbpq_free_index(h)
+    X = ix.base.astype(np.float64)
+    for r in range(12):
+        dd = ((X - Q[r].astype(np.float64)) ** 2).sum(1)
+        order = np.lexsort((np.arange(ix.N), dd))[:k]
+        # integer data: FP32 FBPQ distances are exact here, ties break by id
+        assert np.array_equal(g_ids[r], order), r
+        assert np.array_equal(g_d[r].astype(np.float64), dd[order]), r
+
+
+def test_padding_k_above_L_and_empty(fb):
+    ix = synth.random_index(N=400, T=8, M=4, D=16, seed=12, empty_frac=0.6)
+    rng = np.random.default_rng(1)
+    Q = (rng.random((5, 16)) * 100).astype(np.float32)
+    log("padding: L=7 k=20; nq=0")
+    h = _open(fb, ix)
+    g_ids, g_d = fb.fbpq_search(h, Q, 7, 20)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, 7, 20)
+    assert_topk(ix, Q, 20, g_ids, g_d, o_ids, o_d)
+    assert np.all(g_ids[:, 7:] == -1) and np.all(np.isinf(g_d[:, 7:]))
+    e_ids, e_d = fb.fbpq_search(h, Q[:0], 7, 20)
+    assert e_ids.shape == (0, 20)
+    fb.fbpq_free_index(h)
+
+
+@pytest.mark.parametrize("M,D", [(2, 16), (4, 16), (16, 32), (32, 64)])
+def test_code_lengths(fb, M, D):
+    ix = synth.random_index(N=3000, T=12, M=M, D=D, seed=M)
+    rng = np.random.default_rng(M)
+    Q = (rng.random((6, D)) * 100).astype(np.float32)
+    log(f"code length M={M} D={D}")
+    h = _open(fb, ix)
+    g_ids, g_d = fb.fbpq_search(h, Q, 900, 25)
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, 900, 25)
+    assert_topk(ix, Q, 25, g_ids, g_d, o_ids, o_d)
+
+
+def test_T1_single_cell(fb):
+    ix = synth.random_index(N=3000, T=1, M=8, D=32, seed=9)
+    rng = np.random.default_rng(2)
+    Q = (rng.random((4, 32)) * 50).astype(np.float32)
+    log("T=1 (exhaustive PQ-ADC)")
+    h = _open(fb, ix)
+    g_ids, g_d = fb.fbpq_search(h, Q, 10 ** 9, 40)
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, 10 ** 9, 40)
+    assert_topk(ix, Q, 40, g_ids, g_d, o_ids, o_d)
+
+
+def test_load_index_file_matches_create(fb, gmm_small, tmp_path):
+    ix, Q = gmm_small
+    p = str(tmp_path / "ix.bin")
+    synth.write_index(p, ix)
+    log("load from file")
+    h1 = _open(fb, ix)
+    h2 = fb.fbpq_load_index(p, 0)
+    fb.fbpq_build_tables(h2)
+    a = fb.fbpq_search(h1, Q[:20], 5000, 10)
+    b = fb.fbpq_search(h2, Q[:20], 5000, 10)
+    info = fb.fbpq_info(h2)
+    fb.fbpq_free_index(h1)
+    fb.fbpq_free_index(h2)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert info.tables_ready == 1 and info.table_bytes == 64 * 8 * 256 * 4
+
+
+def test_errors(fb, gmm_small):
+    ix, Q = gmm_small
+    h = fb.fbpq_index_create(ix, 0)
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_search(h, Q[:2], 100, 10)
+    assert e.value.code == fb.FBPQ_E_STATE
+    fb.fbpq_build_tables(h)
+    for L, k in ((0, 10), (100, 0), (100, 2000)):
+        with pytest.raises(fb.FbpqError) as e:
+            fb.fbpq_search(h, Q[:2], L, k)
+        assert e.value.code == fb.FBPQ_E_INVALID
+    fb.fbpq_free_index(h)
