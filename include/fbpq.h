@@ -163,8 +163,10 @@ int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int
 
 /* Tuning knobs (autotuner and tests). Keys: "prefix" (initial sorted-list
  * length P), "max_cells" (initial per-query visited-cell capacity), "chunk"
- * (candidates per scan chunk), "profile" (0/1: time every kernel launch with
- * HIP events, read with fbpq_profile_read). Errors: INVALID. */
+ * (candidates per scan chunk), "items" (0/1: use the work-item scan for
+ * queries whose visited cells hold many points; 0 sends every query to the
+ * two-pass scan), "profile" (0/1: time every kernel launch with HIP events,
+ * read with fbpq_profile_read). Errors: INVALID. */
 int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 
 /* Kernel stages timed by the library's profiler. */
@@ -172,8 +174,10 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 #define FBPQ_STAGE_PREFIX 1    /* sorted prefix of each half list */
 #define FBPQ_STAGE_TRAVERSE 2  /* multi-sequence traversal */
 #define FBPQ_STAGE_LAYOUT 3    /* row-major layout of the visited cells */
-#define FBPQ_STAGE_SCAN 4      /* LUT + FBPQ distance scan + top-k */
-#define FBPQ_NUM_STAGES 5
+#define FBPQ_STAGE_SCAN 4      /* two-pass scan (queries whose cells hold few points) */
+#define FBPQ_STAGE_ITEMS 5     /* item scan: the persistent kernel over work items */
+#define FBPQ_STAGE_MERGE 6     /* item scan: per-query tables, item offsets, final merge */
+#define FBPQ_NUM_STAGES 7
 
 /* Device time per kernel stage, measured with HIP events recorded on the
  * search stream around every launch while profiling is on (option "profile"

@@ -16,7 +16,7 @@
 
 using namespace fbpq;
 
-static constexpr size_t kScanLdsLimit = 76 * 1024;  // two scan workgroups per CU (160 KB LDS)
+static constexpr size_t kScanLdsLimit = 74 * 1024;  // two scan workgroups per CU (160 KB LDS)
 
 namespace {
 
@@ -54,7 +54,7 @@ struct fbpq_index {
     float *CR1 = nullptr, *CR2 = nullptr, *nR = nullptr, *nC1 = nullptr, *nC2 = nullptr;
     size_t base_bytes = 0, table_bytes = 0;
     // workspace, grown on demand
-    DevBuf ws[32];
+    DevBuf ws[40];
     void *pinned = nullptr;
     size_t pinned_cap = 0;
     // profiler: events recorded around launches while `profile` is on
@@ -71,6 +71,8 @@ struct fbpq_index {
     int32_t prefix = 128;
     int64_t max_cells = 4096;
     int32_t chunk = 8192;
+    bool items = true;
+    int item_grid[32] = {0};
 };
 
 namespace {
@@ -78,7 +80,8 @@ namespace {
 enum WsSlot {
     W_Q, W_KEYS, W_LKEY, W_LIDX, W_HDR, W_W, W_ROWNE, W_ROWCAND, W_COLNE, W_COLTOT, W_NECS,
     W_NECNT, W_NEBEG, W_NECST, W_CMCELL, W_CMPRE, W_L, W_K, W_QLIST, W_FAIL, W_IDS, W_D,
-    W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NSLOTS
+    W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NESLOT, W_SLOTIJ, W_ITEMCELL,
+    W_ITEMSUB, W_ITEMSTART, W_COUNTER, W_LQ, W_ITEMOUT, W_ITEMN, W_NSLOTS
 };
 
 #define HCK(ix, expr)                                                                           \
@@ -460,7 +463,7 @@ struct DebugOut {
     } while (0)
 
 int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, const int32_t *d_qlist,
-              int32_t P, int64_t max_cells, const int64_t *d_L, const int32_t *d_k, int32_t k_max,
+              int32_t P, int64_t max_cells, int64_t lcap, const int64_t *d_L, const int32_t *d_k, int32_t k_max,
               int64_t *d_ids, float *d_d, hipStream_t st, const float *keys, int32_t *d_fail,
               const DebugOut *dbg, int64_t *fail_host_count)
 {
@@ -481,6 +484,11 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
     TRY(ws_get(ix, W_NECST, sizeof(float) * nslots * max_cells, &necst));
     TRY(ws_get(ix, W_CMCELL, sizeof(int32_t) * nslots * max_cells, &cmcell));
     TRY(ws_get(ix, W_CMPRE, sizeof(int32_t) * nslots * max_cells, &cmpre));
+    void *neslot, *slotij, *itcell, *itsub;
+    TRY(ws_get(ix, W_NESLOT, sizeof(int32_t) * nslots * max_cells, &neslot));
+    TRY(ws_get(ix, W_SLOTIJ, sizeof(int32_t) * nslots * 2 * P, &slotij));
+    TRY(ws_get(ix, W_ITEMCELL, sizeof(int32_t) * nslots * kMaxItems, &itcell));
+    TRY(ws_get(ix, W_ITEMSUB, sizeof(int32_t) * nslots * kMaxItems, &itsub));
     void *dab = nullptr, *dtake = nullptr, *dbeg = nullptr, *dpos = nullptr, *ddd = nullptr;
     if (dbg && dbg->visit) {
         TRY(ws_get(ix, W_DBGAB, sizeof(int32_t) * 2 * nslots * max_cells, &dab));
@@ -528,7 +536,58 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         la.ne_cst = (float *)necst;
         la.cm_cell = (int32_t *)cmcell;
         la.cm_pre = (int32_t *)cmpre;
+        la.ne_slot = (int32_t *)neslot;
+        la.slot_ij = (int32_t *)slotij;
+        la.item_cell = (int32_t *)itcell;
+        la.item_sub = (int32_t *)itsub;
+        la.allow_items = ix->items ? 1 : 0;
         HCK(ix, timed(ix, FBPQ_STAGE_LAYOUT, st, [&] { return launch_layout(la, nslots, st); }));
+        if (ix->items) {
+            const int wcap = items_wcap(k_max);
+            void *itstart, *items, *lq, *dist;
+            TRY(ws_get(ix, W_ITEMSTART, sizeof(int32_t) * (nslots + 1), &itstart));
+            TRY(ws_get(ix, W_ITEMOUT, sizeof(ItemRec) * nslots * kMaxItems, &items));
+            TRY(ws_get(ix, W_LQ, sizeof(float) * nslots * dv.M * FBPQ_KC, &lq));
+            TRY(ws_get(ix, W_ITEMN, sizeof(float) * nslots * lcap, &dist));
+            ItemArgs ia{};
+            ia.ix = dv;
+            ia.q = d_q;
+            ia.qlist = d_qlist;
+            ia.k = d_k;
+            ia.k_max = k_max;
+            ia.P = P;
+            ia.nslots = nslots;
+            ia.hdr = (const TravHdr *)hdr;
+            ia.max_cells = max_cells;
+            ia.ne_cs = (const int32_t *)necs;
+            ia.ne_cnt = (const int32_t *)necnt;
+            ia.ne_beg = (const int64_t *)nebeg;
+            ia.ne_cst = (const float *)necst;
+            ia.ne_slot = (const int32_t *)neslot;
+            ia.slot_ij = (const int32_t *)slotij;
+            ia.item_cell = (const int32_t *)itcell;
+            ia.item_sub = (const int32_t *)itsub;
+            ia.item_start = (int32_t *)itstart;
+            ia.items = (ItemRec *)items;
+            ia.lq = (float *)lq;
+            ia.dist = (float *)dist;
+            ia.lcap = lcap;
+            ia.wcap = wcap;
+            if (ix->item_grid[dv.M / 2 % 32] == 0) ix->item_grid[dv.M / 2 % 32] = items_grid(dv.M);
+            ia.grid = ix->item_grid[dv.M / 2 % 32];
+            // three selection workgroups per CU
+            int schunk = 12288;
+            while (schunk > 1024 && select_dist_lds(schunk, k_max) > 50 * 1024) schunk -= 1024;
+            ia.chunk = schunk;
+            ia.out_ids = d_ids;
+            ia.out_d = d_d;
+            ia.dbg_pos = (int64_t *)dpos;
+            ia.dbg_d = (float *)ddd;
+            ia.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
+            HCK(ix, timed(ix, FBPQ_STAGE_MERGE, st, [&] { return launch_items_prep(ia, st); }));
+            HCK(ix, timed(ix, FBPQ_STAGE_ITEMS, st, [&] { return launch_items_scan(ia, st); }));
+            HCK(ix, timed(ix, FBPQ_STAGE_MERGE, st, [&] { return launch_items_merge(ia, st); }));
+        }
         ScanArgs sa{};
         sa.ix = dv;
         sa.q = d_q;
@@ -549,6 +608,8 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         sa.ne_cst = (const float *)necst;
         sa.cm_cell = (const int32_t *)cmcell;
         sa.cm_pre = (const int32_t *)cmpre;
+        sa.ne_slot = (const int32_t *)neslot;
+        sa.slot_ij = (const int32_t *)slotij;
         int chunk = ix->chunk;
         while (chunk > 256 && scan_lds_bytes(dv.D, dv.M, chunk, k_max, P) > kScanLdsLimit) chunk >>= 1;
         sa.chunk = chunk;
@@ -665,7 +726,8 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     std::vector<int32_t> failed;
     for (int round = 0;; ++round) {
         int64_t nfail = 0;
-        TRY(run_round(ix, d_q, nq, nslots, qlist, P, max_cells, (const int64_t *)dL, (const int32_t *)dk,
+        TRY(run_round(ix, d_q, nq, nslots, qlist, P, max_cells, std::max<int64_t>(1, std::min(Lmax, ix->dv.N)),
+                      (const int64_t *)dL, (const int32_t *)dk,
                       k_max, d_ids, d_d, st, (const float *)keys, (int32_t *)dfail, dbg, &nfail));
         if (nfail == 0) break;
         // read the failed queries and their reasons, then grow P and/or the cell capacity
@@ -940,6 +1002,8 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
     } else if (!strcmp(key, "max_cells")) {
         if (value < 64 || value > ((int64_t)1 << 26)) return fail(FBPQ_E_INVALID, "max_cells out of range");
         ix->max_cells = value;
+    } else if (!strcmp(key, "items")) {
+        ix->items = value != 0;
     } else if (!strcmp(key, "profile")) {
         ix->profile = value != 0;
     } else if (!strcmp(key, "chunk")) {

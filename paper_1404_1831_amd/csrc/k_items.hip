@@ -1,0 +1,329 @@
+// Item scan: the FBPQ distance (Section 3.1) over work items of uneven size.
+//
+// A work item is up to kItem candidates of one nonempty visited cell (i, j) of
+// one query. Its scoring table is the folded pair
+//   LUT1 = LQ[k < M/2] + CR1[i],   LUT2 = LQ[k >= M/2] + CR2[j]
+// (LQ[k][r] = ||R_k(r)||^2 - 2 <q|k, R_k(r)>, the query part of the ADC table of
+// Section 2.1; CR the centroid-by-codeword tables of equation decomposition),
+// so a candidate costs M lookups plus the cell constant fl32(d1[i] + d2[j]).
+//
+// Kernels, in launch order:
+//  k_lq           per query, LQ into HBM (read by every item of the query);
+//  k_item_offsets exclusive scan of the per-query item counts;
+//  k_item_pack    one 32-byte record per item, at its global index;
+//  k_score_items  persistent, items dealt round-robin: fold the table pair
+//                 into LDS, score the item's candidates (code loads issued
+//                 together from registers), stream the FP32 distances to HBM;
+//  k_select_dist  per query, the k smallest (distance, id) of its distances.
+// Scoring carries no selection, so its only dependent memory round trips per
+// item are the record, the table rows and the codes.
+#include "fbpq_dev.h"
+#include "select_k.h"
+
+namespace fbpq {
+
+namespace {
+
+constexpr int kNT = 256;                // threads of the item scan and merge
+constexpr int kCPT = kItem / kNT;       // candidates per thread of an item
+constexpr int kTieCapI = 256;
+
+template <int MH>
+struct CodeU;
+template <> struct CodeU<1> { using T = uint8_t; };
+template <> struct CodeU<2> { using T = uint16_t; };
+template <> struct CodeU<4> { using T = uint32_t; };
+template <> struct CodeU<8> { using T = uint2; };
+template <> struct CodeU<16> { using T = uint4; };
+
+template <int MH>
+__device__ __forceinline__ typename CodeU<MH>::T load_c(const uint8_t *__restrict__ codes, int64_t p)
+{
+    return *reinterpret_cast<const typename CodeU<MH>::T *>(codes + p * MH);
+}
+
+template <int MH>
+__device__ __forceinline__ float lsum(const float *lut, typename CodeU<MH>::T c)
+{
+    float s = 0.f;
+    if constexpr (MH == 1) {
+        s = lut[c];
+    } else if constexpr (MH == 2) {
+        s = lut[c & 255] + lut[kKc + (c >> 8)];
+    } else if constexpr (MH == 4) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += lut[k * kKc + ((c >> (8 * k)) & 255)];
+    } else if constexpr (MH == 8) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += lut[k * kKc + ((c.x >> (8 * k)) & 255)];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += lut[(k + 4) * kKc + ((c.y >> (8 * k)) & 255)];
+    } else {
+        const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s += lut[(q * 4 + k) * kKc + ((cw[q] >> (8 * k)) & 255)];
+    }
+    return s;
+}
+
+}  // namespace
+
+int items_wcap(int k_max)
+{
+    int KP = 1;
+    while (KP < k_max) KP <<= 1;
+    return KP * 2 < 256 ? 256 : KP * 2;
+}
+
+// LQ[k][r] = ||R_k(r)||^2 - 2 <q|k, R_k(r)>, one workgroup per item-scanned query.
+__global__ __launch_bounds__(256) void k_lq(ItemArgs a)
+{
+    const int slot = blockIdx.x;
+    const TravHdr h = a.hdr[slot];
+    if (h.status != kStOk || h.n_items == 0) return;
+    const int64_t qs = a.qlist ? a.qlist[slot] : slot;
+    const int D = a.ix.D, M = a.ix.M, ds = D / M;
+    __shared__ float qv[1024];
+    for (int t = threadIdx.x; t < D; t += 256) qv[t] = a.q[qs * D + t];
+    __syncthreads();
+    float *out = a.lq + (int64_t)slot * M * kKc;
+    for (int e = threadIdx.x; e < M * kKc; e += 256) {
+        const int k = e / kKc;
+        const float *rw = a.ix.R + (int64_t)e * ds;
+        float acc = 0.f;
+        for (int t = 0; t < ds; ++t) acc = fmaf(qv[k * ds + t], rw[t], acc);
+        out[e] = a.ix.nR[e] - 2.f * acc;
+    }
+}
+
+// Exclusive scan of n_items over the slots (one workgroup, serial over tiles).
+__global__ __launch_bounds__(1024) void k_item_offsets(ItemArgs a)
+{
+    __shared__ int red[16];
+    __shared__ int carry;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int64_t s0 = 0; s0 < a.nslots; s0 += 1024) {
+        const int64_t s = s0 + tid;
+        int v = 0;
+        if (s < a.nslots) {
+            const TravHdr h = a.hdr[s];
+            v = h.status == kStOk ? h.n_items : 0;
+        }
+        int x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) red[wv] = x;
+        __syncthreads();
+        int off = carry, tot = 0;
+        for (int i = 0; i < 16; ++i) {
+            if (i < wv) off += red[i];
+            tot += red[i];
+        }
+        if (s < a.nslots) a.item_start[s] = off + x - v;
+        __syncthreads();
+        if (tid == 0) carry += tot;
+        __syncthreads();
+    }
+    if (tid == 0) a.item_start[a.nslots] = carry;
+}
+
+// One record per item: item li of slot s lands at item_start[s] + li.
+__global__ __launch_bounds__(256) void k_item_pack(ItemArgs a)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t slot = g / kMaxItems;
+    const int li = (int)(g % kMaxItems);
+    if (slot >= a.nslots) return;
+    const TravHdr h = a.hdr[slot];
+    if (h.status != kStOk || li >= h.n_items) return;
+    const int64_t mc = a.max_cells;
+    const int e = a.item_cell[slot * kMaxItems + li];
+    const int sub = a.item_sub[slot * kMaxItems + li];
+    const int32_t cs = a.ne_cs[slot * mc + e];
+    const int32_t cnt = a.ne_cnt[slot * mc + e];
+    const int sl = a.ne_slot[slot * mc + e];
+    const int32_t *slot_ij = a.slot_ij + slot * 2 * a.P;
+    ItemRec r;
+    r.slot = (int32_t)slot;
+    r.n = min(kItem, cnt - sub * kItem);
+    r.t0 = cs + sub * kItem;
+    r.ci = slot_ij[sl & 0xffff];
+    r.cj = slot_ij[sl >> 16];
+    r.cst = a.ne_cst[slot * mc + e];
+    r.p0 = a.ne_beg[slot * mc + e] + (int64_t)sub * kItem;
+    a.items[a.item_start[slot] + li] = r;
+}
+
+template <int MH>
+__global__ __launch_bounds__(kNT) void k_score_items(ItemArgs a)
+{
+    constexpr int LW = MH * kKc;
+    __shared__ __align__(16) float lut[2 * LW];
+    const int tid = threadIdx.x;
+    const int total = a.item_start[a.nslots];
+    const int M = 2 * MH;
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        const ItemRec r = a.items[it];
+        const float *lq = a.lq + (int64_t)r.slot * M * kKc;
+        const float *cr1 = a.ix.CR1 + (int64_t)r.ci * LW;
+        const float *cr2 = a.ix.CR2 + (int64_t)r.cj * LW;
+        __syncthreads();
+#pragma unroll
+        for (int x = tid; x < LW; x += kNT) {
+            lut[x] = lq[x] + cr1[x];
+            lut[LW + x] = lq[LW + x] + cr2[x];
+        }
+        __syncthreads();
+        float *dst = a.dist + (int64_t)r.slot * a.lcap + r.t0;
+#pragma unroll
+        for (int j = 0; j < kCPT; ++j) {
+            const int o = tid + kNT * j;
+            if (o < r.n) {
+                const int64_t p = r.p0 + o;
+                const float d = r.cst + lsum<MH>(lut, load_c<MH>(a.ix.codesA, p)) +
+                                lsum<MH>(lut + LW, load_c<MH>(a.ix.codesB, p));
+                dst[o] = d;
+                if (a.dbg_pos) {
+                    a.dbg_pos[(int64_t)r.slot * a.dbg_cap + r.t0 + o] = p;
+                    a.dbg_d[(int64_t)r.slot * a.dbg_cap + r.t0 + o] = d;
+                }
+            }
+        }
+    }
+}
+
+// The k smallest (distance, id) of one query over its streamed distances,
+// chunk by chunk through LDS with a running list.
+constexpr int kSelNT = 256;
+
+size_t select_dist_lds(int chunk, int k_max)
+{
+    int KP = 1;
+    while (KP < k_max) KP <<= 1;
+    const int wcap = items_wcap(k_max);
+    return (size_t)chunk * 4 + (size_t)(wcap + KP) * 8 + (size_t)kTieCapI * 4;
+}
+
+__global__ __launch_bounds__(kSelNT) void k_select_dist(ItemArgs a)
+{
+    __shared__ SelShared sh;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int slot = blockIdx.x;
+    const int tid = threadIdx.x;
+    const TravHdr h = a.hdr[slot];
+    if (h.status != kStOk || h.n_items == 0) return;
+    const int64_t qs = a.qlist ? a.qlist[slot] : slot;
+    const int kq = a.k[qs];
+    int KP = 1;
+    while (KP < a.k_max) KP <<= 1;
+    float *part = reinterpret_cast<float *>(smem);
+    uint64_t *win = reinterpret_cast<uint64_t *>(part + a.chunk);
+    uint64_t *run = win + a.wcap;
+    uint32_t *tie = reinterpret_cast<uint32_t *>(run + KP);
+    const int64_t mc = a.max_cells;
+    const int32_t *cs = a.ne_cs + slot * mc;
+    const int64_t *beg = a.ne_beg + slot * mc;
+    const int nne = h.nne;
+    const float *src = a.dist + (int64_t)slot * a.lcap;
+    const int64_t ncand = h.ncand;
+    int nrun = 0;
+    for (int64_t c0 = 0; c0 < ncand; c0 += a.chunk) {
+        const int n = (int)(ncand - c0 < a.chunk ? ncand - c0 : a.chunk);
+        for (int e = tid; e < n; e += kSelNT) part[e] = src[c0 + e];
+        __syncthreads();
+        const int nr = nrun;
+        auto visit = [&](auto &&f) __attribute__((always_inline)) {
+            for (int e = tid; e < n; e += kSelNT)
+                f(fkey(part[e]), [&]() __attribute__((always_inline)) {
+                    const int64_t t = c0 + e;
+                    int lo = 0, hi = nne - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (cs[mid] <= t) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    return a.ix.ids[beg[lo] + (t - cs[lo])];
+                });
+            for (int e = tid; e < nr; e += kSelNT)
+                f((uint32_t)(run[e] >> 32), [&]() __attribute__((always_inline)) { return (uint32_t)run[e]; });
+        };
+        nrun = select_k<kSelNT>(visit, n + nr, kq, win, a.wcap, tie, kTieCapI, sh, true, run);
+    }
+    int64_t *oid = a.out_ids + qs * a.k_max;
+    float *od = a.out_d + qs * a.k_max;
+    for (int r = tid; r < a.k_max; r += kSelNT) {
+        if (r < nrun && r < kq) {
+            oid[r] = (int64_t)(uint32_t)run[r];
+            od[r] = unfkey((uint32_t)(run[r] >> 32));
+        } else {
+            oid[r] = -1;
+            od[r] = __builtin_huge_valf();
+        }
+    }
+}
+
+int items_grid(int M)
+{
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 2048;
+    }
+    hipError_t e = hipErrorInvalidValue;
+    switch (M / 2) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_score_items<1>, kNT, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_score_items<2>, kNT, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_score_items<4>, kNT, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_score_items<8>, kNT, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_score_items<16>, kNT, 0); break;
+    default: break;
+    }
+    if (e != hipSuccess || per < 1) {
+        (void)hipGetLastError();
+        per = 4;
+    }
+    return ncu * per;
+}
+
+hipError_t launch_items_prep(const ItemArgs &a, hipStream_t st)
+{
+    if (a.nslots == 0) return hipSuccess;
+    if (a.ix.D > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lq, dim3((unsigned)a.nslots), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_item_offsets, dim3(1), dim3(1024), 0, st, a);
+    const int64_t nth = a.nslots * kMaxItems;
+    hipLaunchKernelGGL(k_item_pack, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_items_scan(const ItemArgs &a, hipStream_t st)
+{
+    if (a.nslots == 0) return hipSuccess;
+    const dim3 g((unsigned)a.grid), b(kNT);
+    switch (a.ix.M / 2) {
+    case 1: hipLaunchKernelGGL(k_score_items<1>, g, b, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_score_items<2>, g, b, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_score_items<4>, g, b, 0, st, a); break;
+    case 8: hipLaunchKernelGGL(k_score_items<8>, g, b, 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_score_items<16>, g, b, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_items_merge(const ItemArgs &a, hipStream_t st)
+{
+    if (a.nslots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select_dist, dim3((unsigned)a.nslots), dim3(kSelNT),
+                       select_dist_lds(a.chunk, a.k_max), st, a);
+    return hipGetLastError();
+}
+
+}  // namespace fbpq

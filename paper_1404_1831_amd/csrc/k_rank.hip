@@ -170,27 +170,30 @@ __device__ int block_excl_scan(int v, int *red, int *total)
     return off + x - v;
 }
 
-// Bitonic sort of n (power of two) (key, idx) pairs in LDS, ascending by (key, idx).
-__device__ void bitonic_kv(uint64_t *sk, int32_t *si, int n)
+// Writes the first `keep` of n (key, idx) pairs in ascending (key, idx) order
+// to ok/oi: each pair's rank is the number of pairs below it (pairs are
+// distinct because indices are). Positions [n, keep), and entries whose index
+// is not a centroid, get (+inf, 0): a key the traversal never visits.
+__device__ void rank_out(const uint64_t *sk, const int32_t *si, int n, int keep, int T,
+                         double *__restrict__ ok, int32_t *__restrict__ oi)
 {
-    for (int size = 2; size <= n; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
-                const int lo = 2 * t - (t & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const uint64_t ka = sk[lo], kb = sk[hi];
-                const int ia = si[lo], ib = si[hi];
-                const bool gt = ka > kb || (ka == kb && ia > ib);
-                if (gt == up) {
-                    sk[lo] = kb;
-                    sk[hi] = ka;
-                    si[lo] = ib;
-                    si[hi] = ia;
-                }
-            }
-            __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint64_t k = sk[i];
+        const int x = si[i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const uint64_t kj = sk[j];
+            rank += kj < k || (kj == k && si[j] < x);
         }
+        if (rank < keep) {
+            const bool valid = x >= 0 && x < T;
+            ok[rank] = valid ? __longlong_as_double((long long)k) : __builtin_huge_val();
+            oi[rank] = valid ? x : 0;
+        }
+    }
+    for (int i = n + threadIdx.x; i < keep; i += blockDim.x) {
+        ok[i] = __builtin_huge_val();
+        oi[i] = 0;
     }
 }
 
@@ -233,27 +236,22 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     const double rn = sqrt(qn) + sqrt((double)cmax) * (1.0 + 1e-6);
     const float err = (float)(1.25 * (h + 8) * 0x1.0p-23 * rn * rn) + 1e-30f;
 
-    int n_out = 0;
     bool done = false;
+    double *ok = lkey + ((int64_t)slot * 2 + half) * P;
+    int32_t *oi = lidx + ((int64_t)slot * 2 + half) * P;
     if (P >= T) {
-        // every centroid: exact keys and sort
-        for (int i = tid; i < S; i += kSelThreads) {
-            if (i < T) {
-                sk[i] = dkey(exact_key(qh, C + (int64_t)i * h, h));
-                si[i] = i;
-            } else {
-                sk[i] = ~0ull;
-                si[i] = 0x7fffffff;
-            }
+        // every centroid: exact keys, ranked
+        for (int i = tid; i < T; i += kSelThreads) {
+            sk[i] = dkey(exact_key(qh, C + (int64_t)i * h, h));
+            si[i] = i;
         }
         __syncthreads();
-        bitonic_kv(sk, si, S);
-        n_out = T;
+        rank_out(sk, si, T, P, T, ok, oi);
         done = true;
     }
     if (!done) {
         // kP: the P-th smallest approximate key, bracketed by value bins
-        float lo = block_reduce(__builtin_huge_valf(), redf, true);
+        float lo = 0.f;
         {
             float mn = __builtin_huge_valf(), mx = -__builtin_huge_valf();
             for (int i = tid; i < T; i += kSelThreads) {
@@ -265,10 +263,12 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
             float hi = block_reduce(mx, redf, false);
             int need = P;
             float kp = hi;
+            int nsurv = T;
             for (int level = 0; level < 3 && hi > lo; ++level) {
                 for (int b = tid; b < kBins; b += kSelThreads) hist[b] = 0;
                 __syncthreads();
                 const float scale = (float)kBins / (hi - lo);
+                if (!(scale < 3.0e38f)) break;
                 for (int i = tid; i < T; i += kSelThreads) {
                     const float x = kv[i];
                     if (x >= lo && x <= hi) {
@@ -320,16 +320,25 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
                 kp = nhi;
                 lo = nlo;
                 hi = nhi;
+                // stop as soon as the survivors of this bound fit the sort buffer
+                const float thr = kp + 2.f * err;
+                int mine = 0;
+                for (int i = tid; i < T; i += kSelThreads) mine += kv[i] <= thr;
+                nsurv = block_sum(mine, redi);
+                if (nsurv <= S) break;
             }
-            if (!(hi > lo)) kp = hi;
+            if (!(hi > lo)) {
+                kp = hi;
+                const float thr = kp + 2.f * err;
+                int mine = 0;
+                for (int i = tid; i < T; i += kSelThreads) mine += kv[i] <= thr;
+                nsurv = block_sum(mine, redi);
+            }
             // survivors: ka <= kp + 2 err (kp is >= the P-th smallest approximate key)
             const float thr = kp + 2.f * err;
             if (tid == 0) s_cnt = 0;
             __syncthreads();
-            int mine = 0;
-            for (int i = tid; i < T; i += kSelThreads) mine += kv[i] <= thr;
-            const int nsurv = block_sum(mine, redi);
-            if (nsurv <= S) {
+            if (nsurv >= P && nsurv <= S) {
                 for (int i = tid; i < T; i += kSelThreads) {
                     if (kv[i] <= thr) {
                         const int w = atomicAdd(&s_cnt, 1);
@@ -340,13 +349,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
                     }
                 }
                 __syncthreads();
-                for (int i = nsurv + tid; i < S; i += kSelThreads) {
-                    sk[i] = ~0ull;
-                    si[i] = 0x7fffffff;
-                }
-                __syncthreads();
-                bitonic_kv(sk, si, S);
-                n_out = P;
+                rank_out(sk, si, nsurv < S ? nsurv : S, P, T, ok, oi);
                 done = true;
             }
         }
@@ -433,19 +436,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
             }
         }
         __syncthreads();
-        for (int i = P + tid; i < S; i += kSelThreads) {
-            sk[i] = ~0ull;
-            si[i] = 0x7fffffff;
-        }
-        __syncthreads();
-        bitonic_kv(sk, si, S);
-        n_out = P;
-    }
-    double *ok = lkey + ((int64_t)slot * 2 + half) * P;
-    int32_t *oi = lidx + ((int64_t)slot * 2 + half) * P;
-    for (int i = tid; i < P; i += kSelThreads) {
-        ok[i] = i < n_out ? __longlong_as_double((long long)sk[i]) : __builtin_huge_val();
-        oi[i] = i < n_out ? si[i] : -1;
+        rank_out(sk, si, P < S ? P : S, P, T, ok, oi);
     }
 }
 

@@ -9,44 +9,23 @@
 //               + sum_{k<M/2}  2 <c2_j|k, R_{M/2+k}(b_{M/2+k})>         [CR2]
 // -- O(M) work per candidate. The two half distances come from the first
 // layer (FP64 keys, added in FP64 and rounded once to FP32: the cell constant).
+// The LQ and CR terms of a half are folded into one table per row i
+// (LUT1_i = LQ[k<M/2] + CR1[i]) or column j (LUT2_j = LQ[k>=M/2] + CR2[j]), so
+// a candidate costs M lookups, and each CR row is read once per query.
 //
-// One workgroup (8 wavefronts) per query. LQ (M x 256 floats) is built in LDS.
-// The visited cells form a Young diagram in rank space, so candidates are
-// scored in two passes over an LDS array of partial sums: pass 1 walks the
-// rows (fixed i) with LUT1 = LQ[k<M/2] + CR1[i] folded in LDS and reads the
-// first M/2 code bytes; pass 2 walks the columns (fixed j) with LUT2 =
-// LQ[k>=M/2] + CR2[j] and reads the last M/2 bytes (codes are stored as two
-// half planes, so each pass reads only its bytes). Each CR row is read once per
-// query rather than once per cell, and a candidate costs M LDS lookups.
-//
-// Within a row (or column) the candidates of its nonempty cells are numbered
-// contiguously; a wavefront takes 64 consecutive candidates, and each lane finds
-// its cell from a 64-bit mask of the cell starts inside the window.
-// Candidates are processed in chunks of `chunk`; after each chunk the k smallest
-// (distance, id) are kept: value bins narrow down to a boundary bin, everything
-// up to it is sorted by (distance, id).
+// This kernel takes the queries the item scan leaves (visited cells holding
+// few points on average, or more work items than it tracks): two passes over
+// an LDS array of partial sums, rows then columns, with each row's and
+// column's folded table built once. It keeps the k smallest (distance, id)
+// with select_k after every chunk of candidates.
 #include "fbpq_dev.h"
+#include "select_k.h"
 
 namespace fbpq {
 
 namespace {
 
-constexpr int kScanThreads = 512;
-constexpr int kNW = kScanThreads / 64;
-constexpr int kSelBins = 1024;
 constexpr int kTieCap = 512;
-
-__device__ __forceinline__ uint32_t fkey(float f)
-{
-    const uint32_t b = __float_as_uint(f);
-    return b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
-}
-
-__device__ __forceinline__ float unfkey(uint32_t k)
-{
-    const uint32_t b = (k & 0x80000000u) ? (k ^ 0x80000000u) : ~k;
-    return __uint_as_float(b);
-}
 
 __device__ __forceinline__ uint64_t wave_or64(uint64_t v)
 {
@@ -55,31 +34,49 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t v)
 }
 
 template <int MH>
-__device__ __forceinline__ float lut_sum(const float *lut, const uint8_t *__restrict__ codes, int64_t p)
+struct CodeT;
+template <> struct CodeT<1> { using T = uint8_t; };
+template <> struct CodeT<2> { using T = uint16_t; };
+template <> struct CodeT<4> { using T = uint32_t; };
+template <> struct CodeT<8> { using T = uint2; };
+template <> struct CodeT<16> { using T = uint4; };
+
+template <int MH>
+__device__ __forceinline__ typename CodeT<MH>::T load_code(const uint8_t *__restrict__ codes, int64_t p)
+{
+    return *reinterpret_cast<const typename CodeT<MH>::T *>(codes + p * MH);
+}
+
+template <int MH>
+__device__ __forceinline__ float lut_sum_c(const float *lut, typename CodeT<MH>::T c)
 {
     float s = 0.f;
-    if constexpr (MH == 4) {
-        const uint32_t c = *reinterpret_cast<const uint32_t *>(codes + p * 4);
+    if constexpr (MH == 1) {
+        s = lut[c];
+    } else if constexpr (MH == 2) {
+        s = lut[c & 255] + lut[kKc + (c >> 8)];
+    } else if constexpr (MH == 4) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) s += lut[k * kKc + ((c >> (8 * k)) & 255)];
     } else if constexpr (MH == 8) {
-        const uint2 c = *reinterpret_cast<const uint2 *>(codes + p * 8);
 #pragma unroll
         for (int k = 0; k < 4; ++k) s += lut[k * kKc + ((c.x >> (8 * k)) & 255)];
 #pragma unroll
         for (int k = 0; k < 4; ++k) s += lut[(k + 4) * kKc + ((c.y >> (8 * k)) & 255)];
-    } else if constexpr (MH == 16) {
-        const uint4 c = *reinterpret_cast<const uint4 *>(codes + p * 16);
+    } else {
         const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int k = 0; k < 4; ++k) s += lut[(q * 4 + k) * kKc + ((cw[q] >> (8 * k)) & 255)];
-    } else {
-#pragma unroll
-        for (int k = 0; k < MH; ++k) s += lut[k * kKc + codes[p * MH + k]];
     }
     return s;
+}
+
+template <int MH>
+__device__ __forceinline__ float lut_sum(const float *lut, const uint8_t *__restrict__ codes, int64_t p)
+{
+    return lut_sum_c<MH>(lut, load_code<MH>(codes, p));
 }
 
 // last index x in [lo, hi) with v[x] <= t (v ascending over the range, v[lo] <= t)
@@ -97,22 +94,22 @@ __device__ __forceinline__ int last_le(P v, int lo, int hi, int64_t t)
 
 }  // namespace
 
+// ============================ two-pass scan ===================================
 template <int MH, bool TAB_LDS>
-__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a)
+__global__ __launch_bounds__(512) void k_scan2(ScanArgs a)
 {
+    constexpr int NT = 512;
+    constexpr int NW = NT / 64;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t hist[kSelBins];
-    __shared__ uint32_t red32[kNW];
-    __shared__ int redi[kNW];
-    __shared__ int s_bin, s_nwin, s_nties, s_alo, s_ahi;
-    __shared__ uint32_t s_before, s_cnt;
+    __shared__ SelShared sh;
+    __shared__ int s_alo, s_ahi;
 
     constexpr int M = 2 * MH;
     const int slot = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t qs = a.qlist ? a.qlist[slot] : slot;
     const TravHdr h = a.hdr[slot];
-    if (h.status != kStOk) return;
+    if (h.status != kStOk || h.n_items != 0) return;
     if (TAB_LDS != (h.nne <= kScanCellsLds)) return;
     const int D = a.ix.D, ds = D / M, P = a.P;
     const int kq = a.k[qs];
@@ -120,7 +117,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a)
     while (KP < a.k_max) KP <<= 1;
     const int WCAP = KP * 2 < 256 ? 256 : KP * 2;
 
-    // ---- LDS carve-up (see scan_lds_bytes)
     float *qv = reinterpret_cast<float *>(smem);
     float *LQ = qv + ((D + 3) & ~3);
     float *LUT = LQ + M * kKc;
@@ -143,7 +139,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a)
     const int32_t *g_cmc = a.cm_cell + slot * mc;
     const int32_t *g_cmp = a.cm_pre + slot * mc;
     if (TAB_LDS) {
-        for (int e = tid; e < nne; e += kScanThreads) {
+        for (int e = tid; e < nne; e += NT) {
             lcs[e] = g_cs[e];
             lbeg[e] = g_beg[e];
             lcst[e] = g_cst[e];
@@ -157,11 +153,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a)
     const int32_t *t_cmc = TAB_LDS ? lcmc : g_cmc;
     const int32_t *t_cmp = TAB_LDS ? lcmp : g_cmp;
 
-    const float *qg = a.q + qs * D;
-    for (int t = tid; t < D; t += kScanThreads) qv[t] = qg[t];
+    for (int t = tid; t < D; t += NT) qv[t] = a.q[qs * D + t];
     __syncthreads();
     // LQ[k][r] = ||R_k(r)||^2 - 2 <q|k, R_k(r)>   (the query part of the ADC table, Section 2.1)
-    for (int e = tid; e < M * kKc; e += kScanThreads) {
+    for (int e = tid; e < M * kKc; e += NT) {
         const int k = e / kKc;
         const float *rw = a.ix.R + (int64_t)e * ds;
         float acc = 0.f;
@@ -190,17 +185,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a)
         __syncthreads();
         const int alo = s_alo, ahi = s_ahi;
 
-        // ---- pass 1: rows, first half of the code, plus the cell constant
+        // pass 1: rows, first half of the code, plus the cell constant
         for (int ar = alo; ar <= ahi; ++ar) {
             const int64_t rs = row_cand[ar] > c0 ? row_cand[ar] : c0;
             const int64_t re = row_cand[ar + 1] < c1 ? row_cand[ar + 1] : c1;
             if (rs >= re) continue;
             __syncthreads();
             const float *cr = a.ix.CR1 + (int64_t)u[ar] * MH * kKc;
-            for (int e = tid; e < MH * kKc; e += kScanThreads) LUT[e] = LQ[e] + cr[e];
+            for (int e = tid; e < MH * kKc; e += NT) LUT[e] = LQ[e] + cr[e];
             __syncthreads();
             const int xb = row_ne[ar], xe = row_ne[ar + 1];
-            for (int64_t t0 = rs + 64 * wv; t0 < re; t0 += 64 * kNW) {
+            for (int64_t t0 = rs + 64 * wv; t0 < re; t0 += 64 * NW) {
                 const int x0 = last_le(t_cs, xb, xe, t0);
                 const int x = x0 + lane;
                 int32_t cs = 0;
@@ -223,16 +218,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a)
                 if (t < re) part[t - c0] = lut_sum<MH>(LUT, a.ix.codesA, bego + (t - cso)) + csto;
             }
         }
-        // ---- pass 2: columns, second half of the code
+        // pass 2: columns, second half of the code
         for (int b = 0; b < B; ++b) {
             const int yb = col_ne[b], ye = col_ne[b + 1];
             if (yb >= ye) continue;
             const int U = col_tot[b];
             __syncthreads();
             const float *cr = a.ix.CR2 + (int64_t)v[b] * MH * kKc;
-            for (int e = tid; e < MH * kKc; e += kScanThreads) LUT[e] = LQ[MH * kKc + e] + cr[e];
+            for (int e = tid; e < MH * kKc; e += NT) LUT[e] = LQ[MH * kKc + e] + cr[e];
             __syncthreads();
-            for (int u0 = 64 * wv; u0 < U; u0 += 64 * kNW) {
+            for (int u0 = 64 * wv; u0 < U; u0 += 64 * NW) {
                 const int y0 = last_le(t_cmp, yb, ye, u0);
                 const int y = y0 + lane;
                 int32_t pre = 0, cs = 0;
@@ -267,217 +262,22 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a)
             }
         }
         __syncthreads();
-
-        // ---- keep the kq smallest (distance, id) of part[0..n) and run[0..nrun)
-        const int ntot = n + nrun;
-        auto key_of = [&](int e) -> uint32_t {
-            return e < n ? fkey(part[e]) : (uint32_t)(run[e - n] >> 32);
+        const int nr = nrun;
+        auto visit = [&](auto &&f) __attribute__((always_inline)) {
+            for (int e = tid; e < n; e += NT)
+                f(fkey(part[e]), [&]() __attribute__((always_inline)) {
+                    const int64_t t = c0 + e;
+                    const int x = last_le(t_cs, 0, nne, t);
+                    return a.ix.ids[t_beg[x] + (t - t_cs[x])];
+                });
+            for (int e = tid; e < nr; e += NT) f((uint32_t)(run[e] >> 32), [&]() __attribute__((always_inline)) { return (uint32_t)run[e]; });
         };
-        auto id_of = [&](int e) -> uint32_t {
-            if (e >= n) return (uint32_t)run[e - n];
-            const int64_t t = c0 + e;
-            const int x = last_le(t_cs, 0, nne, t);
-            return a.ix.ids[t_beg[x] + (t - t_cs[x])];
-        };
-        if (tid == 0) {
-            s_nwin = 0;
-            s_nties = 0;
-        }
-        __syncthreads();
-        if (ntot <= kq) {
-            for (int e = tid; e < ntot; e += kScanThreads) {
-                const int wi = atomicAdd(&s_nwin, 1);
-                if (wi < WCAP) win[wi] = ((uint64_t)key_of(e) << 32) | id_of(e);
-            }
-        } else {
-            uint32_t mn = 0xffffffffu, mx = 0;
-            for (int e = tid; e < ntot; e += kScanThreads) {
-                const uint32_t k = key_of(e);
-                mn = k < mn ? k : mn;
-                mx = k > mx ? k : mx;
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                const uint32_t x1 = __shfl_xor(mn, o), x2 = __shfl_xor(mx, o);
-                mn = x1 < mn ? x1 : mn;
-                mx = x2 > mx ? x2 : mx;
-            }
-            if (lane == 0) red32[wv] = mn;
-            __syncthreads();
-            uint32_t lo = red32[0];
-            for (int i = 1; i < kNW; ++i) lo = red32[i] < lo ? red32[i] : lo;
-            __syncthreads();
-            if (lane == 0) red32[wv] = mx;
-            __syncthreads();
-            uint32_t hi = red32[0];
-            for (int i = 1; i < kNW; ++i) hi = red32[i] > hi ? red32[i] : hi;
-            int need = kq;  // winners still to find among keys in [lo, hi]
-            bool collected = false;
-            for (int level = 0; level < 8 && hi > lo; ++level) {
-                const uint64_t width = (uint64_t)(hi - lo) + 1ull;
-                __syncthreads();
-                for (int bb = tid; bb < kSelBins; bb += kScanThreads) hist[bb] = 0;
-                __syncthreads();
-                for (int e = tid; e < ntot; e += kScanThreads) {
-                    const uint32_t k = key_of(e);
-                    if (k >= lo && k <= hi) atomicAdd(&hist[(uint32_t)(((uint64_t)(k - lo) * kSelBins) / width)], 1u);
-                }
-                __syncthreads();
-                if (tid < 64) {
-                    constexpr int per = kSelBins / 64;
-                    uint32_t c[per], sum = 0;
-                    for (int j = 0; j < per; ++j) {
-                        c[j] = hist[tid * per + j];
-                        sum += c[j];
-                    }
-                    uint32_t x = sum;
-                    for (int o = 1; o < 64; o <<= 1) {
-                        const uint32_t y = __shfl_up(x, o);
-                        if (tid >= o) x += y;
-                    }
-                    uint32_t before = x - sum;
-                    for (int j = 0; j < per; ++j) {
-                        if (before < (uint32_t)need && before + c[j] >= (uint32_t)need) {
-                            s_bin = tid * per + j;
-                            s_before = before;
-                            s_cnt = c[j];
-                        }
-                        before += c[j];
-                    }
-                }
-                __syncthreads();
-                const uint32_t bstar = (uint32_t)s_bin;
-                const int before = (int)s_before, cntb = (int)s_cnt;
-                // key range of the boundary bin
-                uint32_t bmn = 0xffffffffu, bmx = 0;
-                for (int e = tid; e < ntot; e += kScanThreads) {
-                    const uint32_t k = key_of(e);
-                    if (k >= lo && k <= hi && (uint32_t)(((uint64_t)(k - lo) * kSelBins) / width) == bstar) {
-                        bmn = k < bmn ? k : bmn;
-                        bmx = k > bmx ? k : bmx;
-                    }
-                }
-                for (int o = 32; o > 0; o >>= 1) {
-                    const uint32_t x1 = __shfl_xor(bmn, o), x2 = __shfl_xor(bmx, o);
-                    bmn = x1 < bmn ? x1 : bmn;
-                    bmx = x2 > bmx ? x2 : bmx;
-                }
-                __syncthreads();
-                if (lane == 0) red32[wv] = bmn;
-                __syncthreads();
-                uint32_t nlo = red32[0];
-                for (int i = 1; i < kNW; ++i) nlo = red32[i] < nlo ? red32[i] : nlo;
-                __syncthreads();
-                if (lane == 0) red32[wv] = bmx;
-                __syncthreads();
-                uint32_t nhi = red32[0];
-                for (int i = 1; i < kNW; ++i) nhi = red32[i] > nhi ? red32[i] : nhi;
-                const int total = (kq - need) + before + cntb;  // keys <= nhi
-                if (total <= WCAP) {
-                    for (int e = tid; e < ntot; e += kScanThreads) {
-                        const uint32_t k = key_of(e);
-                        if (k <= nhi) {
-                            const int wi = atomicAdd(&s_nwin, 1);
-                            if (wi < WCAP) win[wi] = ((uint64_t)k << 32) | id_of(e);
-                        }
-                    }
-                    collected = true;
-                    break;
-                }
-                need -= before;
-                lo = nlo;
-                hi = nhi;
-            }
-            if (!collected) {
-                // all remaining candidates share the key lo: keys below lo are in,
-                // then the `need` smallest ids among the ties
-                int my_eq = 0;
-                for (int e = tid; e < ntot; e += kScanThreads) {
-                    const uint32_t k = key_of(e);
-                    if (k < lo) {
-                        const int wi = atomicAdd(&s_nwin, 1);
-                        if (wi < WCAP) win[wi] = ((uint64_t)k << 32) | id_of(e);
-                    } else if (k == lo) {
-                        ++my_eq;
-                    }
-                }
-                for (int o = 32; o > 0; o >>= 1) my_eq += __shfl_xor(my_eq, o);
-                __syncthreads();
-                if (lane == 0) redi[wv] = my_eq;
-                __syncthreads();
-                int n_eq = 0;
-                for (int i = 0; i < kNW; ++i) n_eq += redi[i];
-                const bool buffered = n_eq <= kTieCap;
-                if (buffered) {
-                    for (int e = tid; e < ntot; e += kScanThreads)
-                        if (key_of(e) == lo) {
-                            const int ti = atomicAdd(&s_nties, 1);
-                            if (ti < kTieCap) tie[ti] = id_of(e);
-                        }
-                }
-                __syncthreads();
-                uint32_t last = 0;
-                for (int r = 0; r < need; ++r) {
-                    uint32_t m = 0xffffffffu;
-                    if (buffered) {
-                        for (int e = tid; e < n_eq; e += kScanThreads) {
-                            const uint32_t id = tie[e];
-                            if ((r == 0 || id > last) && id < m) m = id;
-                        }
-                    } else {
-                        for (int e = tid; e < ntot; e += kScanThreads) {
-                            if (key_of(e) != lo) continue;
-                            const uint32_t id = id_of(e);
-                            if ((r == 0 || id > last) && id < m) m = id;
-                        }
-                    }
-                    for (int o = 32; o > 0; o >>= 1) {
-                        const uint32_t x1 = __shfl_xor(m, o);
-                        m = x1 < m ? x1 : m;
-                    }
-                    __syncthreads();
-                    if (lane == 0) red32[wv] = m;
-                    __syncthreads();
-                    uint32_t mm = red32[0];
-                    for (int i = 1; i < kNW; ++i) mm = red32[i] < mm ? red32[i] : mm;
-                    if (tid == 0) {
-                        const int wi = atomicAdd(&s_nwin, 1);
-                        if (wi < WCAP) win[wi] = ((uint64_t)lo << 32) | mm;
-                    }
-                    last = mm;
-                }
-            }
-        }
-        __syncthreads();
-        // sort the collected (distance key, id) pairs; the first kq are the new running list
-        const int nwin = s_nwin < WCAP ? s_nwin : WCAP;
-        int S = 1;
-        while (S < nwin) S <<= 1;
-        for (int e = nwin + tid; e < S; e += kScanThreads) win[e] = ~0ull;
-        __syncthreads();
-        for (int size = 2; size <= S; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int t = tid; t < S / 2; t += kScanThreads) {
-                    const int lo2 = 2 * t - (t & (stride - 1));
-                    const int hi2 = lo2 + stride;
-                    const bool up = (lo2 & size) == 0;
-                    const uint64_t x0 = win[lo2], x1 = win[hi2];
-                    if ((x0 > x1) == up) {
-                        win[lo2] = x1;
-                        win[hi2] = x0;
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        const int nkeep = nwin < kq ? nwin : kq;
-        for (int e = tid; e < nkeep; e += kScanThreads) run[e] = win[e];
-        nrun = nkeep;
-        __syncthreads();
+        nrun = select_k<NT>(visit, n + nr, kq, win, WCAP, tie, kTieCap, sh, true, run);
     }
 
     int64_t *oid = a.out_ids + qs * a.k_max;
     float *od = a.out_d + qs * a.k_max;
-    for (int r = tid; r < a.k_max; r += kScanThreads) {
+    for (int r = tid; r < a.k_max; r += NT) {
         if (r < nrun && r < kq) {
             oid[r] = (int64_t)(uint32_t)run[r];
             od[r] = unfkey((uint32_t)(run[r] >> 32));
@@ -488,28 +288,34 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a)
     }
 }
 
-size_t scan_lds_bytes(int D, int M, int chunk, int k_max, int P)
+// ============================ host side =======================================
+static size_t sel_bytes(int k_max)
 {
-    (void)P;
     int KP = 1;
     while (KP < k_max) KP <<= 1;
     const int WCAP = KP * 2 < 256 ? 256 : KP * 2;
+    return (size_t)(WCAP + KP) * 8 + (size_t)kTieCap * 4;
+}
+
+size_t scan_lds_bytes(int D, int M, int chunk, int k_max, int P)
+{
+    (void)P;
     const size_t f = (size_t)((D + 3) & ~3) + (size_t)M * kKc + (size_t)(M / 2) * kKc +
                      (size_t)((chunk + 3) & ~3);
-    return f * 4 + (size_t)(WCAP + KP) * 8 + (size_t)kTieCap * 4 + (size_t)kScanCellsLds * (8 + 4 * 4);
+    return f * 4 + sel_bytes(k_max) + (size_t)kScanCellsLds * (8 + 4 * 4);
 }
 
 template <bool TL>
-static hipError_t launch_scan_t(const ScanArgs &a, int64_t nslots, hipStream_t st)
+static hipError_t launch_scan2(const ScanArgs &a, int64_t nslots, hipStream_t st)
 {
     const size_t lds = scan_lds_bytes(a.ix.D, a.ix.M, a.chunk, a.k_max, a.P);
-    const dim3 g((unsigned)nslots), b(kScanThreads);
+    const dim3 g((unsigned)nslots), b(512);
     switch (a.ix.M / 2) {
-    case 1: hipLaunchKernelGGL((k_scan<1, TL>), g, b, lds, st, a); break;
-    case 2: hipLaunchKernelGGL((k_scan<2, TL>), g, b, lds, st, a); break;
-    case 4: hipLaunchKernelGGL((k_scan<4, TL>), g, b, lds, st, a); break;
-    case 8: hipLaunchKernelGGL((k_scan<8, TL>), g, b, lds, st, a); break;
-    case 16: hipLaunchKernelGGL((k_scan<16, TL>), g, b, lds, st, a); break;
+    case 1: hipLaunchKernelGGL((k_scan2<1, TL>), g, b, lds, st, a); break;
+    case 2: hipLaunchKernelGGL((k_scan2<2, TL>), g, b, lds, st, a); break;
+    case 4: hipLaunchKernelGGL((k_scan2<4, TL>), g, b, lds, st, a); break;
+    case 8: hipLaunchKernelGGL((k_scan2<8, TL>), g, b, lds, st, a); break;
+    case 16: hipLaunchKernelGGL((k_scan2<16, TL>), g, b, lds, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -518,10 +324,9 @@ static hipError_t launch_scan_t(const ScanArgs &a, int64_t nslots, hipStream_t s
 hipError_t launch_scan(const ScanArgs &a, int64_t nslots, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
-    // queries whose nonempty-cell tables fit in LDS, then the others
-    hipError_t e = launch_scan_t<true>(a, nslots, st);
+    hipError_t e = launch_scan2<true>(a, nslots, st);
     if (e != hipSuccess) return e;
-    return launch_scan_t<false>(a, nslots, st);
+    return launch_scan2<false>(a, nslots, st);
 }
 
 }  // namespace fbpq

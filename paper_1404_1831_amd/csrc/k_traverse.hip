@@ -199,6 +199,10 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs args)
         h.cut_a = cut_a;
         h.cut_b = cut_b;
         h.nne = 0;
+        h.a_ne = 0;
+        h.b_ne = 0;
+        h.n_items = 0;
+        h.pad = 0;
         h.ncells = ncells;
         h.ncand = total;
         h.cut_take = cut_take;
@@ -245,6 +249,7 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
     int *rc = reinterpret_cast<int *>(colcur + P);      // [P + 1] first diagram cell of each row
     int *rowcnt = rc + (P + 1);                         // [P + 1] nonempty cells per row
     int *colcnt = rowcnt + (P + 1);                     // [P + 1] nonempty cells per column
+    int *rslot = colcnt + (P + 1);                      // [2P] LUT slot of each row, then column
     const int slot = blockIdx.x;
     const int lane = threadIdx.x;
     TravHdr h = args.hdr[slot];
@@ -286,6 +291,8 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
         rowcnt[a] = 0;
         colcnt[a] = 0;
     }
+    int32_t *ne_slot = args.ne_slot + (int64_t)slot * mc;
+    int32_t *slot_ij = args.slot_ij + (int64_t)slot * 2 * P;
     for (int b = lane; b < P; b += 64) colcur[b] = 0ull;
     __syncthreads();
     const int64_t ncells = run;
@@ -342,9 +349,37 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
         }
     }
     __syncthreads();
+    // LUT slots: rank of each row (column) among rows (columns) that hold a nonempty cell
+    int nr = 0, ncol = 0;
+    for (int a0 = 0; a0 < P; a0 += 64) {
+        const int a = a0 + lane;
+        const bool rne = a < A && rowcnt[a + 1] > rowcnt[a];
+        const bool cne = a < B && colcnt[a + 1] > colcnt[a];
+        const uint64_t mr = __ballot(rne), mcl = __ballot(cne);
+        const uint64_t below = (1ull << lane) - 1ull;
+        if (rne) {
+            rslot[a] = nr + __popcll(mr & below);
+            slot_ij[nr + __popcll(mr & below)] = u[a];
+        }
+        if (cne) {
+            rslot[P + a] = ncol + __popcll(mcl & below);
+        }
+        nr += __popcll(mr);
+        ncol += __popcll(mcl);
+    }
+    __syncthreads();
+    for (int b = lane; b < B; b += 64)
+        if (colcnt[b + 1] > colcnt[b]) slot_ij[nr + rslot[P + b]] = v[b];
+    if (lane == 0) {
+        args.hdr[slot].a_ne = nr;
+        args.hdr[slot].b_ne = ncol;
+    }
+    __syncthreads();
     // pass 2: write the compacted entries
     int64_t crun = 0;
-    int nerun = 0;
+    int nerun = 0, itrun = 0;
+    int32_t *item_cell = args.item_cell + (int64_t)slot * kMaxItems;
+    int32_t *item_sub = args.item_sub + (int64_t)slot * kMaxItems;
     for (int64_t x0 = 0; x0 < ncells; x0 += 64) {
         const int64_t xi = x0 + lane;
         int64_t cnt = 0, beg = 0;
@@ -368,6 +403,14 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
             if (lane >= o) s += y;
         }
         const uint64_t nem = __ballot(cnt > 0);
+        const int nit = (int)((cnt + kItem - 1) / kItem);
+        int is = nit;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(is, o);
+            if (lane >= o) is += y;
+        }
+        const int ibase = itrun + is - nit;
+        itrun += __shfl(is, 63);
         if (xi < ncells) {
             const int64_t cs = crun + s - cnt;
             if (b == 0) row_cand[a] = (int32_t)cs;
@@ -377,6 +420,11 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
                 ne_cnt[e] = (int32_t)cnt;
                 ne_beg[e] = beg;
                 ne_cst[e] = (float)(k1[a] + k2[b]);
+                ne_slot[e] = rslot[a] | ((nr + rslot[P + b]) << 16);
+                for (int it = 0; it < nit && ibase + it < kMaxItems; ++it) {
+                    item_cell[ibase + it] = e;
+                    item_sub[ibase + it] = it;
+                }
                 const unsigned long long old = atomicAdd(&colcur[b], (1ull << 40) + (unsigned long long)cnt);
                 const int slotc = colcnt[b] + (int)(old >> 40);
                 cm_cell[slotc] = e;
@@ -389,13 +437,18 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
     __syncthreads();
     if (lane == 0) row_cand[A] = (int32_t)crun;
     for (int b = lane; b < B; b += 64) col_tot[b] = (int32_t)(colcur[b] & ((1ull << 40) - 1ull));
-    if (lane == 0) args.hdr[slot].nne = nerun;
+    if (lane == 0) {
+        args.hdr[slot].nne = nerun;
+        const bool items = args.allow_items && nerun > 0 && itrun <= kMaxItems &&
+                           crun >= (int64_t)kItemMinAvg * nerun;
+        args.hdr[slot].n_items = items ? itrun : 0;
+    }
 }
 
 hipError_t launch_layout(const LayoutArgs &a, int64_t nslots, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
-    const size_t lds = (size_t)a.P * 8 + (size_t)3 * (a.P + 1) * 4;
+    const size_t lds = (size_t)a.P * 8 + (size_t)3 * (a.P + 1) * 4 + (size_t)2 * a.P * 4;
     hipLaunchKernelGGL(k_layout, dim3((unsigned)nslots), dim3(64), lds, st, a);
     return hipGetLastError();
 }

@@ -137,11 +137,12 @@ def test_visit_tiny_with_ties_and_empty_cells(fb, T, seed):
     fb.fbpq_free_index(h)
 
 
-def test_candidate_distances_within_tolerance(fb, gmm_small):
+@pytest.mark.parametrize("items", [1, 0])
+def test_candidate_distances_within_tolerance(fb, gmm_small, items):
     ix, Q = gmm_small
     L = 10000
-    log("per-candidate FBPQ distances: N=1e5 T=64 M=8 L=1e4")
-    h = _open(fb, ix)
+    log(f"per-candidate FBPQ distances: N=1e5 T=64 M=8 L=1e4 items={items}")
+    h = _open(fb, ix, items=items)
     got = fb.fbpq_debug_dists(h, Q[:20], L, cap=L)
     fb.fbpq_free_index(h)
     for r in range(20):
@@ -169,11 +170,12 @@ def test_candidate_distances_m16_chunked(fb, gmm_m16):
         assert np.all(np.abs(d32 - d64) <= tol(ix, Q[r], pos, d64))
 
 
-def test_search_cfg0_topk(fb, gmm_small):
+@pytest.mark.parametrize("items", [1, 0])
+def test_search_cfg0_topk(fb, gmm_small, items):
     ix, Q = gmm_small
     L, k = 10000, 10
-    log("search: N=1e5 T=64 M=8 nq=100 L=1e4 k=10")
-    h = _open(fb, ix)
+    log(f"search: N=1e5 T=64 M=8 nq=100 L=1e4 k=10 items={items}")
+    h = _open(fb, ix, items=items)
     g_ids, g_d = fb.fbpq_search(h, Q, L, k)
     g2_ids, g2_d = fb.fbpq_search(h, Q, L, k)
     fb.fbpq_free_index(h)
@@ -189,12 +191,12 @@ def test_search_cfg0_topk(fb, gmm_small):
     assert r_gpu == r_orc
 
 
-@pytest.mark.parametrize("chunk", [8192, 512])
-def test_search_m16_k100_chunks(fb, gmm_m16, chunk):
+@pytest.mark.parametrize("chunk,items", [(8192, 1), (8192, 0), (512, 0)])
+def test_search_m16_k100_chunks(fb, gmm_m16, chunk, items):
     ix, Q = gmm_m16
     L, k = 6000, 100
-    log(f"search: T=128 M=16 L=6000 k=100 chunk={chunk}")
-    h = _open(fb, ix, chunk=chunk)
+    log(f"search: T=128 M=16 L=6000 k=100 chunk={chunk} items={items}")
+    h = _open(fb, ix, chunk=chunk, items=items)
     g_ids, g_d = fb.fbpq_search(h, Q, L, k)
     fb.fbpq_free_index(h)
     o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
