@@ -548,7 +548,8 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
             TRY(ws_get(ix, W_ITEMSTART, sizeof(int32_t) * (nslots + 1), &itstart));
             TRY(ws_get(ix, W_ITEMOUT, sizeof(ItemRec) * nslots * kMaxItems, &items));
             TRY(ws_get(ix, W_LQ, sizeof(float) * nslots * dv.M * FBPQ_KC, &lq));
-            TRY(ws_get(ix, W_ITEMN, sizeof(float) * nslots * lcap, &dist));
+            const int64_t dstride = (lcap + 63) & ~(int64_t)63;  // 256-byte aligned distance rows
+            TRY(ws_get(ix, W_ITEMN, sizeof(float) * nslots * dstride, &dist));
             ItemArgs ia{};
             ia.ix = dv;
             ia.q = d_q;
@@ -571,14 +572,10 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
             ia.items = (ItemRec *)items;
             ia.lq = (float *)lq;
             ia.dist = (float *)dist;
-            ia.lcap = lcap;
+            ia.lcap = dstride;
             ia.wcap = wcap;
             if (ix->item_grid[dv.M / 2 % 32] == 0) ix->item_grid[dv.M / 2 % 32] = items_grid(dv.M);
             ia.grid = ix->item_grid[dv.M / 2 % 32];
-            // three selection workgroups per CU
-            int schunk = 12288;
-            while (schunk > 1024 && select_dist_lds(schunk, k_max) > 50 * 1024) schunk -= 1024;
-            ia.chunk = schunk;
             ia.out_ids = d_ids;
             ia.out_d = d_d;
             ia.dbg_pos = (int64_t *)dpos;

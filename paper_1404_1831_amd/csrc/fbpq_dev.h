@@ -167,7 +167,6 @@ struct ItemArgs {
     int64_t lcap;
     int32_t wcap;
     int32_t grid;          // workgroups of the persistent score kernel
-    int32_t chunk;         // candidates per LDS chunk of the select kernel
     int64_t *out_ids;      // [query][k_max]
     float *out_d;
     int64_t *dbg_pos;
@@ -179,6 +178,6 @@ hipError_t launch_items_scan(const ItemArgs &a, hipStream_t st);   // persistent
 hipError_t launch_items_merge(const ItemArgs &a, hipStream_t st);  // per-query top-k
 int items_wcap(int k_max);
 int items_grid(int M);  // persistent score-kernel workgroups that fit the device
-size_t select_dist_lds(int chunk, int k_max);
+size_t select_dist_lds(int k_max);
 
 }  // namespace fbpq

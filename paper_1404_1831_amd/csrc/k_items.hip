@@ -74,7 +74,7 @@ int items_wcap(int k_max)
 {
     int KP = 1;
     while (KP < k_max) KP <<= 1;
-    return KP * 2 < 256 ? 256 : KP * 2;
+    return KP * 2 < 512 ? 512 : KP * 2;
 }
 
 // LQ[k][r] = ||R_k(r)||^2 - 2 <q|k, R_k(r)>, one workgroup per item-scanned query.
@@ -198,62 +198,197 @@ __global__ __launch_bounds__(kNT) void k_score_items(ItemArgs a)
     }
 }
 
-// The k smallest (distance, id) of one query over its streamed distances,
-// chunk by chunk through LDS with a running list.
+// The k smallest (distance, id) of one query over its streamed distances.
+// A pass holds kSelPT distances per thread in registers, plus the running
+// list of the previous pass. Each thread's smallest key is a sample; the
+// kq-th smallest sample bounds the kq-th smallest key from above (kq distinct
+// elements lie at or below it), so the elements at or below it contain the
+// answer. They are appended with one LDS atomic per wave and ranked by
+// (key, id). When they do not fit the window (many equal keys), the general
+// histogram selection runs over the pass instead.
 constexpr int kSelNT = 256;
+constexpr int kSelPT = 48;
+constexpr int kSelChunk = kSelNT * kSelPT;
+constexpr int kRunPT = 1024 / kSelNT;  // k_max is at most 1024
+constexpr int kIdxLds = 512;  // cells whose start offsets are staged in LDS
 
-size_t select_dist_lds(int chunk, int k_max)
+size_t select_dist_lds(int k_max)
 {
     int KP = 1;
     while (KP < k_max) KP <<= 1;
     const int wcap = items_wcap(k_max);
-    return (size_t)chunk * 4 + (size_t)(wcap + KP) * 8 + (size_t)kTieCapI * 4;
+    return (size_t)(wcap + KP) * 8 + (size_t)kTieCapI * 4;
 }
 
 __global__ __launch_bounds__(kSelNT) void k_select_dist(ItemArgs a)
 {
     __shared__ SelShared sh;
+    __shared__ uint32_t smp[kSelNT];
+    __shared__ int32_t s_cs[kIdxLds];
+    __shared__ int64_t s_beg[kIdxLds];
+    __shared__ uint32_t s_tau;
     extern __shared__ __align__(16) unsigned char smem[];
     const int slot = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const TravHdr h = a.hdr[slot];
     if (h.status != kStOk || h.n_items == 0) return;
     const int64_t qs = a.qlist ? a.qlist[slot] : slot;
     const int kq = a.k[qs];
     int KP = 1;
     while (KP < a.k_max) KP <<= 1;
-    float *part = reinterpret_cast<float *>(smem);
-    uint64_t *win = reinterpret_cast<uint64_t *>(part + a.chunk);
-    uint64_t *run = win + a.wcap;
+    const int wcap = a.wcap;
+    uint64_t *win = reinterpret_cast<uint64_t *>(smem);
+    uint64_t *run = win + wcap;
     uint32_t *tie = reinterpret_cast<uint32_t *>(run + KP);
     const int64_t mc = a.max_cells;
     const int32_t *cs = a.ne_cs + slot * mc;
     const int64_t *beg = a.ne_beg + slot * mc;
     const int nne = h.nne;
+    const bool idx_lds = nne <= kIdxLds;
+    if (idx_lds) {
+        for (int e = tid; e < nne; e += kSelNT) {
+            s_cs[e] = cs[e];
+            s_beg[e] = beg[e];
+        }
+    }
+    // id of candidate t (row-major position in the query's candidate list)
+    auto id_of = [&](int64_t t) __attribute__((always_inline)) -> uint32_t {
+        int lo = 0, hi = nne - 1;
+        int64_t p;
+        if (idx_lds) {
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_cs[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            p = s_beg[lo] + (t - s_cs[lo]);
+        } else {
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (cs[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            p = beg[lo] + (t - cs[lo]);
+        }
+        return a.ix.ids[p];
+    };
+    // appends (key, ref) for lanes with pred; the call is wave-uniform
+    auto append = [&](bool pred, uint32_t key, uint32_t ref) __attribute__((always_inline)) {
+        const uint64_t m = __ballot(pred);
+        if (m == 0) return;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&sh.s_nwin, (int)__popcll(m));
+        base = __shfl(base, 0);
+        if (pred) {
+            const int wi = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+            if (wi < wcap) win[wi] = ((uint64_t)key << 32) | ref;
+        }
+    };
     const float *src = a.dist + (int64_t)slot * a.lcap;
     const int64_t ncand = h.ncand;
     int nrun = 0;
-    for (int64_t c0 = 0; c0 < ncand; c0 += a.chunk) {
-        const int n = (int)(ncand - c0 < a.chunk ? ncand - c0 : a.chunk);
-        for (int e = tid; e < n; e += kSelNT) part[e] = src[c0 + e];
-        __syncthreads();
+    for (int64_t c0 = 0; c0 < ncand; c0 += kSelChunk) {
+        const int n = (int)(ncand - c0 < kSelChunk ? ncand - c0 : kSelChunk);
         const int nr = nrun;
-        auto visit = [&](auto &&f) __attribute__((always_inline)) {
-            for (int e = tid; e < n; e += kSelNT)
-                f(fkey(part[e]), [&]() __attribute__((always_inline)) {
-                    const int64_t t = c0 + e;
-                    int lo = 0, hi = nne - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (cs[mid] <= t) lo = mid;
-                        else hi = mid - 1;
+        // element 4 * (tid + kSelNT * j4) + c of the pass sits in v[4 * j4 + c]
+        uint32_t v[kSelPT], rk[kRunPT];
+        const float *sp = src + c0;
+#pragma unroll
+        for (int j4 = 0; j4 < kSelPT / 4; ++j4) {
+            const int e = 4 * (tid + kSelNT * j4);
+            if (e + 3 < n) {
+                const float4 f = *reinterpret_cast<const float4 *>(sp + e);
+                v[4 * j4] = fkey(f.x);
+                v[4 * j4 + 1] = fkey(f.y);
+                v[4 * j4 + 2] = fkey(f.z);
+                v[4 * j4 + 3] = fkey(f.w);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[4 * j4 + c] = e + c < n ? fkey(sp[e + c]) : 0xffffffffu;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kRunPT; ++r) {
+            const int e = tid + kSelNT * r;
+            rk[r] = e < nr ? (uint32_t)(run[e] >> 32) : 0xffffffffu;
+        }
+        if (tid == 0) sh.s_nwin = 0;
+        const int ntot = n + nr;
+        const bool any = 4 * tid < n || tid < nr;
+        const int n4 = (n + 3) / 4;  // threads that own pass elements
+        const int nsamp = (n4 > nr ? n4 : nr) < kSelNT ? (n4 > nr ? n4 : nr) : kSelNT;
+        bool done = false;
+        if (ntot <= kq || nsamp >= kq) {
+            uint32_t tau = 0xffffffffu;
+            if (ntot > kq) {
+                uint32_t mn = 0xffffffffu;
+#pragma unroll
+                for (int j = 0; j < kSelPT; ++j) mn = v[j] < mn ? v[j] : mn;
+#pragma unroll
+                for (int r = 0; r < kRunPT; ++r) mn = rk[r] < mn ? rk[r] : mn;
+                smp[tid] = mn;
+                __syncthreads();
+                if (any) {
+                    int rank = 0;
+                    for (int u = 0; u < kSelNT; ++u) {
+                        const uint32_t x = smp[u];
+                        rank += (x < mn) | ((x == mn) & (u < tid));
                     }
-                    return a.ix.ids[beg[lo] + (t - cs[lo])];
-                });
+                    if (rank == kq - 1) s_tau = mn;
+                }
+                __syncthreads();
+                tau = s_tau;
+            } else {
+                __syncthreads();
+            }
+            // refs: position in the pass, or kSelChunk + index in the running list
+#pragma unroll
+            for (int j = 0; j < kSelPT; ++j) {
+                const int e = 4 * (tid + kSelNT * (j / 4)) + (j % 4);
+                append(e < n && v[j] <= tau, v[j], (uint32_t)e);
+            }
+#pragma unroll
+            for (int r = 0; r < kRunPT; ++r) {
+                const int e = tid + kSelNT * r;
+                append(e < nr && rk[r] <= tau, rk[r], (uint32_t)(kSelChunk + e));
+            }
+            __syncthreads();
+            const int nwin = sh.s_nwin;
+            if (nwin <= wcap) {
+                for (int i = tid; i < nwin; i += kSelNT) {
+                    const uint64_t x = win[i];
+                    const uint32_t ref = (uint32_t)x;
+                    const uint32_t id = ref < (uint32_t)kSelChunk ? id_of(c0 + ref) : (uint32_t)run[ref - kSelChunk];
+                    win[i] = (x & 0xffffffff00000000ull) | id;
+                }
+                __syncthreads();
+                // the (key, id) pairs are distinct, so the ranks are too
+                const int nk = nwin < kq ? nwin : kq;
+                for (int i = tid; i < nwin; i += kSelNT) {
+                    const uint64_t x = win[i];
+                    int rank = 0;
+                    for (int j = 0; j < nwin; ++j) rank += win[j] < x;
+                    if (rank < nk) run[rank] = x;
+                }
+                nrun = nk;
+                done = true;
+            }
+            __syncthreads();
+        } else {
+            __syncthreads();
+        }
+        if (done) continue;
+        // general selection over the pass, read again from global memory and
+        // from the running list (select_k writes run only after its last visit)
+        auto visit = [&](auto &&f) __attribute__((always_inline)) {
+#pragma unroll 1
+            for (int e = tid; e < n; e += kSelNT)
+                f(fkey(src[c0 + e]), [&]() __attribute__((always_inline)) { return id_of(c0 + e); });
+#pragma unroll 1
             for (int e = tid; e < nr; e += kSelNT)
                 f((uint32_t)(run[e] >> 32), [&]() __attribute__((always_inline)) { return (uint32_t)run[e]; });
         };
-        nrun = select_k<kSelNT>(visit, n + nr, kq, win, a.wcap, tie, kTieCapI, sh, true, run);
+        nrun = select_k<kSelNT>(visit, ntot, kq, win, wcap, tie, kTieCapI, sh, true, run);
     }
     int64_t *oid = a.out_ids + qs * a.k_max;
     float *od = a.out_d + qs * a.k_max;
@@ -267,6 +402,7 @@ __global__ __launch_bounds__(kSelNT) void k_select_dist(ItemArgs a)
         }
     }
 }
+
 
 int items_grid(int M)
 {
@@ -322,7 +458,7 @@ hipError_t launch_items_merge(const ItemArgs &a, hipStream_t st)
 {
     if (a.nslots == 0) return hipSuccess;
     hipLaunchKernelGGL(k_select_dist, dim3((unsigned)a.nslots), dim3(kSelNT),
-                       select_dist_lds(a.chunk, a.k_max), st, a);
+                       select_dist_lds(a.k_max), st, a);
     return hipGetLastError();
 }
 

@@ -117,9 +117,11 @@ __device__ __forceinline__ int select_k(Visit &&visit, int ntot, int kq, uint64_
         int need = kq;
         bool collected = false;
         for (int level = 0; level < 8 && hi > lo; ++level) {
-            const uint64_t width = (uint64_t)(hi - lo) + 1ull;
+            // monotone bin map of [lo, hi] onto kSelBins bins (float scaling)
+            const float scale = (float)kSelBins / ((float)(hi - lo) + 1.0f);
             auto bin_of = [&](uint32_t k) __attribute__((always_inline)) {
-                return (uint32_t)(((uint64_t)(k - lo) * kSelBins) / width);
+                const int b = (int)((float)(k - lo) * scale);
+                return (uint32_t)(b < kSelBins ? b : kSelBins - 1);
             };
             for (int b = tid; b < kSelBins; b += NT) sh.hist[b] = 0;
             __syncthreads();
