@@ -13,7 +13,9 @@
 //     below a bound e(q) that holds for any summation order;
 //  2. per (query, half), with kP the P-th smallest approximate key, every
 //     centroid with ka <= kP + 2e can be among the exact P smallest; those
-//     survivors (about P) get their exact FP64 key and are sorted.
+//     survivors get their exact FP64 key and are sorted. kP is bounded from
+//     above by a sample (the P-th smallest of the per-thread minima); value
+//     bins bracket kP more tightly when that bound leaves too many survivors.
 // A query whose survivor set is too large falls back to an exact radix select
 // that recomputes FP64 keys for all centroids.
 #include "fbpq_dev.h"
@@ -111,10 +113,31 @@ constexpr int kBins = 1024;
 __device__ __forceinline__ uint64_t dkey(double x) { return (uint64_t)__double_as_longlong(x); }
 
 // Exact traversal key of centroid c: FP64, increasing t, one fma per coordinate.
+// When h is a multiple of 4 the centroid row is fetched 32 floats at a time
+// (eight 16-byte loads in flight); the arithmetic order is unchanged.
 __device__ __forceinline__ double exact_key(const float *qh, const float *__restrict__ Crow, int h)
 {
     double acc = 0.0;
-    for (int t = 0; t < h; ++t) {
+    int t = 0;
+    if ((h & 3) == 0) {
+        for (; t + 32 <= h; t += 32) {
+            float4 c[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) c[u] = *reinterpret_cast<const float4 *>(Crow + t + 4 * u);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float4 qv = *reinterpret_cast<const float4 *>(qh + t + 4 * u);
+                const float qa[4] = {qv.x, qv.y, qv.z, qv.w};
+                const float ca[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double e = (double)qa[v] - (double)ca[v];
+                    acc = __builtin_fma(e, e, acc);
+                }
+            }
+        }
+    }
+    for (; t < h; ++t) {
         const double e = (double)qh[t] - (double)Crow[t];
         acc = __builtin_fma(e, e, acc);
     }
@@ -211,6 +234,8 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     __shared__ int redi[kSelThreads / 64];
     __shared__ uint64_t red64[kSelThreads / 64];
     __shared__ int s_cnt, s_bin, s_need;
+    __shared__ float smp[kSelThreads];
+    __shared__ float s_tau;
     const int slot = blockIdx.x, half = blockIdx.y, tid = threadIdx.x;
     const int h = D / 2;
     const int64_t qs = qlist ? qlist[slot] : slot;
@@ -231,8 +256,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     const float *kv = lds_ka ? kal : kg;
 
     // error bound of the approximate keys (any summation order, FP32)
-    double qn = 0.0;
-    for (int t = 0; t < h; ++t) qn += (double)qh[t] * (double)qh[t];
+    double qn = 0.0;  // each wave sums ||q_half||^2 on its own (any order suits a bound)
+    for (int t = tid & 63; t < h; t += 64) qn += (double)qh[t] * (double)qh[t];
+    for (int o = 32; o > 0; o >>= 1) qn += __shfl_xor(qn, o);
     const double rn = sqrt(qn) + sqrt((double)cmax) * (1.0 + 1e-6);
     const float err = (float)(1.25 * (h + 8) * 0x1.0p-23 * rn * rn) + 1e-30f;
 
@@ -248,6 +274,42 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
         __syncthreads();
         rank_out(sk, si, T, P, T, ok, oi);
         done = true;
+    }
+    if (!done && (T < kSelThreads ? T : kSelThreads) >= P) {
+        // Each thread's smallest approximate key is a sample; P distinct
+        // centroids lie at or below the P-th smallest sample, so it bounds kP
+        // (the P-th smallest approximate key) from above.
+        float mn = __builtin_huge_valf();
+        for (int i = tid; i < T; i += kSelThreads) mn = kv[i] < mn ? kv[i] : mn;
+        smp[tid] = mn;
+        if (tid == 0) s_cnt = 0;
+        __syncthreads();
+        if (tid < T) {
+            int rank = 0;
+            for (int u = 0; u < kSelThreads; ++u) {
+                const float x = smp[u];
+                rank += (x < mn) | ((x == mn) & (u < tid));
+            }
+            if (rank == P - 1) s_tau = mn;
+        }
+        __syncthreads();
+        const float thr = s_tau + 2.f * err;
+        for (int i = tid; i < T; i += kSelThreads) {
+            if (kv[i] <= thr) {
+                const int w = atomicAdd(&s_cnt, 1);
+                if (w < S) si[w] = i;
+            }
+        }
+        __syncthreads();
+        const int nsurv = s_cnt;
+        if (nsurv <= S) {
+            for (int w = tid; w < nsurv; w += kSelThreads)
+                sk[w] = dkey(exact_key(qh, C + (int64_t)si[w] * h, h));
+            __syncthreads();
+            rank_out(sk, si, nsurv, P, T, ok, oi);
+            done = true;
+        }
+        __syncthreads();
     }
     if (!done) {
         // kP: the P-th smallest approximate key, bracketed by value bins
@@ -342,14 +404,15 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
                 for (int i = tid; i < T; i += kSelThreads) {
                     if (kv[i] <= thr) {
                         const int w = atomicAdd(&s_cnt, 1);
-                        if (w < S) {
-                            sk[w] = dkey(exact_key(qh, C + (int64_t)i * h, h));
-                            si[w] = i;
-                        }
+                        if (w < S) si[w] = i;
                     }
                 }
                 __syncthreads();
-                rank_out(sk, si, nsurv < S ? nsurv : S, P, T, ok, oi);
+                const int ns = nsurv < S ? nsurv : S;
+                for (int w = tid; w < ns; w += kSelThreads)
+                    sk[w] = dkey(exact_key(qh, C + (int64_t)si[w] * h, h));
+                __syncthreads();
+                rank_out(sk, si, ns, P, T, ok, oi);
                 done = true;
             }
         }
@@ -443,7 +506,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
 int select_sort_size(int P, int T)
 {
     int S = 1;
-    const int need = P >= T ? T : 2 * P;
+    const int need = P >= T ? T : (4 * P < T ? 4 * P : T);
     while (S < need) S <<= 1;
     return S < 64 ? 64 : S;
 }
