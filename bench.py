@@ -46,6 +46,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run a plain elementwise copy of this many MiB (read once, written once), "
+                         "the reference dispatch for scaling HBM traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this search runs on one GPU; --gpus above 1 is not supported"}))
@@ -143,6 +146,16 @@ def main() -> int:
                "sample": f"first {n1} of the {nq} queries, same index, L={L}, k={k}",
                "topk_overlap_with_gpu": overlap, "max_rel_dist_diff": float(rel.max())}
         log(f"cpu oracle: {n1} queries in {t_cpu:.1f}s on {threads} threads")
+
+    if args.calibrate_copy_mib > 0:
+        nel = args.calibrate_copy_mib * (1 << 20) // 4
+        x = torch.ones(nel, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.calibrate_copy_mib} MiB read + written")
+        del x, y
 
     fbpq.fbpq_free_index(h)
     out = {

@@ -33,7 +33,7 @@ struct TravHdr {
 
 // Work items of the item scan: up to kItem candidates of one nonempty cell.
 constexpr int kItem = 2048;
-constexpr int kMaxItems = 24;      // items per query (more: the two-pass kernel)
+constexpr int kMaxItems = 64;      // items per query (more: the two-pass kernel)
 constexpr int kItemMinAvg = 128;   // mean points per nonempty cell for the item scan
 
 // Device view of an index and its tables.
