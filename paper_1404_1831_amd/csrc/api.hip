@@ -72,7 +72,6 @@ struct fbpq_index {
     int64_t max_cells = 4096;
     int32_t chunk = 8192;
     bool items = true;
-    int item_grid[32] = {0};
 };
 
 namespace {
@@ -80,8 +79,8 @@ namespace {
 enum WsSlot {
     W_Q, W_KEYS, W_LKEY, W_LIDX, W_HDR, W_W, W_ROWNE, W_ROWCAND, W_COLNE, W_COLTOT, W_NECS,
     W_NECNT, W_NEBEG, W_NECST, W_CMCELL, W_CMPRE, W_L, W_K, W_QLIST, W_FAIL, W_IDS, W_D,
-    W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NESLOT, W_SLOTIJ, W_ITEMCELL,
-    W_ITEMSUB, W_ITEMSTART, W_COUNTER, W_LQ, W_ITEMOUT, W_ITEMN, W_NSLOTS
+    W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NESLOT, W_SLOTIJ, W_COUNTER,
+    W_LQ, W_ITEMN, W_NSLOTS
 };
 
 #define HCK(ix, expr)                                                                           \
@@ -484,11 +483,9 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
     TRY(ws_get(ix, W_NECST, sizeof(float) * nslots * max_cells, &necst));
     TRY(ws_get(ix, W_CMCELL, sizeof(int32_t) * nslots * max_cells, &cmcell));
     TRY(ws_get(ix, W_CMPRE, sizeof(int32_t) * nslots * max_cells, &cmpre));
-    void *neslot, *slotij, *itcell, *itsub;
+    void *neslot, *slotij;
     TRY(ws_get(ix, W_NESLOT, sizeof(int32_t) * nslots * max_cells, &neslot));
     TRY(ws_get(ix, W_SLOTIJ, sizeof(int32_t) * nslots * 2 * P, &slotij));
-    TRY(ws_get(ix, W_ITEMCELL, sizeof(int32_t) * nslots * kMaxItems, &itcell));
-    TRY(ws_get(ix, W_ITEMSUB, sizeof(int32_t) * nslots * kMaxItems, &itsub));
     void *dab = nullptr, *dtake = nullptr, *dbeg = nullptr, *dpos = nullptr, *ddd = nullptr;
     if (dbg && dbg->visit) {
         TRY(ws_get(ix, W_DBGAB, sizeof(int32_t) * 2 * nslots * max_cells, &dab));
@@ -538,15 +535,11 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         la.cm_pre = (int32_t *)cmpre;
         la.ne_slot = (int32_t *)neslot;
         la.slot_ij = (int32_t *)slotij;
-        la.item_cell = (int32_t *)itcell;
-        la.item_sub = (int32_t *)itsub;
         la.allow_items = ix->items ? 1 : 0;
         HCK(ix, timed(ix, FBPQ_STAGE_LAYOUT, st, [&] { return launch_layout(la, nslots, st); }));
         if (ix->items) {
             const int wcap = items_wcap(k_max);
-            void *itstart, *items, *lq, *dist;
-            TRY(ws_get(ix, W_ITEMSTART, sizeof(int32_t) * (nslots + 1), &itstart));
-            TRY(ws_get(ix, W_ITEMOUT, sizeof(ItemRec) * nslots * kMaxItems, &items));
+            void *lq, *dist;
             TRY(ws_get(ix, W_LQ, sizeof(float) * nslots * dv.M * FBPQ_KC, &lq));
             const int64_t dstride = (lcap + 63) & ~(int64_t)63;  // 256-byte aligned distance rows
             TRY(ws_get(ix, W_ITEMN, sizeof(float) * nslots * dstride, &dist));
@@ -566,16 +559,10 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
             ia.ne_cst = (const float *)necst;
             ia.ne_slot = (const int32_t *)neslot;
             ia.slot_ij = (const int32_t *)slotij;
-            ia.item_cell = (const int32_t *)itcell;
-            ia.item_sub = (const int32_t *)itsub;
-            ia.item_start = (int32_t *)itstart;
-            ia.items = (ItemRec *)items;
             ia.lq = (float *)lq;
             ia.dist = (float *)dist;
             ia.lcap = dstride;
             ia.wcap = wcap;
-            if (ix->item_grid[dv.M / 2 % 32] == 0) ix->item_grid[dv.M / 2 % 32] = items_grid(dv.M);
-            ia.grid = ix->item_grid[dv.M / 2 % 32];
             ia.out_ids = d_ids;
             ia.out_d = d_d;
             ia.dbg_pos = (int64_t *)dpos;

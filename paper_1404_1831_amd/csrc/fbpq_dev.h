@@ -24,16 +24,15 @@ struct TravHdr {
     int32_t nne;      // nonempty visited cells (set by the layout kernel)
     int32_t a_ne;     // rows holding a nonempty cell (layout kernel)
     int32_t b_ne;     // columns holding a nonempty cell (layout kernel)
-    int32_t n_items;  // scan work items of the query (0: scanned by the two-pass kernel)
+    int32_t n_items;  // blocks of kItem candidates (0: scanned by the two-pass kernel)
     int32_t pad;
     int64_t ncells;   // visited cells (= sum of w)
     int64_t ncand;    // candidates (= min(L, N))
     int64_t cut_take; // points taken from the last visited cell
 };
 
-// Work items of the item scan: up to kItem candidates of one nonempty cell.
+// Candidate block of the cell scan: up to kItem candidates of one nonempty cell.
 constexpr int kItem = 2048;
-constexpr int kMaxItems = 64;      // items per query (more: the two-pass kernel)
 constexpr int kItemMinAvg = 128;   // mean points per nonempty cell for the item scan
 
 // Device view of an index and its tables.
@@ -101,8 +100,6 @@ struct LayoutArgs {
     int32_t *cm_pre;       // candidates before it in its column
     int32_t *ne_slot;      // [slot][max_cells] LUT slots of the cell: row slot | (col slot << 16)
     int32_t *slot_ij;      // [slot][2P] centroid of each LUT slot: rows, then columns
-    int32_t *item_cell;    // [slot][kMaxItems] compacted cell of each work item
-    int32_t *item_sub;     // [slot][kMaxItems] block of kItem candidates inside the cell
     int32_t allow_items;   // 0: every query goes to the two-pass scan
 };
 hipError_t launch_layout(const LayoutArgs &a, int64_t nslots, hipStream_t st);
@@ -136,15 +133,6 @@ size_t scan_lds_bytes(int D, int M, int chunk, int k_max, int P);
 constexpr int kScanCellsLds = 256;  // nonempty cells whose tables the scan keeps in LDS
 
 // One work item of the score kernel (32 bytes, written by k_item_pack).
-struct ItemRec {
-    int32_t slot;
-    int32_t n;      // candidates in the item (<= kItem)
-    int32_t t0;     // row-major candidate index of its first candidate
-    int32_t ci, cj; // half centroids of the cell
-    float cst;      // fl32(d1[ci] + d2[cj])
-    int64_t p0;     // storage position of its first candidate
-};
-
 struct ItemArgs {
     DevIndex ix;
     const float *q;        // [query][D]
@@ -159,25 +147,20 @@ struct ItemArgs {
     const int64_t *ne_beg;
     const float *ne_cst;
     const int32_t *ne_slot, *slot_ij;
-    const int32_t *item_cell, *item_sub;
-    int32_t *item_start;   // [nslots + 1] first global item of each slot
-    ItemRec *items;        // [nslots * kMaxItems] packed work items
     float *lq;             // [slot][M][Kc] query tables
     float *dist;           // [slot][lcap] FP32 distance of every candidate (row-major index)
     int64_t lcap;
     int32_t wcap;
-    int32_t grid;          // workgroups of the persistent score kernel
     int64_t *out_ids;      // [query][k_max]
     float *out_d;
     int64_t *dbg_pos;
     float *dbg_d;
     int64_t dbg_cap;
 };
-hipError_t launch_items_prep(const ItemArgs &a, hipStream_t st);   // LQ tables, offsets, records
-hipError_t launch_items_scan(const ItemArgs &a, hipStream_t st);   // persistent score kernel
+hipError_t launch_items_prep(const ItemArgs &a, hipStream_t st);   // LQ tables
+hipError_t launch_items_scan(const ItemArgs &a, hipStream_t st);   // query-major cell scan
 hipError_t launch_items_merge(const ItemArgs &a, hipStream_t st);  // per-query top-k
 int items_wcap(int k_max);
-int items_grid(int M);  // persistent score-kernel workgroups that fit the device
 size_t select_dist_lds(int k_max);
 
 }  // namespace fbpq

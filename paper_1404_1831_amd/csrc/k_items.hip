@@ -1,22 +1,19 @@
-// Item scan: the FBPQ distance (Section 3.1) over work items of uneven size.
+// Cell scan: the FBPQ distance (Section 3.1) of every candidate of a query.
 //
-// A work item is up to kItem candidates of one nonempty visited cell (i, j) of
-// one query. Its scoring table is the folded pair
+// A candidate of nonempty visited cell (i, j) is scored with the folded pair
 //   LUT1 = LQ[k < M/2] + CR1[i],   LUT2 = LQ[k >= M/2] + CR2[j]
 // (LQ[k][r] = ||R_k(r)||^2 - 2 <q|k, R_k(r)>, the query part of the ADC table of
 // Section 2.1; CR the centroid-by-codeword tables of equation decomposition),
-// so a candidate costs M lookups plus the cell constant fl32(d1[i] + d2[j]).
+// so it costs M lookups plus the cell constant fl32(d1[i] + d2[j]).
 //
 // Kernels, in launch order:
-//  k_lq           per query, LQ into HBM (read by every item of the query);
-//  k_item_offsets exclusive scan of the per-query item counts;
-//  k_item_pack    one 32-byte record per item, at its global index;
-//  k_score_items  persistent, items dealt round-robin: fold the table pair
-//                 into LDS, score the item's candidates (code loads issued
-//                 together from registers), stream the FP32 distances to HBM;
+//  k_lq           per query, LQ into HBM;
+//  k_score_query  one workgroup per query walks its nonempty cells in
+//                 row-major order: LQ sits in LDS, LUT1 is rebuilt only when
+//                 the row changes (the paper's per-row table reuse), LUT2 once
+//                 per cell; the cell's first block of codes is requested before
+//                 its table rows, and the FP32 distances stream to HBM;
 //  k_select_dist  per query, the k smallest (distance, id) of its distances.
-// Scoring carries no selection, so its only dependent memory round trips per
-// item are the record, the table rows and the codes.
 #include "fbpq_dev.h"
 #include "select_k.h"
 
@@ -98,100 +95,118 @@ __global__ __launch_bounds__(256) void k_lq(ItemArgs a)
     }
 }
 
-// Exclusive scan of n_items over the slots (one workgroup, serial over tiles).
-__global__ __launch_bounds__(1024) void k_item_offsets(ItemArgs a)
-{
-    __shared__ int red[16];
-    __shared__ int carry;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    for (int64_t s0 = 0; s0 < a.nslots; s0 += 1024) {
-        const int64_t s = s0 + tid;
-        int v = 0;
-        if (s < a.nslots) {
-            const TravHdr h = a.hdr[s];
-            v = h.status == kStOk ? h.n_items : 0;
-        }
-        int x = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) red[wv] = x;
-        __syncthreads();
-        int off = carry, tot = 0;
-        for (int i = 0; i < 16; ++i) {
-            if (i < wv) off += red[i];
-            tot += red[i];
-        }
-        if (s < a.nslots) a.item_start[s] = off + x - v;
-        __syncthreads();
-        if (tid == 0) carry += tot;
-        __syncthreads();
-    }
-    if (tid == 0) a.item_start[a.nslots] = carry;
-}
-
-// One record per item: item li of slot s lands at item_start[s] + li.
-__global__ __launch_bounds__(256) void k_item_pack(ItemArgs a)
-{
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t slot = g / kMaxItems;
-    const int li = (int)(g % kMaxItems);
-    if (slot >= a.nslots) return;
-    const TravHdr h = a.hdr[slot];
-    if (h.status != kStOk || li >= h.n_items) return;
-    const int64_t mc = a.max_cells;
-    const int e = a.item_cell[slot * kMaxItems + li];
-    const int sub = a.item_sub[slot * kMaxItems + li];
-    const int32_t cs = a.ne_cs[slot * mc + e];
-    const int32_t cnt = a.ne_cnt[slot * mc + e];
-    const int sl = a.ne_slot[slot * mc + e];
-    const int32_t *slot_ij = a.slot_ij + slot * 2 * a.P;
-    ItemRec r;
-    r.slot = (int32_t)slot;
-    r.n = min(kItem, cnt - sub * kItem);
-    r.t0 = cs + sub * kItem;
-    r.ci = slot_ij[sl & 0xffff];
-    r.cj = slot_ij[sl >> 16];
-    r.cst = a.ne_cst[slot * mc + e];
-    r.p0 = a.ne_beg[slot * mc + e] + (int64_t)sub * kItem;
-    a.items[a.item_start[slot] + li] = r;
-}
+// Per-cell values staged in LDS for the first kMetaLds cells of a query.
+constexpr int kMetaLds = 64;
 
 template <int MH>
-__global__ __launch_bounds__(kNT) void k_score_items(ItemArgs a)
+__global__ __launch_bounds__(kNT) void k_score_query(ItemArgs a)
 {
-    constexpr int LW = MH * kKc;
-    __shared__ __align__(16) float lut[2 * LW];
+    constexpr int LW = MH * kKc;   // floats of one half table
+    constexpr int PT = LW / kNT;   // table floats per thread
+    using CodeT = typename CodeU<MH>::T;
+    __shared__ __align__(16) float lq[2 * LW];
+    __shared__ __align__(16) float lut1[LW];
+    __shared__ __align__(16) float lut2[LW];
+    __shared__ int64_t m_p0[kMetaLds];
+    __shared__ int32_t m_n[kMetaLds], m_t0[kMetaLds], m_rs[kMetaLds], m_i[kMetaLds], m_j[kMetaLds];
+    __shared__ float m_cst[kMetaLds];
+    const int slot = blockIdx.x;
+    const TravHdr h = a.hdr[slot];
+    if (h.status != kStOk || h.n_items == 0) return;
     const int tid = threadIdx.x;
-    const int total = a.item_start[a.nslots];
-    const int M = 2 * MH;
-    for (int it = blockIdx.x; it < total; it += gridDim.x) {
-        const ItemRec r = a.items[it];
-        const float *lq = a.lq + (int64_t)r.slot * M * kKc;
-        const float *cr1 = a.ix.CR1 + (int64_t)r.ci * LW;
-        const float *cr2 = a.ix.CR2 + (int64_t)r.cj * LW;
-        __syncthreads();
-#pragma unroll
-        for (int x = tid; x < LW; x += kNT) {
-            lut[x] = lq[x] + cr1[x];
-            lut[LW + x] = lq[LW + x] + cr2[x];
+    const int64_t mc = a.max_cells;
+    const int32_t *g_cs = a.ne_cs + slot * mc, *g_cnt = a.ne_cnt + slot * mc;
+    const int32_t *g_sl = a.ne_slot + slot * mc;
+    const int64_t *g_beg = a.ne_beg + slot * mc;
+    const float *g_cst = a.ne_cst + slot * mc;
+    const int32_t *sij = a.slot_ij + (int64_t)slot * 2 * a.P;
+    const int nne = h.nne;
+    for (int e = tid; e < nne && e < kMetaLds; e += kNT) {
+        const int sl = g_sl[e];
+        m_p0[e] = g_beg[e];
+        m_n[e] = g_cnt[e];
+        m_t0[e] = g_cs[e];
+        m_rs[e] = sl & 0xffff;
+        m_i[e] = sij[sl & 0xffff];
+        m_j[e] = sij[sl >> 16];
+        m_cst[e] = g_cst[e];
+    }
+    const float4 *lqg = reinterpret_cast<const float4 *>(a.lq + (int64_t)slot * 2 * LW);
+    for (int x = tid; x < 2 * LW / 4; x += kNT) reinterpret_cast<float4 *>(lq)[x] = lqg[x];
+    __syncthreads();
+    float *dst = a.dist + (int64_t)slot * a.lcap;
+    int cur_rs = -1;
+    for (int e = 0; e < nne; ++e) {
+        int64_t p0;
+        int n, t0, rs, ci, cj;
+        float cst;
+        if (e < kMetaLds) {
+            p0 = m_p0[e];
+            n = m_n[e];
+            t0 = m_t0[e];
+            rs = m_rs[e];
+            ci = m_i[e];
+            cj = m_j[e];
+            cst = m_cst[e];
+        } else {
+            const int sl = g_sl[e];
+            p0 = g_beg[e];
+            n = g_cnt[e];
+            t0 = g_cs[e];
+            rs = sl & 0xffff;
+            ci = sij[sl & 0xffff];
+            cj = sij[sl >> 16];
+            cst = g_cst[e];
         }
-        __syncthreads();
-        float *dst = a.dist + (int64_t)r.slot * a.lcap + r.t0;
+        CodeT ca[kCPT], cb[kCPT];
 #pragma unroll
         for (int j = 0; j < kCPT; ++j) {
             const int o = tid + kNT * j;
-            if (o < r.n) {
-                const int64_t p = r.p0 + o;
-                const float d = r.cst + lsum<MH>(lut, load_c<MH>(a.ix.codesA, p)) +
-                                lsum<MH>(lut + LW, load_c<MH>(a.ix.codesB, p));
-                dst[o] = d;
-                if (a.dbg_pos) {
-                    a.dbg_pos[(int64_t)r.slot * a.dbg_cap + r.t0 + o] = p;
-                    a.dbg_d[(int64_t)r.slot * a.dbg_cap + r.t0 + o] = d;
+            if (o < n) {
+                ca[j] = load_c<MH>(a.ix.codesA, p0 + o);
+                cb[j] = load_c<MH>(a.ix.codesB, p0 + o);
+            }
+        }
+        const bool newrow = rs != cur_rs;
+        float c1[PT], c2[PT];
+        const float *cr2 = a.ix.CR2 + (int64_t)cj * LW;
+#pragma unroll
+        for (int u = 0; u < PT; ++u) c2[u] = cr2[tid + kNT * u];
+        if (newrow) {
+            const float *cr1 = a.ix.CR1 + (int64_t)ci * LW;
+#pragma unroll
+            for (int u = 0; u < PT; ++u) c1[u] = cr1[tid + kNT * u];
+        }
+        __syncthreads();  // the previous cell's lookups are done
+#pragma unroll
+        for (int u = 0; u < PT; ++u) lut2[tid + kNT * u] = lq[LW + tid + kNT * u] + c2[u];
+        if (newrow) {
+#pragma unroll
+            for (int u = 0; u < PT; ++u) lut1[tid + kNT * u] = lq[tid + kNT * u] + c1[u];
+        }
+        cur_rs = rs;
+        __syncthreads();
+        for (int o0 = 0; o0 < n; o0 += kItem) {
+            if (o0 > 0) {
+#pragma unroll
+                for (int j = 0; j < kCPT; ++j) {
+                    const int o = o0 + tid + kNT * j;
+                    if (o < n) {
+                        ca[j] = load_c<MH>(a.ix.codesA, p0 + o);
+                        cb[j] = load_c<MH>(a.ix.codesB, p0 + o);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kCPT; ++j) {
+                const int o = o0 + tid + kNT * j;
+                if (o < n) {
+                    const float d = cst + lsum<MH>(lut1, ca[j]) + lsum<MH>(lut2, cb[j]);
+                    dst[t0 + o] = d;
+                    if (a.dbg_pos) {
+                        a.dbg_pos[(int64_t)slot * a.dbg_cap + t0 + o] = p0 + o;
+                        a.dbg_d[(int64_t)slot * a.dbg_cap + t0 + o] = d;
+                    }
                 }
             }
         }
@@ -404,51 +419,24 @@ __global__ __launch_bounds__(kSelNT) void k_select_dist(ItemArgs a)
 }
 
 
-int items_grid(int M)
-{
-    int dev = 0, ncu = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-        (void)hipGetLastError();
-        return 2048;
-    }
-    hipError_t e = hipErrorInvalidValue;
-    switch (M / 2) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_score_items<1>, kNT, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_score_items<2>, kNT, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_score_items<4>, kNT, 0); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_score_items<8>, kNT, 0); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_score_items<16>, kNT, 0); break;
-    default: break;
-    }
-    if (e != hipSuccess || per < 1) {
-        (void)hipGetLastError();
-        per = 4;
-    }
-    return ncu * per;
-}
-
 hipError_t launch_items_prep(const ItemArgs &a, hipStream_t st)
 {
     if (a.nslots == 0) return hipSuccess;
     if (a.ix.D > 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_lq, dim3((unsigned)a.nslots), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_item_offsets, dim3(1), dim3(1024), 0, st, a);
-    const int64_t nth = a.nslots * kMaxItems;
-    hipLaunchKernelGGL(k_item_pack, dim3((unsigned)((nth + 255) / 256)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_items_scan(const ItemArgs &a, hipStream_t st)
 {
     if (a.nslots == 0) return hipSuccess;
-    const dim3 g((unsigned)a.grid), b(kNT);
+    const dim3 g((unsigned)a.nslots), b(kNT);
     switch (a.ix.M / 2) {
-    case 1: hipLaunchKernelGGL(k_score_items<1>, g, b, 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_score_items<2>, g, b, 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_score_items<4>, g, b, 0, st, a); break;
-    case 8: hipLaunchKernelGGL(k_score_items<8>, g, b, 0, st, a); break;
-    case 16: hipLaunchKernelGGL(k_score_items<16>, g, b, 0, st, a); break;
+    case 1: hipLaunchKernelGGL(k_score_query<1>, g, b, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_score_query<2>, g, b, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_score_query<4>, g, b, 0, st, a); break;
+    case 8: hipLaunchKernelGGL(k_score_query<8>, g, b, 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_score_query<16>, g, b, 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

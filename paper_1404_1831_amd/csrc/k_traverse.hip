@@ -378,8 +378,6 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
     // pass 2: write the compacted entries
     int64_t crun = 0;
     int nerun = 0, itrun = 0;
-    int32_t *item_cell = args.item_cell + (int64_t)slot * kMaxItems;
-    int32_t *item_sub = args.item_sub + (int64_t)slot * kMaxItems;
     for (int64_t x0 = 0; x0 < ncells; x0 += 64) {
         const int64_t xi = x0 + lane;
         int64_t cnt = 0, beg = 0;
@@ -409,7 +407,6 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
             const int y = __shfl_up(is, o);
             if (lane >= o) is += y;
         }
-        const int ibase = itrun + is - nit;
         itrun += __shfl(is, 63);
         if (xi < ncells) {
             const int64_t cs = crun + s - cnt;
@@ -421,10 +418,6 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
                 ne_beg[e] = beg;
                 ne_cst[e] = (float)(k1[a] + k2[b]);
                 ne_slot[e] = rslot[a] | ((nr + rslot[P + b]) << 16);
-                for (int it = 0; it < nit && ibase + it < kMaxItems; ++it) {
-                    item_cell[ibase + it] = e;
-                    item_sub[ibase + it] = it;
-                }
                 const unsigned long long old = atomicAdd(&colcur[b], (1ull << 40) + (unsigned long long)cnt);
                 const int slotc = colcnt[b] + (int)(old >> 40);
                 cm_cell[slotc] = e;
@@ -439,8 +432,7 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
     for (int b = lane; b < B; b += 64) col_tot[b] = (int32_t)(colcur[b] & ((1ull << 40) - 1ull));
     if (lane == 0) {
         args.hdr[slot].nne = nerun;
-        const bool items = args.allow_items && nerun > 0 && itrun <= kMaxItems &&
-                           crun >= (int64_t)kItemMinAvg * nerun;
+        const bool items = args.allow_items && nerun > 0 && crun >= (int64_t)kItemMinAvg * nerun;
         args.hdr[slot].n_items = items ? itrun : 0;
     }
 }
