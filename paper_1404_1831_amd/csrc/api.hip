@@ -80,7 +80,7 @@ enum WsSlot {
     W_Q, W_KEYS, W_LKEY, W_LIDX, W_HDR, W_W, W_ROWNE, W_ROWCAND, W_COLNE, W_COLTOT, W_NECS,
     W_NECNT, W_NEBEG, W_NECST, W_CMCELL, W_CMPRE, W_L, W_K, W_QLIST, W_FAIL, W_IDS, W_D,
     W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NESLOT, W_SLOTIJ, W_COUNTER,
-    W_LQ, W_ITEMN, W_NSLOTS
+    W_LQ, W_ITEMN, W_PSTAT, W_NSLOTS
 };
 
 #define HCK(ix, expr)                                                                           \
@@ -497,7 +497,9 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         TRY(ws_get(ix, W_DBGD, sizeof(float) * nslots * dbg->dcap, &ddd));
     }
     HCK(ix, hipMemsetAsync(d_fail, 0, sizeof(int32_t), st));
-    HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_select_prefix(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, st); }));
+    void *pstat;
+    TRY(ws_get(ix, W_PSTAT, sizeof(int32_t) * nslots * 2, &pstat));
+    HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_select_prefix(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, st); }));
     TravArgs ta{};
     ta.ix = dv;
     ta.lkey = (const double *)lkey;
@@ -951,8 +953,10 @@ int fbpq_debug_rank(fbpq_index *ix, const float *q, int64_t nq, int32_t P, doubl
     TRY(ws_get(ix, W_LIDX, sizeof(int32_t) * nq * 2 * P, &lidx));
     HCK(ix, hipMemcpyAsync(dq, q, sizeof(float) * nq * ix->dv.D, hipMemcpyHostToDevice, ix->stream));
     HCK(ix, launch_half_approx(ix->dv, (const float *)dq, nq, (float *)dkeys, ix->stream));
+    void *pstat;
+    TRY(ws_get(ix, W_PSTAT, sizeof(int32_t) * nq * 2, &pstat));
     HCK(ix, launch_select_prefix(ix->dv, (const float *)dq, (const float *)dkeys, nq, nullptr, P,
-                                 (double *)lkey, (int32_t *)lidx, ix->stream));
+                                 (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, ix->stream));
     HCK(ix, hipMemcpyAsync(keys, lkey, sizeof(double) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
     HCK(ix, hipMemcpyAsync(idx, lidx, sizeof(int32_t) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
     HCK(ix, hipStreamSynchronize(ix->stream));

@@ -58,9 +58,10 @@ hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, 
 hipError_t launch_half_approx(const DevIndex &ix, const float *q, int64_t nq, float *ka,
                               hipStream_t st);
 
+// pstat [nslots][2] is scratch for the wave select (nullptr: workgroup kernel only)
 hipError_t launch_select_prefix(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
                                 const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
-                                hipStream_t st);
+                                int32_t *pstat, hipStream_t st);
 
 struct TravArgs {
     DevIndex ix;

@@ -97,14 +97,16 @@ __global__ __launch_bounds__(256) void k_lq(ItemArgs a)
 
 // Per-cell values staged in LDS for the first kMetaLds cells of a query.
 constexpr int kMetaLds = 64;
+#ifndef QWAVES
+#define QWAVES 4
+#endif
 
 template <int MH>
-__global__ __launch_bounds__(kNT) void k_score_query(ItemArgs a)
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) void k_score_query(ItemArgs a)
 {
     constexpr int LW = MH * kKc;   // floats of one half table
     constexpr int PT = LW / kNT;   // table floats per thread
     using CodeT = typename CodeU<MH>::T;
-    __shared__ __align__(16) float lq[2 * LW];
     __shared__ __align__(16) float lut1[LW];
     __shared__ __align__(16) float lut2[LW];
     __shared__ int64_t m_p0[kMetaLds];
@@ -131,8 +133,14 @@ __global__ __launch_bounds__(kNT) void k_score_query(ItemArgs a)
         m_j[e] = sij[sl >> 16];
         m_cst[e] = g_cst[e];
     }
-    const float4 *lqg = reinterpret_cast<const float4 *>(a.lq + (int64_t)slot * 2 * LW);
-    for (int x = tid; x < 2 * LW / 4; x += kNT) reinterpret_cast<float4 *>(lq)[x] = lqg[x];
+    // each thread folds the same table positions for every cell: LQ in registers
+    const float *lqg = a.lq + (int64_t)slot * 2 * LW;
+    float lql[PT], lqh[PT];
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        lql[u] = lqg[tid + kNT * u];
+        lqh[u] = lqg[LW + tid + kNT * u];
+    }
     __syncthreads();
     float *dst = a.dist + (int64_t)slot * a.lcap;
     int cur_rs = -1;
@@ -179,10 +187,10 @@ __global__ __launch_bounds__(kNT) void k_score_query(ItemArgs a)
         }
         __syncthreads();  // the previous cell's lookups are done
 #pragma unroll
-        for (int u = 0; u < PT; ++u) lut2[tid + kNT * u] = lq[LW + tid + kNT * u] + c2[u];
+        for (int u = 0; u < PT; ++u) lut2[tid + kNT * u] = lqh[u] + c2[u];
         if (newrow) {
 #pragma unroll
-            for (int u = 0; u < PT; ++u) lut1[tid + kNT * u] = lq[tid + kNT * u] + c1[u];
+            for (int u = 0; u < PT; ++u) lut1[tid + kNT * u] = lql[u] + c1[u];
         }
         cur_rs = rs;
         __syncthreads();

@@ -226,8 +226,10 @@ constexpr int kApproxLds = 16384;
 __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     const float *__restrict__ kapprox, const float *__restrict__ Q, int D,
     const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, int T,
-    const int32_t *qlist, int P, int S, double *__restrict__ lkey, int32_t *__restrict__ lidx)
+    const int32_t *qlist, int P, int S, double *__restrict__ lkey, int32_t *__restrict__ lidx,
+    const int32_t *__restrict__ pstat)
 {
+    if (pstat && pstat[(int64_t)blockIdx.x * 2 + blockIdx.y] == 0) return;  // done by the wave select
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t hist[kBins];
     __shared__ float redf[kSelThreads / 64];
@@ -503,6 +505,137 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     }
 }
 
+// ---- wave select: one wavefront per (query, half), no workgroup barriers ----
+// Samples: the minimum approximate key of each of the 256 centroid groups
+// {c : c = g mod 256}; the P-th smallest sample (found bit by bit with ballot
+// counts) bounds kP from above, as P distinct centroids lie at or below it.
+// Survivors (ka <= bound + 2e) are compacted with ballots, get their exact
+// FP64 keys and are ranked by (key, index) inside the wave. When more than
+// kWaveS survive, pstat keeps the pair for the workgroup kernel.
+constexpr int kWaveS = 512;
+constexpr int kWPB = 4;  // wavefronts (query halves) per workgroup
+
+__device__ __forceinline__ uint32_t okey(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+}
+
+__device__ __forceinline__ float unokey(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
+}
+
+__global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
+    const float *__restrict__ kapprox, const float *__restrict__ Q, int D,
+    const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, int T,
+    const int32_t *qlist, int64_t nslots, int P, double *__restrict__ lkey, int32_t *__restrict__ lidx,
+    int32_t *__restrict__ pstat)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t pair = (int64_t)blockIdx.x * kWPB + wv;
+    if (pair >= nslots * 2) return;
+    const int64_t slot = pair >> 1;
+    const int half = (int)(pair & 1);
+    const int h = D / 2, hpad = (h + 3) & ~3;
+    float *qh = reinterpret_cast<float *>(smem) + (size_t)wv * hpad;
+    int32_t *sidx = reinterpret_cast<int32_t *>(reinterpret_cast<float *>(smem) + (size_t)kWPB * hpad) +
+                    (size_t)wv * kWaveS;
+    uint64_t *skey = reinterpret_cast<uint64_t *>(reinterpret_cast<int32_t *>(reinterpret_cast<float *>(smem) +
+                                                                              (size_t)kWPB * hpad) +
+                                                  (size_t)kWPB * kWaveS) +
+                     (size_t)wv * kWaveS;
+    const int64_t qs = qlist ? qlist[slot] : slot;
+    const float *C = half ? C2 : C1;
+    const float cmax = half ? cmax2 : cmax1;
+    const float *kg = kapprox + (qs * 2 + half) * (int64_t)T;
+    for (int t = lane; t < h; t += 64) qh[t] = Q[qs * D + half * h + t];
+
+    // samples: 4 per lane, group g = 64 s + lane
+    float smp[4] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
+#pragma unroll 4
+    for (int c0 = 0; c0 < T; c0 += 256) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = c0 + 64 * q + lane;
+            if (c < T) {
+                const float x = kg[c];
+                smp[q] = x < smp[q] ? x : smp[q];
+            }
+        }
+    }
+    uint32_t u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = okey(smp[q]);
+    // the P-th smallest sample key, one bit at a time from the top
+    uint32_t pre = 0;
+    int need = P;
+    for (int b = 31; b >= 0; --b) {
+        const uint32_t hm = b == 31 ? 0u : (0xffffffffu << (b + 1));
+        int cnt = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            cnt += __popcll(__ballot(((u[q] & hm) == pre) && !((u[q] >> b) & 1u)));
+        if (cnt < need) {
+            pre |= 1u << b;
+            need -= cnt;
+        }
+    }
+    // error bound of the approximate keys (any summation order, FP32)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double qn = 0.0;
+    for (int t = lane; t < h; t += 64) qn += (double)qh[t] * (double)qh[t];
+    for (int o = 32; o > 0; o >>= 1) qn += __shfl_xor(qn, o);
+    const double rn = sqrt(qn) + sqrt((double)cmax) * (1.0 + 1e-6);
+    const float err = (float)(1.25 * (h + 8) * 0x1.0p-23 * rn * rn) + 1e-30f;
+    const float thr = unokey(pre) + 2.f * err;
+
+    // survivors, compacted in centroid order
+    const uint64_t below = (1ull << lane) - 1ull;
+    int n = 0;
+#pragma unroll 8
+    for (int c0 = 0; c0 < T; c0 += 64) {
+        const int c = c0 + lane;
+        const bool m = c < T && kg[c] <= thr;
+        const uint64_t bm = __ballot(m);
+        if (m) {
+            const int w = n + __popcll(bm & below);
+            if (w < kWaveS) sidx[w] = c;
+        }
+        n += __popcll(bm);
+    }
+    if (n > kWaveS) {
+        if (lane == 0) pstat[pair] = 1;
+        return;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int i = lane; i < n; i += 64) skey[i] = dkey(exact_key(qh, C + (int64_t)sidx[i] * h, h));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double *ok = lkey + (slot * 2 + half) * (int64_t)P;
+    int32_t *oi = lidx + (slot * 2 + half) * (int64_t)P;
+    for (int i = lane; i < n; i += 64) {
+        const uint64_t k = skey[i];
+        const int x = sidx[i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const uint64_t kj = skey[j];
+            rank += (kj < k) | ((kj == k) & (sidx[j] < x));
+        }
+        if (rank < P) {
+            ok[rank] = __longlong_as_double((long long)k);
+            oi[rank] = x;
+        }
+    }
+    if (lane == 0) pstat[pair] = 0;
+}
+
 int select_sort_size(int P, int T)
 {
     int S = 1;
@@ -520,13 +653,23 @@ size_t select_lds_bytes(int D, int T, int S)
 
 hipError_t launch_select_prefix(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
                                 const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
-                                hipStream_t st)
+                                int32_t *pstat, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
-    const int S = select_sort_size(P, ix.T);
-    const size_t lds = select_lds_bytes(ix.D, ix.T, S);
+    const int T = ix.T;
+    const bool wave = pstat && T >= 256 && P <= 256 && P < T;
+    if (wave) {
+        const int hpad = (ix.D / 2 + 3) & ~3;
+        const size_t lds = (size_t)kWPB * ((size_t)hpad * 4 + (size_t)kWaveS * 12);
+        const int64_t pairs = nslots * 2;
+        hipLaunchKernelGGL(k_prefix_wave, dim3((unsigned)((pairs + kWPB - 1) / kWPB)), dim3(kWPB * 64), lds, st,
+                           ka, q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, T, qlist, nslots, P, lkey, lidx, pstat);
+    }
+    const int S = select_sort_size(P, T);
+    const size_t lds = select_lds_bytes(ix.D, T, S);
     hipLaunchKernelGGL(k_select_prefix, dim3((unsigned)nslots, 2), dim3(kSelThreads), lds, st, ka,
-                       q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist, P, S, lkey, lidx);
+                       q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, T, qlist, P, S, lkey, lidx,
+                       wave ? (const int32_t *)pstat : nullptr);
     return hipGetLastError();
 }
 
