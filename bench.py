@@ -8,7 +8,8 @@ traversal, layout, scan with fused top-k), queries and results resident in HBM.
 
 Prints one JSON line: queries/s, step latency percentiles, per-kernel device
 time from HIP events, the scan kernel's achieved bandwidth against the HBM
-roofline, and the FP64 CPU oracle timed on a bounded sample of the same batch.
+roofline (HIP events around that one kernel inside the timed steps), and the
+FP64 CPU oracle timed on a bounded sample of the same batch.
 """
 
 from __future__ import annotations
@@ -25,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+FP32_MFMA_TFLOPS = 157.3
 
 WORKLOADS = {
     "batched": dict(N=10_000_000, T=4096, M=16, nq=10_000, L=10_000, k=100),
@@ -34,6 +36,46 @@ WORKLOADS = {
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
+
+
+def roofline_models(ix, nq: int, L: int, k: int, ncand: int) -> dict:
+    """Algorithmic work per launch of the kernels a roofline is reported for.
+
+    score:     M code bytes per candidate (the scan's HBM stream)
+    select:    the 4-byte distance of every candidate, plus k (id, distance) results per query
+    prefix:    the 4-byte approximate key of every (query, half, centroid), plus P (key, index) outputs
+    half_keys: 2 (D/2) FLOP per (query, half, centroid) on the FP32 matrix cores
+    """
+    P = 128
+    csrc = os.path.join(ROOT, "paper_1404_1831_amd", "csrc")
+    gbs = dict(bound="hbm", peak=HBM_PEAK_GBPS, unit="GB/s", scale=1e9)
+    return {
+        "score": dict(gbs, kernel="k_score_query", amount=ncand * ix.M, what="code bytes",
+                      source=os.path.join(csrc, "k_items.hip")),
+        "select": dict(gbs, kernel="k_select_dist", amount=ncand * 4 + nq * k * 12, what="distance and result bytes",
+                       source=os.path.join(csrc, "k_items.hip")),
+        "prefix": dict(gbs, kernel="k_prefix_wave", amount=nq * 2 * ix.T * 4 + nq * 2 * P * 12,
+                       what="approximate-key and prefix bytes", source=os.path.join(csrc, "k_rank.hip")),
+        "half_keys": dict(bound="mfma", peak=FP32_MFMA_TFLOPS, unit="TFLOP/s", scale=1e12, kernel="k_half_approx",
+                          amount=nq * 2 * ix.T * (ix.D // 2) * 2, what="FP32 matrix-core FLOP",
+                          source=os.path.join(csrc, "k_rank.hip")),
+    }
+
+
+def traffic_from_profile(kernel: str, source: str):
+    """HBM bytes per launch from the committed counter summary of this kernel,
+    if the kernel's source file is unchanged since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(source, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def main() -> int:
@@ -46,6 +88,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=3,
+                    help="untimed steps with every kernel timed, for the per-kernel breakdown")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (read once, written once), "
                          "the reference dispatch for scaling HBM traffic counters")
@@ -91,9 +135,27 @@ def main() -> int:
         fbpq.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, stream)
         log(f"warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
+
+    # per-kernel breakdown (untimed): HIP events around every launch
     fbpq.fbpq_set_option(h, "profile", 1)
+    fbpq.fbpq_set_option(h, "profile_mask", -1)
     for s in range(len(fbpq.STAGES)):
         fbpq.fbpq_profile_read(h, s, reset=True)
+    for _ in range(args.profile_steps):
+        fbpq.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, stream)
+    torch.cuda.synchronize()
+    prof = {}
+    for s, name in enumerate(fbpq.STAGES):
+        ms, n = fbpq.fbpq_profile_read(h, s, reset=True)
+        prof[name] = {"ms_per_launch": ms / n if n else None, "launches": n}
+    log("kernels: " + ", ".join(f"{n}={v['ms_per_launch']:.4f}" for n, v in prof.items() if v["ms_per_launch"]))
+
+    # the dominant kernel among those with a roofline model
+    ncand = nq * min(L, ix.N)
+    models = roofline_models(ix, nq, L, k, ncand)
+    dom = max(models, key=lambda s: prof[s]["ms_per_launch"] or 0.0)
+    fbpq.fbpq_set_option(h, "profile_mask", 1 << fbpq.STAGES.index(dom))
+
     step_ms = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -105,23 +167,21 @@ def main() -> int:
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t_start
     log(f"timed {args.steps} steps in {total_s:.3f}s")
+    dom_ms, dom_n = fbpq.fbpq_profile_read(h, fbpq.STAGES.index(dom), reset=True)
     fbpq.fbpq_set_option(h, "profile", 0)
-    prof = {}
-    for s, name in enumerate(fbpq.STAGES):
-        ms, n = fbpq.fbpq_profile_read(h, s)
-        prof[name] = {"ms_per_launch": ms / n if n else None, "launches": n}
+    dom_ms = dom_ms / dom_n if dom_n else None
 
     ms_per_step = total_s * 1e3 / args.steps
     qps = nq / (ms_per_step / 1e3)
-    # the dominant kernel: the item scan unless the two-pass scan took longer
-    dom = max(("items", "scan2"), key=lambda s: (prof[s]["ms_per_launch"] or 0.0))
-    kname = {"items": "k_scan_items", "scan2": "k_scan2"}[dom]
-    n_scan_launch = prof[dom]["launches"]
-    scan_ms = (prof["items"]["ms_per_launch"] or 0.0) + (prof["scan2"]["ms_per_launch"] or 0.0)
-    # algorithmic bytes of one scan pass: M code bytes per candidate plus 4-byte ids of the results
-    ncand = nq * min(L, ix.N)
-    scan_bytes = ncand * ix.M + nq * k * 4
-    achieved = scan_bytes / (scan_ms * 1e-3) / 1e9 if scan_ms else None
+    model = models[dom]
+    achieved = model["amount"] / (dom_ms * 1e-3) / model["scale"] if dom_ms else None
+    roof = {"bound": model["bound"], "achieved": achieved, "peak": model["peak"], "unit": model["unit"],
+            "frac": achieved / model["peak"] if achieved else None,
+            "traffic": traffic_from_profile(model["kernel"], model["source"]),
+            "kernel": model["kernel"], "algorithmic_per_launch": model["amount"], "what": model["what"],
+            "ms_per_launch": dom_ms, "launches": dom_n}
+    score_ms = prof["score"]["ms_per_launch"]
+    scan_GBps = ncand * ix.M / (score_ms * 1e-3) / 1e9 if score_ms else None
 
     res_ids = d_ids.cpu().numpy()
     res_d = d_d.cpu().numpy()
@@ -177,11 +237,8 @@ def main() -> int:
                                f"nq={nq} per batch, L={L}, k={k}",
                    "N": ix.N, "T": ix.T, "M": ix.M, "nq": nq, "L": L, "k": k},
         "kernels": prof,
-        "scan_GBps": achieved,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": None,
-                     "kernel": kname, "bytes_per_launch": scan_bytes,
-                     "launches": n_scan_launch},
+        "scan_GBps": scan_GBps,
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -163,21 +163,25 @@ int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int
 
 /* Tuning knobs (autotuner and tests). Keys: "prefix" (initial sorted-list
  * length P), "max_cells" (initial per-query visited-cell capacity), "chunk"
- * (candidates per scan chunk), "items" (0/1: use the work-item scan for
+ * (candidates per scan chunk), "items" (0/1: use the cell scan for
  * queries whose visited cells hold many points; 0 sends every query to the
- * two-pass scan), "profile" (0/1: time every kernel launch with HIP events,
- * read with fbpq_profile_read). Errors: INVALID. */
+ * two-pass scan), "profile" (0/1: time kernel launches with HIP events,
+ * read with fbpq_profile_read), "profile_mask" (bit s set: stage s is timed
+ * while profiling is on; default all). Errors: INVALID. */
 int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 
-/* Kernel stages timed by the library's profiler. */
-#define FBPQ_STAGE_HALF_KEYS 0 /* first-layer FP64 half distances */
-#define FBPQ_STAGE_PREFIX 1    /* sorted prefix of each half list */
-#define FBPQ_STAGE_TRAVERSE 2  /* multi-sequence traversal */
-#define FBPQ_STAGE_LAYOUT 3    /* row-major layout of the visited cells */
-#define FBPQ_STAGE_SCAN 4      /* two-pass scan (queries whose cells hold few points) */
-#define FBPQ_STAGE_ITEMS 5     /* item scan: the persistent kernel over work items */
-#define FBPQ_STAGE_MERGE 6     /* item scan: per-query tables, item offsets, final merge */
-#define FBPQ_NUM_STAGES 7
+/* Kernel stages timed by the library's profiler (one kernel each, except
+ * SCAN2, which launches one kernel per table placement). */
+#define FBPQ_STAGE_HALF_KEYS 0 /* first layer: approximate half distances on the matrix cores */
+#define FBPQ_STAGE_PREFIX 1    /* sorted prefix of each half list: one wavefront per half */
+#define FBPQ_STAGE_PREFIX_FB 2 /* sorted prefix: workgroup select for the halves left over */
+#define FBPQ_STAGE_TRAVERSE 3  /* multi-sequence traversal */
+#define FBPQ_STAGE_LAYOUT 4    /* row-major layout of the visited cells */
+#define FBPQ_STAGE_LQ 5        /* per-query tables LQ of the cell scan */
+#define FBPQ_STAGE_SCORE 6     /* cell scan: FP32 distance of every candidate */
+#define FBPQ_STAGE_SELECT 7    /* per-query k smallest of the scored candidates */
+#define FBPQ_STAGE_SCAN2 8     /* two-pass scan (queries whose cells hold few points) */
+#define FBPQ_NUM_STAGES 9
 
 /* Device time per kernel stage, measured with HIP events recorded on the
  * search stream around every launch while profiling is on (option "profile"

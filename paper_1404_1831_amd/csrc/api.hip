@@ -59,6 +59,7 @@ struct fbpq_index {
     size_t pinned_cap = 0;
     // profiler: events recorded around launches while `profile` is on
     bool profile = false;
+    int64_t prof_mask = -1;  // stages timed while profiling
     struct Ev {
         hipEvent_t a, b;
         int stage;
@@ -80,7 +81,7 @@ enum WsSlot {
     W_Q, W_KEYS, W_LKEY, W_LIDX, W_HDR, W_W, W_ROWNE, W_ROWCAND, W_COLNE, W_COLTOT, W_NECS,
     W_NECNT, W_NEBEG, W_NECST, W_CMCELL, W_CMPRE, W_L, W_K, W_QLIST, W_FAIL, W_IDS, W_D,
     W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NESLOT, W_SLOTIJ, W_COUNTER,
-    W_LQ, W_ITEMN, W_PSTAT, W_NSLOTS
+    W_LQ, W_ITEMN, W_PSTAT, W_SELDONE, W_NSLOTS
 };
 
 #define HCK(ix, expr)                                                                           \
@@ -156,7 +157,7 @@ hipEvent_t ev_take(fbpq_index *ix)
 template <typename F>
 hipError_t timed(fbpq_index *ix, int stage, hipStream_t st, F &&launch)
 {
-    if (!ix->profile) return launch();
+    if (!ix->profile || !((ix->prof_mask >> stage) & 1)) return launch();
     hipEvent_t a = ev_take(ix), b = ev_take(ix);
     if (a) (void)hipEventRecord(a, st);
     const hipError_t e = launch();
@@ -499,7 +500,10 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
     HCK(ix, hipMemsetAsync(d_fail, 0, sizeof(int32_t), st));
     void *pstat;
     TRY(ws_get(ix, W_PSTAT, sizeof(int32_t) * nslots * 2, &pstat));
-    HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_select_prefix(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, st); }));
+    const bool pwave = prefix_wave_ok(dv, P);
+    if (pwave)
+        HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_wave(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, st); }));
+    HCK(ix, timed(ix, pwave ? FBPQ_STAGE_PREFIX_FB : FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_block(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, pwave ? (const int32_t *)pstat : nullptr, st); }));
     TravArgs ta{};
     ta.ix = dv;
     ta.lkey = (const double *)lkey;
@@ -541,7 +545,8 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         HCK(ix, timed(ix, FBPQ_STAGE_LAYOUT, st, [&] { return launch_layout(la, nslots, st); }));
         if (ix->items) {
             const int wcap = items_wcap(k_max);
-            void *lq, *dist;
+            void *lq, *dist, *seldone;
+            TRY(ws_get(ix, W_SELDONE, sizeof(int32_t) * nslots, &seldone));
             TRY(ws_get(ix, W_LQ, sizeof(float) * nslots * dv.M * FBPQ_KC, &lq));
             const int64_t dstride = (lcap + 63) & ~(int64_t)63;  // 256-byte aligned distance rows
             TRY(ws_get(ix, W_ITEMN, sizeof(float) * nslots * dstride, &dist));
@@ -565,14 +570,15 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
             ia.dist = (float *)dist;
             ia.lcap = dstride;
             ia.wcap = wcap;
+            ia.sel_done = (int32_t *)seldone;
             ia.out_ids = d_ids;
             ia.out_d = d_d;
             ia.dbg_pos = (int64_t *)dpos;
             ia.dbg_d = (float *)ddd;
             ia.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
-            HCK(ix, timed(ix, FBPQ_STAGE_MERGE, st, [&] { return launch_items_prep(ia, st); }));
-            HCK(ix, timed(ix, FBPQ_STAGE_ITEMS, st, [&] { return launch_items_scan(ia, st); }));
-            HCK(ix, timed(ix, FBPQ_STAGE_MERGE, st, [&] { return launch_items_merge(ia, st); }));
+            HCK(ix, timed(ix, FBPQ_STAGE_LQ, st, [&] { return launch_items_prep(ia, st); }));
+            HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_scan(ia, st); }));
+            HCK(ix, timed(ix, FBPQ_STAGE_SELECT, st, [&] { return launch_items_merge(ia, st); }));
         }
         ScanArgs sa{};
         sa.ix = dv;
@@ -604,7 +610,7 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         sa.dbg_pos = (int64_t *)dpos;
         sa.dbg_d = (float *)ddd;
         sa.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
-        HCK(ix, timed(ix, FBPQ_STAGE_SCAN, st, [&] { return launch_scan(sa, nslots, st); }));
+        HCK(ix, timed(ix, FBPQ_STAGE_SCAN2, st, [&] { return launch_scan(sa, nslots, st); }));
     }
     // how many slots need another round
     // bytes [0, 64) of the pinned buffer hold the failure count; the L/k staging starts at 64
@@ -955,8 +961,12 @@ int fbpq_debug_rank(fbpq_index *ix, const float *q, int64_t nq, int32_t P, doubl
     HCK(ix, launch_half_approx(ix->dv, (const float *)dq, nq, (float *)dkeys, ix->stream));
     void *pstat;
     TRY(ws_get(ix, W_PSTAT, sizeof(int32_t) * nq * 2, &pstat));
-    HCK(ix, launch_select_prefix(ix->dv, (const float *)dq, (const float *)dkeys, nq, nullptr, P,
-                                 (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, ix->stream));
+    const bool pwave = prefix_wave_ok(ix->dv, P);
+    if (pwave)
+        HCK(ix, launch_prefix_wave(ix->dv, (const float *)dq, (const float *)dkeys, nq, nullptr, P,
+                                   (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, ix->stream));
+    HCK(ix, launch_prefix_block(ix->dv, (const float *)dq, (const float *)dkeys, nq, nullptr, P, (double *)lkey,
+                                (int32_t *)lidx, pwave ? (const int32_t *)pstat : nullptr, ix->stream));
     HCK(ix, hipMemcpyAsync(keys, lkey, sizeof(double) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
     HCK(ix, hipMemcpyAsync(idx, lidx, sizeof(int32_t) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
     HCK(ix, hipStreamSynchronize(ix->stream));
@@ -994,6 +1004,8 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
         ix->items = value != 0;
     } else if (!strcmp(key, "profile")) {
         ix->profile = value != 0;
+    } else if (!strcmp(key, "profile_mask")) {
+        ix->prof_mask = value;
     } else if (!strcmp(key, "chunk")) {
         if (value < 256 || value > (1 << 16)) return fail(FBPQ_E_INVALID, "chunk out of range");
         ix->chunk = (int32_t)value;

@@ -58,10 +58,17 @@ hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, 
 hipError_t launch_half_approx(const DevIndex &ix, const float *q, int64_t nq, float *ka,
                               hipStream_t st);
 
-// pstat [nslots][2] is scratch for the wave select (nullptr: workgroup kernel only)
-hipError_t launch_select_prefix(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
-                                const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
-                                int32_t *pstat, hipStream_t st);
+// Sorted prefix of each half list. The wave select handles the (query, half)
+// pairs it can and records in pstat [nslots][2] (0 done, 1 left over) which
+// remain; the workgroup kernel then takes the pairs left over (every pair when
+// pstat is null).
+bool prefix_wave_ok(const DevIndex &ix, int32_t P);
+hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
+                              const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
+                              int32_t *pstat, hipStream_t st);
+hipError_t launch_prefix_block(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
+                               const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
+                               const int32_t *pstat, hipStream_t st);
 
 struct TravArgs {
     DevIndex ix;
@@ -152,6 +159,7 @@ struct ItemArgs {
     float *dist;           // [slot][lcap] FP32 distance of every candidate (row-major index)
     int64_t lcap;
     int32_t wcap;
+    int32_t *sel_done;     // [slot] 1: top-k written by the cell scan itself
     int64_t *out_ids;      // [query][k_max]
     float *out_d;
     int64_t *dbg_pos;

@@ -13,7 +13,9 @@
 //                 the row changes (the paper's per-row table reuse), LUT2 once
 //                 per cell; the cell's first block of codes is requested before
 //                 its table rows, and the FP32 distances stream to HBM;
-//  k_select_dist  per query, the k smallest (distance, id) of its distances.
+//                 A query whose k fits is then selected in the same workgroup;
+//  k_select_dist  per query left over, the k smallest (distance, id) of its
+//                 distances.
 #include "fbpq_dev.h"
 #include "select_k.h"
 
@@ -97,6 +99,7 @@ __global__ __launch_bounds__(256) void k_lq(ItemArgs a)
 
 // Per-cell values staged in LDS for the first kMetaLds cells of a query.
 constexpr int kMetaLds = 64;
+constexpr int kFWin = 512;  // candidates the fused selection can rank
 #ifndef QWAVES
 #define QWAVES 4
 #endif
@@ -112,10 +115,15 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
     __shared__ int64_t m_p0[kMetaLds];
     __shared__ int32_t m_n[kMetaLds], m_t0[kMetaLds], m_rs[kMetaLds], m_i[kMetaLds], m_j[kMetaLds];
     __shared__ float m_cst[kMetaLds];
+    __shared__ uint32_t s_smp[kNT];
+    __shared__ uint64_t s_win[kFWin];
+    __shared__ uint32_t s_tau;
+    __shared__ int s_nwin;
     const int slot = blockIdx.x;
     const TravHdr h = a.hdr[slot];
     if (h.status != kStOk || h.n_items == 0) return;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid == 0) a.sel_done[slot] = 0;
     const int64_t mc = a.max_cells;
     const int32_t *g_cs = a.ne_cs + slot * mc, *g_cnt = a.ne_cnt + slot * mc;
     const int32_t *g_sl = a.ne_slot + slot * mc;
@@ -143,6 +151,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
     }
     __syncthreads();
     float *dst = a.dist + (int64_t)slot * a.lcap;
+    float smin = __builtin_huge_valf();  // this thread's smallest distance: a selection sample
+    bool scored = false;
     int cur_rs = -1;
     for (int e = 0; e < nne; ++e) {
         int64_t p0;
@@ -211,6 +221,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
                 if (o < n) {
                     const float d = cst + lsum<MH>(lut1, ca[j]) + lsum<MH>(lut2, cb[j]);
                     dst[t0 + o] = d;
+                    smin = d < smin ? d : smin;
+                    scored = true;
                     if (a.dbg_pos) {
                         a.dbg_pos[(int64_t)slot * a.dbg_cap + t0 + o] = p0 + o;
                         a.dbg_d[(int64_t)slot * a.dbg_cap + t0 + o] = d;
@@ -219,6 +231,109 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
             }
         }
     }
+
+    // Fused selection of the kq smallest (distance, id), with the bound of
+    // k_select_dist: the kq-th smallest per-thread minimum. The distances are
+    // read back while they are still in the cache. Queries with kq above the
+    // thread count, too few samples or too many candidates at or below the
+    // bound are left to k_select_dist.
+    const int64_t qs = a.qlist ? a.qlist[slot] : slot;
+    const int kq = a.k[qs];
+    const int64_t ncand = h.ncand;
+    if (kq > kNT) return;
+    s_smp[tid] = scored ? fkey(smin) : 0xffffffffu;
+    if (tid == 0) s_nwin = 0;
+    __syncthreads();  // samples, and every thread's distance stores
+    if (tid < 64) {
+        uint32_t u[kNT / 64];
+#pragma unroll
+        for (int q = 0; q < kNT / 64; ++q) u[q] = s_smp[lane + 64 * q];
+        uint32_t pre = 0;
+        int need = kq;
+        for (int b = 31; b >= 0; --b) {
+            const uint32_t hm = b == 31 ? 0u : (0xffffffffu << (b + 1));
+            int cnt = 0;
+#pragma unroll
+            for (int q = 0; q < kNT / 64; ++q)
+                cnt += __popcll(__ballot(((u[q] & hm) == pre) && !((u[q] >> b) & 1u)));
+            if (cnt < need) {
+                pre |= 1u << b;
+                need -= cnt;
+            }
+        }
+        if (tid == 0) s_tau = ncand <= kq ? 0xffffffffu : pre;
+    }
+    __syncthreads();
+    const uint32_t tau = s_tau;
+    if (tau == 0xffffffffu && ncand > kq) return;  // fewer than kq samples
+    constexpr int kFB = 16;  // distances per thread loaded before they are tested
+    for (int64_t b0 = 0; b0 < ncand; b0 += kNT * kFB) {
+        float dv[kFB];
+#pragma unroll
+        for (int j = 0; j < kFB; ++j) {
+            const int64_t t = b0 + tid + kNT * j;
+            dv[j] = t < ncand ? dst[t] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < kFB; ++j) {
+            const int64_t t = b0 + tid + kNT * j;
+            const uint32_t key = fkey(dv[j]);
+            const bool pred = t < ncand && key <= tau;
+            const uint64_t m = __ballot(pred);
+            if (m) {
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&s_nwin, (int)__popcll(m));
+                base = __shfl(base, 0);
+                if (pred) {
+                    const int wi = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+                    if (wi < kFWin) s_win[wi] = ((uint64_t)key << 32) | (uint32_t)t;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int nwin = s_nwin;
+    if (nwin > kFWin) return;
+    for (int i = tid; i < nwin; i += kNT) {
+        const uint64_t x = s_win[i];
+        const int64_t t = (uint32_t)x;
+        int lo = 0, hi = nne - 1;
+        int64_t p;
+        if (nne <= kMetaLds) {
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (m_t0[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            p = m_p0[lo] + (t - m_t0[lo]);
+        } else {
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (g_cs[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            p = g_beg[lo] + (t - g_cs[lo]);
+        }
+        s_win[i] = (x & 0xffffffff00000000ull) | a.ix.ids[p];
+    }
+    __syncthreads();
+    int64_t *oid = a.out_ids + qs * a.k_max;
+    float *od = a.out_d + qs * a.k_max;
+    const int nk = nwin < kq ? nwin : kq;
+    for (int i = tid; i < nwin; i += kNT) {
+        const uint64_t x = s_win[i];
+        int rank = 0;
+        for (int j = 0; j < nwin; ++j) rank += s_win[j] < x;
+        if (rank < nk) {
+            oid[rank] = (int64_t)(uint32_t)x;
+            od[rank] = unfkey((uint32_t)(x >> 32));
+        }
+    }
+    for (int r = nk + tid; r < a.k_max; r += kNT) {
+        oid[r] = -1;
+        od[r] = __builtin_huge_valf();
+    }
+    if (tid == 0) a.sel_done[slot] = 1;
 }
 
 // The k smallest (distance, id) of one query over its streamed distances.
@@ -255,6 +370,7 @@ __global__ __launch_bounds__(kSelNT) void k_select_dist(ItemArgs a)
     const int tid = threadIdx.x, lane = tid & 63;
     const TravHdr h = a.hdr[slot];
     if (h.status != kStOk || h.n_items == 0) return;
+    if (a.sel_done[slot]) return;  // selected inside the cell scan
     const int64_t qs = a.qlist ? a.qlist[slot] : slot;
     const int kq = a.k[qs];
     int KP = 1;

@@ -651,25 +651,31 @@ size_t select_lds_bytes(int D, int T, int S)
     return f * 4 + (size_t)S * (sizeof(uint64_t) + sizeof(int32_t));
 }
 
-hipError_t launch_select_prefix(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
-                                const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
-                                int32_t *pstat, hipStream_t st)
+bool prefix_wave_ok(const DevIndex &ix, int32_t P) { return ix.T >= 256 && P <= 256 && P < ix.T; }
+
+hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
+                              const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
+                              int32_t *pstat, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
-    const int T = ix.T;
-    const bool wave = pstat && T >= 256 && P <= 256 && P < T;
-    if (wave) {
-        const int hpad = (ix.D / 2 + 3) & ~3;
-        const size_t lds = (size_t)kWPB * ((size_t)hpad * 4 + (size_t)kWaveS * 12);
-        const int64_t pairs = nslots * 2;
-        hipLaunchKernelGGL(k_prefix_wave, dim3((unsigned)((pairs + kWPB - 1) / kWPB)), dim3(kWPB * 64), lds, st,
-                           ka, q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, T, qlist, nslots, P, lkey, lidx, pstat);
-    }
-    const int S = select_sort_size(P, T);
-    const size_t lds = select_lds_bytes(ix.D, T, S);
+    if (!prefix_wave_ok(ix, P) || !pstat) return hipErrorInvalidValue;
+    const int hpad = (ix.D / 2 + 3) & ~3;
+    const size_t lds = (size_t)kWPB * ((size_t)hpad * 4 + (size_t)kWaveS * 12);
+    const int64_t pairs = nslots * 2;
+    hipLaunchKernelGGL(k_prefix_wave, dim3((unsigned)((pairs + kWPB - 1) / kWPB)), dim3(kWPB * 64), lds, st,
+                       ka, q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist, nslots, P, lkey, lidx, pstat);
+    return hipGetLastError();
+}
+
+hipError_t launch_prefix_block(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
+                               const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
+                               const int32_t *pstat, hipStream_t st)
+{
+    if (nslots == 0) return hipSuccess;
+    const int S = select_sort_size(P, ix.T);
+    const size_t lds = select_lds_bytes(ix.D, ix.T, S);
     hipLaunchKernelGGL(k_select_prefix, dim3((unsigned)nslots, 2), dim3(kSelThreads), lds, st, ka,
-                       q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, T, qlist, P, S, lkey, lidx,
-                       wave ? (const int32_t *)pstat : nullptr);
+                       q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist, P, S, lkey, lidx, pstat);
     return hipGetLastError();
 }
 

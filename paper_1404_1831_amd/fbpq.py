@@ -32,7 +32,7 @@ EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbp
            "fbpq_debug_dists", "fbpq_debug_tables", "fbpq_debug_rank", "fbpq_info",
            "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_free_index",
            "fbpq_last_error")
-STAGES = ("half_keys", "prefix", "traverse", "layout", "scan2", "items", "items_aux")
+STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2")
 
 
 class FbpqError(RuntimeError):
