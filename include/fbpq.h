@@ -167,7 +167,8 @@ int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int
  * queries whose visited cells hold many points; 0 sends every query to the
  * two-pass scan), "profile" (0/1: time kernel launches with HIP events,
  * read with fbpq_profile_read), "profile_mask" (bit s set: stage s is timed
- * while profiling is on; default all). Errors: INVALID. */
+ * while profiling is on; default all), "stats" (0/1: path counters, read
+ * with fbpq_stats_read). Errors: INVALID, DEVICE. */
 int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 
 /* Kernel stages timed by the library's profiler (one kernel each, except
@@ -182,6 +183,20 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 #define FBPQ_STAGE_SELECT 7    /* per-query k smallest of the scored candidates */
 #define FBPQ_STAGE_SCAN2 8     /* two-pass scan (queries whose cells hold few points) */
 #define FBPQ_NUM_STAGES 9
+
+/* Path counters, accumulated on the device while option "stats" is 1 (setting
+ * it to 1 clears them). fbpq_stats_read copies min(n, FBPQ_NUM_STATS) of them
+ * to out[] and, if reset != 0, clears them. The counters say which kernels
+ * served each query, for tests and tuning. Errors: INVALID, DEVICE, STATE
+ * (stats not enabled). */
+#define FBPQ_STAT_CELL_SCAN 0   /* queries scored by the query-major cell scan */
+#define FBPQ_STAT_FUSED_TOPK 1  /* ... of which the top-k was selected inside the scan */
+#define FBPQ_STAT_TWO_PASS 2    /* queries scored by the two-pass scan */
+#define FBPQ_STAT_PREFIX_WAVE 3 /* (query, half) prefixes finished by the wavefront select */
+#define FBPQ_STAT_PREFIX_WG 4   /* (query, half) prefixes finished by the workgroup select */
+#define FBPQ_STAT_RETRIED 5     /* queries traversed again with a longer prefix or more cells */
+#define FBPQ_NUM_STATS 6
+int fbpq_stats_read(fbpq_index *ix, int64_t *out, int32_t n, int32_t reset);
 
 /* Device time per kernel stage, measured with HIP events recorded on the
  * search stream around every launch while profiling is on (option "profile"

@@ -73,6 +73,9 @@ struct fbpq_index {
     int64_t max_cells = 4096;
     int32_t chunk = 8192;
     bool items = true;
+    // path counters (option "stats")
+    unsigned long long *stats_dev = nullptr;
+    int64_t stat_retried = 0;
 };
 
 namespace {
@@ -225,7 +228,7 @@ void free_all(fbpq_index *ix)
     (void)hipSetDevice(ix->device);
     if (ix->stream) (void)hipStreamSynchronize(ix->stream);
     void *ps[] = {ix->C1, ix->C2, ix->R, ix->offsets, ix->codesA, ix->codesB, ix->ids,
-                  ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2};
+                  ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2, ix->stats_dev};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     for (auto &b : ix->ws)
@@ -502,8 +505,8 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
     TRY(ws_get(ix, W_PSTAT, sizeof(int32_t) * nslots * 2, &pstat));
     const bool pwave = prefix_wave_ok(dv, P);
     if (pwave)
-        HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_wave(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, st); }));
-    HCK(ix, timed(ix, pwave ? FBPQ_STAGE_PREFIX_FB : FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_block(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, pwave ? (const int32_t *)pstat : nullptr, st); }));
+        HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_wave(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, ix->stats_dev, st); }));
+    HCK(ix, timed(ix, pwave ? FBPQ_STAGE_PREFIX_FB : FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_block(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, pwave ? (const int32_t *)pstat : nullptr, ix->stats_dev, st); }));
     TravArgs ta{};
     ta.ix = dv;
     ta.lkey = (const double *)lkey;
@@ -571,6 +574,7 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
             ia.lcap = dstride;
             ia.wcap = wcap;
             ia.sel_done = (int32_t *)seldone;
+            ia.stats = ix->stats_dev;
             ia.out_ids = d_ids;
             ia.out_d = d_d;
             ia.dbg_pos = (int64_t *)dpos;
@@ -610,6 +614,7 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         sa.dbg_pos = (int64_t *)dpos;
         sa.dbg_d = (float *)ddd;
         sa.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
+        sa.stats = ix->stats_dev;
         HCK(ix, timed(ix, FBPQ_STAGE_SCAN2, st, [&] { return launch_scan(sa, nslots, st); }));
     }
     // how many slots need another round
@@ -722,6 +727,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
                       (const int64_t *)dL, (const int32_t *)dk,
                       k_max, d_ids, d_d, st, (const float *)keys, (int32_t *)dfail, dbg, &nfail));
         if (nfail == 0) break;
+        ix->stat_retried += nfail;
         // read the failed queries and their reasons, then grow P and/or the cell capacity
         failed.resize(nfail);
         HCK(ix, hipMemcpy(failed.data(), (int32_t *)dfail + 1, sizeof(int32_t) * nfail, hipMemcpyDeviceToHost));
@@ -964,9 +970,10 @@ int fbpq_debug_rank(fbpq_index *ix, const float *q, int64_t nq, int32_t P, doubl
     const bool pwave = prefix_wave_ok(ix->dv, P);
     if (pwave)
         HCK(ix, launch_prefix_wave(ix->dv, (const float *)dq, (const float *)dkeys, nq, nullptr, P,
-                                   (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, ix->stream));
+                                   (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, ix->stats_dev, ix->stream));
     HCK(ix, launch_prefix_block(ix->dv, (const float *)dq, (const float *)dkeys, nq, nullptr, P, (double *)lkey,
-                                (int32_t *)lidx, pwave ? (const int32_t *)pstat : nullptr, ix->stream));
+                                (int32_t *)lidx, pwave ? (const int32_t *)pstat : nullptr, ix->stats_dev,
+                                ix->stream));
     HCK(ix, hipMemcpyAsync(keys, lkey, sizeof(double) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
     HCK(ix, hipMemcpyAsync(idx, lidx, sizeof(int32_t) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
     HCK(ix, hipStreamSynchronize(ix->stream));
@@ -1006,6 +1013,21 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
         ix->profile = value != 0;
     } else if (!strcmp(key, "profile_mask")) {
         ix->prof_mask = value;
+    } else if (!strcmp(key, "stats")) {
+        if (value) {
+            HCK(ix, hipSetDevice(ix->device));
+            if (!ix->stats_dev) {
+                void *p = nullptr;
+                HCK(ix, hipMalloc(&p, sizeof(unsigned long long) * kNumStatSlots));
+                ix->stats_dev = (unsigned long long *)p;
+            }
+            HCK(ix, hipMemset(ix->stats_dev, 0, sizeof(unsigned long long) * kNumStatSlots));
+            ix->stat_retried = 0;
+        } else if (ix->stats_dev) {
+            HCK(ix, hipDeviceSynchronize());
+            (void)hipFree(ix->stats_dev);
+            ix->stats_dev = nullptr;
+        }
     } else if (!strcmp(key, "chunk")) {
         if (value < 256 || value > (1 << 16)) return fail(FBPQ_E_INVALID, "chunk out of range");
         ix->chunk = (int32_t)value;
@@ -1024,6 +1046,24 @@ int fbpq_profile_read(fbpq_index *ix, int32_t stage, int32_t reset, double *ms, 
     if (reset) {
         ix->prof_ms[stage] = 0;
         ix->prof_n[stage] = 0;
+    }
+    return FBPQ_OK;
+}
+
+int fbpq_stats_read(fbpq_index *ix, int64_t *out, int32_t n, int32_t reset)
+{
+    TRY(check_handle(ix));
+    if (!out || n < 0) return fail(FBPQ_E_INVALID, "bad arguments");
+    if (!ix->stats_dev) return fail(FBPQ_E_STATE, "path counters are off (option \"stats\")");
+    HCK(ix, hipSetDevice(ix->device));
+    unsigned long long h[kNumStatSlots];
+    HCK(ix, hipDeviceSynchronize());
+    HCK(ix, hipMemcpy(h, ix->stats_dev, sizeof(h), hipMemcpyDeviceToHost));
+    h[FBPQ_STAT_RETRIED] = (unsigned long long)ix->stat_retried;
+    for (int i = 0; i < n && i < FBPQ_NUM_STATS; ++i) out[i] = (int64_t)h[i];
+    if (reset) {
+        HCK(ix, hipMemset(ix->stats_dev, 0, sizeof(h)));
+        ix->stat_retried = 0;
     }
     return FBPQ_OK;
 }

@@ -31,6 +31,10 @@ struct TravHdr {
     int64_t cut_take; // points taken from the last visited cell
 };
 
+// Path counters (slots of FBPQ_STAT_*), incremented when the pointer is set.
+constexpr int kStatCellScan = 0, kStatFused = 1, kStatTwoPass = 2, kStatPrefixWave = 3, kStatPrefixWG = 4;
+constexpr int kNumStatSlots = 8;
+
 // Candidate block of the cell scan: up to kItem candidates of one nonempty cell.
 constexpr int kItem = 2048;
 constexpr int kItemMinAvg = 128;   // mean points per nonempty cell for the item scan
@@ -65,10 +69,10 @@ hipError_t launch_half_approx(const DevIndex &ix, const float *q, int64_t nq, fl
 bool prefix_wave_ok(const DevIndex &ix, int32_t P);
 hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
                               const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
-                              int32_t *pstat, hipStream_t st);
+                              int32_t *pstat, unsigned long long *stats, hipStream_t st);
 hipError_t launch_prefix_block(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
                                const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
-                               const int32_t *pstat, hipStream_t st);
+                               const int32_t *pstat, unsigned long long *stats, hipStream_t st);
 
 struct TravArgs {
     DevIndex ix;
@@ -134,13 +138,13 @@ struct ScanArgs {
     int64_t *dbg_pos;      // optional [slot][dbg_cap]
     float *dbg_d;
     int64_t dbg_cap;
+    unsigned long long *stats;  // optional path counters
 };
 hipError_t launch_scan(const ScanArgs &a, int64_t nslots, hipStream_t st);
 
 size_t scan_lds_bytes(int D, int M, int chunk, int k_max, int P);
 constexpr int kScanCellsLds = 256;  // nonempty cells whose tables the scan keeps in LDS
 
-// One work item of the score kernel (32 bytes, written by k_item_pack).
 struct ItemArgs {
     DevIndex ix;
     const float *q;        // [query][D]
@@ -165,6 +169,7 @@ struct ItemArgs {
     int64_t *dbg_pos;
     float *dbg_d;
     int64_t dbg_cap;
+    unsigned long long *stats;  // optional path counters
 };
 hipError_t launch_items_prep(const ItemArgs &a, hipStream_t st);   // LQ tables
 hipError_t launch_items_scan(const ItemArgs &a, hipStream_t st);   // query-major cell scan

@@ -123,7 +123,10 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
     const TravHdr h = a.hdr[slot];
     if (h.status != kStOk || h.n_items == 0) return;
     const int tid = threadIdx.x, lane = tid & 63;
-    if (tid == 0) a.sel_done[slot] = 0;
+    if (tid == 0) {
+        a.sel_done[slot] = 0;
+        if (a.stats) atomicAdd(&a.stats[kStatCellScan], 1ull);
+    }
     const int64_t mc = a.max_cells;
     const int32_t *g_cs = a.ne_cs + slot * mc, *g_cnt = a.ne_cnt + slot * mc;
     const int32_t *g_sl = a.ne_slot + slot * mc;
@@ -333,7 +336,10 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
         oid[r] = -1;
         od[r] = __builtin_huge_valf();
     }
-    if (tid == 0) a.sel_done[slot] = 1;
+    if (tid == 0) {
+        a.sel_done[slot] = 1;
+        if (a.stats) atomicAdd(&a.stats[kStatFused], 1ull);
+    }
 }
 
 // The k smallest (distance, id) of one query over its streamed distances.

@@ -227,9 +227,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     const float *__restrict__ kapprox, const float *__restrict__ Q, int D,
     const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, int T,
     const int32_t *qlist, int P, int S, double *__restrict__ lkey, int32_t *__restrict__ lidx,
-    const int32_t *__restrict__ pstat)
+    const int32_t *__restrict__ pstat, unsigned long long *stats)
 {
     if (pstat && pstat[(int64_t)blockIdx.x * 2 + blockIdx.y] == 0) return;  // done by the wave select
+    if (stats && threadIdx.x == 0) atomicAdd(&stats[kStatPrefixWG], 1ull);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t hist[kBins];
     __shared__ float redf[kSelThreads / 64];
@@ -506,9 +507,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
 }
 
 // ---- wave select: one wavefront per (query, half), no workgroup barriers ----
-// Samples: the minimum approximate key of each of the 256 centroid groups
-// {c : c = g mod 256}; the P-th smallest sample (found bit by bit with ballot
-// counts) bounds kP from above, as P distinct centroids lie at or below it.
+// Samples: the minimum approximate key of each of the G = 64 SPL centroid
+// groups {c : c = g mod G} (SPL samples per lane, G >= 2P); the P-th smallest
+// sample (found bit by bit with ballot counts) bounds kP from above, as P
+// distinct centroids lie at or below it.
 // Survivors (ka <= bound + 2e) are compacted with ballots, get their exact
 // FP64 keys and are ranked by (key, index) inside the wave. When more than
 // kWaveS survive, pstat keeps the pair for the workgroup kernel.
@@ -526,11 +528,12 @@ __device__ __forceinline__ float unokey(uint32_t k)
     return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
 }
 
+template <int SPL>
 __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
     const float *__restrict__ kapprox, const float *__restrict__ Q, int D,
     const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, int T,
     const int32_t *qlist, int64_t nslots, int P, double *__restrict__ lkey, int32_t *__restrict__ lidx,
-    int32_t *__restrict__ pstat)
+    int32_t *__restrict__ pstat, unsigned long long *stats)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -552,12 +555,14 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
     const float *kg = kapprox + (qs * 2 + half) * (int64_t)T;
     for (int t = lane; t < h; t += 64) qh[t] = Q[qs * D + half * h + t];
 
-    // samples: 4 per lane, group g = 64 s + lane
-    float smp[4] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
-#pragma unroll 4
-    for (int c0 = 0; c0 < T; c0 += 256) {
+    // samples: SPL per lane, group g = 64 s + lane
+    float smp[SPL];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < SPL; ++q) smp[q] = __builtin_huge_valf();
+#pragma unroll 2
+    for (int c0 = 0; c0 < T; c0 += 64 * SPL) {
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
             const int c = c0 + 64 * q + lane;
             if (c < T) {
                 const float x = kg[c];
@@ -565,9 +570,9 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
             }
         }
     }
-    uint32_t u[4];
+    uint32_t u[SPL];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) u[q] = okey(smp[q]);
+    for (int q = 0; q < SPL; ++q) u[q] = okey(smp[q]);
     // the P-th smallest sample key, one bit at a time from the top
     uint32_t pre = 0;
     int need = P;
@@ -575,7 +580,7 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
         const uint32_t hm = b == 31 ? 0u : (0xffffffffu << (b + 1));
         int cnt = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < SPL; ++q)
             cnt += __popcll(__ballot(((u[q] & hm) == pre) && !((u[q] >> b) & 1u)));
         if (cnt < need) {
             pre |= 1u << b;
@@ -633,7 +638,10 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
             oi[rank] = x;
         }
     }
-    if (lane == 0) pstat[pair] = 0;
+    if (lane == 0) {
+        pstat[pair] = 0;
+        if (stats) atomicAdd(&stats[kStatPrefixWave], 1ull);
+    }
 }
 
 int select_sort_size(int P, int T)
@@ -655,27 +663,32 @@ bool prefix_wave_ok(const DevIndex &ix, int32_t P) { return ix.T >= 256 && P <= 
 
 hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
                               const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
-                              int32_t *pstat, hipStream_t st)
+                              int32_t *pstat, unsigned long long *stats, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
     if (!prefix_wave_ok(ix, P) || !pstat) return hipErrorInvalidValue;
     const int hpad = (ix.D / 2 + 3) & ~3;
     const size_t lds = (size_t)kWPB * ((size_t)hpad * 4 + (size_t)kWaveS * 12);
     const int64_t pairs = nslots * 2;
-    hipLaunchKernelGGL(k_prefix_wave, dim3((unsigned)((pairs + kWPB - 1) / kWPB)), dim3(kWPB * 64), lds, st,
-                       ka, q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist, nslots, P, lkey, lidx, pstat);
+    const dim3 g((unsigned)((pairs + kWPB - 1) / kWPB)), b(kWPB * 64);
+    if (P <= 128)
+        hipLaunchKernelGGL(k_prefix_wave<4>, g, b, lds, st, ka, q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T,
+                           qlist, nslots, P, lkey, lidx, pstat, stats);
+    else
+        hipLaunchKernelGGL(k_prefix_wave<8>, g, b, lds, st, ka, q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T,
+                           qlist, nslots, P, lkey, lidx, pstat, stats);
     return hipGetLastError();
 }
 
 hipError_t launch_prefix_block(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
                                const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
-                               const int32_t *pstat, hipStream_t st)
+                               const int32_t *pstat, unsigned long long *stats, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
     const int S = select_sort_size(P, ix.T);
     const size_t lds = select_lds_bytes(ix.D, ix.T, S);
     hipLaunchKernelGGL(k_select_prefix, dim3((unsigned)nslots, 2), dim3(kSelThreads), lds, st, ka,
-                       q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist, P, S, lkey, lidx, pstat);
+                       q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist, P, S, lkey, lidx, pstat, stats);
     return hipGetLastError();
 }
 

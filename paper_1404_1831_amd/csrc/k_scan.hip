@@ -111,6 +111,7 @@ __global__ __launch_bounds__(512) void k_scan2(ScanArgs a)
     const TravHdr h = a.hdr[slot];
     if (h.status != kStOk || h.n_items != 0) return;
     if (TAB_LDS != (h.nne <= kScanCellsLds)) return;
+    if (a.stats && tid == 0) atomicAdd(&a.stats[kStatTwoPass], 1ull);
     const int D = a.ix.D, ds = D / M, P = a.P;
     const int kq = a.k[qs];
     int KP = 1;

@@ -30,9 +30,10 @@ FBPQ_K_MAX = 1024
 EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbpq_build_tables",
            "fbpq_search", "fbpq_search_uneven", "fbpq_search_device", "fbpq_debug_visit",
            "fbpq_debug_dists", "fbpq_debug_tables", "fbpq_debug_rank", "fbpq_info",
-           "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_free_index",
-           "fbpq_last_error")
+           "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_stats_read",
+           "fbpq_free_index", "fbpq_last_error")
 STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2")
+STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried")
 
 
 class FbpqError(RuntimeError):
@@ -76,6 +77,7 @@ def _load():
         "fbpq_table_bytes": ([i64, i64, i64, P, P], ctypes.c_int),
         "fbpq_set_option": ([P, ctypes.c_char_p, i64], ctypes.c_int),
         "fbpq_profile_read": ([P, i32, i32, P, P], ctypes.c_int),
+        "fbpq_stats_read": ([P, P, i32, i32], ctypes.c_int),
         "fbpq_free_index": ([P], None),
         "fbpq_last_error": ([], ctypes.c_char_p),
     }
@@ -150,6 +152,13 @@ def fbpq_profile_read(h, stage: int, reset: bool = False):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(lib.fbpq_profile_read(h, int(stage), int(reset), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def fbpq_stats_read(h, reset: bool = False) -> dict:
+    """Path counters (option "stats" must be on), by name."""
+    out = np.zeros(len(STATS), np.int64)
+    _check(lib.fbpq_stats_read(h, _p(out), len(STATS), int(reset)))
+    return dict(zip(STATS, out.tolist()))
 
 
 def fbpq_free_index(h) -> None:

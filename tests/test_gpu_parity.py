@@ -97,7 +97,8 @@ def test_rank_prefix_ties(fb):
 
 
 def _check_visit(fb, h, ix, Q, L):
-    got = fb.fbpq_debug_visit(h, Q, L, cells_cap=ix.T * ix.T + 1, pos_cap=max(1, min(L, ix.N)))
+    cap = min(ix.T * ix.T + 1, 1 << 16)
+    got = fb.fbpq_debug_visit(h, Q, L, cells_cap=cap, pos_cap=max(1, min(L, ix.N)))
     for r in range(Q.shape[0]):
         cells, pos = oracle.visit(ix, Q[r], L)
         gc, gp = got[r]
@@ -304,3 +305,116 @@ def test_errors(fb, gmm_small):
             fb.fbpq_search(h, Q[:2], L, k)
         assert e.value.code == fb.FBPQ_E_INVALID
     fb.fbpq_free_index(h)
+
+
+# ---- wavefront prefix select (T >= 256, P <= 256) -------------------------------
+
+@pytest.fixture(scope="module")
+def gmm_wide():
+    """GMM indexes with T = 256, 1000 and 4096 centroids per half (built on the GPU)."""
+    import torch
+    dev = torch.device("cuda:0")
+    means = synth.gmm_means(0)
+    base = synth.sample_points(200000, means, 1, dev)
+    out = {}
+    for T in (256, 1000, 4096):
+        out[T] = synth.build_index(base, T, 8, train_n=20000, keep_base=False)
+    Q = synth.make_queries(40, means, 2)
+    return out, Q
+
+
+@pytest.mark.parametrize("T,P", [(256, 128), (256, 255), (1000, 1), (1000, 100), (4096, 128), (4096, 256)])
+def test_rank_prefix_wave_bitexact(fb, gmm_wide, T, P):
+    idxs, Q = gmm_wide
+    ix = idxs[T]
+    log(f"rank prefix (wavefront select): T={T} P={P}")
+    h = _open(fb, ix, stats=1)
+    keys, idx = fb.fbpq_debug_rank(h, Q, P)
+    st = fb.fbpq_stats_read(h)
+    fb.fbpq_free_index(h)
+    log(f"  counters {st}")
+    assert st["prefix_wave"] + st["prefix_wg"] == 2 * Q.shape[0]
+    assert st["prefix_wave"] > 0
+    for r in range(Q.shape[0]):
+        d1, d2, u, v = oracle.rank_lists(ix, Q[r])
+        assert np.array_equal(idx[r, 0], u[:P]) and np.array_equal(idx[r, 1], v[:P]), r
+        assert np.array_equal(keys[r, 0], d1[u[:P]]) and np.array_equal(keys[r, 1], d2[v[:P]]), r
+
+
+def test_search_T1000_visit_and_topk(fb, gmm_wide):
+    idxs, Q = gmm_wide
+    ix = idxs[1000]
+    L, k = 3000, 20
+    log("search: N=2e5 T=1000 M=8 L=3000 k=20")
+    h = _open(fb, ix, stats=1)
+    _check_visit(fb, h, ix, Q[:12], L)
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    log(f"  counters {fb.fbpq_stats_read(h)}")
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
+# ---- the selection fused into the cell scan and its fallbacks --------------------
+
+def _dense_index(const_codes: bool):
+    # 16 cells of 1500 points each: every query takes the cell scan
+    ix = synth.tiny_index(4, np.full(16, 1500), M=2, D=4, seed=21)
+    if const_codes:
+        ix.codes[:] = 7  # every point of a cell at the same distance: ties far beyond the window
+    return ix
+
+
+@pytest.mark.parametrize("const_codes,k", [(False, 10), (False, 100), (False, 256), (False, 300),
+                                           (False, 1024), (True, 10), (True, 100)])
+def test_fused_topk_and_fallbacks(fb, const_codes, k):
+    ix = _dense_index(const_codes)
+    rng = np.random.default_rng(8)
+    Q = rng.integers(0, 6, (24, 4)).astype(np.float32)
+    L = 8000
+    log(f"fused top-k: dense cells, const_codes={const_codes} k={k}")
+    h = _open(fb, ix, stats=1)
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    st = fb.fbpq_stats_read(h)
+    fb.fbpq_free_index(h)
+    log(f"  counters {st}")
+    assert st["cell_scan"] == Q.shape[0] and st["two_pass"] == 0
+    if k > 256:
+        assert st["fused_topk"] == 0  # k above the sample count
+    elif const_codes:
+        assert st["fused_topk"] < Q.shape[0]  # a whole cell ties at the bound: window overflow
+    elif k <= 100:
+        assert st["fused_topk"] > 0  # (k near the sample count overflows the window: fallback)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
+# ---- the full batched workload, in the launch configuration the benchmark times ---
+
+def test_full_batched_10M_sampled(fb):
+    import torch
+    dev = torch.device("cuda:0")
+    means = synth.gmm_means(0)
+    base = synth.sample_points(10_000_000, means, 1, dev)
+    ix = synth.build_index(base, 4096, 16, keep_base=False)
+    del base
+    nq, L, k = 10000, 10000, 100
+    Q = synth.make_queries(nq, means, 2, dev)
+    log(f"full batch: N={ix.N} T=4096 M=16 nq={nq} L={L} k={k}")
+    h = _open(fb, ix, stats=1)
+    d_q = torch.from_numpy(Q).to(dev).contiguous()
+    d_ids = torch.empty(nq, k, dtype=torch.int64, device=dev)
+    d_d = torch.empty(nq, k, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    fb.fbpq_search_device(h, d_q, np.full(nq, L, np.int64), np.full(nq, k, np.int32), k, d_ids, d_d, stream)
+    torch.cuda.synchronize()
+    st = fb.fbpq_stats_read(h)
+    log(f"  counters {st}")
+    g_ids, g_d = d_ids.cpu().numpy(), d_d.cpu().numpy()
+    sample = np.random.default_rng(17).choice(nq, 48, replace=False)
+    _check_visit(fb, h, ix, Q[sample[:6]], L)
+    fb.fbpq_free_index(h)
+    assert st["prefix_wave"] + st["prefix_wg"] == 2 * nq
+    assert st["cell_scan"] + st["two_pass"] == nq
+    o_ids, o_d, _, _ = oracle.search(ix, Q[sample], L, k)
+    assert_topk(ix, Q[sample], k, g_ids[sample], g_d[sample], o_ids, o_d)
