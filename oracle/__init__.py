@@ -137,7 +137,7 @@ def search(ix, Q: np.ndarray, L, k, kmax: int | None = None, nthreads: int | Non
     ncand = np.empty(nq, np.int64)
     ncells = np.empty(nq, np.int64)
     if nthreads is None:
-        nthreads = os.cpu_count() or 1
+        nthreads = min(16, os.cpu_count() or 1)
     nthreads = max(1, min(int(nthreads), max(nq, 1)))
     rc = _load().orc_search(*args, _p(Q), nq, _p(L), _p(k), kmax, _p(ids), _p(d), _p(ncand),
                             _p(ncells), nthreads)

@@ -391,9 +391,13 @@ int orc_search(int D, int T, int M, int Kc, int64_t N, const float *C1, const fl
         orc_worker(&jobs[0]);
         return jobs[0].err;
     }
-    for (int t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, orc_worker, &jobs[t]);
+    /* a job whose thread cannot be created runs in the calling thread */
+    int started[256];
+    for (int t = 0; t < nthreads; ++t) started[t] = pthread_create(&th[t], NULL, orc_worker, &jobs[t]) == 0;
+    for (int t = 0; t < nthreads; ++t)
+        if (!started[t]) orc_worker(&jobs[t]);
     for (int t = 0; t < nthreads; ++t) {
-        pthread_join(th[t], NULL);
+        if (started[t]) pthread_join(th[t], NULL);
         if (jobs[t].err) err = jobs[t].err;
     }
     return err;
