@@ -55,22 +55,64 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
     for (int j = 0; j < 8; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
     float qnorm = 0.f;  // thread tid < 64 accumulates ||q_tid||^2 over the slabs
 
+    const bool vec = (h & 3) == 0;
     for (int t0 = 0; t0 < h; t0 += 64) {
         const int tn = min(64, h - t0);
         __syncthreads();
-        for (int e = tid; e < kAQ * 64; e += 256) {
-            const int qq = e >> 6, t = e & 63;
-            const int64_t qi = q0 + qq;
-            qs[qq * kAS + t] = (qi < nq && t < tn) ? Q[qi * D + half * h + t0 + t] : 0.f;
-        }
-        for (int e = tid; e < kAC * 64; e += 256) {
-            const int cc = e >> 6, t = e & 63;
-            const int ci = c0 + cc;
-            cs[cc * kAS + t] = (ci < T && t < tn) ? C[(int64_t)ci * h + t0 + t] : 0.f;
+        if (vec) {
+            // 16-byte loads, all issued before the LDS stores: 4 of the query
+            // slab and 8 of the centroid slab per thread
+            float4 qv[4], cv[8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = tid + 256 * i, row = e >> 4, t = 4 * (e & 15);
+                const int64_t qi = q0 + row;
+                qv[i] = (qi < nq && t < tn)
+                            ? *reinterpret_cast<const float4 *>(Q + qi * D + half * h + t0 + t)
+                            : float4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = tid + 256 * i, row = e >> 4, t = 4 * (e & 15);
+                const int ci = c0 + row;
+                cv[i] = (ci < T && t < tn) ? *reinterpret_cast<const float4 *>(C + (int64_t)ci * h + t0 + t)
+                                           : float4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = tid + 256 * i;
+                *reinterpret_cast<float4 *>(&qs[(e >> 4) * kAS + 4 * (e & 15)]) = qv[i];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = tid + 256 * i;
+                *reinterpret_cast<float4 *>(&cs[(e >> 4) * kAS + 4 * (e & 15)]) = cv[i];
+            }
+        } else {
+            for (int e = tid; e < kAQ * 64; e += 256) {
+                const int qq = e >> 6, t = e & 63;
+                const int64_t qi = q0 + qq;
+                qs[qq * kAS + t] = (qi < nq && t < tn) ? Q[qi * D + half * h + t0 + t] : 0.f;
+            }
+            for (int e = tid; e < kAC * 64; e += 256) {
+                const int cc = e >> 6, t = e & 63;
+                const int ci = c0 + cc;
+                cs[cc * kAS + t] = (ci < T && t < tn) ? C[(int64_t)ci * h + t0 + t] : 0.f;
+            }
         }
         __syncthreads();
-        if (tid < kAQ)
-            for (int t = 0; t < tn; ++t) qnorm = fmaf(qs[tid * kAS + t], qs[tid * kAS + t], qnorm);
+        if (tid < kAQ) {
+            // any summation order suits the error bound: four partial sums
+            float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+            for (int t = 0; t < 64; t += 4) {
+                const float4 x = *reinterpret_cast<const float4 *>(&qs[tid * kAS + t]);  // zero beyond tn
+                p0 = fmaf(x.x, x.x, p0);
+                p1 = fmaf(x.y, x.y, p1);
+                p2 = fmaf(x.z, x.z, p2);
+                p3 = fmaf(x.w, x.w, p3);
+            }
+            qnorm += (p0 + p1) + (p2 + p3);
+        }
         for (int s = 0; s < 16; ++s) {
             const float a = qs[(wv * 16 + li) * kAS + 4 * s + lk];
 #pragma unroll
@@ -113,19 +155,35 @@ constexpr int kBins = 1024;
 __device__ __forceinline__ uint64_t dkey(double x) { return (uint64_t)__double_as_longlong(x); }
 
 // Exact traversal key of centroid c: FP64, increasing t, one fma per coordinate.
-// When h is a multiple of 4 the centroid row is fetched 32 floats at a time
-// (eight 16-byte loads in flight); the arithmetic order is unchanged.
+// When h is a multiple of 4 the centroid row is fetched 64 floats at a time
+// (sixteen 16-byte loads in flight); the arithmetic order is unchanged.
 __device__ __forceinline__ double exact_key(const float *qh, const float *__restrict__ Crow, int h)
 {
     double acc = 0.0;
     int t = 0;
     if ((h & 3) == 0) {
-        for (; t + 32 <= h; t += 32) {
-            float4 c[8];
+        for (; t + 64 <= h; t += 64) {
+            float4 c[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) c[u] = *reinterpret_cast<const float4 *>(Crow + t + 4 * u);
+            for (int u = 0; u < 16; ++u) c[u] = *reinterpret_cast<const float4 *>(Crow + t + 4 * u);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 16; ++u) {
+                const float4 qv = *reinterpret_cast<const float4 *>(qh + t + 4 * u);
+                const float qa[4] = {qv.x, qv.y, qv.z, qv.w};
+                const float ca[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double e = (double)qa[v] - (double)ca[v];
+                    acc = __builtin_fma(e, e, acc);
+                }
+            }
+        }
+        for (; t + 16 <= h; t += 16) {
+            float4 c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c[u] = *reinterpret_cast<const float4 *>(Crow + t + 4 * u);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
                 const float4 qv = *reinterpret_cast<const float4 *>(qh + t + 4 * u);
                 const float qa[4] = {qv.x, qv.y, qv.z, qv.w};
                 const float ca[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
@@ -555,20 +613,42 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
     const float *kg = kapprox + (qs * 2 + half) * (int64_t)T;
     for (int t = lane; t < h; t += 64) qh[t] = Q[qs * D + half * h + t];
 
-    // samples: SPL per lane, group g = 64 s + lane
+    // Keys are read 16 bytes per lane, kF4 loads per lane per chunk of
+    // kChunk centroids; element c = cb + 4 (lane + 64 m) + j of chunk cb falls
+    // in sample s = j + 4 (m mod SPL/4) of this lane (64 SPL disjoint groups).
+    // A single chunk (T <= kChunk) stays in registers for the survivor pass.
+    constexpr int kF4 = 16, kChunk = 64 * 4 * kF4;
+    const bool v4 = (T & 3) == 0;
+    float x[4 * kF4];
+    auto load_chunk = [&](int cb) __attribute__((always_inline)) {
+#pragma unroll
+        for (int m = 0; m < kF4; ++m) {
+            const int c = cb + 4 * (lane + 64 * m);
+            if (v4 && c + 3 < T) {
+                const float4 f = *reinterpret_cast<const float4 *>(kg + c);
+                x[4 * m] = f.x;
+                x[4 * m + 1] = f.y;
+                x[4 * m + 2] = f.z;
+                x[4 * m + 3] = f.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) x[4 * m + j] = c + j < T ? kg[c + j] : __builtin_huge_valf();
+            }
+        }
+    };
     float smp[SPL];
 #pragma unroll
     for (int q = 0; q < SPL; ++q) smp[q] = __builtin_huge_valf();
-#pragma unroll 2
-    for (int c0 = 0; c0 < T; c0 += 64 * SPL) {
+    const int nch = (T + kChunk - 1) / kChunk;
+    for (int ch = 0; ch < nch; ++ch) {
+        load_chunk(ch * kChunk);
 #pragma unroll
-        for (int q = 0; q < SPL; ++q) {
-            const int c = c0 + 64 * q + lane;
-            if (c < T) {
-                const float x = kg[c];
-                smp[q] = x < smp[q] ? x : smp[q];
+        for (int m = 0; m < kF4; ++m)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int q = j + 4 * (m % (SPL / 4));
+                smp[q] = x[4 * m + j] < smp[q] ? x[4 * m + j] : smp[q];
             }
-        }
     }
     uint32_t u[SPL];
 #pragma unroll
@@ -598,19 +678,24 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
     const float err = (float)(1.25 * (h + 8) * 0x1.0p-23 * rn * rn) + 1e-30f;
     const float thr = unokey(pre) + 2.f * err;
 
-    // survivors, compacted in centroid order
+    // survivors (ka <= thr), compacted with ballots
     const uint64_t below = (1ull << lane) - 1ull;
     int n = 0;
-#pragma unroll 8
-    for (int c0 = 0; c0 < T; c0 += 64) {
-        const int c = c0 + lane;
-        const bool m = c < T && kg[c] <= thr;
-        const uint64_t bm = __ballot(m);
-        if (m) {
-            const int w = n + __popcll(bm & below);
-            if (w < kWaveS) sidx[w] = c;
-        }
-        n += __popcll(bm);
+    for (int ch = 0; ch < nch; ++ch) {
+        if (nch > 1) load_chunk(ch * kChunk);
+#pragma unroll
+        for (int m = 0; m < kF4; ++m)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = ch * kChunk + 4 * (lane + 64 * m) + j;
+                const bool sv = c < T && x[4 * m + j] <= thr;
+                const uint64_t bm = __ballot(sv);
+                if (sv) {
+                    const int w = n + __popcll(bm & below);
+                    if (w < kWaveS) sidx[w] = c;
+                }
+                n += __popcll(bm);
+            }
     }
     if (n > kWaveS) {
         if (lane == 0) pstat[pair] = 1;
