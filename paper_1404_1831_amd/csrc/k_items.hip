@@ -115,7 +115,6 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
     __shared__ int64_t m_p0[kMetaLds];
     __shared__ int32_t m_n[kMetaLds], m_t0[kMetaLds], m_rs[kMetaLds], m_i[kMetaLds], m_j[kMetaLds];
     __shared__ float m_cst[kMetaLds];
-    __shared__ uint32_t s_smp[kNT];
     __shared__ uint64_t s_win[kFWin];
     __shared__ uint32_t s_tau;
     __shared__ int s_nwin;
@@ -235,41 +234,45 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
         }
     }
 
-    // Fused selection of the kq smallest (distance, id), with the bound of
-    // k_select_dist: the kq-th smallest per-thread minimum. The distances are
-    // read back while they are still in the cache. Queries with kq above the
-    // thread count, too few samples or too many candidates at or below the
+    // Fused selection of the kq smallest (distance, id). Per-thread minima are
+    // samples, each the distance of a distinct candidate, so any value with kq
+    // samples at or below it bounds the kq-th smallest distance. The distances
+    // are read back while they are still in the cache. Queries with kq above
+    // the thread count, too few samples or too many candidates at or below the
     // bound are left to k_select_dist.
     const int64_t qs = a.qlist ? a.qlist[slot] : slot;
     const int kq = a.k[qs];
     const int64_t ncand = h.ncand;
     if (kq > kNT) return;
-    s_smp[tid] = scored ? fkey(smin) : 0xffffffffu;
+    // Each wavefront finds the ceil(kq/4)-th smallest of its own 64 samples;
+    // the largest of the four has at least kq samples at or below it.
+    __shared__ uint32_t s_wtau[kNT / 64];
     if (tid == 0) s_nwin = 0;
-    __syncthreads();  // samples, and every thread's distance stores
-    if (tid < 64) {
-        uint32_t u[kNT / 64];
-#pragma unroll
-        for (int q = 0; q < kNT / 64; ++q) u[q] = s_smp[lane + 64 * q];
+    {
+        const uint32_t u = scored ? fkey(smin) : 0xffffffffu;
+        const int kw = (kq + kNT / 64 - 1) / (kNT / 64);
         uint32_t pre = 0;
-        int need = kq;
+        int need = kw;
         for (int b = 31; b >= 0; --b) {
             const uint32_t hm = b == 31 ? 0u : (0xffffffffu << (b + 1));
-            int cnt = 0;
-#pragma unroll
-            for (int q = 0; q < kNT / 64; ++q)
-                cnt += __popcll(__ballot(((u[q] & hm) == pre) && !((u[q] >> b) & 1u)));
+            const int cnt = __popcll(__ballot(((u & hm) == pre) && !((u >> b) & 1u)));
             if (cnt < need) {
                 pre |= 1u << b;
                 need -= cnt;
             }
         }
-        if (tid == 0) s_tau = ncand <= kq ? 0xffffffffu : pre;
+        if (lane == 0) s_wtau[tid >> 6] = pre;
+    }
+    __syncthreads();  // the wavefront bounds, and every thread's distance stores
+    if (tid == 0) {
+        uint32_t m = 0;
+        for (int w = 0; w < kNT / 64; ++w) m = s_wtau[w] > m ? s_wtau[w] : m;
+        s_tau = ncand <= kq ? 0xffffffffu : m;
     }
     __syncthreads();
     const uint32_t tau = s_tau;
     if (tau == 0xffffffffu && ncand > kq) return;  // fewer than kq samples
-    constexpr int kFB = 16;  // distances per thread loaded before they are tested
+    constexpr int kFB = 24;  // distances per thread loaded before they are tested
     for (int64_t b0 = 0; b0 < ncand; b0 += kNT * kFB) {
         float dv[kFB];
 #pragma unroll
