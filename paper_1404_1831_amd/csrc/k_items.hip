@@ -76,24 +76,63 @@ int items_wcap(int k_max)
     return KP * 2 < 512 ? 512 : KP * 2;
 }
 
-// LQ[k][r] = ||R_k(r)||^2 - 2 <q|k, R_k(r)>, one workgroup per item-scanned query.
+// LQ[k][r] = ||R_k(r)||^2 - 2 <q|k, R_k(r)> for kLqQ queries per workgroup:
+// each thread reads one codeword R_k(r) and scores it against every query of
+// the group, so the codebooks are read once per kLqQ queries.
+constexpr int kLqQ = 16;
+
+// DS > 0: the subspace width, codeword held in registers; DS == 0: any width.
+template <int DS>
 __global__ __launch_bounds__(256) void k_lq(ItemArgs a)
 {
-    const int slot = blockIdx.x;
-    const TravHdr h = a.hdr[slot];
-    if (h.status != kStOk || h.n_items == 0) return;
-    const int64_t qs = a.qlist ? a.qlist[slot] : slot;
-    const int D = a.ix.D, M = a.ix.M, ds = D / M;
-    __shared__ float qv[1024];
-    for (int t = threadIdx.x; t < D; t += 256) qv[t] = a.q[qs * D + t];
+    extern __shared__ __align__(16) float qv[];  // [kLqQ][D]
+    __shared__ int64_t slots[kLqQ];
+    __shared__ int nsel;
+    const int D = a.ix.D, M = a.ix.M, ds = DS > 0 ? DS : D / M;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int n = 0;
+        for (int i = 0; i < kLqQ; ++i) {
+            const int64_t slot = (int64_t)blockIdx.x * kLqQ + i;
+            if (slot >= a.nslots) break;
+            const TravHdr h = a.hdr[slot];
+            if (h.status == kStOk && h.n_items != 0) slots[n++] = slot;
+        }
+        nsel = n;
+    }
     __syncthreads();
-    float *out = a.lq + (int64_t)slot * M * kKc;
-    for (int e = threadIdx.x; e < M * kKc; e += 256) {
+    const int n = nsel;
+    if (n == 0) return;
+    for (int e = tid; e < n * D; e += 256) {
+        const int i = e / D, t = e - i * D;
+        const int64_t slot = slots[i];
+        const int64_t qs = a.qlist ? a.qlist[slot] : slot;
+        qv[i * D + t] = a.q[qs * D + t];
+    }
+    __syncthreads();
+    for (int e = tid; e < M * kKc; e += 256) {
         const int k = e / kKc;
         const float *rw = a.ix.R + (int64_t)e * ds;
-        float acc = 0.f;
-        for (int t = 0; t < ds; ++t) acc = fmaf(qv[k * ds + t], rw[t], acc);
-        out[e] = a.ix.nR[e] - 2.f * acc;
+        const float nr = a.ix.nR[e];
+        if constexpr (DS > 0) {
+            float r[DS];
+#pragma unroll
+            for (int t = 0; t < DS; ++t) r[t] = rw[t];
+            for (int i = 0; i < n; ++i) {
+                const float *qk = qv + i * D + k * DS;
+                float acc = 0.f;
+#pragma unroll
+                for (int t = 0; t < DS; ++t) acc = fmaf(qk[t], r[t], acc);
+                a.lq[slots[i] * M * kKc + e] = nr - 2.f * acc;
+            }
+        } else {
+            for (int i = 0; i < n; ++i) {
+                const float *qk = qv + i * D + k * ds;
+                float acc = 0.f;
+                for (int t = 0; t < ds; ++t) acc = fmaf(qk[t], rw[t], acc);
+                a.lq[slots[i] * M * kKc + e] = nr - 2.f * acc;
+            }
+        }
     }
 }
 
@@ -556,7 +595,15 @@ hipError_t launch_items_prep(const ItemArgs &a, hipStream_t st)
 {
     if (a.nslots == 0) return hipSuccess;
     if (a.ix.D > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_lq, dim3((unsigned)a.nslots), dim3(256), 0, st, a);
+    const dim3 g((unsigned)((a.nslots + kLqQ - 1) / kLqQ)), b(256);
+    const size_t lds = (size_t)kLqQ * a.ix.D * sizeof(float);
+    switch (a.ix.D / a.ix.M) {
+    case 2: hipLaunchKernelGGL(k_lq<2>, g, b, lds, st, a); break;
+    case 4: hipLaunchKernelGGL(k_lq<4>, g, b, lds, st, a); break;
+    case 8: hipLaunchKernelGGL(k_lq<8>, g, b, lds, st, a); break;
+    case 16: hipLaunchKernelGGL(k_lq<16>, g, b, lds, st, a); break;
+    default: hipLaunchKernelGGL(k_lq<0>, g, b, lds, st, a); break;
+    }
     return hipGetLastError();
 }
 

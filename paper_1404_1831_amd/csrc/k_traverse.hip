@@ -8,11 +8,11 @@
 // So the frontier is one candidate cell per row: (a, w[a]), available when
 // a == 0 or w[a-1] > w[a]. Each lane owns rows a = lane + 64*r in registers
 // (width, width of the row above, key of its next cell); a pop is a wave-wide
-// argmin over (key, a) and touches at most two rows. Pops are taken 64 at a
-// time; the 64 cells' point counts are then read from the offsets array in one
-// vector load and prefix-summed, and the batch is cut at the cell that
-// completes min(L, N) points (that cell is truncated in storage order, pops
-// after it are undone).
+// argmin over (key, a) and touches at most two rows. Pops are taken in
+// batches (16, then 64 at a time); a batch's point counts are then read from
+// the offsets array in one vector load and prefix-summed, and the batch is cut
+// at the cell that completes min(L, N) points (that cell is truncated in
+// storage order, pops after it are undone).
 //
 // Only the first P ranks of each half list are known. A cell outside the
 // P x P window has key >= min(k1[P-1] + k2[0], k1[0] + k2[P-1]); the query is
@@ -63,12 +63,13 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs args)
     int64_t cut_take = 0;
     int jc = -1, nb_last = 0, pa = -1, pb = -1;
     bool done = Leff <= 0;
+    int bsz = 16;  // pops per batch: 16 first (most queries end there), then 64
     while (!done) {
         pa = -1;
         pb = -1;
         int nb = 0;
         bool exhausted = false;
-        for (int j = 0; j < 64; ++j) {
+        for (int j = 0; j < bsz; ++j) {
             double bk = INF;
             int ba = 0x7fffffff;
 #pragma unroll
@@ -162,6 +163,7 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs args)
         const int64_t last_cnt = __shfl(cnt, last);
         ncells += nkeep;
         nb_last = nb;
+        bsz = 64;
         if (jc >= 0) {
             cut_take = Leff - last_excl;
             total = Leff;
