@@ -88,6 +88,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-queries", type=int, default=200,
+                    help="queries searched one launch sequence at a time, for the per-query comparison")
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="untimed steps with every kernel timed, for the per-kernel breakdown")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -171,6 +173,32 @@ def main() -> int:
     fbpq.fbpq_set_option(h, "profile", 0)
     dom_ms = dom_ms / dom_n if dom_n else None
 
+    # the same batch with the first round replayed from a captured HIP graph
+    fbpq.fbpq_set_option(h, "graph", 1)
+    for _ in range(2):  # the first call captures
+        fbpq.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, stream)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(args.steps):
+        fbpq.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, stream)
+        torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - a) * 1e3 / args.steps
+    fbpq.fbpq_set_option(h, "graph", 0)
+    log(f"graph replays: {graph_ms:.3f} ms per batch")
+
+    # plain per-query launches at equal L and k, on the first queries of the batch
+    npl = min(nq, args.plain_queries)
+    Ls1, ks1 = np.full(1, L, np.int64), np.full(1, k, np.int32)
+    for i in range(min(npl, 5)):
+        fbpq.fbpq_search_device(h, d_q[i:i + 1], Ls1, ks1, k, d_ids[i:i + 1], d_d[i:i + 1], stream)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for i in range(npl):
+        fbpq.fbpq_search_device(h, d_q[i:i + 1], Ls1, ks1, k, d_ids[i:i + 1], d_d[i:i + 1], stream)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - a
+    log(f"plain per-query launches: {npl} queries in {plain_s:.3f}s")
+
     ms_per_step = total_s * 1e3 / args.steps
     qps = nq / (ms_per_step / 1e3)
     model = models[dom]
@@ -237,6 +265,9 @@ def main() -> int:
                                f"nq={nq} per batch, L={L}, k={k}",
                    "N": ix.N, "T": ix.T, "M": ix.M, "nq": nq, "L": L, "k": k},
         "kernels": prof,
+        "graph_replay": {"ms_per_step": graph_ms, "value": nq / (graph_ms / 1e3)},
+        "plain_per_query": {"queries": npl, "value": npl / plain_s, "unit": "queries/s",
+                            "ms_per_query": plain_s * 1e3 / npl},
         "scan_GBps": scan_GBps,
         "roofline": roof,
         "cpu_baseline": cpu,

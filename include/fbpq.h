@@ -168,7 +168,11 @@ int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int
  * two-pass scan), "profile" (0/1: time kernel launches with HIP events,
  * read with fbpq_profile_read), "profile_mask" (bit s set: stage s is timed
  * while profiling is on; default all), "stats" (0/1: path counters, read
- * with fbpq_stats_read). Errors: INVALID, DEVICE. */
+ * with fbpq_stats_read), "graph" (0/1: the first traversal round of a search
+ * is captured once into a HIP graph and replayed on later searches with the
+ * same queries buffer, result buffers, nq, k_max, min(L, N) and options;
+ * retry rounds and profiled or debug searches run eagerly). Errors: INVALID,
+ * DEVICE. */
 int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 
 /* Kernel stages timed by the library's profiler (one kernel each, except
@@ -184,6 +188,18 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 #define FBPQ_STAGE_SCAN2 8     /* two-pass scan (queries whose cells hold few points) */
 #define FBPQ_NUM_STAGES 9
 
+/* Autotuner. Times fbpq_search_device on the caller's batch (device queries
+ * d_q [nq][D], per-query host L and k, device results as in
+ * fbpq_search_device, on hip_stream) under each candidate setting of the
+ * options "prefix" (64, 128, 256, 512, capped at T) and "items" (1, 0): one
+ * warm search, then `reps` searches timed with HIP events, median kept. The
+ * fastest setting stays set on the handle; chosen[0] = prefix, chosen[1] =
+ * items, chosen[2] = its median microseconds per search. Synchronizes the
+ * stream. Profiling and graph replay are off while it runs. Errors: INVALID,
+ * STATE, DEVICE, CAPACITY, OOM (then the handle keeps its previous options). */
+int fbpq_autotune(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
+                  int32_t k_max, int64_t *d_ids, float *d_dists, void *hip_stream, int32_t reps, int64_t *chosen);
+
 /* Path counters, accumulated on the device while option "stats" is 1 (setting
  * it to 1 clears them). fbpq_stats_read copies min(n, FBPQ_NUM_STATS) of them
  * to out[] and, if reset != 0, clears them. The counters say which kernels
@@ -195,7 +211,8 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 #define FBPQ_STAT_PREFIX_WAVE 3 /* (query, half) prefixes finished by the wavefront select */
 #define FBPQ_STAT_PREFIX_WG 4   /* (query, half) prefixes finished by the workgroup select */
 #define FBPQ_STAT_RETRIED 5     /* queries traversed again with a longer prefix or more cells */
-#define FBPQ_NUM_STATS 6
+#define FBPQ_STAT_GRAPH_REPLAYS 6 /* searches whose first round was a replayed graph */
+#define FBPQ_NUM_STATS 7
 int fbpq_stats_read(fbpq_index *ix, int64_t *out, int32_t n, int32_t reset);
 
 /* Device time per kernel stage, measured with HIP events recorded on the

@@ -120,6 +120,10 @@ def visit(ix, q: np.ndarray, L: int, cells_cap: int = 1 << 20):
     return cells[:ncell].copy(), pos[:n].copy()
 
 
+# threads of `search` when the caller names none (None: up to 16 host threads)
+DEFAULT_THREADS = None
+
+
 def search(ix, Q: np.ndarray, L, k, kmax: int | None = None, nthreads: int | None = None):
     """Top-k (ids int64, dists float64, ncand, ncells) for every query.
 
@@ -137,7 +141,7 @@ def search(ix, Q: np.ndarray, L, k, kmax: int | None = None, nthreads: int | Non
     ncand = np.empty(nq, np.int64)
     ncells = np.empty(nq, np.int64)
     if nthreads is None:
-        nthreads = min(16, os.cpu_count() or 1)
+        nthreads = DEFAULT_THREADS or min(16, os.cpu_count() or 1)
     nthreads = max(1, min(int(nthreads), max(nq, 1)))
     rc = _load().orc_search(*args, _p(Q), nq, _p(L), _p(k), kmax, _p(ids), _p(d), _p(ncand),
                             _p(ncells), nthreads)

@@ -76,6 +76,26 @@ struct fbpq_index {
     // path counters (option "stats")
     unsigned long long *stats_dev = nullptr;
     int64_t stat_retried = 0;
+    // captured first round (option "graph"): replayed while its key matches
+    bool graph = false;
+    int64_t ws_gen = 0;  // bumped whenever a workspace buffer moves
+    hipGraphExec_t gexec = nullptr;
+    struct GraphKey {
+        const float *d_q;
+        int64_t nq, lcap, max_cells, ws_gen;
+        int64_t *d_ids;
+        float *d_d;
+        int32_t k_max, P, chunk;
+        bool items;
+        unsigned long long *stats;
+        bool operator==(const GraphKey &o) const
+        {
+            return d_q == o.d_q && nq == o.nq && lcap == o.lcap && max_cells == o.max_cells &&
+                   ws_gen == o.ws_gen && d_ids == o.d_ids && d_d == o.d_d && k_max == o.k_max && P == o.P &&
+                   chunk == o.chunk && items == o.items && stats == o.stats;
+        }
+    } gkey{};
+    int64_t graph_replays = 0;
 };
 
 namespace {
@@ -108,6 +128,7 @@ int ws_get(fbpq_index *ix, int slot, size_t bytes, void **out)
             b.cap = 0;
         }
         const size_t nb = std::max(bytes, b.cap + b.cap / 2);
+        if (slot != W_QLIST) ++ix->ws_gen;  // the query list is read only by retry rounds, never captured
         hipError_t e = hipMalloc(&b.p, nb);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -239,6 +260,7 @@ void free_all(fbpq_index *ix)
         (void)hipEventDestroy(e.b);
     }
     for (auto e : ix->ev_pool) (void)hipEventDestroy(e);
+    if (ix->gexec) (void)hipGraphExecDestroy(ix->gexec);
     if (ix->stream) (void)hipStreamDestroy(ix->stream);
     delete ix;
 }
@@ -465,10 +487,14 @@ struct DebugOut {
         if (r_) return r_;       \
     } while (0)
 
+// One traversal round over nslots queries: launches every kernel of the
+// round on st. With launch_only (graph capture) it stops there; otherwise it
+// copies the debug outputs, waits for the stream and returns the number of
+// queries that need another round.
 int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, const int32_t *d_qlist,
               int32_t P, int64_t max_cells, int64_t lcap, const int64_t *d_L, const int32_t *d_k, int32_t k_max,
               int64_t *d_ids, float *d_d, hipStream_t st, const float *keys, int32_t *d_fail,
-              const DebugOut *dbg, int64_t *fail_host_count)
+              const DebugOut *dbg, int64_t *fail_host_count, bool launch_only = false)
 {
     DevIndex &dv = ix->dv;
     void *lkey, *lidx, *hdr, *w, *rowne, *rowcand, *colne, *coltot, *necs, *necnt, *nebeg, *necst, *cmcell,
@@ -500,7 +526,7 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         TRY(ws_get(ix, W_DBGPOS, sizeof(int64_t) * nslots * dbg->dcap, &dpos));
         TRY(ws_get(ix, W_DBGD, sizeof(float) * nslots * dbg->dcap, &ddd));
     }
-    HCK(ix, hipMemsetAsync(d_fail, 0, sizeof(int32_t), st));
+    HCK(ix, launch_fill_i32(d_fail, 0, 1, st));
     void *pstat;
     TRY(ws_get(ix, W_PSTAT, sizeof(int32_t) * nslots * 2, &pstat));
     const bool pwave = prefix_wave_ok(dv, P);
@@ -617,6 +643,7 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         sa.stats = ix->stats_dev;
         HCK(ix, timed(ix, FBPQ_STAGE_SCAN2, st, [&] { return launch_scan(sa, nslots, st); }));
     }
+    if (launch_only) return FBPQ_OK;
     // how many slots need another round
     // bytes [0, 64) of the pinned buffer hold the failure count; the L/k staging starts at 64
     void *pin;
@@ -712,21 +739,62 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     HCK(ix, hipMemcpyAsync(dL, stage, sizeof(int64_t) * nq, hipMemcpyHostToDevice, st));
     HCK(ix, hipMemcpyAsync(dk, stage + sizeof(int64_t) * nq, sizeof(int32_t) * nq,
                            hipMemcpyHostToDevice, st));
-    HCK(ix, timed(ix, FBPQ_STAGE_HALF_KEYS, st, [&] { return launch_half_approx(ix->dv, d_q, nq, (float *)keys, st); }));
-
     const int T = ix->dv.T;
     int32_t P = std::min<int32_t>(std::max<int32_t>(ix->prefix, 1), T);
     P = std::min<int32_t>(P, kMaxPrefix);
     int64_t max_cells = std::max<int64_t>(ix->max_cells, 64);
+    const int64_t lcap = std::max<int64_t>(1, std::min(Lmax, ix->dv.N));
     int64_t nslots = nq;
     const int32_t *qlist = nullptr;
     std::vector<int32_t> failed;
-    for (int round = 0;; ++round) {
-        int64_t nfail = 0;
-        TRY(run_round(ix, d_q, nq, nslots, qlist, P, max_cells, std::max<int64_t>(1, std::min(Lmax, ix->dv.N)),
-                      (const int64_t *)dL, (const int32_t *)dk,
+    int64_t nfail = 0;
+
+    // first round: replay the captured graph when the launch sequence is the
+    // same, else run it eagerly (and capture it for the next call)
+    const bool use_graph = ix->graph && !dbg && !ix->profile;
+    fbpq_index::GraphKey key{d_q, nq, lcap, max_cells, ix->ws_gen, d_ids, d_d, k_max, P, ix->chunk, ix->items,
+                             ix->stats_dev};
+    if (use_graph && ix->gexec && ix->gkey == key) {
+        HCK(ix, hipGraphLaunch(ix->gexec, st));
+        ++ix->graph_replays;
+        int32_t *hcount = (int32_t *)pin;  // bytes [0, 64) of the pinned buffer
+        HCK(ix, hipMemcpyAsync(hcount, dfail, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HCK(ix, hipStreamSynchronize(st));
+        nfail = hcount[0];
+    } else {
+        HCK(ix, timed(ix, FBPQ_STAGE_HALF_KEYS, st, [&] { return launch_half_approx(ix->dv, d_q, nq, (float *)keys, st); }));
+        TRY(run_round(ix, d_q, nq, nslots, qlist, P, max_cells, lcap, (const int64_t *)dL, (const int32_t *)dk,
                       k_max, d_ids, d_d, st, (const float *)keys, (int32_t *)dfail, dbg, &nfail));
-        if (nfail == 0) break;
+        if (use_graph) {
+            // every workspace buffer of this shape exists now: capture the round
+            hipStream_t cs = ix->stream;
+            HCK(ix, hipStreamSynchronize(cs));
+            const int64_t gen0 = ix->ws_gen;
+            HCK(ix, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            hipError_t e = launch_half_approx(ix->dv, d_q, nq, (float *)keys, cs);
+            int rc = FBPQ_OK;
+            if (e == hipSuccess)
+                rc = run_round(ix, d_q, nq, nq, nullptr, P, max_cells, lcap, (const int64_t *)dL,
+                               (const int32_t *)dk, k_max, d_ids, d_d, cs, (const float *)keys, (int32_t *)dfail,
+                               nullptr, nullptr, true);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (e != hipSuccess || rc != FBPQ_OK || e2 != hipSuccess || !g || ix->ws_gen != gen0) {
+                if (g) (void)hipGraphDestroy(g);
+                (void)hipGetLastError();
+                return rc != FBPQ_OK ? rc : fail(FBPQ_E_DEVICE, "graph capture of the search failed");
+            }
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HCK(ix, e3);
+            if (ix->gexec) (void)hipGraphExecDestroy(ix->gexec);
+            ix->gexec = ex;
+            ix->gkey = key;
+            ix->gkey.ws_gen = ix->ws_gen;
+        }
+    }
+    for (int round = 1; nfail > 0; ++round) {
         ix->stat_retried += nfail;
         // read the failed queries and their reasons, then grow P and/or the cell capacity
         failed.resize(nfail);
@@ -758,6 +826,9 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
         qlist = (const int32_t *)ql;
         nslots = nfail;
         if (round > 64) return fail(FBPQ_E_CAPACITY, "traversal did not converge");
+        nfail = 0;
+        TRY(run_round(ix, d_q, nq, nslots, qlist, P, max_cells, lcap, (const int64_t *)dL, (const int32_t *)dk,
+                      k_max, d_ids, d_d, st, (const float *)keys, (int32_t *)dfail, dbg, &nfail));
     }
     return FBPQ_OK;
 }
@@ -1013,6 +1084,13 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
         ix->profile = value != 0;
     } else if (!strcmp(key, "profile_mask")) {
         ix->prof_mask = value;
+    } else if (!strcmp(key, "graph")) {
+        ix->graph = value != 0;
+        if (!ix->graph && ix->gexec) {
+            HCK(ix, hipDeviceSynchronize());
+            (void)hipGraphExecDestroy(ix->gexec);
+            ix->gexec = nullptr;
+        }
     } else if (!strcmp(key, "stats")) {
         if (value) {
             HCK(ix, hipSetDevice(ix->device));
@@ -1023,6 +1101,7 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
             }
             HCK(ix, hipMemset(ix->stats_dev, 0, sizeof(unsigned long long) * kNumStatSlots));
             ix->stat_retried = 0;
+            ix->graph_replays = 0;
         } else if (ix->stats_dev) {
             HCK(ix, hipDeviceSynchronize());
             (void)hipFree(ix->stats_dev);
@@ -1050,6 +1129,67 @@ int fbpq_profile_read(fbpq_index *ix, int32_t stage, int32_t reset, double *ms, 
     return FBPQ_OK;
 }
 
+int fbpq_autotune(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
+                  int32_t k_max, int64_t *d_ids, float *d_dists, void *hip_stream, int32_t reps, int64_t *chosen)
+{
+    TRY(check_handle(ix));
+    if (reps < 1 || reps > 100 || !chosen) return fail(FBPQ_E_INVALID, "bad autotune arguments");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const bool prof0 = ix->profile, graph0 = ix->graph;
+    ix->profile = false;
+    ix->graph = false;
+    const int32_t T = ix->dv.T;
+    struct Cand {
+        int32_t prefix;
+        bool items;
+    };
+    std::vector<Cand> cands;
+    for (int32_t p : {64, 128, 256, 512})
+        if (p <= std::min<int32_t>(T, kMaxPrefix)) {
+            cands.push_back({p, true});
+            cands.push_back({p, false});
+        }
+    if (cands.empty()) cands.push_back({std::min<int32_t>(T, kMaxPrefix), true});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HCK(ix, hipEventCreate(&e0));
+    HCK(ix, hipEventCreate(&e1));
+    double best = -1.0;
+    Cand bestc = cands[0];
+    int rc = FBPQ_OK;
+    for (const Cand &c : cands) {
+        ix->prefix = c.prefix;
+        ix->items = c.items;
+        rc = search_impl(ix, d_q, nq, L, k, k_max, d_ids, d_dists, st, nullptr);  // warm: workspace, retries
+        if (rc) break;
+        std::vector<float> t(reps);
+        for (int r = 0; r < reps && !rc; ++r) {
+            if (hipEventRecord(e0, st) != hipSuccess) rc = fail(FBPQ_E_DEVICE, "event record failed");
+            if (!rc) rc = search_impl(ix, d_q, nq, L, k, k_max, d_ids, d_dists, st, nullptr);
+            if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&t[r], e0, e1) != hipSuccess))
+                rc = fail(FBPQ_E_DEVICE, "event timing failed");
+        }
+        if (rc) break;
+        std::sort(t.begin(), t.end());
+        const double med = t[t.size() / 2];
+        if (best < 0 || med < best) {
+            best = med;
+            bestc = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ix->prefix = bestc.prefix;
+    ix->items = bestc.items;
+    ix->profile = prof0;
+    ix->graph = graph0;
+    if (rc) return rc;
+    chosen[0] = bestc.prefix;
+    chosen[1] = bestc.items ? 1 : 0;
+    chosen[2] = (int64_t)(best * 1000.0);  // microseconds per search of the batch
+    return FBPQ_OK;
+}
+
 int fbpq_stats_read(fbpq_index *ix, int64_t *out, int32_t n, int32_t reset)
 {
     TRY(check_handle(ix));
@@ -1060,10 +1200,12 @@ int fbpq_stats_read(fbpq_index *ix, int64_t *out, int32_t n, int32_t reset)
     HCK(ix, hipDeviceSynchronize());
     HCK(ix, hipMemcpy(h, ix->stats_dev, sizeof(h), hipMemcpyDeviceToHost));
     h[FBPQ_STAT_RETRIED] = (unsigned long long)ix->stat_retried;
+    h[FBPQ_STAT_GRAPH_REPLAYS] = (unsigned long long)ix->graph_replays;
     for (int i = 0; i < n && i < FBPQ_NUM_STATS; ++i) out[i] = (int64_t)h[i];
     if (reset) {
         HCK(ix, hipMemset(ix->stats_dev, 0, sizeof(h)));
         ix->stat_retried = 0;
+        ix->graph_replays = 0;
     }
     return FBPQ_OK;
 }

@@ -56,6 +56,8 @@ struct DevIndex {
 hipError_t launch_tables(const DevIndex &ix, float *CR1, float *CR2, float *nR, float *nC1,
                          float *nC2, hipStream_t st);
 
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+
 hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, uint8_t *b,
                               hipStream_t st);
 

@@ -84,6 +84,21 @@ __global__ void k_split_codes(const uint8_t *__restrict__ src, int64_t n, int M,
     else b[p * Mh + (k - Mh)] = src[e];
 }
 
+// Fills n int32 with v (a kernel rather than a memset, so that it can sit in
+// a captured graph).
+__global__ void k_fill_i32(int32_t *__restrict__ p, int32_t v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, uint8_t *b,
                               hipStream_t st)
 {

@@ -30,10 +30,10 @@ FBPQ_K_MAX = 1024
 EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbpq_build_tables",
            "fbpq_search", "fbpq_search_uneven", "fbpq_search_device", "fbpq_debug_visit",
            "fbpq_debug_dists", "fbpq_debug_tables", "fbpq_debug_rank", "fbpq_info",
-           "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_stats_read",
+           "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_stats_read", "fbpq_autotune",
            "fbpq_free_index", "fbpq_last_error")
 STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2")
-STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried")
+STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried", "graph_replays")
 
 
 class FbpqError(RuntimeError):
@@ -78,6 +78,7 @@ def _load():
         "fbpq_set_option": ([P, ctypes.c_char_p, i64], ctypes.c_int),
         "fbpq_profile_read": ([P, i32, i32, P, P], ctypes.c_int),
         "fbpq_stats_read": ([P, P, i32, i32], ctypes.c_int),
+        "fbpq_autotune": ([P, P, i64, P, P, i32, P, P, P, i32, P], ctypes.c_int),
         "fbpq_free_index": ([P], None),
         "fbpq_last_error": ([], ctypes.c_char_p),
     }
@@ -159,6 +160,18 @@ def fbpq_stats_read(h, reset: bool = False) -> dict:
     out = np.zeros(len(STATS), np.int64)
     _check(lib.fbpq_stats_read(h, _p(out), len(STATS), int(reset)))
     return dict(zip(STATS, out.tolist()))
+
+
+def fbpq_autotune(h, d_q, L, k, k_max: int, d_ids, d_dists, stream, reps: int = 3) -> dict:
+    """Tune "prefix" and "items" on a device batch (torch tensors); returns the choice."""
+    nq = d_q.shape[0]
+    L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, np.int64), (nq,)))
+    k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
+    out = np.zeros(3, np.int64)
+    _check(lib.fbpq_autotune(h, ctypes.c_void_p(d_q.data_ptr()), nq, _p(L), _p(k), int(k_max),
+                             ctypes.c_void_p(d_ids.data_ptr()), ctypes.c_void_p(d_dists.data_ptr()),
+                             ctypes.c_void_p(stream.cuda_stream), int(reps), _p(out)))
+    return {"prefix": int(out[0]), "items": int(out[1]), "us_per_search": int(out[2])}
 
 
 def fbpq_free_index(h) -> None:

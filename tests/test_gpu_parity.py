@@ -14,6 +14,9 @@ from parity import assert_topk, log, oracle_dists, tol
 
 pytestmark = pytest.mark.gpu
 
+# the oracle runs in the calling thread inside the GPU test process
+oracle.DEFAULT_THREADS = 1
+
 
 @pytest.fixture(scope="module")
 def fb():
@@ -418,3 +421,64 @@ def test_full_batched_10M_sampled(fb):
     assert st["cell_scan"] + st["two_pass"] == nq
     o_ids, o_d, _, _ = oracle.search(ix, Q[sample], L, k)
     assert_topk(ix, Q[sample], k, g_ids[sample], g_d[sample], o_ids, o_d)
+
+
+# ---- graph capture of the first round -------------------------------------------
+
+@pytest.mark.parametrize("T,min_replays", [(256, 3), (1000, 3)])
+def test_graph_replays_match_eager(fb, gmm_wide, T, min_replays):
+    # cells hold few points here: most queries need a retry round with a
+    # longer prefix, whose larger buffers force one recapture
+    import torch
+    idxs, _ = gmm_wide
+    ix = idxs[T]
+    dev = torch.device("cuda:0")
+    means = synth.gmm_means(0)
+    nq, L, k = 64, 3000, 20
+    log(f"graph replays: N=2e5 T={T} M=8 nq=64 L=3000 k=20")
+    hg = _open(fb, ix, stats=1, graph=1)
+    he = _open(fb, ix)
+    d_q = torch.empty(nq, ix.D, dtype=torch.float32, device=dev)
+    d_ids = torch.empty(nq, k, dtype=torch.int64, device=dev)
+    d_d = torch.empty(nq, k, dtype=torch.float32, device=dev)
+    e_ids = torch.empty_like(d_ids)
+    e_d = torch.empty_like(d_d)
+    Ls, ks = np.full(nq, L, np.int64), np.full(nq, k, np.int32)
+    stream = torch.cuda.current_stream(dev)
+    for rep in range(5):
+        Q = synth.make_queries(nq, means, 100 + rep)
+        d_q.copy_(torch.from_numpy(Q))
+        fb.fbpq_search_device(hg, d_q, Ls, ks, k, d_ids, d_d, stream)
+        # the program's own eager work between replays
+        scratch = torch.randn(1 << 20, device=dev).sum()
+        torch.cuda.synchronize()
+        fb.fbpq_search_device(he, d_q, Ls, ks, k, e_ids, e_d, stream)
+        torch.cuda.synchronize()
+        assert torch.equal(d_ids, e_ids) and torch.equal(d_d, e_d), rep
+        assert float(scratch) == float(scratch)
+    st = fb.fbpq_stats_read(hg)
+    fb.fbpq_free_index(hg)
+    fb.fbpq_free_index(he)
+    log(f"  counters {st}")
+    assert st["graph_replays"] >= min_replays
+
+
+def test_autotune_then_parity(fb, gmm_wide):
+    import torch
+    idxs, Q = gmm_wide
+    ix = idxs[256]
+    dev = torch.device("cuda:0")
+    nq, L, k = Q.shape[0], 2000, 10
+    log("autotune: N=2e5 T=256 M=8 nq=40 L=2000 k=10")
+    h = _open(fb, ix)
+    d_q = torch.from_numpy(Q).to(dev).contiguous()
+    d_ids = torch.empty(nq, k, dtype=torch.int64, device=dev)
+    d_d = torch.empty(nq, k, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    choice = fb.fbpq_autotune(h, d_q, L, k, k, d_ids, d_d, stream, reps=2)
+    log(f"  chosen {choice}")
+    assert choice["prefix"] in (64, 128, 256) and choice["items"] in (0, 1) and choice["us_per_search"] > 0
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
