@@ -482,3 +482,35 @@ def test_autotune_then_parity(fb, gmm_wide):
     fb.fbpq_free_index(h)
     o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
     assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
+@pytest.mark.timeout(400)
+def test_full_uneven_100M_sampled(fb):
+    """N = 1e8, T = 16384, M = 8, 2e4 queries, L log-uniform in [1e3, 1e5], k in {1, 10, 100}."""
+    import torch
+    dev = torch.device("cuda:0")
+    means = synth.gmm_means(0)
+    base = synth.sample_points(100_000_000, means, 1, dev)
+    ix = synth.build_index(base, 16384, 8, keep_base=False)
+    del base
+    torch.cuda.empty_cache()
+    nq, kmax = 20000, 100
+    Q = synth.make_queries(nq, means, 2, dev)
+    L, k = synth.draw_L_k(nq, 3)
+    log(f"full uneven batch: N={ix.N} T=16384 M=8 nq={nq} mean L={L.mean():.0f}")
+    h = _open(fb, ix, stats=1)
+    d_q = torch.from_numpy(Q).to(dev).contiguous()
+    d_ids = torch.empty(nq, kmax, dtype=torch.int64, device=dev)
+    d_d = torch.empty(nq, kmax, dtype=torch.float32, device=dev)
+    fb.fbpq_search_device(h, d_q, L, k, kmax, d_ids, d_d, torch.cuda.current_stream(dev))
+    torch.cuda.synchronize()
+    st = fb.fbpq_stats_read(h)
+    log(f"  counters {st}")
+    g_ids, g_d = d_ids.cpu().numpy(), d_d.cpu().numpy()
+    sample = np.random.default_rng(19).choice(nq, 24, replace=False)
+    _check_visit(fb, h, ix, Q[sample[:4]], int(L[sample[:4]].max()))
+    fb.fbpq_free_index(h)
+    assert st["prefix_wave"] + st["prefix_wg"] == 2 * nq
+    assert st["cell_scan"] + st["two_pass"] == nq
+    o_ids, o_d, _, _ = oracle.search(ix, Q[sample], L[sample], k[sample], kmax=kmax)
+    assert_topk(ix, Q[sample], k[sample], g_ids[sample], g_d[sample], o_ids, o_d)
