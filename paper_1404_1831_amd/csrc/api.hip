@@ -487,13 +487,32 @@ struct DebugOut {
         if (r_) return r_;       \
     } while (0)
 
+// First layer of a round: the sorted P-prefix of both half lists of every slot
+// into lkey/lidx: the approximate key array of the round's slots, the
+// wavefront select and, for the pairs it leaves over, the workgroup select.
+int first_layer(fbpq_index *ix, const float *d_q, int64_t nslots, const int32_t *d_qlist, int32_t P,
+                double *lkey, int32_t *lidx, hipStream_t st)
+{
+    const DevIndex &dv = ix->dv;
+    void *pstat;
+    TRY(ws_get(ix, W_PSTAT, sizeof(int32_t) * nslots * 2, &pstat));
+    void *keys;
+    TRY(ws_get(ix, W_KEYS, sizeof(float) * nslots * 2 * dv.T, &keys));
+    HCK(ix, timed(ix, FBPQ_STAGE_HALF_KEYS, st, [&] { return launch_half_approx(dv, d_q, d_qlist, nslots, (float *)keys, st); }));
+    const bool pwave = prefix_wave_ok(dv, P);
+    if (pwave)
+        HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_wave(dv, d_q, (const float *)keys, nslots, d_qlist, P, lkey, lidx, (int32_t *)pstat, ix->stats_dev, st); }));
+    HCK(ix, timed(ix, pwave ? FBPQ_STAGE_PREFIX_FB : FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_block(dv, d_q, (const float *)keys, nslots, d_qlist, P, lkey, lidx, pwave ? (const int32_t *)pstat : nullptr, ix->stats_dev, st); }));
+    return FBPQ_OK;
+}
+
 // One traversal round over nslots queries: launches every kernel of the
 // round on st. With launch_only (graph capture) it stops there; otherwise it
 // copies the debug outputs, waits for the stream and returns the number of
 // queries that need another round.
 int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, const int32_t *d_qlist,
               int32_t P, int64_t max_cells, int64_t lcap, const int64_t *d_L, const int32_t *d_k, int32_t k_max,
-              int64_t *d_ids, float *d_d, hipStream_t st, const float *keys, int32_t *d_fail,
+              int64_t *d_ids, float *d_d, hipStream_t st, int32_t *d_fail,
               const DebugOut *dbg, int64_t *fail_host_count, bool launch_only = false)
 {
     DevIndex &dv = ix->dv;
@@ -527,12 +546,7 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         TRY(ws_get(ix, W_DBGD, sizeof(float) * nslots * dbg->dcap, &ddd));
     }
     HCK(ix, launch_fill_i32(d_fail, 0, 1, st));
-    void *pstat;
-    TRY(ws_get(ix, W_PSTAT, sizeof(int32_t) * nslots * 2, &pstat));
-    const bool pwave = prefix_wave_ok(dv, P);
-    if (pwave)
-        HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_wave(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, ix->stats_dev, st); }));
-    HCK(ix, timed(ix, pwave ? FBPQ_STAGE_PREFIX_FB : FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_block(dv, d_q, keys, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, pwave ? (const int32_t *)pstat : nullptr, ix->stats_dev, st); }));
+    TRY(first_layer(ix, d_q, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, st));
     TravArgs ta{};
     ta.ix = dv;
     ta.lkey = (const double *)lkey;
@@ -727,8 +741,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     }
     if (std::min<int64_t>(Lmax, ix->dv.N) > 0x7fffffffLL)
         return fail(FBPQ_E_CAPACITY, "min(L, N) must stay below 2^31 candidates per query");
-    void *keys, *dL, *dk, *dfail, *pin;
-    TRY(ws_get(ix, W_KEYS, sizeof(float) * nq * 2 * ix->dv.T, &keys));
+    void *dL, *dk, *dfail, *pin;
     TRY(ws_get(ix, W_L, sizeof(int64_t) * nq, &dL));
     TRY(ws_get(ix, W_K, sizeof(int32_t) * nq, &dk));
     TRY(ws_get(ix, W_FAIL, sizeof(int32_t) * (nq + 1), &dfail));
@@ -762,21 +775,18 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
         HCK(ix, hipStreamSynchronize(st));
         nfail = hcount[0];
     } else {
-        HCK(ix, timed(ix, FBPQ_STAGE_HALF_KEYS, st, [&] { return launch_half_approx(ix->dv, d_q, nq, (float *)keys, st); }));
         TRY(run_round(ix, d_q, nq, nslots, qlist, P, max_cells, lcap, (const int64_t *)dL, (const int32_t *)dk,
-                      k_max, d_ids, d_d, st, (const float *)keys, (int32_t *)dfail, dbg, &nfail));
+                      k_max, d_ids, d_d, st, (int32_t *)dfail, dbg, &nfail));
         if (use_graph) {
             // every workspace buffer of this shape exists now: capture the round
             hipStream_t cs = ix->stream;
             HCK(ix, hipStreamSynchronize(cs));
             const int64_t gen0 = ix->ws_gen;
             HCK(ix, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            hipError_t e = launch_half_approx(ix->dv, d_q, nq, (float *)keys, cs);
-            int rc = FBPQ_OK;
-            if (e == hipSuccess)
-                rc = run_round(ix, d_q, nq, nq, nullptr, P, max_cells, lcap, (const int64_t *)dL,
-                               (const int32_t *)dk, k_max, d_ids, d_d, cs, (const float *)keys, (int32_t *)dfail,
-                               nullptr, nullptr, true);
+            const hipError_t e = hipSuccess;
+            const int rc = run_round(ix, d_q, nq, nq, nullptr, P, max_cells, lcap, (const int64_t *)dL,
+                                     (const int32_t *)dk, k_max, d_ids, d_d, cs, (int32_t *)dfail, nullptr, nullptr,
+                                     true);
             hipGraph_t g = nullptr;
             const hipError_t e2 = hipStreamEndCapture(cs, &g);
             if (e != hipSuccess || rc != FBPQ_OK || e2 != hipSuccess || !g || ix->ws_gen != gen0) {
@@ -828,7 +838,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
         if (round > 64) return fail(FBPQ_E_CAPACITY, "traversal did not converge");
         nfail = 0;
         TRY(run_round(ix, d_q, nq, nslots, qlist, P, max_cells, lcap, (const int64_t *)dL, (const int32_t *)dk,
-                      k_max, d_ids, d_d, st, (const float *)keys, (int32_t *)dfail, dbg, &nfail));
+                      k_max, d_ids, d_d, st, (int32_t *)dfail, dbg, &nfail));
     }
     return FBPQ_OK;
 }
@@ -1029,22 +1039,12 @@ int fbpq_debug_rank(fbpq_index *ix, const float *q, int64_t nq, int32_t P, doubl
         return fail(FBPQ_E_INVALID, "bad arguments");
     if (nq == 0) return FBPQ_OK;
     if (!ix->tables) return fail(FBPQ_E_STATE, "fbpq_build_tables has not been called");
-    void *dq, *dkeys, *lkey, *lidx;
+    void *dq, *lkey, *lidx;
     TRY(ws_get(ix, W_Q, sizeof(float) * nq * ix->dv.D, &dq));
-    TRY(ws_get(ix, W_KEYS, sizeof(float) * nq * 2 * ix->dv.T, &dkeys));
     TRY(ws_get(ix, W_LKEY, sizeof(double) * nq * 2 * P, &lkey));
     TRY(ws_get(ix, W_LIDX, sizeof(int32_t) * nq * 2 * P, &lidx));
     HCK(ix, hipMemcpyAsync(dq, q, sizeof(float) * nq * ix->dv.D, hipMemcpyHostToDevice, ix->stream));
-    HCK(ix, launch_half_approx(ix->dv, (const float *)dq, nq, (float *)dkeys, ix->stream));
-    void *pstat;
-    TRY(ws_get(ix, W_PSTAT, sizeof(int32_t) * nq * 2, &pstat));
-    const bool pwave = prefix_wave_ok(ix->dv, P);
-    if (pwave)
-        HCK(ix, launch_prefix_wave(ix->dv, (const float *)dq, (const float *)dkeys, nq, nullptr, P,
-                                   (double *)lkey, (int32_t *)lidx, (int32_t *)pstat, ix->stats_dev, ix->stream));
-    HCK(ix, launch_prefix_block(ix->dv, (const float *)dq, (const float *)dkeys, nq, nullptr, P, (double *)lkey,
-                                (int32_t *)lidx, pwave ? (const int32_t *)pstat : nullptr, ix->stats_dev,
-                                ix->stream));
+    TRY(first_layer(ix, (const float *)dq, nq, nullptr, P, (double *)lkey, (int32_t *)lidx, ix->stream));
     HCK(ix, hipMemcpyAsync(keys, lkey, sizeof(double) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
     HCK(ix, hipMemcpyAsync(idx, lidx, sizeof(int32_t) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
     HCK(ix, hipStreamSynchronize(ix->stream));

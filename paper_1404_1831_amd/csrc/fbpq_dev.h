@@ -61,13 +61,18 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, uint8_t *b,
                               hipStream_t st);
 
-hipError_t launch_half_approx(const DevIndex &ix, const float *q, int64_t nq, float *ka,
-                              hipStream_t st);
+// Approximate half keys ||q||^2 + ||c||^2 - 2 <q, c> into ka [slot][2][T]
+// (slot s holds query qlist[s], or s when qlist is null).
+hipError_t launch_half_approx(const DevIndex &ix, const float *q, const int32_t *qlist, int64_t nslots,
+                              float *ka, hipStream_t st);
 
-// Sorted prefix of each half list. The wave select handles the (query, half)
-// pairs it can and records in pstat [nslots][2] (0 done, 1 left over) which
-// remain; the workgroup kernel then takes the pairs left over (every pair when
-// pstat is null).
+constexpr int kWaveS = 512;  // survivors a wavefront select ranks
+
+// Sorted prefix of each half list from the key array ka [slot][2][T]. The
+// wave select handles the (slot, half) pairs it can and records in pstat
+// [nslots][2] (0 done, 1 left over) which remain; the workgroup kernel then
+// takes the pairs left over (every pair when pstat is null), from ka, or by
+// an exact radix select alone when ka is null.
 bool prefix_wave_ok(const DevIndex &ix, int32_t P);
 hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
                               const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,

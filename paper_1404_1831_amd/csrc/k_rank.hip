@@ -32,12 +32,14 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kAQ = 64, kAC = 128, kAS = 68;  // LDS row stride 68 floats: conflict-free reads
 
 __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q, int64_t nq, int D,
+                                                     const int32_t *__restrict__ qlist,
                                                      const float *__restrict__ C1,
                                                      const float *__restrict__ C2,
                                                      const float *__restrict__ nC1,
                                                      const float *__restrict__ nC2, int T,
                                                      float *__restrict__ ka)
 {
+    // rows are slots 0..nq-1; slot s holds query qlist[s] (or s); ka is [slot][2][T]
     __shared__ __align__(16) float qs[kAQ * kAS];
     __shared__ __align__(16) float cs[kAC * kAS];
     __shared__ float qn[kAQ];
@@ -67,8 +69,9 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
             for (int i = 0; i < 4; ++i) {
                 const int e = tid + 256 * i, row = e >> 4, t = 4 * (e & 15);
                 const int64_t qi = q0 + row;
+                const int64_t qr = qi < nq ? (qlist ? qlist[qi] : qi) : 0;
                 qv[i] = (qi < nq && t < tn)
-                            ? *reinterpret_cast<const float4 *>(Q + qi * D + half * h + t0 + t)
+                            ? *reinterpret_cast<const float4 *>(Q + qr * D + half * h + t0 + t)
                             : float4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
@@ -92,7 +95,8 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
             for (int e = tid; e < kAQ * 64; e += 256) {
                 const int qq = e >> 6, t = e & 63;
                 const int64_t qi = q0 + qq;
-                qs[qq * kAS + t] = (qi < nq && t < tn) ? Q[qi * D + half * h + t0 + t] : 0.f;
+                const int64_t qr = qi < nq ? (qlist ? qlist[qi] : qi) : 0;
+                qs[qq * kAS + t] = (qi < nq && t < tn) ? Q[qr * D + half * h + t0 + t] : 0.f;
             }
             for (int e = tid; e < kAC * 64; e += 256) {
                 const int cc = e >> 6, t = e & 63;
@@ -138,12 +142,12 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
     }
 }
 
-hipError_t launch_half_approx(const DevIndex &ix, const float *q, int64_t nq, float *ka,
-                              hipStream_t st)
+hipError_t launch_half_approx(const DevIndex &ix, const float *q, const int32_t *qlist, int64_t nslots,
+                              float *ka, hipStream_t st)
 {
-    if (nq == 0) return hipSuccess;
-    dim3 grid((unsigned)((ix.T + kAC - 1) / kAC), (unsigned)((nq + kAQ - 1) / kAQ), 2);
-    hipLaunchKernelGGL(k_half_approx, grid, dim3(256), 0, st, q, nq, ix.D, ix.C1, ix.C2, ix.nC1,
+    if (nslots == 0) return hipSuccess;
+    dim3 grid((unsigned)((ix.T + kAC - 1) / kAC), (unsigned)((nslots + kAQ - 1) / kAQ), 2);
+    hipLaunchKernelGGL(k_half_approx, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2, ix.nC1,
                        ix.nC2, ix.T, ka);
     return hipGetLastError();
 }
@@ -302,13 +306,15 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     const int64_t qs = qlist ? qlist[slot] : slot;
     const float *C = half ? C2 : C1;
     const float cmax = half ? cmax2 : cmax1;
-    const bool lds_ka = T <= kApproxLds;
+    // kapprox null: no approximate keys, straight to the exact radix select
+    const bool have_ka = kapprox != nullptr;
+    const bool lds_ka = have_ka && T <= kApproxLds;
     float *qh = reinterpret_cast<float *>(smem);
     const int hpad = (h + 3) & ~3;
     float *kal = qh + hpad;
     uint64_t *sk = reinterpret_cast<uint64_t *>(kal + (lds_ka ? ((T + 1) & ~1) : 0));
     int32_t *si = reinterpret_cast<int32_t *>(sk + S);
-    const float *kg = kapprox + (qs * 2 + half) * (int64_t)T;
+    const float *kg = have_ka ? kapprox + ((int64_t)slot * 2 + half) * (int64_t)T : nullptr;
 
     for (int t = tid; t < h; t += kSelThreads) qh[t] = Q[qs * D + half * h + t];
     if (lds_ka)
@@ -336,7 +342,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
         rank_out(sk, si, T, P, T, ok, oi);
         done = true;
     }
-    if (!done && (T < kSelThreads ? T : kSelThreads) >= P) {
+    if (!done && have_ka && (T < kSelThreads ? T : kSelThreads) >= P) {
         // Each thread's smallest approximate key is a sample; P distinct
         // centroids lie at or below the P-th smallest sample, so it bounds kP
         // (the P-th smallest approximate key) from above.
@@ -372,7 +378,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
         }
         __syncthreads();
     }
-    if (!done) {
+    if (!done && have_ka) {
         // kP: the P-th smallest approximate key, bracketed by value bins
         float lo = 0.f;
         {
@@ -572,7 +578,6 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
 // Survivors (ka <= bound + 2e) are compacted with ballots, get their exact
 // FP64 keys and are ranked by (key, index) inside the wave. When more than
 // kWaveS survive, pstat keeps the pair for the workgroup kernel.
-constexpr int kWaveS = 512;
 constexpr int kWPB = 4;  // wavefronts (query halves) per workgroup
 
 __device__ __forceinline__ uint32_t okey(float f)
@@ -610,7 +615,7 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
     const int64_t qs = qlist ? qlist[slot] : slot;
     const float *C = half ? C2 : C1;
     const float cmax = half ? cmax2 : cmax1;
-    const float *kg = kapprox + (qs * 2 + half) * (int64_t)T;
+    const float *kg = kapprox + (slot * 2 + half) * (int64_t)T;
     for (int t = lane; t < h; t += 64) qh[t] = Q[qs * D + half * h + t];
 
     // Keys are read 16 bytes per lane, kF4 loads per lane per chunk of
