@@ -188,6 +188,34 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 #define FBPQ_STAGE_SCAN2 8     /* two-pass scan (queries whose cells hold few points) */
 #define FBPQ_NUM_STAGES 9
 
+/* ---- served form: continuous batching (Section 4 measures per-query time;
+ * a server keeps the GPU busy with overlapping batches of arriving queries) --
+ *
+ * fbpq_server_create: a server over a handle whose tables are built. It owns
+ *   nlanes (1..16) lanes, each with its own HIP stream and workspace over the
+ *   handle's index arrays, and one host worker thread per lane. A lane that is
+ *   free takes every pending request, up to max_batch, and searches them as one
+ *   batch; the lanes' batches overlap on the GPU. Results have k_max columns.
+ *   The handle must outlive the server and must not be searched directly while
+ *   the server runs. Errors: INVALID, STATE, DEVICE.
+ * fbpq_server_submit: queues one query (host, D floats, copied), its L >= 1 and
+ *   1 <= k <= k_max, under a caller tag. Thread-safe. Errors: INVALID, STATE.
+ * fbpq_server_poll: moves up to max_n finished requests out, waiting up to
+ *   wait_s seconds for the first: tags[n], ids/dists [n][k_max] (padded with
+ *   -1 / +inf past k), times[n][3] = submit, batch start, batch end (seconds on
+ *   the host steady clock), status[n] = the batch's return code. Writes the
+ *   count to *n_out. Errors: INVALID.
+ * fbpq_server_counts: requests still queued, batches run, requests batched.
+ * fbpq_server_destroy: finishes every queued request, then frees the lanes;
+ *   results not polled are dropped. */
+typedef struct fbpq_server fbpq_server;
+int fbpq_server_create(fbpq_index *ix, int32_t max_batch, int32_t nlanes, int32_t k_max, fbpq_server **out);
+int fbpq_server_submit(fbpq_server *s, const float *q, int64_t L, int32_t k, int64_t tag);
+int fbpq_server_poll(fbpq_server *s, int32_t max_n, double wait_s, int64_t *tags, int64_t *ids, float *dists,
+                     double *times, int32_t *status, int32_t *n_out);
+int fbpq_server_counts(fbpq_server *s, int64_t *pending, int64_t *batches, int64_t *batched);
+void fbpq_server_destroy(fbpq_server *s);
+
 /* Autotuner. Times fbpq_search_device on the caller's batch (device queries
  * d_q [nq][D], per-query host L and k, device results as in
  * fbpq_search_device, on hip_stream) under each candidate setting of the

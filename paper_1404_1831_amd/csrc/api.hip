@@ -42,6 +42,7 @@ struct DevBuf {
 
 struct fbpq_index {
     int device = 0;
+    bool shared = false;  // a serving lane: index arrays belong to another handle
     bool poisoned = false;
     bool tables = false;
     DevIndex dv{};
@@ -249,9 +250,11 @@ void free_all(fbpq_index *ix)
     (void)hipSetDevice(ix->device);
     if (ix->stream) (void)hipStreamSynchronize(ix->stream);
     void *ps[] = {ix->C1, ix->C2, ix->R, ix->offsets, ix->codesA, ix->codesB, ix->ids,
-                  ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2, ix->stats_dev};
-    for (void *p : ps)
-        if (p) (void)hipFree(p);
+                  ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2};
+    if (!ix->shared)
+        for (void *p : ps)
+            if (p) (void)hipFree(p);
+    if (ix->stats_dev) (void)hipFree(ix->stats_dev);
     for (auto &b : ix->ws)
         if (b.p) (void)hipFree(b.p);
     if (ix->pinned) (void)hipHostFree(ix->pinned);
@@ -844,6 +847,51 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
 }
 
 }  // namespace
+
+namespace fbpq {
+
+// A handle over the same index arrays with its own stream, workspace and
+// pinned staging (one per concurrent batch of the serving layer). It copies
+// the source handle's options. Freed with fbpq_free_index, which leaves the
+// shared arrays alone; the source handle must outlive it.
+int lane_create(fbpq_index *src, fbpq_index **out)
+{
+    TRY(check_handle(src));
+    if (!src->tables) return fail(FBPQ_E_STATE, "fbpq_build_tables has not been called");
+    fbpq_index *ix = new fbpq_index();
+    ix->device = src->device;
+    ix->shared = true;
+    if (hipSetDevice(src->device) != hipSuccess || hipStreamCreate(&ix->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ix;
+        return fail(FBPQ_E_DEVICE, "cannot create a stream on device %d", src->device);
+    }
+    ix->tables = true;
+    ix->dv = src->dv;
+    ix->C1 = src->C1;
+    ix->C2 = src->C2;
+    ix->R = src->R;
+    ix->offsets = src->offsets;
+    ix->codesA = src->codesA;
+    ix->codesB = src->codesB;
+    ix->ids = src->ids;
+    ix->CR1 = src->CR1;
+    ix->CR2 = src->CR2;
+    ix->nR = src->nR;
+    ix->nC1 = src->nC1;
+    ix->nC2 = src->nC2;
+    ix->prefix = src->prefix;
+    ix->max_cells = src->max_cells;
+    ix->chunk = src->chunk;
+    ix->items = src->items;
+    *out = ix;
+    return FBPQ_OK;
+}
+
+int lane_device(const fbpq_index *ix) { return ix->device; }
+int lane_dim(const fbpq_index *ix) { return ix->dv.D; }
+
+}  // namespace fbpq
 
 // ============================== C ABI ========================================
 extern "C" {

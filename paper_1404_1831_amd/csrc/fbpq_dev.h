@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct fbpq_index;
+
 namespace fbpq {
 
 constexpr int kWave = 64;
@@ -183,5 +185,10 @@ hipError_t launch_items_scan(const ItemArgs &a, hipStream_t st);   // query-majo
 hipError_t launch_items_merge(const ItemArgs &a, hipStream_t st);  // per-query top-k
 int items_wcap(int k_max);
 size_t select_dist_lds(int k_max);
+
+// Serving lanes (api.hip): handles over another handle's index arrays.
+int lane_create(fbpq_index *src, fbpq_index **out);
+int lane_device(const fbpq_index *ix);
+int lane_dim(const fbpq_index *ix);
 
 }  // namespace fbpq

@@ -31,7 +31,8 @@ EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbp
            "fbpq_search", "fbpq_search_uneven", "fbpq_search_device", "fbpq_debug_visit",
            "fbpq_debug_dists", "fbpq_debug_tables", "fbpq_debug_rank", "fbpq_info",
            "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_stats_read", "fbpq_autotune",
-           "fbpq_free_index", "fbpq_last_error")
+           "fbpq_free_index", "fbpq_last_error", "fbpq_server_create", "fbpq_server_submit",
+           "fbpq_server_poll", "fbpq_server_counts", "fbpq_server_destroy")
 STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2")
 STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried", "graph_replays")
 
@@ -80,6 +81,11 @@ def _load():
         "fbpq_stats_read": ([P, P, i32, i32], ctypes.c_int),
         "fbpq_autotune": ([P, P, i64, P, P, i32, P, P, P, i32, P], ctypes.c_int),
         "fbpq_free_index": ([P], None),
+        "fbpq_server_create": ([P, i32, i32, i32, P], ctypes.c_int),
+        "fbpq_server_submit": ([P, P, i64, i32, i64], ctypes.c_int),
+        "fbpq_server_poll": ([P, i32, ctypes.c_double, P, P, P, P, P, P], ctypes.c_int),
+        "fbpq_server_counts": ([P, P, P, P], ctypes.c_int),
+        "fbpq_server_destroy": ([P], None),
         "fbpq_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -255,3 +261,39 @@ def fbpq_debug_rank(h, q: np.ndarray, P: int):
     idx = np.empty((nq, 2, P), np.int32)
     _check(lib.fbpq_debug_rank(h, _p(q), nq, int(P), _p(keys), _p(idx)))
     return keys, idx
+
+
+def fbpq_server_create(h, max_batch: int, nlanes: int, k_max: int) -> ctypes.c_void_p:
+    s = ctypes.c_void_p()
+    _check(lib.fbpq_server_create(h, int(max_batch), int(nlanes), int(k_max), ctypes.byref(s)))
+    return s
+
+
+def fbpq_server_submit(s, q: np.ndarray, L: int, k: int, tag: int) -> None:
+    q = np.ascontiguousarray(q, np.float32)
+    _check(lib.fbpq_server_submit(s, _p(q), int(L), int(k), int(tag)))
+
+
+def fbpq_server_poll(s, max_n: int, k_max: int, D: int = 0, wait_s: float = 0.0):
+    """(tags, ids [n][k_max], dists, times [n][3], status) of finished requests."""
+    tags = np.empty(max_n, np.int64)
+    ids = np.empty((max_n, k_max), np.int64)
+    d = np.empty((max_n, k_max), np.float32)
+    times = np.empty((max_n, 3), np.float64)
+    st = np.empty(max_n, np.int32)
+    n = ctypes.c_int32()
+    _check(lib.fbpq_server_poll(s, int(max_n), float(wait_s), _p(tags), _p(ids), _p(d), _p(times), _p(st),
+                                ctypes.byref(n)))
+    k = n.value
+    return tags[:k], ids[:k], d[:k], times[:k], st[:k]
+
+
+def fbpq_server_counts(s):
+    p, b, n = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.fbpq_server_counts(s, ctypes.byref(p), ctypes.byref(b), ctypes.byref(n)))
+    return p.value, b.value, n.value
+
+
+def fbpq_server_destroy(s) -> None:
+    lib.fbpq_server_destroy(s)
+

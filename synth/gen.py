@@ -298,15 +298,18 @@ def zipf_index(N: int, T: int, M: int, D: int = 128, s: float = 1.1, seed: int =
     ref = build_index(tr, T, M, seed=codebook_seed, train_n=20000, keep_base=False)
     g = _gen(seed, device)
     C = T * T
-    ranks = torch.arange(1, C + 1, device=device, dtype=torch.float64)
-    p = ranks.pow(-s)
-    p /= p.sum()
+    # inverse-CDF draw of Zipf ranks (FP64 CDF over all C ranks)
+    cdf = torch.arange(1, C + 1, device=device, dtype=torch.float64).pow_(-s).cumsum_(0)
+    cdf /= cdf[-1].clone()
     counts = torch.zeros(C, dtype=torch.int64, device=device)
     step = 1 << 26
     for s0 in range(0, N, step):
         n = min(step, N - s0)
-        r = torch.multinomial(p.to(torch.float32), n, replacement=True, generator=g)
+        u = torch.rand(n, generator=g, device=device, dtype=torch.float64)
+        r = torch.searchsorted(cdf, u).clamp_(max=C - 1)
         counts += torch.bincount(r, minlength=C)
+        del u, r
+    del cdf
     perm = torch.randperm(C, generator=g, device=device)
     cell_counts = torch.empty_like(counts)
     cell_counts[perm] = counts

@@ -514,3 +514,43 @@ def test_full_uneven_100M_sampled(fb):
     assert st["cell_scan"] + st["two_pass"] == nq
     o_ids, o_d, _, _ = oracle.search(ix, Q[sample], L[sample], k[sample], kmax=kmax)
     assert_topk(ix, Q[sample], k[sample], g_ids[sample], g_d[sample], o_ids, o_d)
+
+
+# ---- served form ----------------------------------------------------------------
+
+def test_server_continuous_batching(fb, gmm_small):
+    import time
+    ix, Q0 = gmm_small
+    means = synth.gmm_means(0)
+    nreq, kmax = 300, 100
+    Q = synth.make_queries(nreq, means, 7)
+    rng = np.random.default_rng(31)
+    L = rng.integers(1, 30000, nreq)
+    k = rng.choice([1, 10, 100], nreq).astype(np.int32)
+    log(f"server: N=1e5 T=64 M=8, {nreq} requests, 2 lanes, batches of at most 64")
+    h = _open(fb, ix)
+    s = fb.fbpq_server_create(h, 64, 2, kmax)
+    got = {}
+    try:
+        for i in range(nreq):
+            fb.fbpq_server_submit(s, Q[i], int(L[i]), int(k[i]), i)
+            if i % 50 == 49:
+                time.sleep(0.002)  # arrivals in bursts
+        deadline = time.time() + 60
+        while len(got) < nreq and time.time() < deadline:
+            tags, ids, d, times, st = fb.fbpq_server_poll(s, 128, kmax, wait_s=0.2)
+            for j, t in enumerate(tags):
+                assert st[j] == 0
+                assert times[j, 0] <= times[j, 1] <= times[j, 2]
+                got[int(t)] = (ids[j], d[j])
+        pending, batches, batched = fb.fbpq_server_counts(s)
+    finally:
+        fb.fbpq_server_destroy(s)
+        fb.fbpq_free_index(h)
+    log(f"  {batches} batches for {batched} requests")
+    assert len(got) == nreq and batched == nreq and pending == 0
+    assert batches < nreq  # requests were batched together
+    g_ids = np.stack([got[i][0] for i in range(nreq)])
+    g_d = np.stack([got[i][1] for i in range(nreq)])
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k, kmax=kmax)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
