@@ -31,6 +31,9 @@ FP32_MFMA_TFLOPS = 157.3
 WORKLOADS = {
     "batched": dict(N=10_000_000, T=4096, M=16, nq=10_000, L=10_000, k=100),
     "plain": dict(N=100_000, T=64, M=8, nq=100, L=10_000, k=10),
+    # served: Zipf(1.1) cell sizes over T^2 cells, Poisson arrivals
+    "served": dict(N=1_000_000_000, T=16384, M=8, L=(10_000, 30_000, 100_000), k=10,
+                   offered=(1000, 2000, 5000, 10000, 20000)),
 }
 
 
@@ -88,6 +91,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--served-n", type=int, default=0, help="served workload: points (default 1e9)")
+    ap.add_argument("--served-seconds", type=float, default=2.0, help="served workload: seconds per offered load")
+    ap.add_argument("--served-lanes", type=int, default=2)
+    ap.add_argument("--served-batch", type=int, default=512)
     ap.add_argument("--plain-queries", type=int, default=200,
                     help="queries searched one launch sequence at a time, for the per-query comparison")
     ap.add_argument("--profile-steps", type=int, default=3,
@@ -110,6 +117,8 @@ def main() -> int:
     from paper_1404_1831_amd import fbpq
 
     w = dict(WORKLOADS[args.workload])
+    if args.workload == "served":
+        return run_served(args, w)
     if args.nq:
         w["nq"] = args.nq
     dev = torch.device("cuda:0")
@@ -271,6 +280,106 @@ def main() -> int:
         "scan_GBps": scan_GBps,
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def run_served(args, w) -> int:
+    """Continuous batching under Poisson arrivals: per offered load, the achieved
+    rate and the latency from submit to result on the host (p50, p99)."""
+    import threading
+
+    import torch
+
+    import synth
+    from paper_1404_1831_amd.build import LIB
+    if not os.path.exists(LIB):
+        from paper_1404_1831_amd.build import build
+        build()
+    from paper_1404_1831_amd import fbpq
+
+    N = args.served_n or w["N"]
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    ix = synth.zipf_index(N, w["T"], w["M"], device=dev)
+    torch.cuda.empty_cache()
+    cnt = np.diff(ix.offsets)
+    log(f"zipf index built in {time.time() - t0:.1f}s: N={ix.N} T={ix.T} M={ix.M} "
+        f"largest cell={int(cnt.max())} nonempty={float((cnt > 0).mean()):.3f}")
+    h = fbpq.fbpq_index_create(ix, 0)
+    fbpq.fbpq_build_tables(h)
+    means = synth.gmm_means(0)
+    k, Ls = w["k"], np.asarray(w["L"], np.int64)
+    rng = np.random.default_rng(4)
+    # one direct batch first: the same search the lanes run
+    Qc = synth.make_queries(64, means, 3)
+    a = time.perf_counter()
+    try:
+        fbpq.fbpq_search_uneven(h, Qc, np.full(64, int(Ls.max()), np.int64), np.full(64, k, np.int32), k)
+        msg = "all served"
+    except fbpq.FbpqError as e:
+        if e.code != fbpq.FBPQ_E_CAPACITY:
+            raise
+        msg = str(e)
+    log(f"direct batch of 64 at L={int(Ls.max())}: {(time.perf_counter() - a) * 1e3:.1f} ms ({msg})")
+    rows = []
+    for rate in w["offered"]:
+        nreq = int(rate * args.served_seconds)
+        Q = synth.make_queries(nreq, means, 2)
+        L = Ls[rng.integers(0, len(Ls), nreq)]
+        gaps = rng.exponential(1.0 / rate, nreq)
+        s = fbpq.fbpq_server_create(h, args.served_batch, args.served_lanes, k)
+        lat, done_t, nfail = [], [], 0
+
+        def submit():
+            t = time.perf_counter()
+            for i in range(nreq):
+                t += gaps[i]
+                dt = t - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                fbpq.fbpq_server_submit(s, Q[i], int(L[i]), k, i)
+
+        th = threading.Thread(target=submit)
+        a = time.perf_counter()
+        th.start()
+        got = 0
+        while got < nreq:
+            tags, ids, d, times, st = fbpq.fbpq_server_poll(s, 4096, k, wait_s=0.05)
+            got += len(tags)
+            ok = st == 0
+            nfail += int((~ok).sum())
+            lat.extend((times[ok, 2] - times[ok, 0]).tolist())
+            if len(tags):
+                done_t.append(time.perf_counter())
+            if time.perf_counter() - a > args.served_seconds * 20 + 60:
+                break
+        th.join()
+        elapsed = (done_t[-1] if done_t else time.perf_counter()) - a
+        _, batches, batched = fbpq.fbpq_server_counts(s)
+        err = fbpq.fbpq_server_first_error(s)
+        fbpq.fbpq_server_destroy(s)
+        if nfail:
+            log(f"offered {rate}/s: {nfail} requests failed: {err}")
+        lat_ms = np.asarray(lat) * 1e3
+        row = {"offered_qps": rate, "requests": nreq, "completed": got - nfail, "failed": nfail,
+               "achieved_qps": (got - nfail) / elapsed,
+               "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+               "mean_batch": batched / max(1, batches)}
+        rows.append(row)
+        log(f"offered {rate}/s: achieved {row['achieved_qps']:.0f}/s p50 {row['p50_ms']:.2f} ms "
+            f"p99 {row['p99_ms']:.2f} ms mean batch {row['mean_batch']:.1f}")
+    fbpq.fbpq_free_index(h)
+    best = max(rows, key=lambda r: r["achieved_qps"])
+    out = {
+        "metric": "served queries: achieved rate and p50/p99 latency vs offered load, 1 GPU",
+        "value": best["achieved_qps"], "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"served FBPQ: N={ix.N} with Zipf(1.1) cell sizes, T={ix.T} per half, "
+                               f"M={ix.M}, L in {Ls.tolist()}, k={k}, {args.served_lanes} lanes, "
+                               f"batches of at most {args.served_batch}"},
+        "served": rows,
     }
     print(json.dumps(out))
     return 0

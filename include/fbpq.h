@@ -108,7 +108,10 @@ int fbpq_build_tables(fbpq_index *ix);
 
 /* Search nq queries (host memory, float [nq][D]) with one budget L >= 1 and
  * 1 <= k <= FBPQ_K_MAX; writes host ids [nq][k] and dists [nq][k].
- * nq == 0 is a no-op. Errors: INVALID, STATE, CAPACITY, OOM, DEVICE. */
+ * nq == 0 is a no-op. Errors: INVALID, STATE, CAPACITY, OOM, DEVICE.
+ * CAPACITY (for every search entry point): some queries need more than the
+ * traversal supports (2048 ranks of a half list, or 2^26 visited cells);
+ * their rows hold id -2 and NaN distances, every other row is complete. */
 int fbpq_search(fbpq_index *ix, const float *q, int64_t nq, int64_t L, int32_t k,
                 int64_t *ids, float *dists);
 
@@ -206,6 +209,7 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
  *   the host steady clock), status[n] = the batch's return code. Writes the
  *   count to *n_out. Errors: INVALID.
  * fbpq_server_counts: requests still queued, batches run, requests batched.
+ * fbpq_server_first_error: message of the first failed batch ("" if none).
  * fbpq_server_destroy: finishes every queued request, then frees the lanes;
  *   results not polled are dropped. */
 typedef struct fbpq_server fbpq_server;
@@ -214,6 +218,7 @@ int fbpq_server_submit(fbpq_server *s, const float *q, int64_t L, int32_t k, int
 int fbpq_server_poll(fbpq_server *s, int32_t max_n, double wait_s, int64_t *tags, int64_t *ids, float *dists,
                      double *times, int32_t *status, int32_t *n_out);
 int fbpq_server_counts(fbpq_server *s, int64_t *pending, int64_t *batches, int64_t *batched);
+const char *fbpq_server_first_error(fbpq_server *s);
 void fbpq_server_destroy(fbpq_server *s);
 
 /* Autotuner. Times fbpq_search_device on the caller's batch (device queries

@@ -743,7 +743,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
         Lmax = std::max(Lmax, L[i]);
     }
     if (std::min<int64_t>(Lmax, ix->dv.N) > 0x7fffffffLL)
-        return fail(FBPQ_E_CAPACITY, "min(L, N) must stay below 2^31 candidates per query");
+        return fail(FBPQ_E_INVALID, "min(L, N) must stay below 2^31 candidates per query");
     void *dL, *dk, *dfail, *pin;
     TRY(ws_get(ix, W_L, sizeof(int64_t) * nq, &dL));
     TRY(ws_get(ix, W_K, sizeof(int32_t) * nq, &dk));
@@ -762,7 +762,6 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     const int64_t lcap = std::max<int64_t>(1, std::min(Lmax, ix->dv.N));
     int64_t nslots = nq;
     const int32_t *qlist = nullptr;
-    std::vector<int32_t> failed;
     int64_t nfail = 0;
 
     // first round: replay the captured graph when the launch sequence is the
@@ -807,42 +806,66 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
             ix->gkey.ws_gen = ix->ws_gen;
         }
     }
+    // Retry rounds. A query whose traversal ran out of prefix ranks or cell
+    // capacity is searched again with 4x the ranks or 8x the cells; one that
+    // already had the most the traversal supports is a terminal failure: its
+    // result row is filled with (-2, NaN) and the others complete.
+    const int32_t Pcap = std::min<int32_t>(T, kMaxPrefix);
+    const int64_t ccap = ((int64_t)1 << 31) / 32;
+    std::vector<int32_t> cur;  // query of each slot of the last round (empty: slot = query)
+    int64_t nterminal = 0;
     for (int round = 1; nfail > 0; ++round) {
         ix->stat_retried += nfail;
-        // read the failed queries and their reasons, then grow P and/or the cell capacity
-        failed.resize(nfail);
-        HCK(ix, hipMemcpy(failed.data(), (int32_t *)dfail + 1, sizeof(int32_t) * nfail, hipMemcpyDeviceToHost));
         std::vector<TravHdr> hh(nslots);
-        void *hdr = ix->ws[W_HDR].p;
-        HCK(ix, hipMemcpy(hh.data(), hdr, sizeof(TravHdr) * nslots, hipMemcpyDeviceToHost));
-        bool need_prefix = false, need_cells = false;
-        for (int64_t s = 0; s < nslots; ++s) {
-            need_prefix |= hh[s].status == kStNeedPrefix;
-            need_cells |= hh[s].status == kStNeedCells;
+        HCK(ix, hipMemcpy(hh.data(), ix->ws[W_HDR].p, sizeof(TravHdr) * nslots, hipMemcpyDeviceToHost));
+        std::vector<int32_t> retry, terminal;
+        bool grow_p = false, grow_c = false;
+        for (int64_t sl = 0; sl < nslots; ++sl) {
+            const int32_t q = cur.empty() ? (int32_t)sl : cur[sl];
+            if (hh[sl].status == kStNeedPrefix) {
+                if (P >= Pcap) terminal.push_back(q);
+                else {
+                    retry.push_back(q);
+                    grow_p = true;
+                }
+            } else if (hh[sl].status == kStNeedCells) {
+                if (max_cells >= ccap) terminal.push_back(q);
+                else {
+                    retry.push_back(q);
+                    grow_c = true;
+                }
+            }
         }
-        const int32_t Pcap = std::min<int32_t>(T, kMaxPrefix);
-        if (need_prefix) {
-            if (P >= Pcap)
-                return fail(FBPQ_E_CAPACITY, "a query needs more than %d ranks per half list", Pcap);
-            P = std::min<int32_t>(Pcap, P * 4);
+        if (!terminal.empty() && d_ids && d_d) {
+            const std::vector<int64_t> rid((size_t)k_max, -2);
+            const std::vector<float> rd((size_t)k_max, __builtin_nanf(""));
+            for (int32_t q : terminal) {
+                HCK(ix, hipMemcpyAsync(d_ids + (int64_t)q * k_max, rid.data(), sizeof(int64_t) * k_max,
+                                       hipMemcpyHostToDevice, st));
+                HCK(ix, hipMemcpyAsync(d_d + (int64_t)q * k_max, rd.data(), sizeof(float) * k_max,
+                                       hipMemcpyHostToDevice, st));
+            }
+            HCK(ix, hipStreamSynchronize(st));
         }
-        if (need_cells) {
-            const int64_t cap = ((int64_t)1 << 31) / 32;
-            if (max_cells >= cap)
-                return fail(FBPQ_E_CAPACITY, "a query visits more than %lld cells", (long long)cap);
-            // enough cells for the worst failing query at the current density bound
-            max_cells = std::min<int64_t>(cap, max_cells * 8);
-        }
+        nterminal += (int64_t)terminal.size();
+        if (grow_p) P = std::min<int32_t>(Pcap, P * 4);
+        if (grow_c) max_cells = std::min<int64_t>(ccap, max_cells * 8);
+        if (retry.empty()) break;
         void *ql;
-        TRY(ws_get(ix, W_QLIST, sizeof(int32_t) * nfail, &ql));
-        HCK(ix, hipMemcpy(ql, failed.data(), sizeof(int32_t) * nfail, hipMemcpyHostToDevice));
+        TRY(ws_get(ix, W_QLIST, sizeof(int32_t) * retry.size(), &ql));
+        HCK(ix, hipMemcpy(ql, retry.data(), sizeof(int32_t) * retry.size(), hipMemcpyHostToDevice));
         qlist = (const int32_t *)ql;
-        nslots = nfail;
+        nslots = (int64_t)retry.size();
+        cur.swap(retry);
         if (round > 64) return fail(FBPQ_E_CAPACITY, "traversal did not converge");
         nfail = 0;
         TRY(run_round(ix, d_q, nq, nslots, qlist, P, max_cells, lcap, (const int64_t *)dL, (const int32_t *)dk,
                       k_max, d_ids, d_d, st, (int32_t *)dfail, dbg, &nfail));
     }
+    if (nterminal)
+        return fail(FBPQ_E_CAPACITY,
+                    "%lld queries need more than %d ranks per half list or %lld cells (their rows are -2 / NaN)",
+                    (long long)nterminal, Pcap, (long long)ccap);
     return FBPQ_OK;
 }
 
@@ -1007,13 +1030,15 @@ static int host_search(fbpq_index *ix, const float *q, int64_t nq, const int64_t
         TRY(ws_get(ix, W_D, sizeof(float) * nq * k_max, &dd));
     }
     HCK(ix, hipMemcpyAsync(dq, q, sizeof(float) * nq * ix->dv.D, hipMemcpyHostToDevice, ix->stream));
-    TRY(search_impl(ix, (const float *)dq, nq, L, k, k_max, (int64_t *)dids, (float *)dd, ix->stream, dbg));
+    // CAPACITY: some rows are marked (-2, NaN), the others are complete
+    const int rc = search_impl(ix, (const float *)dq, nq, L, k, k_max, (int64_t *)dids, (float *)dd, ix->stream, dbg);
+    if (rc && rc != FBPQ_E_CAPACITY) return rc;
     if (outputs) {
         HCK(ix, hipMemcpyAsync(ids, dids, sizeof(int64_t) * nq * k_max, hipMemcpyDeviceToHost, ix->stream));
         HCK(ix, hipMemcpyAsync(dists, dd, sizeof(float) * nq * k_max, hipMemcpyDeviceToHost, ix->stream));
         HCK(ix, hipStreamSynchronize(ix->stream));
     }
-    return FBPQ_OK;
+    return rc;
 }
 
 int fbpq_search_uneven(fbpq_index *ix, const float *q, int64_t nq, const int64_t *L, const int32_t *k,

@@ -282,13 +282,13 @@ __device__ void rank_out(const uint64_t *sk, const int32_t *si, int n, int keep,
     }
 }
 
-// LDS: qh[h] floats | ka[T] floats (when T <= kApproxLds) | sort keys u64[S] | sort idx i32[S]
+// LDS: qh[h] floats | ka[T] floats (when staged) | sort keys u64[S] | sort idx i32[S]
 constexpr int kApproxLds = 16384;
 
 __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     const float *__restrict__ kapprox, const float *__restrict__ Q, int D,
     const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, int T,
-    const int32_t *qlist, int P, int S, double *__restrict__ lkey, int32_t *__restrict__ lidx,
+    const int32_t *qlist, int P, int S, int stage_ka, double *__restrict__ lkey, int32_t *__restrict__ lidx,
     const int32_t *__restrict__ pstat, unsigned long long *stats)
 {
     if (pstat && pstat[(int64_t)blockIdx.x * 2 + blockIdx.y] == 0) return;  // done by the wave select
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     const float cmax = half ? cmax2 : cmax1;
     // kapprox null: no approximate keys, straight to the exact radix select
     const bool have_ka = kapprox != nullptr;
-    const bool lds_ka = have_ka && T <= kApproxLds;
+    const bool lds_ka = have_ka && stage_ka;  // key row staged in LDS (decided by the launcher)
     float *qh = reinterpret_cast<float *>(smem);
     const int hpad = (h + 3) & ~3;
     float *kal = qh + hpad;
@@ -742,10 +742,11 @@ int select_sort_size(int P, int T)
     return S < 64 ? 64 : S;
 }
 
-size_t select_lds_bytes(int D, int T, int S)
+// Dynamic LDS of the workgroup select, with or without the staged key row.
+size_t select_lds_bytes(int D, int T, int S, bool stage_ka)
 {
     const int h = D / 2;
-    const size_t f = (size_t)((h + 3) & ~3) + (T <= kApproxLds ? (size_t)((T + 1) & ~1) : 0);
+    const size_t f = (size_t)((h + 3) & ~3) + (stage_ka ? (size_t)((T + 1) & ~1) : 0);
     return f * 4 + (size_t)S * (sizeof(uint64_t) + sizeof(int32_t));
 }
 
@@ -776,9 +777,14 @@ hipError_t launch_prefix_block(const DevIndex &ix, const float *q, const float *
 {
     if (nslots == 0) return hipSuccess;
     const int S = select_sort_size(P, ix.T);
-    const size_t lds = select_lds_bytes(ix.D, ix.T, S);
+    // stage the key row in LDS when it and the sort buffer fit (static LDS of
+    // the kernel is about 6 KB; the device offers 160 KB per workgroup)
+    const bool stage = ka && ix.T <= kApproxLds && select_lds_bytes(ix.D, ix.T, S, true) <= 144 * 1024;
+    const size_t lds = select_lds_bytes(ix.D, ix.T, S, stage);
+    if (lds > 144 * 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_select_prefix, dim3((unsigned)nslots, 2), dim3(kSelThreads), lds, st, ka,
-                       q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist, P, S, lkey, lidx, pstat, stats);
+                       q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist, P, S, stage ? 1 : 0, lkey, lidx,
+                       pstat, stats);
     return hipGetLastError();
 }
 

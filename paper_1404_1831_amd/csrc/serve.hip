@@ -13,6 +13,7 @@
 #include <condition_variable>
 #include <deque>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -56,6 +57,7 @@ struct fbpq_server {
     std::deque<Done> done;
     bool stop = false;
     int64_t batches = 0, batched = 0;
+    std::string last_err;  // message of the first failed batch
 };
 
 namespace {
@@ -97,10 +99,12 @@ void worker(fbpq_server *s, fbpq_index *lane)
         const double t_done = now_s();
         {
             std::lock_guard<std::mutex> lk(s->mu);
+            if (rc && s->last_err.empty()) s->last_err = fbpq_last_error();
             for (int64_t i = 0; i < n; ++i) {
                 Done r;
                 r.tag = batch[i].tag;
-                r.rc = rc;
+                // CAPACITY marks only the rows it could not serve
+                r.rc = rc == FBPQ_E_CAPACITY ? (ids[i * s->k_max] == -2 ? rc : FBPQ_OK) : rc;
                 r.t_submit = batch[i].t_submit;
                 r.t_start = t_start;
                 r.t_done = t_done;
@@ -192,6 +196,15 @@ int fbpq_server_counts(fbpq_server *s, int64_t *pending, int64_t *batches, int64
     *batches = s->batches;
     *batched = s->batched;
     return FBPQ_OK;
+}
+
+const char *fbpq_server_first_error(fbpq_server *s)
+{
+    if (!s) return "";
+    std::lock_guard<std::mutex> lk(s->mu);
+    thread_local std::string copy;
+    copy = s->last_err;
+    return copy.c_str();
 }
 
 void fbpq_server_destroy(fbpq_server *s)

@@ -32,7 +32,7 @@ EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbp
            "fbpq_debug_dists", "fbpq_debug_tables", "fbpq_debug_rank", "fbpq_info",
            "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_stats_read", "fbpq_autotune",
            "fbpq_free_index", "fbpq_last_error", "fbpq_server_create", "fbpq_server_submit",
-           "fbpq_server_poll", "fbpq_server_counts", "fbpq_server_destroy")
+           "fbpq_server_poll", "fbpq_server_counts", "fbpq_server_first_error", "fbpq_server_destroy")
 STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2")
 STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried", "graph_replays")
 
@@ -85,6 +85,7 @@ def _load():
         "fbpq_server_submit": ([P, P, i64, i32, i64], ctypes.c_int),
         "fbpq_server_poll": ([P, i32, ctypes.c_double, P, P, P, P, P, P], ctypes.c_int),
         "fbpq_server_counts": ([P, P, P, P], ctypes.c_int),
+        "fbpq_server_first_error": ([P], ctypes.c_char_p),
         "fbpq_server_destroy": ([P], None),
         "fbpq_last_error": ([], ctypes.c_char_p),
     }
@@ -292,6 +293,10 @@ def fbpq_server_counts(s):
     p, b, n = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(lib.fbpq_server_counts(s, ctypes.byref(p), ctypes.byref(b), ctypes.byref(n)))
     return p.value, b.value, n.value
+
+
+def fbpq_server_first_error(s) -> str:
+    return lib.fbpq_server_first_error(s).decode()
 
 
 def fbpq_server_destroy(s) -> None:
