@@ -110,7 +110,7 @@ int fbpq_build_tables(fbpq_index *ix);
  * 1 <= k <= FBPQ_K_MAX; writes host ids [nq][k] and dists [nq][k].
  * nq == 0 is a no-op. Errors: INVALID, STATE, CAPACITY, OOM, DEVICE.
  * CAPACITY (for every search entry point): some queries need more than the
- * traversal supports (2048 ranks of a half list, or 2^26 visited cells);
+ * traversal supports (4096 ranks of a half list, or 2^26 visited cells);
  * their rows hold id -2 and NaN distances, every other row is complete. */
 int fbpq_search(fbpq_index *ix, const float *q, int64_t nq, int64_t L, int32_t k,
                 int64_t *ids, float *dists);
@@ -171,7 +171,10 @@ int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int
  * two-pass scan), "profile" (0/1: time kernel launches with HIP events,
  * read with fbpq_profile_read), "profile_mask" (bit s set: stage s is timed
  * while profiling is on; default all), "stats" (0/1: path counters, read
- * with fbpq_stats_read), "graph" (0/1: the first traversal round of a search
+ * with fbpq_stats_read), "pop_budget" (cells the traversal visits one at a
+ * time before it switches to threshold steps, which load the point counts of
+ * many cells at once; 0 switches at once; default 512; the visited cells are
+ * the same either way), "graph" (0/1: the first traversal round of a search
  * is captured once into a HIP graph and replayed on later searches with the
  * same queries buffer, result buffers, nq, k_max, min(L, N) and options;
  * retry rounds and profiled or debug searches run eagerly). Errors: INVALID,
@@ -189,7 +192,8 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 #define FBPQ_STAGE_SCORE 6     /* cell scan: FP32 distance of every candidate */
 #define FBPQ_STAGE_SELECT 7    /* per-query k smallest of the scored candidates */
 #define FBPQ_STAGE_SCAN2 8     /* two-pass scan (queries whose cells hold few points) */
-#define FBPQ_NUM_STAGES 9
+#define FBPQ_STAGE_TRAVERSE_WIDE 9 /* threshold-stepping traversal (queries with many visited cells) */
+#define FBPQ_NUM_STAGES 10
 
 /* ---- served form: continuous batching (Section 4 measures per-query time;
  * a server keeps the GPU busy with overlapping batches of arriving queries) --
@@ -245,7 +249,8 @@ int fbpq_autotune(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L
 #define FBPQ_STAT_PREFIX_WG 4   /* (query, half) prefixes finished by the workgroup select */
 #define FBPQ_STAT_RETRIED 5     /* queries traversed again with a longer prefix or more cells */
 #define FBPQ_STAT_GRAPH_REPLAYS 6 /* searches whose first round was a replayed graph */
-#define FBPQ_NUM_STATS 7
+#define FBPQ_STAT_WIDE 7        /* queries traversed by threshold steps */
+#define FBPQ_NUM_STATS 8
 int fbpq_stats_read(fbpq_index *ix, int64_t *out, int32_t n, int32_t reset);
 
 /* Device time per kernel stage, measured with HIP events recorded on the

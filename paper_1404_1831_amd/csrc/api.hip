@@ -54,8 +54,10 @@ struct fbpq_index {
     uint32_t *ids = nullptr;
     float *CR1 = nullptr, *CR2 = nullptr, *nR = nullptr, *nC1 = nullptr, *nC2 = nullptr;
     size_t base_bytes = 0, table_bytes = 0;
-    // workspace, grown on demand
-    DevBuf ws[40];
+    // workspace, grown on demand: slots [0, 40) for the first round of a
+    // search (the round a graph captures), [40, 80) for its retry rounds
+    DevBuf ws[80];
+    int ws_base = 0;
     void *pinned = nullptr;
     size_t pinned_cap = 0;
     // profiler: events recorded around launches while `profile` is on
@@ -74,6 +76,7 @@ struct fbpq_index {
     int64_t max_cells = 4096;
     int32_t chunk = 8192;
     bool items = true;
+    int32_t pop_budget = 512;  // cells popped one at a time before the threshold kernel takes over
     // path counters (option "stats")
     unsigned long long *stats_dev = nullptr;
     int64_t stat_retried = 0;
@@ -86,14 +89,14 @@ struct fbpq_index {
         int64_t nq, lcap, max_cells, ws_gen;
         int64_t *d_ids;
         float *d_d;
-        int32_t k_max, P, chunk;
+        int32_t k_max, P, chunk, pop_budget;
         bool items;
         unsigned long long *stats;
         bool operator==(const GraphKey &o) const
         {
             return d_q == o.d_q && nq == o.nq && lcap == o.lcap && max_cells == o.max_cells &&
                    ws_gen == o.ws_gen && d_ids == o.d_ids && d_d == o.d_d && k_max == o.k_max && P == o.P &&
-                   chunk == o.chunk && items == o.items && stats == o.stats;
+                   chunk == o.chunk && pop_budget == o.pop_budget && items == o.items && stats == o.stats;
         }
     } gkey{};
     int64_t graph_replays = 0;
@@ -107,6 +110,8 @@ enum WsSlot {
     W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NESLOT, W_SLOTIJ, W_COUNTER,
     W_LQ, W_ITEMN, W_PSTAT, W_SELDONE, W_NSLOTS
 };
+constexpr int kWsSet = 40;  // slots per workspace set
+static_assert(W_NSLOTS <= kWsSet, "workspace slots");
 
 #define HCK(ix, expr)                                                                           \
     do {                                                                                        \
@@ -119,7 +124,7 @@ enum WsSlot {
 
 int ws_get(fbpq_index *ix, int slot, size_t bytes, void **out)
 {
-    DevBuf &b = ix->ws[slot];
+    DevBuf &b = ix->ws[slot + ix->ws_base];
     if (bytes == 0) bytes = 8;
     if (b.cap < bytes) {
         if (b.p) {
@@ -129,7 +134,7 @@ int ws_get(fbpq_index *ix, int slot, size_t bytes, void **out)
             b.cap = 0;
         }
         const size_t nb = std::max(bytes, b.cap + b.cap / 2);
-        if (slot != W_QLIST) ++ix->ws_gen;  // the query list is read only by retry rounds, never captured
+        if (ix->ws_base == 0) ++ix->ws_gen;  // a buffer a captured round may use moved
         hipError_t e = hipMalloc(&b.p, nb);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -565,7 +570,14 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
     ta.dbg_ab = (int32_t *)dab;
     ta.dbg_take = (int64_t *)dtake;
     ta.dbg_beg = (int64_t *)dbeg;
-    HCK(ix, timed(ix, FBPQ_STAGE_TRAVERSE, st, [&] { return launch_traverse(ta, nslots, st); }));
+    ta.stats = ix->stats_dev;
+    // one cell at a time while the prefix fits its registers, then (for the
+    // queries it leaves over, or all of them) the threshold-stepping kernel
+    const bool pop = P <= kMaxPopPrefix && ix->pop_budget > 0;
+    ta.pop_budget = pop ? ix->pop_budget : 0;
+    ta.wide_all = pop ? 0 : 1;
+    if (pop) HCK(ix, timed(ix, FBPQ_STAGE_TRAVERSE, st, [&] { return launch_traverse(ta, nslots, st); }));
+    HCK(ix, timed(ix, FBPQ_STAGE_TRAVERSE_WIDE, st, [&] { return launch_traverse_wide(ta, nslots, st); }));
     if (!(dbg && dbg->visit)) {
         LayoutArgs la{};
         la.ix = dv;
@@ -767,7 +779,8 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     // first round: replay the captured graph when the launch sequence is the
     // same, else run it eagerly (and capture it for the next call)
     const bool use_graph = ix->graph && !dbg && !ix->profile;
-    fbpq_index::GraphKey key{d_q, nq, lcap, max_cells, ix->ws_gen, d_ids, d_d, k_max, P, ix->chunk, ix->items,
+    fbpq_index::GraphKey key{d_q, nq, lcap, max_cells, ix->ws_gen, d_ids, d_d, k_max, P, ix->chunk, ix->pop_budget,
+                             ix->items,
                              ix->stats_dev};
     if (use_graph && ix->gexec && ix->gkey == key) {
         HCK(ix, hipGraphLaunch(ix->gexec, st));
@@ -814,14 +827,23 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     const int64_t ccap = ((int64_t)1 << 31) / 32;
     std::vector<int32_t> cur;  // query of each slot of the last round (empty: slot = query)
     int64_t nterminal = 0;
+    // retry rounds take their buffers from the second workspace set, so that
+    // they never move a buffer of the first round (and of its graph)
+    struct WsBaseReset {
+        fbpq_index *ix;
+        ~WsBaseReset() { ix->ws_base = 0; }
+    } ws_reset{ix};
     for (int round = 1; nfail > 0; ++round) {
         ix->stat_retried += nfail;
         std::vector<TravHdr> hh(nslots);
-        HCK(ix, hipMemcpy(hh.data(), ix->ws[W_HDR].p, sizeof(TravHdr) * nslots, hipMemcpyDeviceToHost));
+        HCK(ix, hipMemcpy(hh.data(), ix->ws[W_HDR + ix->ws_base].p, sizeof(TravHdr) * nslots,
+                          hipMemcpyDeviceToHost));
         std::vector<int32_t> retry, terminal;
         bool grow_p = false, grow_c = false;
+        int64_t need_cells = 0;  // cells a failed query is known to need (threshold kernel)
         for (int64_t sl = 0; sl < nslots; ++sl) {
             const int32_t q = cur.empty() ? (int32_t)sl : cur[sl];
+            if (hh[sl].status != kStOk) need_cells = std::max(need_cells, hh[sl].ncells);
             if (hh[sl].status == kStNeedPrefix) {
                 if (P >= Pcap) terminal.push_back(q);
                 else {
@@ -850,7 +872,14 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
         nterminal += (int64_t)terminal.size();
         if (grow_p) P = std::min<int32_t>(Pcap, P * 4);
         if (grow_c) max_cells = std::min<int64_t>(ccap, max_cells * 8);
+        if (need_cells > max_cells) {
+            // the next power of two: few distinct buffer sizes across batches
+            int64_t c = max_cells;
+            while (c < need_cells) c *= 2;
+            max_cells = std::min<int64_t>(ccap, c);
+        }
         if (retry.empty()) break;
+        ix->ws_base = kWsSet;
         void *ql;
         TRY(ws_get(ix, W_QLIST, sizeof(int32_t) * retry.size(), &ql));
         HCK(ix, hipMemcpy(ql, retry.data(), sizeof(int32_t) * retry.size(), hipMemcpyHostToDevice));
@@ -907,6 +936,7 @@ int lane_create(fbpq_index *src, fbpq_index **out)
     ix->max_cells = src->max_cells;
     ix->chunk = src->chunk;
     ix->items = src->items;
+    ix->pop_budget = src->pop_budget;
     *out = ix;
     return FBPQ_OK;
 }
@@ -1180,6 +1210,9 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
             (void)hipFree(ix->stats_dev);
             ix->stats_dev = nullptr;
         }
+    } else if (!strcmp(key, "pop_budget")) {
+        if (value < 0 || value > ((int64_t)1 << 26)) return fail(FBPQ_E_INVALID, "pop_budget out of range");
+        ix->pop_budget = (int32_t)value;
     } else if (!strcmp(key, "chunk")) {
         if (value < 256 || value > (1 << 16)) return fail(FBPQ_E_INVALID, "chunk out of range");
         ix->chunk = (int32_t)value;

@@ -10,11 +10,14 @@ namespace fbpq {
 
 constexpr int kWave = 64;
 constexpr int kKc = 256;
-constexpr int kMaxPrefix = 2048;  // longest sorted half list the traversal tracks
+constexpr int kMaxPrefix = 4096;  // longest sorted half list the traversal tracks
+constexpr int kMaxPopPrefix = 2048;  // longest one the one-cell-at-a-time traversal holds
 constexpr int kMaxK = 1024;
 
 // Per-query traversal status written by the traversal kernel.
-enum : int32_t { kStOk = 0, kStNeedPrefix = 1, kStNeedCells = 2 };
+// kStDefer: the one-cell-at-a-time kernel used up its pop budget and leaves
+// the query to the threshold-stepping kernel (never seen by the host).
+enum : int32_t { kStOk = 0, kStNeedPrefix = 1, kStNeedCells = 2, kStDefer = 3 };
 
 // Per-query traversal summary (one record per workspace slot).
 struct TravHdr {
@@ -35,6 +38,7 @@ struct TravHdr {
 
 // Path counters (slots of FBPQ_STAT_*), incremented when the pointer is set.
 constexpr int kStatCellScan = 0, kStatFused = 1, kStatTwoPass = 2, kStatPrefixWave = 3, kStatPrefixWG = 4;
+constexpr int kStatWide = 7;
 constexpr int kNumStatSlots = 8;
 
 // Candidate block of the cell scan: up to kItem candidates of one nonempty cell.
@@ -98,8 +102,13 @@ struct TravArgs {
     int32_t *dbg_ab;       // optional [slot][max_cells][2] visited (a, b) in order
     int64_t *dbg_take;     // optional [slot][max_cells] points taken
     int64_t *dbg_beg;      // optional [slot][max_cells] storage begin of the cell
+    int32_t pop_budget;    // pops before a query is left to the threshold kernel (0: none)
+    int32_t wide_all;      // threshold kernel: take every slot, not only deferred ones
+    unsigned long long *stats;  // optional path counters
 };
 hipError_t launch_traverse(const TravArgs &a, int64_t nslots, hipStream_t st);
+hipError_t launch_traverse_wide(const TravArgs &a, int64_t nslots, hipStream_t st);
+size_t wide_lds_bytes(int P);
 
 struct LayoutArgs {
     DevIndex ix;

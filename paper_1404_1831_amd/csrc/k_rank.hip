@@ -737,7 +737,10 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
 int select_sort_size(int P, int T)
 {
     int S = 1;
-    const int need = P >= T ? T : (4 * P < T ? 4 * P : T);
+    // room for 4P survivors of the approximate threshold (2P beyond 2048 ranks,
+    // so that the buffer stays within LDS); more survivors take the exact select
+    const int want = P <= 2048 ? 4 * P : 2 * P;
+    const int need = P >= T ? T : (want < T ? want : T);
     while (S < need) S <<= 1;
     return S < 64 ? 64 : S;
 }

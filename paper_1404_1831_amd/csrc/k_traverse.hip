@@ -14,6 +14,9 @@
 // at the cell that completes min(L, N) points (that cell is truncated in
 // storage order, pops after it are undone).
 //
+// A query still unfinished after pop_budget cells is marked kStDefer and left
+// to the threshold-stepping kernel, which starts it again from the first cell.
+//
 // Only the first P ranks of each half list are known. A cell outside the
 // P x P window has key >= min(k1[P-1] + k2[0], k1[0] + k2[P-1]); the query is
 // flagged for a longer prefix when the next pop reaches that bound.
@@ -65,6 +68,10 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs args)
     bool done = Leff <= 0;
     int bsz = 16;  // pops per batch: 16 first (most queries end there), then 64
     while (!done) {
+        if (args.pop_budget > 0 && ncells >= args.pop_budget) {
+            status = kStDefer;  // large visited set: the threshold kernel takes over
+            break;
+        }
         pa = -1;
         pb = -1;
         int nb = 0;
@@ -215,7 +222,7 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs args)
             h.ncand = 0;
         }
         args.hdr[slot] = h;
-        if (status != kStOk) args.fail_list[atomicAdd(args.fail_count, 1)] = (int32_t)qs;
+        if (status != kStOk && status != kStDefer) args.fail_list[atomicAdd(args.fail_count, 1)] = (int32_t)qs;
     }
 }
 

@@ -1,0 +1,616 @@
+// Threshold-stepping form of the multi-sequence traversal (Section 2.3.3), for
+// queries whose visited set is too large to pop one cell at a time.
+//
+// Cells are visited in ascending (key, a, b), key = fl64(k1[a] + k2[b]) over
+// the rank pairs of the two sorted half lists. For a threshold t, the cells
+// with key <= t form a Young diagram: row a holds the first w_t(a) cells,
+// found by one binary search per row because keys grow along every row and
+// column. The visited prefix is therefore grown in bands: pick t_new > t, load
+// the point counts of the cells with t < key <= t_new in parallel, and accept
+// the band while the running total stays below min(L, N). The band that
+// reaches min(L, N) is sorted by (key, a, b) and cut at the cell that
+// completes the count. This gives exactly the cells, order and truncated last
+// cell of the one-at-a-time traversal.
+//
+// Band sizes. A first band of a few hundred cells measures the points per
+// cell. Later bands aim at part of the cells still expected, and only their
+// counts are summed. The band expected to hold the cut has at most kWCap
+// cells, so that it fits in LDS for the sort. A summed band that overshoots
+// is dropped and a smaller one is taken. A band whose cells all share one key
+// (t and t_new adjacent doubles) is already in (a, b) order; it is walked in
+// chunks of kWCap cells.
+//
+// One workgroup per query; thread t owns rows a = t + NT r (r < kWRows).
+// Queries whose visited set exceeds the cell capacity keep counting (without
+// writing cells) so that the header reports the capacity they need.
+#include "fbpq_dev.h"
+
+namespace fbpq {
+
+constexpr int kWRows = 8;      // rows per thread: P <= NT * kWRows
+constexpr int kWCap = 2048;    // cells of a band held in LDS
+constexpr int kWPos = 8;       // band positions per thread per pass
+constexpr int64_t kWHardCells = (int64_t)1 << 26;  // counting past the capacity stops here
+
+// order-preserving map of doubles to unsigned integers, and its inverse
+__device__ __forceinline__ uint64_t dord(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double dunord(uint64_t o)
+{
+    const uint64_t b = (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o;
+    return __longlong_as_double((long long)b);
+}
+
+template <int NT>
+__device__ __forceinline__ int64_t wg_sum(int64_t v, int64_t *red)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t r = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) r += red[i];
+    return r;
+}
+
+template <int NT>
+__device__ __forceinline__ int64_t wg_min(int64_t v, int64_t *red)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t x = __shfl_xor(v, o);
+        v = x < v ? x : v;
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t r = red[0];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) r = red[i] < r ? red[i] : r;
+    return r;
+}
+
+// exclusive prefix of v over the workgroup in thread order; *total gets the sum
+template <int NT>
+__device__ __forceinline__ int64_t wg_scan(int64_t v, int64_t *red, int64_t *total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) red[wv] = x;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        const int64_t t = red[i];
+        before += i < wv ? t : 0;
+        tot += t;
+    }
+    *total = tot;
+    return before + x - v;
+}
+
+// Row widths at threshold t: out[r] = first b in [lo[r], hi[r]) with
+// k1r[r] + k2s[b] > t (hi[r] if none). All rows step together.
+__device__ __forceinline__ void widths_at(double t, const double *k1r, const int *lo0, const int *hi0, int *out,
+                                          const double *k2s)
+{
+    int lo[kWRows], hi[kWRows];
+#pragma unroll
+    for (int r = 0; r < kWRows; ++r) {
+        lo[r] = lo0[r];
+        hi[r] = hi0[r];
+    }
+    bool any = true;
+    while (any) {
+        any = false;
+#pragma unroll
+        for (int r = 0; r < kWRows; ++r) {
+            if (lo[r] < hi[r]) {
+                const int mid = (lo[r] + hi[r]) >> 1;
+                if (k1r[r] + k2s[mid] <= t) lo[r] = mid + 1;
+                else hi[r] = mid;
+                any |= lo[r] < hi[r];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kWRows; ++r) out[r] = lo[r];
+}
+
+// (a, b) of band positions xs[e] (rowpre: exclusive prefix of the row lengths,
+// wsh: first band column of each row). Positions must be < rowpre[P].
+__device__ __forceinline__ void locate(const int *xs, int n, const int *rowpre, const int *wsh, int P, int *as,
+                                       int *bs)
+{
+    int lo[kWPos], hi[kWPos];
+#pragma unroll
+    for (int e = 0; e < kWPos; ++e) {
+        lo[e] = 0;
+        hi[e] = e < n ? P - 1 : 0;
+    }
+    bool any = true;
+    while (any) {
+        any = false;
+#pragma unroll
+        for (int e = 0; e < kWPos; ++e) {
+            if (lo[e] < hi[e]) {
+                const int mid = (lo[e] + hi[e] + 1) >> 1;
+                if (rowpre[mid] <= xs[e]) lo[e] = mid;
+                else hi[e] = mid - 1;
+                any |= lo[e] < hi[e];
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < kWPos; ++e) {
+        as[e] = lo[e];
+        bs[e] = e < n ? wsh[lo[e]] + (xs[e] - rowpre[lo[e]]) : 0;
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_traverse_wide(TravArgs args)
+{
+    constexpr int R = kWRows;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int64_t red[NT / 64];
+    __shared__ int64_t s_cut[4];
+    const int P = args.P;
+    const int slot = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (!args.wide_all && args.hdr[slot].status != kStDefer) return;
+    double *k2s = reinterpret_cast<double *>(smem);                 // [P]
+    double *bkey = k2s + P;                                         // [kWCap]
+    int64_t *bcnt = reinterpret_cast<int64_t *>(bkey + kWCap);      // [kWCap]
+    int *wsh = reinterpret_cast<int *>(bcnt + kWCap);               // [P]
+    int *rowpre = wsh + P;                                          // [P + 1]
+    uint32_t *bab = reinterpret_cast<uint32_t *>(rowpre + P + 1);   // [kWCap]
+
+    const int64_t qs = args.qlist ? args.qlist[slot] : slot;
+    const int T = args.ix.T;
+    const double *k1 = args.lkey + (int64_t)slot * 2 * P;
+    const double *k2 = k1 + P;
+    const int32_t *u = args.lidx + (int64_t)slot * 2 * P;
+    const int32_t *v = u + P;
+    const int64_t *off = args.ix.offsets;
+    for (int i = tid; i < P; i += NT) k2s[i] = k2[i];
+    if (args.stats && tid == 0) atomicAdd(&args.stats[kStatWide], 1ull);
+    __syncthreads();
+
+    const int64_t L = args.L[qs];
+    const int64_t Leff = L < args.ix.N ? L : args.ix.N;
+    const bool full = P >= T;
+    const double INF = __builtin_huge_val();
+    const double DMAX = 1.7976931348623157e308;
+    // every visited cell has key <= tmax: below the smallest key outside the
+    // P x P window, or the largest key when the lists are complete
+    double tmax;
+    if (full) {
+        tmax = k1[P - 1] + k2s[P - 1];
+    } else {
+        const double kb = fmin(k1[P - 1] + k2s[0], k1[0] + k2s[P - 1]);
+        tmax = dunord(dord(kb) - 1);
+    }
+    if (!(tmax < INF)) tmax = DMAX;
+
+    double k1r[R];
+    int w[R], wmax[R], wn[R];
+    {
+        int zero[R], top[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int a = tid + NT * r;
+            k1r[r] = a < P ? k1[a] : INF;
+            w[r] = 0;
+            zero[r] = 0;
+            top[r] = a < P ? P : 0;
+        }
+        widths_at(tmax, k1r, zero, top, wmax, k2s);
+    }
+    int64_t my = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) my += wmax[r];
+    const int64_t navail = wg_sum<NT>(my, red);
+
+    int64_t tot = 0, nc = 0;
+    double tcur = dunord(dord(k1[0] + k2s[0]) - 1);  // below every key: nothing visited
+    double rho = -1.0;                               // points per cell of the last band
+    int status = kStOk;
+    bool done = Leff <= 0;
+    bool over = false;  // visited cells exceed the capacity: count only
+    int cut_a = -1, cut_b = -1;
+    int64_t cut_take = 0;
+    const bool dbg = args.dbg_ab != nullptr;
+
+    while (!done) {
+        const int64_t need = Leff - tot;
+        const int64_t rem = navail - nc;
+        if (rem <= 0) {
+            status = kStNeedPrefix;
+            break;
+        }
+        if (nc > kWHardCells) break;  // over the capacity by far: report what was counted
+        // band size window [lo_t, hi_t]
+        const double est = rho > 0.0 ? (double)need / rho : 384.0;
+        const double e125 = est * 1.25 + 32.0;
+        bool store;
+        int64_t lo_t, hi_t;
+        if (dbg || e125 <= (double)kWCap) {
+            store = true;
+            lo_t = (int64_t)fmin(e125, 0.75 * kWCap);
+            hi_t = lo_t * 2 < kWCap ? lo_t * 2 : kWCap;
+        } else {
+            store = false;
+            const double e = fmin(est, 4.0e15);
+            lo_t = (int64_t)(0.6 * e);
+            hi_t = (int64_t)(0.85 * e);
+        }
+        if (!over) {
+            const int64_t room = args.max_cells - nc + 1;  // a band this large fails the capacity
+            if (room >= 1 && hi_t > room) hi_t = room;
+        }
+        if (lo_t > hi_t) lo_t = hi_t;
+        if (lo_t < 1) lo_t = 1;
+        if (hi_t < 1) hi_t = 1;
+
+        // choose the band (tcur, tnew]
+        double tnew;
+        int64_t nb;
+        bool tie = false;
+        if (rem <= hi_t) {
+            tnew = tmax;
+#pragma unroll
+            for (int r = 0; r < R; ++r) wn[r] = wmax[r];
+            nb = rem;
+        } else {
+            double tl = tcur, th = tmax;
+            int64_t cl = 0, ch = rem;
+            int wl[R], wh[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                wl[r] = w[r];
+                wh[r] = wmax[r];
+            }
+            const double tgt = 0.5 * (double)(lo_t + hi_t);
+            double fl = -tgt, fh = (double)ch - tgt;
+            int side = 0;
+            bool found = false;
+            // regula falsi (Illinois) on the band size, every fourth step a
+            // bisection of the bit range, so that tl and th meet within 256 steps
+            for (int it = 0; it < 260; ++it) {
+                const uint64_t ol = dord(tl), oh = dord(th);
+                if (oh - ol <= 1) break;
+                double tm = tl + (th - tl) * (-fl / (fh - fl));
+                if ((it & 3) == 3 || !(tm > tl) || !(tm < th)) tm = dunord(ol + (oh - ol) / 2);
+                int wm[R];
+                widths_at(tm, k1r, wl, wh, wm, k2s);
+                int64_t m2 = 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) m2 += wm[r] - w[r];
+                const int64_t cm = wg_sum<NT>(m2, red);
+                if (cm < lo_t) {
+                    tl = tm;
+                    cl = cm;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) wl[r] = wm[r];
+                    fl = (double)cm - tgt;
+                    if (side < 0) fh *= 0.5;
+                    side = -1;
+                } else if (cm > hi_t) {
+                    th = tm;
+                    ch = cm;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) wh[r] = wm[r];
+                    fh = (double)cm - tgt;
+                    if (side > 0) fl *= 0.5;
+                    side = 1;
+                } else {
+                    tnew = tm;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) wn[r] = wm[r];
+                    nb = cm;
+                    found = true;
+                    break;
+                }
+            }
+            if (!found) {
+                if (cl > 0) {
+                    tnew = tl;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) wn[r] = wl[r];
+                    nb = cl;
+                } else {
+                    tnew = th;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) wn[r] = wh[r];
+                    nb = ch;
+                    tie = dord(th) - dord(tl) <= 1;  // every band cell has key th
+                }
+            }
+        }
+
+        // band layout: row a holds columns [wsh[a], wsh[a] + len(a)); rowpre is
+        // the exclusive prefix of the lengths
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int a = tid + NT * r;
+            if (a < P) {
+                wsh[a] = w[r];
+                rowpre[a] = wn[r] - w[r];
+            }
+        }
+        __syncthreads();
+        {
+            int loc[R];
+            int64_t s = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int a = tid * R + r;
+                loc[r] = a < P ? rowpre[a] : 0;
+                s += loc[r];
+            }
+            int64_t tl;
+            int64_t run = wg_scan<NT>(s, red, &tl);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int a = tid * R + r;
+                if (a < P) rowpre[a] = (int)run;
+                run += loc[r];
+            }
+            if (tid == 0) rowpre[P] = (int)tl;
+        }
+        __syncthreads();
+
+        if (nb > kWCap && !tie) {
+            // summed band: accept it if it stays below min(L, N), else retry smaller
+            int64_t s = 0;
+            for (int64_t x0 = 0; x0 < nb; x0 += (int64_t)NT * kWPos) {
+                int xs[kWPos], as[kWPos], bs[kWPos];
+                int n = 0;
+#pragma unroll
+                for (int e = 0; e < kWPos; ++e) {
+                    const int64_t x = x0 + tid + (int64_t)NT * e;
+                    xs[e] = (int)x;
+                    n += x < nb;
+                }
+                locate(xs, n, rowpre, wsh, P, as, bs);
+#pragma unroll
+                for (int e = 0; e < kWPos; ++e) {
+                    if (e < n) {
+                        const int64_t c = (int64_t)u[as[e]] * T + v[bs[e]];
+                        s += off[c + 1] - off[c];
+                    }
+                }
+            }
+            s = wg_sum<NT>(s, red);
+            rho = fmax((double)s, 0.5) / (double)nb;
+            if (tot + s < Leff) {
+                tot += s;
+                nc += nb;
+                tcur = tnew;
+#pragma unroll
+                for (int r = 0; r < R; ++r) w[r] = wn[r];
+                if (nc > args.max_cells) over = true;
+            }
+            continue;
+        }
+
+        // stored band (nb <= kWCap), or an equal-key band in (a, b) order
+        const int64_t nc0 = nc;
+        int64_t bsum = 0;
+        for (int64_t x0 = 0; x0 < nb && !done; x0 += kWCap) {
+            const int n = (int)(nb - x0 < kWCap ? nb - x0 : kWCap);
+            int npad = 64;
+            while (npad < n) npad <<= 1;
+            int64_t s = 0;
+            for (int i0 = 0; i0 < npad; i0 += NT * kWPos) {
+                int xs[kWPos], as[kWPos], bs[kWPos];
+                int nv = 0;
+#pragma unroll
+                for (int e = 0; e < kWPos; ++e) {
+                    const int i = i0 + tid + NT * e;
+                    xs[e] = (int)(x0 + i);
+                    nv += i < n;
+                }
+                locate(xs, nv, rowpre, wsh, P, as, bs);
+#pragma unroll
+                for (int e = 0; e < kWPos; ++e) {
+                    const int i = i0 + tid + NT * e;
+                    if (i < n) {
+                        const int64_t c = (int64_t)u[as[e]] * T + v[bs[e]];
+                        const int64_t cnt = off[c + 1] - off[c];
+                        bkey[i] = k1[as[e]] + k2s[bs[e]];
+                        bab[i] = ((uint32_t)as[e] << 16) | (uint32_t)bs[e];
+                        bcnt[i] = cnt;
+                        s += cnt;
+                    } else if (i < npad) {
+                        bkey[i] = INF;
+                        bab[i] = 0xffffffffu;
+                        bcnt[i] = 0;
+                    }
+                }
+            }
+            s = wg_sum<NT>(s, red);  // its barriers also publish the LDS writes
+            const bool hit = tot + s >= Leff;
+            if (hit || dbg) {
+                if (!tie) {
+                    // bitonic sort of [0, npad) by (key, a, b)
+                    for (int kk = 2; kk <= npad; kk <<= 1) {
+                        for (int j = kk >> 1; j > 0; j >>= 1) {
+                            for (int i = tid; i < npad / 2; i += NT) {
+                                const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                                const int hi = lo + j;
+                                const double ka = bkey[lo], kb = bkey[hi];
+                                const uint32_t aa = bab[lo], ab = bab[hi];
+                                const bool gt = ka > kb || (ka == kb && aa > ab);
+                                if (gt == ((lo & kk) == 0)) {
+                                    bkey[lo] = kb;
+                                    bkey[hi] = ka;
+                                    bab[lo] = ab;
+                                    bab[hi] = aa;
+                                    const int64_t t = bcnt[lo];
+                                    bcnt[lo] = bcnt[hi];
+                                    bcnt[hi] = t;
+                                }
+                            }
+                            __syncthreads();
+                        }
+                    }
+                }
+                // running totals in sorted order; first entry that reaches min(L, N)
+                const int EP = (npad + NT - 1) / NT;
+                const int i0 = tid * EP, i1 = i0 + EP < n ? i0 + EP : n;
+                int64_t ls = 0;
+                for (int i = i0; i < i1; ++i) ls += bcnt[i];
+                int64_t ctot;
+                const int64_t ex = wg_scan<NT>(ls, red, &ctot);
+                int64_t run = tot + ex;
+                int64_t jmine = INT64_MAX, take_mine = 0;
+                for (int i = i0; i < i1; ++i) {
+                    const int64_t c = bcnt[i];
+                    if (hit && jmine == INT64_MAX && run + c >= Leff) {
+                        jmine = i;
+                        take_mine = Leff - run;  // points taken if this is the cut cell
+                    }
+                    run += c;
+                }
+                const int64_t j = hit ? wg_min<NT>(jmine, red) : INT64_MAX;
+                if (hit && jmine == j) s_cut[1] = take_mine;  // one thread owns entry j
+                const int nkeep = hit ? (int)j + 1 : n;
+                if (dbg && !over) {
+                    int64_t r2 = tot + ex;
+                    for (int i = i0; i < i1 && i < nkeep; ++i) {
+                        const int64_t o = nc0 + x0 + i;
+                        const int64_t c = bcnt[i];
+                        if (o < args.max_cells) {
+                            const int a = (int)(bab[i] >> 16), b = (int)(bab[i] & 0xffffu);
+                            const int64_t cell = (int64_t)u[a] * T + v[b];
+                            const int64_t so = (int64_t)slot * args.max_cells + o;
+                            args.dbg_ab[2 * so] = a;
+                            args.dbg_ab[2 * so + 1] = b;
+                            args.dbg_take[so] = i == j ? Leff - r2 : c;
+                            args.dbg_beg[so] = off[cell];
+                        }
+                        r2 += c;
+                    }
+                }
+                if (hit) {
+                    __syncthreads();
+                    const uint32_t abj = bab[j];
+                    cut_a = (int)(abj >> 16);
+                    cut_b = (int)(abj & 0xffffu);
+                    cut_take = s_cut[1];
+                    // widths: cells of earlier chunks (row-major positions < x0),
+                    // then the kept entries of this chunk, counted per row
+                    int base[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int a = tid + NT * r;
+                        base[r] = 0;
+                        if (a < P) {
+                            const int64_t f = x0 - rowpre[a];
+                            const int len = wn[r] - w[r];
+                            base[r] = f <= 0 ? 0 : (f >= len ? len : (int)f);
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int a = tid + NT * r;
+                        if (a < P) rowpre[a] = 0;
+                    }
+                    __syncthreads();
+                    for (int i = tid; i <= (int)j; i += NT) atomicAdd(&rowpre[bab[i] >> 16], 1);
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int a = tid + NT * r;
+                        if (a < P) w[r] += base[r] + rowpre[a];
+                    }
+                    nc = nc0 + x0 + nkeep;
+                    tot = Leff;
+                    if (nc > args.max_cells) over = true;
+                    done = true;
+                }
+            }
+            if (!done) {
+                tot += s;
+                bsum += s;
+            }
+            __syncthreads();
+        }
+        if (!done) {
+            nc = nc0 + nb;
+            tcur = tnew;
+#pragma unroll
+            for (int r = 0; r < R; ++r) w[r] = wn[r];
+            rho = fmax((double)bsum, 0.5) / (double)nb;
+            if (nc > args.max_cells) over = true;
+        }
+    }
+    if (status == kStOk && (over || !done)) status = kStNeedCells;
+
+    // outputs, as the one-at-a-time kernel writes them
+    int myA = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int a = tid + NT * r;
+        if (a < P) {
+            args.w[(int64_t)slot * P + a] = w[r];
+            myA += w[r] > 0;
+        }
+    }
+    const int64_t A = wg_sum<NT>(myA, red);
+    if (tid == 0) {
+        TravHdr h;
+        h.status = status;
+        h.A = (int32_t)A;
+        h.B = w[0];
+        h.cut_a = cut_a;
+        h.cut_b = cut_b;
+        h.nne = 0;
+        h.a_ne = 0;
+        h.b_ne = 0;
+        h.n_items = 0;
+        h.pad = 0;
+        h.ncells = nc;
+        h.ncand = tot;
+        h.cut_take = cut_take;
+        if (Leff <= 0) {
+            h.A = 0;
+            h.B = 0;
+            h.ncells = 0;
+            h.ncand = 0;
+        }
+        args.hdr[slot] = h;
+        if (status != kStOk) args.fail_list[atomicAdd(args.fail_count, 1)] = (int32_t)qs;
+    }
+}
+
+size_t wide_lds_bytes(int P)
+{
+    return (size_t)P * 8 + (size_t)kWCap * (8 + 8) + (size_t)P * 4 + (size_t)(P + 1) * 4 + (size_t)kWCap * 4;
+}
+
+hipError_t launch_traverse_wide(const TravArgs &a, int64_t nslots, hipStream_t st)
+{
+    if (nslots == 0) return hipSuccess;
+    const size_t lds = wide_lds_bytes(a.P);
+    const dim3 g((unsigned)nslots);
+    if (a.P <= 256 * kWRows) hipLaunchKernelGGL(k_traverse_wide<256>, g, dim3(256), lds, st, a);
+    else if (a.P <= 512 * kWRows) hipLaunchKernelGGL(k_traverse_wide<512>, g, dim3(512), lds, st, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace fbpq

@@ -33,8 +33,10 @@ EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbp
            "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_stats_read", "fbpq_autotune",
            "fbpq_free_index", "fbpq_last_error", "fbpq_server_create", "fbpq_server_submit",
            "fbpq_server_poll", "fbpq_server_counts", "fbpq_server_first_error", "fbpq_server_destroy")
-STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2")
-STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried", "graph_replays")
+STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2",
+          "traverse_wide")
+STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried", "graph_replays",
+         "wide")
 
 
 class FbpqError(RuntimeError):

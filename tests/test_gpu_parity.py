@@ -99,8 +99,8 @@ def test_rank_prefix_ties(fb):
     fb.fbpq_free_index(h)
 
 
-def _check_visit(fb, h, ix, Q, L):
-    cap = min(ix.T * ix.T + 1, 1 << 16)
+def _check_visit(fb, h, ix, Q, L, cap=1 << 16):
+    cap = min(ix.T * ix.T + 1, cap)
     got = fb.fbpq_debug_visit(h, Q, L, cells_cap=cap, pos_cap=max(1, min(L, ix.N)))
     for r in range(Q.shape[0]):
         cells, pos = oracle.visit(ix, Q[r], L)
@@ -356,6 +356,99 @@ def test_search_T1000_visit_and_topk(fb, gmm_wide):
     fb.fbpq_free_index(h)
     o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
     assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
+# ---- threshold-stepping traversal ------------------------------------------------
+# pop_budget=0 sends every query to the threshold kernel, pop_budget=1 defers
+# every query the first batch of pops does not finish.
+
+@pytest.mark.parametrize("budget", [0, 1])
+@pytest.mark.parametrize("L", [1, 777, 10000, 250000])
+def test_visit_threshold_steps_gmm(fb, gmm_small, budget, L):
+    ix, Q = gmm_small
+    log(f"visit by threshold steps: N=1e5 T=64 L={L} pop_budget={budget}")
+    h = _open(fb, ix, pop_budget=budget, stats=1)
+    _check_visit(fb, h, ix, Q[:30], L)
+    if budget == 0:
+        assert fb.fbpq_stats_read(h)["wide"] >= 30
+    fb.fbpq_free_index(h)
+
+
+@pytest.mark.parametrize("budget", [0, 1])
+def test_visit_threshold_steps_retries(fb, gmm_small, budget):
+    ix, Q = gmm_small
+    log(f"visit by threshold steps with prefix=1, max_cells=64, pop_budget={budget}")
+    h = _open(fb, ix, prefix=1, max_cells=64, pop_budget=budget, stats=1)
+    _check_visit(fb, h, ix, Q[:20], 10000)
+    assert fb.fbpq_stats_read(h)["retried"] > 0
+    fb.fbpq_free_index(h)
+
+
+@pytest.mark.parametrize("T,seed", [(2, 1), (3, 2), (8, 3), (16, 4), (40, 5)])
+def test_visit_threshold_steps_ties(fb, T, seed):
+    # integer centroids and queries: many cells share one key
+    rng = np.random.default_rng(200 + seed)
+    counts = rng.integers(0, 5, T * T) * (rng.random(T * T) < 0.5)
+    if counts.sum() == 0:
+        counts[0] = 2
+    ix = synth.tiny_index(T, counts, M=2, D=4, seed=seed)
+    Q = rng.integers(0, 6, (6, 4)).astype(np.float32)
+    log(f"visit tiny by threshold steps: T={T} N={ix.N}")
+    h = _open(fb, ix, pop_budget=0)
+    for L in sorted({1, 2, max(1, ix.N // 2), ix.N, ix.N + 3}):
+        _check_visit(fb, h, ix, Q, L)
+    fb.fbpq_free_index(h)
+
+
+@pytest.mark.parametrize("budget", [0, 1])
+def test_visit_one_key_band_in_chunks(fb, budget):
+    # every centroid of a half is the same point: all 4096 cells share one key,
+    # so the band is walked in (a, b) order in chunks of 2048 cells
+    T = 64
+    rng = np.random.default_rng(77)
+    counts = rng.integers(0, 3, T * T)
+    C1 = np.tile(np.array([[1.0, 2.0]], np.float32), (T, 1))
+    C2 = np.tile(np.array([[0.0, 3.0]], np.float32), (T, 1))
+    ix = synth.tiny_index(T, counts, M=2, D=4, seed=9, C1=C1, C2=C2)
+    Q = rng.integers(0, 6, (3, 4)).astype(np.float32)
+    log(f"visit one-key band: T={T} N={ix.N} pop_budget={budget}")
+    h = _open(fb, ix, pop_budget=budget)
+    for L in (1, ix.N // 3, ix.N - 1, ix.N):
+        _check_visit(fb, h, ix, Q, L)
+    fb.fbpq_free_index(h)
+
+
+@pytest.mark.parametrize("budget", [512, 0])
+def test_search_threshold_steps_topk(fb, gmm_small, budget):
+    ix, Q = gmm_small
+    L, k = 20000, 100
+    log(f"search: N=1e5 T=64 L={L} k={k} pop_budget={budget}")
+    h = _open(fb, ix, pop_budget=budget)
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
+@pytest.mark.parametrize("P", [3000, 4096])
+def test_long_prefix_rank_visit_and_topk(fb, gmm_wide, P):
+    # prefixes longer than the one-at-a-time traversal holds (T = 4096)
+    idxs, Q = gmm_wide
+    ix = idxs[4096]
+    log(f"long prefix: N=2e5 T=4096 P={P}")
+    h = _open(fb, ix, prefix=P, stats=1)
+    keys, idx = fb.fbpq_debug_rank(h, Q[:6], P)
+    for r in range(6):
+        d1, d2, u, v = oracle.rank_lists(ix, Q[r])
+        assert np.array_equal(idx[r, 0], u[:P]) and np.array_equal(idx[r, 1], v[:P]), r
+        assert np.array_equal(keys[r, 0], d1[u[:P]]) and np.array_equal(keys[r, 1], d2[v[:P]]), r
+    _check_visit(fb, h, ix, Q[:4], 3000, cap=1 << 20)  # sparse cells: about 10^5 visited
+    L, k = 5000, 10
+    g_ids, g_d = fb.fbpq_search(h, Q[:16], L, k)
+    assert fb.fbpq_stats_read(h)["wide"] >= 16
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q[:16], L, k)
+    assert_topk(ix, Q[:16], k, g_ids, g_d, o_ids, o_d)
 
 
 # ---- the selection fused into the cell scan and its fallbacks --------------------
