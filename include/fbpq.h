@@ -193,7 +193,8 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 #define FBPQ_STAGE_SELECT 7    /* per-query k smallest of the scored candidates */
 #define FBPQ_STAGE_SCAN2 8     /* two-pass scan (queries whose cells hold few points) */
 #define FBPQ_STAGE_TRAVERSE_WIDE 9 /* threshold-stepping traversal (queries with many visited cells) */
-#define FBPQ_NUM_STAGES 10
+#define FBPQ_STAGE_SCAN_WIDE 10 /* two-pass scan with sums in HBM (many candidates in sparse cells) */
+#define FBPQ_NUM_STAGES 11
 
 /* ---- served form: continuous batching (Section 4 measures per-query time;
  * a server keeps the GPU busy with overlapping batches of arriving queries) --

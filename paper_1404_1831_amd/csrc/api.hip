@@ -77,6 +77,9 @@ struct fbpq_index {
     int32_t chunk = 8192;
     bool items = true;
     int32_t pop_budget = 512;  // cells popped one at a time before the threshold kernel takes over
+    // per floor(log2(min(L, N))): the prefix length at which retried queries of
+    // that budget last succeeded; retry rounds start there instead of at 4P
+    int32_t p_hint[64] = {0};
     // path counters (option "stats")
     unsigned long long *stats_dev = nullptr;
     int64_t stat_retried = 0;
@@ -601,44 +604,44 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         la.slot_ij = (int32_t *)slotij;
         la.allow_items = ix->items ? 1 : 0;
         HCK(ix, timed(ix, FBPQ_STAGE_LAYOUT, st, [&] { return launch_layout(la, nslots, st); }));
-        if (ix->items) {
-            const int wcap = items_wcap(k_max);
-            void *lq, *dist, *seldone;
-            TRY(ws_get(ix, W_SELDONE, sizeof(int32_t) * nslots, &seldone));
-            TRY(ws_get(ix, W_LQ, sizeof(float) * nslots * dv.M * FBPQ_KC, &lq));
-            const int64_t dstride = (lcap + 63) & ~(int64_t)63;  // 256-byte aligned distance rows
-            TRY(ws_get(ix, W_ITEMN, sizeof(float) * nslots * dstride, &dist));
-            ItemArgs ia{};
-            ia.ix = dv;
-            ia.q = d_q;
-            ia.qlist = d_qlist;
-            ia.k = d_k;
-            ia.k_max = k_max;
-            ia.P = P;
-            ia.nslots = nslots;
-            ia.hdr = (const TravHdr *)hdr;
-            ia.max_cells = max_cells;
-            ia.ne_cs = (const int32_t *)necs;
-            ia.ne_cnt = (const int32_t *)necnt;
-            ia.ne_beg = (const int64_t *)nebeg;
-            ia.ne_cst = (const float *)necst;
-            ia.ne_slot = (const int32_t *)neslot;
-            ia.slot_ij = (const int32_t *)slotij;
-            ia.lq = (float *)lq;
-            ia.dist = (float *)dist;
-            ia.lcap = dstride;
-            ia.wcap = wcap;
-            ia.sel_done = (int32_t *)seldone;
-            ia.stats = ix->stats_dev;
-            ia.out_ids = d_ids;
-            ia.out_d = d_d;
-            ia.dbg_pos = (int64_t *)dpos;
-            ia.dbg_d = (float *)ddd;
-            ia.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
-            HCK(ix, timed(ix, FBPQ_STAGE_LQ, st, [&] { return launch_items_prep(ia, st); }));
-            HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_scan(ia, st); }));
-            HCK(ix, timed(ix, FBPQ_STAGE_SELECT, st, [&] { return launch_items_merge(ia, st); }));
-        }
+        HCK(ix, timed(ix, FBPQ_STAGE_LAYOUT, st, [&] { return launch_layout_wide(la, nslots, st); }));
+        // query tables and per-candidate distance rows: the cell scan and the
+        // wide two-pass scan write the rows, the distance select reads them
+        const int wcap = items_wcap(k_max);
+        void *lq, *dist, *seldone;
+        TRY(ws_get(ix, W_SELDONE, sizeof(int32_t) * nslots, &seldone));
+        TRY(ws_get(ix, W_LQ, sizeof(float) * nslots * dv.M * FBPQ_KC, &lq));
+        const int64_t dstride = (lcap + 63) & ~(int64_t)63;  // 256-byte aligned distance rows
+        TRY(ws_get(ix, W_ITEMN, sizeof(float) * nslots * dstride, &dist));
+        ItemArgs ia{};
+        ia.ix = dv;
+        ia.q = d_q;
+        ia.qlist = d_qlist;
+        ia.k = d_k;
+        ia.k_max = k_max;
+        ia.P = P;
+        ia.nslots = nslots;
+        ia.hdr = (const TravHdr *)hdr;
+        ia.max_cells = max_cells;
+        ia.ne_cs = (const int32_t *)necs;
+        ia.ne_cnt = (const int32_t *)necnt;
+        ia.ne_beg = (const int64_t *)nebeg;
+        ia.ne_cst = (const float *)necst;
+        ia.ne_slot = (const int32_t *)neslot;
+        ia.slot_ij = (const int32_t *)slotij;
+        ia.lq = (float *)lq;
+        ia.dist = (float *)dist;
+        ia.lcap = dstride;
+        ia.wcap = wcap;
+        ia.sel_done = (int32_t *)seldone;
+        ia.stats = ix->stats_dev;
+        ia.out_ids = d_ids;
+        ia.out_d = d_d;
+        ia.dbg_pos = (int64_t *)dpos;
+        ia.dbg_d = (float *)ddd;
+        ia.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
+        HCK(ix, timed(ix, FBPQ_STAGE_LQ, st, [&] { return launch_items_prep(ia, st); }));
+        if (ix->items) HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_scan(ia, st); }));
         ScanArgs sa{};
         sa.ix = dv;
         sa.q = d_q;
@@ -670,6 +673,11 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         sa.dbg_d = (float *)ddd;
         sa.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
         sa.stats = ix->stats_dev;
+        sa.lq = (const float *)lq;
+        sa.dist = (float *)dist;
+        sa.lcap = dstride;
+        HCK(ix, timed(ix, FBPQ_STAGE_SCAN_WIDE, st, [&] { return launch_scan_wide(sa, nslots, st); }));
+        HCK(ix, timed(ix, FBPQ_STAGE_SELECT, st, [&] { return launch_items_merge(ia, st); }));
         HCK(ix, timed(ix, FBPQ_STAGE_SCAN2, st, [&] { return launch_scan(sa, nslots, st); }));
     }
     if (launch_only) return FBPQ_OK;
@@ -827,12 +835,14 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     const int64_t ccap = ((int64_t)1 << 31) / 32;
     std::vector<int32_t> cur;  // query of each slot of the last round (empty: slot = query)
     int64_t nterminal = 0;
+    bool round_hint_set[64] = {false};  // hint buckets already written by this search
     // retry rounds take their buffers from the second workspace set, so that
     // they never move a buffer of the first round (and of its graph)
     struct WsBaseReset {
         fbpq_index *ix;
         ~WsBaseReset() { ix->ws_base = 0; }
     } ws_reset{ix};
+    auto lbucket = [&](int32_t q) { return 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(1, std::min(L[q], ix->dv.N))); };
     for (int round = 1; nfail > 0; ++round) {
         ix->stat_retried += nfail;
         std::vector<TravHdr> hh(nslots);
@@ -843,6 +853,11 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
         int64_t need_cells = 0;  // cells a failed query is known to need (threshold kernel)
         for (int64_t sl = 0; sl < nslots; ++sl) {
             const int32_t q = cur.empty() ? (int32_t)sl : cur[sl];
+            if (hh[sl].status == kStOk && !cur.empty()) {
+                int32_t &hb = ix->p_hint[lbucket(q)];
+                hb = round_hint_set[lbucket(q)] ? std::max(hb, P) : P;  // success of a retry round at P
+                round_hint_set[lbucket(q)] = true;
+            }
             if (hh[sl].status != kStOk) need_cells = std::max(need_cells, hh[sl].ncells);
             if (hh[sl].status == kStNeedPrefix) {
                 if (P >= Pcap) terminal.push_back(q);
@@ -870,7 +885,14 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
             HCK(ix, hipStreamSynchronize(st));
         }
         nterminal += (int64_t)terminal.size();
-        if (grow_p) P = std::min<int32_t>(Pcap, P * 4);
+        if (grow_p) {
+            int32_t Pn = std::min<int32_t>(Pcap, P * 4);
+            for (size_t i = 0; i < retry.size(); ++i) {
+                const int32_t hq = ix->p_hint[lbucket(retry[i])];
+                if (hq > Pn) Pn = std::min<int32_t>(Pcap, hq);
+            }
+            P = Pn;
+        }
         if (grow_c) max_cells = std::min<int64_t>(ccap, max_cells * 8);
         if (need_cells > max_cells) {
             // the next power of two: few distinct buffer sizes across batches
@@ -890,6 +912,14 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
         nfail = 0;
         TRY(run_round(ix, d_q, nq, nslots, qlist, P, max_cells, lcap, (const int64_t *)dL, (const int32_t *)dk,
                       k_max, d_ids, d_d, st, (int32_t *)dfail, dbg, &nfail));
+        if (nfail == 0) {
+            // every query of this retry round succeeded at P
+            for (int32_t q : cur) {
+                int32_t &hb = ix->p_hint[lbucket(q)];
+                hb = round_hint_set[lbucket(q)] ? std::max(hb, P) : P;
+                round_hint_set[lbucket(q)] = true;
+            }
+        }
     }
     if (nterminal)
         return fail(FBPQ_E_CAPACITY,

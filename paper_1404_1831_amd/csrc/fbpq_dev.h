@@ -29,8 +29,8 @@ struct TravHdr {
     int32_t nne;      // nonempty visited cells (set by the layout kernel)
     int32_t a_ne;     // rows holding a nonempty cell (layout kernel)
     int32_t b_ne;     // columns holding a nonempty cell (layout kernel)
-    int32_t n_items;  // blocks of kItem candidates (0: scanned by the two-pass kernel)
-    int32_t pad;
+    int32_t n_items;  // blocks of kItem candidates (0: scanned by a two-pass kernel)
+    int32_t gscan;    // 1: two-pass scan with partial sums in HBM (many candidates in sparse cells)
     int64_t ncells;   // visited cells (= sum of w)
     int64_t ncand;    // candidates (= min(L, N))
     int64_t cut_take; // points taken from the last visited cell
@@ -44,6 +44,7 @@ constexpr int kNumStatSlots = 8;
 // Candidate block of the cell scan: up to kItem candidates of one nonempty cell.
 constexpr int kItem = 2048;
 constexpr int kItemMinAvg = 128;   // mean points per nonempty cell for the item scan
+constexpr int kScanWideMin = 8192; // candidates above which a sparse query keeps its sums in HBM
 
 // Device view of an index and its tables.
 struct DevIndex {
@@ -133,6 +134,8 @@ struct LayoutArgs {
     int32_t allow_items;   // 0: every query goes to the two-pass scan
 };
 hipError_t launch_layout(const LayoutArgs &a, int64_t nslots, hipStream_t st);
+hipError_t launch_layout_wide(const LayoutArgs &a, int64_t nslots, hipStream_t st);
+constexpr int64_t kLayoutWaveMax = 4096;  // visited cells above which the workgroup layout runs
 
 struct ScanArgs {
     DevIndex ix;
@@ -151,6 +154,9 @@ struct ScanArgs {
     const int32_t *cm_cell, *cm_pre;
     const int32_t *ne_slot, *slot_ij;
     int32_t chunk;         // candidates per LDS chunk
+    const float *lq;       // [slot][M][Kc] query tables (wide scan)
+    float *dist;           // [slot][lcap] partial and final distances (wide scan)
+    int64_t lcap;
     int64_t *out_ids;      // [query][k_max]
     float *out_d;
     int64_t *dbg_pos;      // optional [slot][dbg_cap]
@@ -159,6 +165,7 @@ struct ScanArgs {
     unsigned long long *stats;  // optional path counters
 };
 hipError_t launch_scan(const ScanArgs &a, int64_t nslots, hipStream_t st);
+hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st);
 
 size_t scan_lds_bytes(int D, int M, int chunk, int k_max, int P);
 constexpr int kScanCellsLds = 256;  // nonempty cells whose tables the scan keeps in LDS

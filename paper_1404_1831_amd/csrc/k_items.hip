@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_lq(ItemArgs a)
             const int64_t slot = (int64_t)blockIdx.x * kLqQ + i;
             if (slot >= a.nslots) break;
             const TravHdr h = a.hdr[slot];
-            if (h.status == kStOk && h.n_items != 0) slots[n++] = slot;
+            if (h.status == kStOk && (h.n_items != 0 || h.gscan)) slots[n++] = slot;
         }
         nsel = n;
     }
@@ -417,8 +417,8 @@ __global__ __launch_bounds__(kSelNT) void k_select_dist(ItemArgs a)
     const int slot = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
     const TravHdr h = a.hdr[slot];
-    if (h.status != kStOk || h.n_items == 0) return;
-    if (a.sel_done[slot]) return;  // selected inside the cell scan
+    if (h.status != kStOk || (h.n_items == 0 && !h.gscan)) return;
+    if (h.n_items != 0 && a.sel_done[slot]) return;  // selected inside the cell scan
     const int64_t qs = a.qlist ? a.qlist[slot] : slot;
     const int kq = a.k[qs];
     int KP = 1;

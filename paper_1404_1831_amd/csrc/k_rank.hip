@@ -256,27 +256,67 @@ __device__ int block_excl_scan(int v, int *red, int *total)
 }
 
 // Writes the first `keep` of n (key, idx) pairs in ascending (key, idx) order
-// to ok/oi: each pair's rank is the number of pairs below it (pairs are
-// distinct because indices are). Positions [n, keep), and entries whose index
-// is not a centroid, get (+inf, 0): a key the traversal never visits.
-__device__ void rank_out(const uint64_t *sk, const int32_t *si, int n, int keep, int T,
+// to ok/oi. Up to 512 pairs, each pair's rank is the number of pairs below it
+// (pairs are distinct because indices are); beyond that the pairs are sorted
+// in place by a bitonic network over the next power of two (<= cap, the
+// buffers' length). Positions [n, keep), and entries whose index is not a
+// centroid, get (+inf, 0): a key the traversal never visits. Every thread of
+// the block calls it.
+__device__ void rank_out(uint64_t *sk, int32_t *si, int n, int cap, int keep, int T,
                          double *__restrict__ ok, int32_t *__restrict__ oi)
 {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint64_t k = sk[i];
-        const int x = si[i];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const uint64_t kj = sk[j];
-            rank += kj < k || (kj == k && si[j] < x);
+    const int tid = threadIdx.x;
+    if (n <= 512) {
+        for (int i = tid; i < n; i += blockDim.x) {
+            const uint64_t k = sk[i];
+            const int x = si[i];
+            int rank = 0;
+            for (int j = 0; j < n; ++j) {
+                const uint64_t kj = sk[j];
+                rank += kj < k || (kj == k && si[j] < x);
+            }
+            if (rank < keep) {
+                const bool valid = x >= 0 && x < T;
+                ok[rank] = valid ? __longlong_as_double((long long)k) : __builtin_huge_val();
+                oi[rank] = valid ? x : 0;
+            }
         }
-        if (rank < keep) {
+    } else {
+        int np = 1;
+        while (np < n) np <<= 1;
+        if (np > cap) np = cap;  // n <= cap always; cap is a power of two
+        for (int i = n + tid; i < np; i += blockDim.x) {
+            sk[i] = ~0ull;
+            si[i] = 0x7fffffff;
+        }
+        __syncthreads();
+        for (int kk = 2; kk <= np; kk <<= 1) {
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int i = tid; i < np / 2; i += blockDim.x) {
+                    const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                    const int hi = lo + j;
+                    const uint64_t ka = sk[lo], kb = sk[hi];
+                    const int xa = si[lo], xb = si[hi];
+                    const bool gt = ka > kb || (ka == kb && xa > xb);
+                    if (gt == ((lo & kk) == 0)) {
+                        sk[lo] = kb;
+                        sk[hi] = ka;
+                        si[lo] = xb;
+                        si[hi] = xa;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        const int m = n < keep ? n : keep;
+        for (int i = tid; i < m; i += blockDim.x) {
+            const int x = si[i];
             const bool valid = x >= 0 && x < T;
-            ok[rank] = valid ? __longlong_as_double((long long)k) : __builtin_huge_val();
-            oi[rank] = valid ? x : 0;
+            ok[i] = valid ? __longlong_as_double((long long)sk[i]) : __builtin_huge_val();
+            oi[i] = valid ? x : 0;
         }
     }
-    for (int i = n + threadIdx.x; i < keep; i += blockDim.x) {
+    for (int i = n + tid; i < keep; i += blockDim.x) {
         ok[i] = __builtin_huge_val();
         oi[i] = 0;
     }
@@ -339,7 +379,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
             si[i] = i;
         }
         __syncthreads();
-        rank_out(sk, si, T, P, T, ok, oi);
+        rank_out(sk, si, T, S, P, T, ok, oi);
         done = true;
     }
     if (!done && have_ka && (T < kSelThreads ? T : kSelThreads) >= P) {
@@ -373,7 +413,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
             for (int w = tid; w < nsurv; w += kSelThreads)
                 sk[w] = dkey(exact_key(qh, C + (int64_t)si[w] * h, h));
             __syncthreads();
-            rank_out(sk, si, nsurv, P, T, ok, oi);
+            rank_out(sk, si, nsurv, S, P, T, ok, oi);
             done = true;
         }
         __syncthreads();
@@ -479,7 +519,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
                 for (int w = tid; w < ns; w += kSelThreads)
                     sk[w] = dkey(exact_key(qh, C + (int64_t)si[w] * h, h));
                 __syncthreads();
-                rank_out(sk, si, ns, P, T, ok, oi);
+                rank_out(sk, si, ns, S, P, T, ok, oi);
                 done = true;
             }
         }
@@ -566,7 +606,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
             }
         }
         __syncthreads();
-        rank_out(sk, si, P < S ? P : S, P, T, ok, oi);
+        rank_out(sk, si, P < S ? P : S, S, P, T, ok, oi);
     }
 }
 

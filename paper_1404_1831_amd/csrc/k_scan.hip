@@ -109,7 +109,7 @@ __global__ __launch_bounds__(512) void k_scan2(ScanArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t qs = a.qlist ? a.qlist[slot] : slot;
     const TravHdr h = a.hdr[slot];
-    if (h.status != kStOk || h.n_items != 0) return;
+    if (h.status != kStOk || h.n_items != 0 || h.gscan) return;
     if (TAB_LDS != (h.nne <= kScanCellsLds)) return;
     if (a.stats && tid == 0) atomicAdd(&a.stats[kStatTwoPass], 1ull);
     const int D = a.ix.D, ds = D / M, P = a.P;
@@ -289,6 +289,172 @@ __global__ __launch_bounds__(512) void k_scan2(ScanArgs a)
     }
 }
 
+// ============================ wide two-pass scan ==============================
+// Queries with more than kScanWideMin candidates in sparse cells. The partial
+// sums live in the query's HBM distance row (index = row-major candidate
+// number), so every row table LUT1_i and column table LUT2_j is folded once
+// per query however many candidates there are. Each wavefront takes whole rows
+// (then whole columns) and folds their tables in its own LDS region, without
+// workgroup barriers; the k smallest are selected afterwards from the row.
+constexpr int kWideNT = 256;
+
+template <int MH>
+__global__ __launch_bounds__(kWideNT) void k_scan_wide(ScanArgs a)
+{
+    constexpr int NW = kWideNT / 64;
+    constexpr int TL = MH * kKc;  // floats of one folded half table
+    extern __shared__ __align__(16) float wlut[];  // [NW][TL]
+    const int slot = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const TravHdr h = a.hdr[slot];
+    if (h.status != kStOk || !h.gscan) return;
+    if (a.stats && tid == 0) atomicAdd(&a.stats[kStatTwoPass], 1ull);
+    float *lut = wlut + wv * TL;
+    const int P = a.P;
+    const int64_t mc = a.max_cells;
+    const int32_t *t_cs = a.ne_cs + slot * mc;
+    const int64_t *t_beg = a.ne_beg + slot * mc;
+    const float *t_cst = a.ne_cst + slot * mc;
+    const int32_t *t_cmc = a.cm_cell + slot * mc;
+    const int32_t *t_cmp = a.cm_pre + slot * mc;
+    const int32_t *u = a.lidx + (int64_t)slot * 2 * P;
+    const int32_t *v = u + P;
+    const int32_t *row_ne = a.row_ne + (int64_t)slot * (P + 1);
+    const int32_t *row_cand = a.row_cand + (int64_t)slot * (P + 1);
+    const int32_t *col_ne = a.col_ne + (int64_t)slot * (P + 1);
+    const int32_t *col_tot = a.col_tot + (int64_t)slot * P;
+    const float *lq = a.lq + (int64_t)slot * 2 * TL;
+    float *dist = a.dist + (int64_t)slot * a.lcap;
+    const uint64_t below_lane = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int A = h.A, B = h.B;
+
+    // The first candidate chunk of a row (column) starts at its first cell; each
+    // next chunk starts at the cell holding the previous chunk's last candidate,
+    // or at the one after it. The folded table of the next row (column) is
+    // loaded into registers while the current one is scored.
+    constexpr int TQ = TL / 4 / 64 > 0 ? TL / 4 / 64 : 1;  // float4 of a table per lane
+    const bool tq_full = TL / 4 >= 64;
+    float4 nxt[TQ];
+    auto fetch = [&](const float *crrow) __attribute__((always_inline)) {
+        const float4 *cr = reinterpret_cast<const float4 *>(crrow);
+#pragma unroll
+        for (int e = 0; e < TQ; ++e) {
+            const int f = lane + 64 * e;
+            if (tq_full || f < TL / 4) nxt[e] = cr[f];
+        }
+    };
+    auto fold = [&](const float *lqh) __attribute__((always_inline)) {
+        const float4 *lq4 = reinterpret_cast<const float4 *>(lqh);
+        __builtin_amdgcn_wave_barrier();  // the previous table's lookups are done
+#pragma unroll
+        for (int e = 0; e < TQ; ++e) {
+            const int f = lane + 64 * e;
+            if (tq_full || f < TL / 4) {
+                const float4 x = lq4[f], y = nxt[e];
+                reinterpret_cast<float4 *>(lut)[f] = make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    auto next_row = [&](int ar) __attribute__((always_inline)) {
+        while (ar < A && row_cand[ar] >= row_cand[ar + 1]) ar += NW;
+        return ar;
+    };
+    auto next_col = [&](int b) __attribute__((always_inline)) {
+        while (b < B && col_ne[b] >= col_ne[b + 1]) b += NW;
+        return b;
+    };
+
+    // pass 1: rows, first half of the code plus the cell constant
+    int ar = next_row(wv);
+    if (ar < A) fetch(a.ix.CR1 + (int64_t)u[ar] * TL);
+    while (ar < A) {
+        fold(lq);
+        const int an = next_row(ar + NW);
+        if (an < A) fetch(a.ix.CR1 + (int64_t)u[an] * TL);
+        const int64_t rs = row_cand[ar], re = row_cand[ar + 1];
+        const int xe = row_ne[ar + 1];
+        int x0 = row_ne[ar];
+        for (int64_t t0 = rs; t0 < re; t0 += 64) {
+            const int x = x0 + lane;
+            int32_t cs = 0;
+            int64_t beg = 0;
+            float cst = 0.f;
+            bool vc = false;
+            if (x < xe) {
+                cs = t_cs[x];
+                vc = cs < t0 + 64;
+                beg = t_beg[x];
+                cst = t_cst[x];
+            }
+            const int sr = cs > t0 ? (int)(cs - t0) : 0;
+            const uint64_t mask = wave_or64(vc ? (1ull << sr) : 0ull);
+            const int owner = __popcll(mask & below_lane) - 1;
+            const int32_t cso = __shfl(cs, owner);
+            const int64_t bego = __shfl(beg, owner);
+            const float csto = __shfl(cst, owner);
+            const int64_t t = t0 + lane;
+            if (t < re) dist[t] = lut_sum<MH>(lut, a.ix.codesA, bego + (t - cso)) + csto;
+            // cell of candidate t0 + 64: that of lane 63's candidate, or the next
+            int xn = x0 + __shfl(owner, 63);
+            const int csn = __shfl(cs, (__shfl(owner, 63) + 1) & 63);
+            if (__shfl(owner, 63) < 63 && xn + 1 < xe && csn <= t0 + 64) ++xn;
+            else if (__shfl(owner, 63) == 63 && xn + 1 < xe && t_cs[xn + 1] <= t0 + 64) ++xn;
+            x0 = xn;
+        }
+        ar = an;
+    }
+    __syncthreads();  // every partial sum of the query is stored
+    // pass 2: columns, second half of the code
+    int b = next_col(wv);
+    if (b < B) fetch(a.ix.CR2 + (int64_t)v[b] * TL);
+    while (b < B) {
+        fold(lq + TL);
+        const int bn = next_col(b + NW);
+        if (bn < B) fetch(a.ix.CR2 + (int64_t)v[bn] * TL);
+        const int ye = col_ne[b + 1];
+        const int U = col_tot[b];
+        int y0 = col_ne[b];
+        for (int u0 = 0; u0 < U; u0 += 64) {
+            const int y = y0 + lane;
+            int32_t pre = 0, cs = 0;
+            int64_t beg = 0;
+            bool vc = false;
+            if (y < ye) {
+                pre = t_cmp[y];
+                vc = pre < u0 + 64;
+                const int e = t_cmc[y];
+                cs = t_cs[e];
+                beg = t_beg[e];
+            }
+            const int sr = pre > u0 ? pre - u0 : 0;
+            const uint64_t mask = wave_or64(vc ? (1ull << sr) : 0ull);
+            const int owner = __popcll(mask & below_lane) - 1;
+            const int32_t preo = __shfl(pre, owner);
+            const int32_t cso = __shfl(cs, owner);
+            const int64_t bego = __shfl(beg, owner);
+            const int uu = u0 + lane;
+            if (uu < U) {
+                const int64_t t = cso + (uu - preo);
+                const int64_t p = bego + (t - cso);
+                const float d = dist[t] + lut_sum<MH>(lut, a.ix.codesB, p);
+                dist[t] = d;
+                if (a.dbg_pos) {
+                    a.dbg_pos[(int64_t)slot * a.dbg_cap + t] = p;
+                    a.dbg_d[(int64_t)slot * a.dbg_cap + t] = d;
+                }
+            }
+            const int o63 = __shfl(owner, 63);
+            int yn = y0 + o63;
+            const int pren = __shfl(pre, (o63 + 1) & 63);
+            if (o63 < 63 && yn + 1 < ye && pren <= u0 + 64) ++yn;
+            else if (o63 == 63 && yn + 1 < ye && t_cmp[yn + 1] <= u0 + 64) ++yn;
+            y0 = yn;
+        }
+        b = bn;
+    }
+}
+
 // ============================ host side =======================================
 static size_t sel_bytes(int k_max)
 {
@@ -328,6 +494,22 @@ hipError_t launch_scan(const ScanArgs &a, int64_t nslots, hipStream_t st)
     hipError_t e = launch_scan2<true>(a, nslots, st);
     if (e != hipSuccess) return e;
     return launch_scan2<false>(a, nslots, st);
+}
+
+hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st)
+{
+    if (nslots == 0) return hipSuccess;
+    const size_t lds = (size_t)(kWideNT / 64) * (a.ix.M / 2) * kKc * sizeof(float);
+    const dim3 g((unsigned)nslots), b(kWideNT);
+    switch (a.ix.M / 2) {
+    case 1: hipLaunchKernelGGL(k_scan_wide<1>, g, b, lds, st, a); break;
+    case 2: hipLaunchKernelGGL(k_scan_wide<2>, g, b, lds, st, a); break;
+    case 4: hipLaunchKernelGGL(k_scan_wide<4>, g, b, lds, st, a); break;
+    case 8: hipLaunchKernelGGL(k_scan_wide<8>, g, b, lds, st, a); break;
+    case 16: hipLaunchKernelGGL(k_scan_wide<16>, g, b, lds, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace fbpq

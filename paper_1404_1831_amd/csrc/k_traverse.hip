@@ -211,7 +211,7 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs args)
         h.a_ne = 0;
         h.b_ne = 0;
         h.n_items = 0;
-        h.pad = 0;
+        h.gscan = 0;
         h.ncells = ncells;
         h.ncand = total;
         h.cut_take = cut_take;
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
     const int slot = blockIdx.x;
     const int lane = threadIdx.x;
     TravHdr h = args.hdr[slot];
-    if (h.status != kStOk) return;
+    if (h.status != kStOk || h.ncells > kLayoutWaveMax) return;
     const int A = h.A, B = h.B;
     const int T = args.ix.T;
     const int32_t *w = args.w + (int64_t)slot * P;
@@ -443,6 +443,7 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
         args.hdr[slot].nne = nerun;
         const bool items = args.allow_items && nerun > 0 && crun >= (int64_t)kItemMinAvg * nerun;
         args.hdr[slot].n_items = items ? itrun : 0;
+        args.hdr[slot].gscan = !items && crun > kScanWideMin ? 1 : 0;
     }
 }
 

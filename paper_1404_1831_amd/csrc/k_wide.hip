@@ -582,7 +582,7 @@ __global__ __launch_bounds__(NT) void k_traverse_wide(TravArgs args)
         h.a_ne = 0;
         h.b_ne = 0;
         h.n_items = 0;
-        h.pad = 0;
+        h.gscan = 0;
         h.ncells = nc;
         h.ncand = tot;
         h.cut_take = cut_take;
@@ -610,6 +610,217 @@ hipError_t launch_traverse_wide(const TravArgs &a, int64_t nslots, hipStream_t s
     if (a.P <= 256 * kWRows) hipLaunchKernelGGL(k_traverse_wide<256>, g, dim3(256), lds, st, a);
     else if (a.P <= 512 * kWRows) hipLaunchKernelGGL(k_traverse_wide<512>, g, dim3(512), lds, st, a);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---- workgroup form of the row-major layout, for large visited sets ---------
+// Same outputs as the one-wavefront layout kernel (compacted nonempty cells in
+// row-major order, per-row and per-column starts, column lists, LUT slots),
+// with 256 threads taking kLayE consecutive cells each per step, so that a
+// query with 10^5 visited cells needs about a hundred dependent steps.
+constexpr int kLayNT = 256;
+constexpr int kLayE = 4;
+
+// exclusive prefix of x[0..n) in place (n <= kLayNT * per), returns the total
+template <int NT>
+__device__ __forceinline__ int64_t wg_scan_array(int *x, int n, int64_t *red)
+{
+    const int per = (n + NT - 1) / NT;
+    const int i0 = threadIdx.x * per, i1 = i0 + per < n ? i0 + per : n;
+    int64_t s = 0;
+    for (int i = i0; i < i1; ++i) s += x[i];
+    int64_t tot;
+    int64_t run = wg_scan<NT>(s, red, &tot);
+    for (int i = i0; i < i1; ++i) {
+        const int v = x[i];
+        x[i] = (int)run;
+        run += v;
+    }
+    __syncthreads();
+    return tot;
+}
+
+__global__ __launch_bounds__(kLayNT) void k_layout_wide(LayoutArgs args)
+{
+    constexpr int NT = kLayNT, E = kLayE;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int64_t red[NT / 64];
+    const int P = args.P;
+    unsigned long long *colcur = reinterpret_cast<unsigned long long *>(smem);  // [P] cells | candidates
+    int *rc = reinterpret_cast<int *>(colcur + P);      // [P + 1] first diagram cell of each row
+    int *rowcnt = rc + (P + 1);                         // [P + 1] nonempty cells per row, then starts
+    int *colcnt = rowcnt + (P + 1);                     // [P + 1] same per column
+    int *rslot = colcnt + (P + 1);                      // [2P] LUT slot of each row, then column
+    const int slot = blockIdx.x;
+    const int tid = threadIdx.x;
+    const TravHdr h = args.hdr[slot];
+    if (h.status != kStOk || h.ncells <= kLayoutWaveMax) return;
+    const int A = h.A, B = h.B;
+    const int T = args.ix.T;
+    const int32_t *w = args.w + (int64_t)slot * P;
+    const double *k1 = args.lkey + (int64_t)slot * 2 * P;
+    const double *k2 = k1 + P;
+    const int32_t *u = args.lidx + (int64_t)slot * 2 * P;
+    const int32_t *v = u + P;
+    const int64_t *off = args.ix.offsets;
+    const int64_t mc = args.max_cells;
+    int32_t *row_ne = args.row_ne + (int64_t)slot * (P + 1);
+    int32_t *row_cand = args.row_cand + (int64_t)slot * (P + 1);
+    int32_t *col_ne = args.col_ne + (int64_t)slot * (P + 1);
+    int32_t *col_tot = args.col_tot + (int64_t)slot * P;
+    int32_t *ne_cs = args.ne_cs + (int64_t)slot * mc;
+    int32_t *ne_cnt = args.ne_cnt + (int64_t)slot * mc;
+    int64_t *ne_beg = args.ne_beg + (int64_t)slot * mc;
+    float *ne_cst = args.ne_cst + (int64_t)slot * mc;
+    int32_t *cm_cell = args.cm_cell + (int64_t)slot * mc;
+    int32_t *cm_pre = args.cm_pre + (int64_t)slot * mc;
+    int32_t *ne_slot = args.ne_slot + (int64_t)slot * mc;
+    int32_t *slot_ij = args.slot_ij + (int64_t)slot * 2 * P;
+
+    // first diagram cell of each row (exclusive prefix of the widths)
+    for (int a = tid; a <= P; a += NT) rc[a] = a < A ? w[a] : 0;
+    __syncthreads();
+    const int64_t ncells = wg_scan_array<NT>(rc, A + 1, red);
+    if (ncells > mc) return;
+    for (int a = tid; a <= P; a += NT) {
+        rowcnt[a] = 0;
+        colcnt[a] = 0;
+    }
+    for (int b = tid; b < P; b += NT) colcur[b] = 0ull;
+    __syncthreads();
+
+    // cell of diagram position xi: row by binary search over rc, then column
+    auto cells = [&](int64_t x0, int *as, int *bs, int64_t *begs, int64_t *cnts) __attribute__((always_inline)) {
+        int lo[E], hi[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            lo[e] = 0;
+            hi[e] = x0 + e < ncells ? A - 1 : 0;
+        }
+        bool any = true;
+        while (any) {
+            any = false;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (lo[e] < hi[e]) {
+                    const int mid = (lo[e] + hi[e] + 1) >> 1;
+                    if (rc[mid] <= x0 + e) lo[e] = mid;
+                    else hi[e] = mid - 1;
+                    any |= lo[e] < hi[e];
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            as[e] = lo[e];
+            bs[e] = (int)(x0 + e - rc[lo[e]]);
+            begs[e] = 0;
+            cnts[e] = 0;
+            if (x0 + e < ncells) {
+                const int64_t c = (int64_t)u[as[e]] * T + v[bs[e]];
+                begs[e] = off[c];
+                cnts[e] = (as[e] == h.cut_a && bs[e] == h.cut_b) ? h.cut_take : off[c + 1] - begs[e];
+            }
+        }
+    };
+
+    // pass 1: nonempty cells per row and per column
+    for (int64_t xb = 0; xb < ncells; xb += (int64_t)NT * E) {
+        int as[E], bs[E];
+        int64_t begs[E], cnts[E];
+        cells(xb + (int64_t)tid * E, as, bs, begs, cnts);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (cnts[e] > 0) {
+                atomicAdd(&rowcnt[as[e]], 1);
+                atomicAdd(&colcnt[bs[e]], 1);
+            }
+        }
+    }
+    __syncthreads();
+    // rows and columns holding a nonempty cell get LUT slots in order
+    for (int a = tid; a < P; a += NT) {
+        rslot[a] = a < A && rowcnt[a] > 0;
+        rslot[P + a] = a < B && colcnt[a] > 0;
+    }
+    __syncthreads();
+    const int64_t tne = wg_scan_array<NT>(rowcnt, A + 1, red);
+    (void)wg_scan_array<NT>(colcnt, B + 1, red);
+    const int nr = (int)wg_scan_array<NT>(rslot, P, red);
+    const int ncol = (int)wg_scan_array<NT>(rslot + P, P, red);
+    for (int a = tid; a <= A; a += NT) row_ne[a] = rowcnt[a];
+    for (int b = tid; b <= B; b += NT) col_ne[b] = colcnt[b];
+    for (int a = tid; a < A; a += NT)
+        if (rowcnt[a + 1] > rowcnt[a]) slot_ij[rslot[a]] = u[a];
+    for (int b = tid; b < B; b += NT)
+        if (colcnt[b + 1] > colcnt[b]) slot_ij[nr + rslot[P + b]] = v[b];
+    if (tid == 0) {
+        args.hdr[slot].a_ne = nr;
+        args.hdr[slot].b_ne = ncol;
+    }
+    __syncthreads();
+
+    // pass 2: compacted entries, candidates numbered in row-major order
+    int64_t crun = 0, nerun = 0, itrun = 0;
+    for (int64_t xb = 0; xb < ncells; xb += (int64_t)NT * E) {
+        const int64_t x0 = xb + (int64_t)tid * E;
+        int as[E], bs[E];
+        int64_t begs[E], cnts[E];
+        cells(x0, as, bs, begs, cnts);
+        int64_t lc = 0, ln = 0, li = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            lc += cnts[e];
+            ln += cnts[e] > 0;
+            li += (cnts[e] + kItem - 1) / kItem;
+        }
+        int64_t tc, tn;
+        const int64_t cb = wg_scan<NT>(lc, red, &tc);
+        const int64_t nb = wg_scan<NT>(ln, red, &tn);
+        const int64_t ti = wg_sum<NT>(li, red);
+        int64_t cs = crun + cb, ne = nerun + nb;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (x0 + e < ncells) {
+                const int a = as[e], b = bs[e];
+                if (b == 0) row_cand[a] = (int32_t)cs;
+                if (cnts[e] > 0) {
+                    ne_cs[ne] = (int32_t)cs;
+                    ne_cnt[ne] = (int32_t)cnts[e];
+                    ne_beg[ne] = begs[e];
+                    ne_cst[ne] = (float)(k1[a] + k2[b]);
+                    ne_slot[ne] = rslot[a] | ((nr + rslot[P + b]) << 16);
+                    const unsigned long long old =
+                        atomicAdd(&colcur[b], (1ull << 40) + (unsigned long long)cnts[e]);
+                    const int slotc = colcnt[b] + (int)(old >> 40);
+                    cm_cell[slotc] = (int32_t)ne;
+                    cm_pre[slotc] = (int32_t)(old & ((1ull << 40) - 1ull));
+                    ++ne;
+                }
+                cs += cnts[e];
+            }
+        }
+        crun += tc;
+        nerun += tn;
+        itrun += ti;
+    }
+    __syncthreads();
+    if (tid == 0) row_cand[A] = (int32_t)crun;
+    for (int b = tid; b < B; b += NT) col_tot[b] = (int32_t)(colcur[b] & ((1ull << 40) - 1ull));
+    if (tid == 0) {
+        args.hdr[slot].nne = (int32_t)nerun;
+        const bool items = args.allow_items && nerun > 0 && crun >= (int64_t)kItemMinAvg * nerun;
+        args.hdr[slot].n_items = items ? (int32_t)itrun : 0;
+        args.hdr[slot].gscan = !items && crun > kScanWideMin ? 1 : 0;
+    }
+    (void)tne;
+}
+
+hipError_t launch_layout_wide(const LayoutArgs &a, int64_t nslots, hipStream_t st)
+{
+    if (nslots == 0) return hipSuccess;
+    const size_t lds = (size_t)a.P * 8 + (size_t)3 * (a.P + 1) * 4 + (size_t)2 * a.P * 4;
+    hipLaunchKernelGGL(k_layout_wide, dim3((unsigned)nslots), dim3(kLayNT), lds, st, a);
     return hipGetLastError();
 }
 

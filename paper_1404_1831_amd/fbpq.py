@@ -34,7 +34,7 @@ EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbp
            "fbpq_free_index", "fbpq_last_error", "fbpq_server_create", "fbpq_server_submit",
            "fbpq_server_poll", "fbpq_server_counts", "fbpq_server_first_error", "fbpq_server_destroy")
 STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2",
-          "traverse_wide")
+          "traverse_wide", "scan_wide")
 STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried", "graph_replays",
          "wide")
 

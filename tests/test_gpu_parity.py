@@ -451,6 +451,33 @@ def test_long_prefix_rank_visit_and_topk(fb, gmm_wide, P):
     assert_topk(ix, Q[:16], k, g_ids, g_d, o_ids, o_d)
 
 
+@pytest.mark.parametrize("items", [1, 0])
+def test_wide_scan_sparse_cells(fb, gmm_wide, items):
+    # T = 1000 with 2e5 points: about 0.2 points per cell, so L = 20000 gives a
+    # query more than 8192 candidates in sparse cells (the HBM two-pass scan)
+    idxs, Q = gmm_wide
+    ix = idxs[1000]
+    L, k = 20000, 50
+    log(f"wide two-pass scan: N=2e5 T=1000 L={L} k={k} items={items}")
+    h = _open(fb, ix, items=items, stats=1)
+    got = fb.fbpq_debug_dists(h, Q[:4], L, cap=L)
+    for r in range(4):
+        pos, d32 = got[r]
+        _, opos = oracle.visit(ix, Q[r], L)
+        assert np.array_equal(np.sort(pos), np.sort(opos)), r
+        d64 = oracle_dists(ix, Q[r], pos)
+        err = np.abs(d32.astype(np.float64) - d64)
+        assert np.all(err <= tol(ix, Q[r], pos, d64)), r
+    fb.fbpq_stats_read(h, reset=True)
+    g_ids, g_d = fb.fbpq_search(h, Q[:12], L, k)
+    st = fb.fbpq_stats_read(h)
+    fb.fbpq_free_index(h)
+    log(f"  counters {st}")
+    assert st["two_pass"] >= 12
+    o_ids, o_d, _, _ = oracle.search(ix, Q[:12], L, k)
+    assert_topk(ix, Q[:12], k, g_ids, g_d, o_ids, o_d)
+
+
 # ---- the selection fused into the cell scan and its fallbacks --------------------
 
 def _dense_index(const_codes: bool):
