@@ -251,7 +251,10 @@ int fbpq_autotune(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L
 #define FBPQ_STAT_RETRIED 5     /* queries traversed again with a longer prefix or more cells */
 #define FBPQ_STAT_GRAPH_REPLAYS 6 /* searches whose first round was a replayed graph */
 #define FBPQ_STAT_WIDE 7        /* queries traversed by threshold steps */
-#define FBPQ_NUM_STATS 8
+#define FBPQ_STAT_WIDE_BANDS 8  /* ... bands of cells they took (dropped ones included) */
+#define FBPQ_STAT_WIDE_EVALS 9  /* ... row widths evaluated at a threshold (per query) */
+#define FBPQ_STAT_WIDE_LOADS 10 /* ... cell point counts they loaded */
+#define FBPQ_NUM_STATS 11
 int fbpq_stats_read(fbpq_index *ix, int64_t *out, int32_t n, int32_t reset);
 
 /* Device time per kernel stage, measured with HIP events recorded on the

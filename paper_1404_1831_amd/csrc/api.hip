@@ -80,6 +80,7 @@ struct fbpq_index {
     // per floor(log2(min(L, N))): the prefix length at which retried queries of
     // that budget last succeeded; retry rounds start there instead of at 4P
     int32_t p_hint[64] = {0};
+    int64_t c_hint[64] = {0};  // ... and the visited cells they needed
     // path counters (option "stats")
     unsigned long long *stats_dev = nullptr;
     int64_t stat_retried = 0;
@@ -836,6 +837,17 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     std::vector<int32_t> cur;  // query of each slot of the last round (empty: slot = query)
     int64_t nterminal = 0;
     bool round_hint_set[64] = {false};  // hint buckets already written by this search
+    auto record_hint = [&](int32_t q, int32_t Pq, int64_t cells) {
+        const int b = 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(1, std::min(L[q], ix->dv.N)));
+        if (!round_hint_set[b]) {
+            ix->p_hint[b] = Pq;
+            ix->c_hint[b] = cells;
+            round_hint_set[b] = true;
+        } else {
+            ix->p_hint[b] = std::max(ix->p_hint[b], Pq);
+            ix->c_hint[b] = std::max(ix->c_hint[b], cells);
+        }
+    };
     // retry rounds take their buffers from the second workspace set, so that
     // they never move a buffer of the first round (and of its graph)
     struct WsBaseReset {
@@ -853,11 +865,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
         int64_t need_cells = 0;  // cells a failed query is known to need (threshold kernel)
         for (int64_t sl = 0; sl < nslots; ++sl) {
             const int32_t q = cur.empty() ? (int32_t)sl : cur[sl];
-            if (hh[sl].status == kStOk && !cur.empty()) {
-                int32_t &hb = ix->p_hint[lbucket(q)];
-                hb = round_hint_set[lbucket(q)] ? std::max(hb, P) : P;  // success of a retry round at P
-                round_hint_set[lbucket(q)] = true;
-            }
+            if (hh[sl].status == kStOk && !cur.empty()) record_hint(q, P, hh[sl].ncells);  // a retry round's success
             if (hh[sl].status != kStOk) need_cells = std::max(need_cells, hh[sl].ncells);
             if (hh[sl].status == kStNeedPrefix) {
                 if (P >= Pcap) terminal.push_back(q);
@@ -894,6 +902,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
             P = Pn;
         }
         if (grow_c) max_cells = std::min<int64_t>(ccap, max_cells * 8);
+        for (int32_t q : retry) need_cells = std::max(need_cells, ix->c_hint[lbucket(q)]);
         if (need_cells > max_cells) {
             // the next power of two: few distinct buffer sizes across batches
             int64_t c = max_cells;
@@ -914,11 +923,10 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
                       k_max, d_ids, d_d, st, (int32_t *)dfail, dbg, &nfail));
         if (nfail == 0) {
             // every query of this retry round succeeded at P
-            for (int32_t q : cur) {
-                int32_t &hb = ix->p_hint[lbucket(q)];
-                hb = round_hint_set[lbucket(q)] ? std::max(hb, P) : P;
-                round_hint_set[lbucket(q)] = true;
-            }
+            std::vector<TravHdr> hl(nslots);
+            HCK(ix, hipMemcpy(hl.data(), ix->ws[W_HDR + ix->ws_base].p, sizeof(TravHdr) * nslots,
+                              hipMemcpyDeviceToHost));
+            for (int64_t sl = 0; sl < nslots; ++sl) record_hint(cur[sl], P, hl[sl].ncells);
         }
     }
     if (nterminal)

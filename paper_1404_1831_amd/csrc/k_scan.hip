@@ -296,12 +296,14 @@ __global__ __launch_bounds__(512) void k_scan2(ScanArgs a)
 // per query however many candidates there are. Each wavefront takes whole rows
 // (then whole columns) and folds their tables in its own LDS region, without
 // workgroup barriers; the k smallest are selected afterwards from the row.
-constexpr int kWideNT = 256;
+// Wavefronts per query: as many as 64 KB of folded tables allow, up to 16.
+template <int MH>
+constexpr int wide_waves() { return MH <= 4 ? 16 : (MH == 8 ? 8 : 4); }
 
 template <int MH>
-__global__ __launch_bounds__(kWideNT) void k_scan_wide(ScanArgs a)
+__global__ __launch_bounds__(64 * wide_waves<MH>()) void k_scan_wide(ScanArgs a)
 {
-    constexpr int NW = kWideNT / 64;
+    constexpr int NW = wide_waves<MH>();
     constexpr int TL = MH * kKc;  // floats of one folded half table
     extern __shared__ __align__(16) float wlut[];  // [NW][TL]
     const int slot = blockIdx.x;
@@ -499,16 +501,21 @@ hipError_t launch_scan(const ScanArgs &a, int64_t nslots, hipStream_t st)
 hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
-    const size_t lds = (size_t)(kWideNT / 64) * (a.ix.M / 2) * kKc * sizeof(float);
-    const dim3 g((unsigned)nslots), b(kWideNT);
+    const dim3 g((unsigned)nslots);
+#define FBPQ_WIDE_CASE(MH)                                                                        \
+    case MH:                                                                                      \
+        hipLaunchKernelGGL(k_scan_wide<MH>, g, dim3(64 * wide_waves<MH>()),                       \
+                           (size_t)wide_waves<MH>() * MH * kKc * sizeof(float), st, a);            \
+        break;
     switch (a.ix.M / 2) {
-    case 1: hipLaunchKernelGGL(k_scan_wide<1>, g, b, lds, st, a); break;
-    case 2: hipLaunchKernelGGL(k_scan_wide<2>, g, b, lds, st, a); break;
-    case 4: hipLaunchKernelGGL(k_scan_wide<4>, g, b, lds, st, a); break;
-    case 8: hipLaunchKernelGGL(k_scan_wide<8>, g, b, lds, st, a); break;
-    case 16: hipLaunchKernelGGL(k_scan_wide<16>, g, b, lds, st, a); break;
+        FBPQ_WIDE_CASE(1)
+        FBPQ_WIDE_CASE(2)
+        FBPQ_WIDE_CASE(4)
+        FBPQ_WIDE_CASE(8)
+        FBPQ_WIDE_CASE(16)
     default: return hipErrorInvalidValue;
     }
+#undef FBPQ_WIDE_CASE
     return hipGetLastError();
 }
 

@@ -230,6 +230,7 @@ __global__ __launch_bounds__(NT) void k_traverse_wide(TravArgs args)
     int cut_a = -1, cut_b = -1;
     int64_t cut_take = 0;
     const bool dbg = args.dbg_ab != nullptr;
+    int64_t n_bands = 0, n_evals = 1, n_loads = 0;  // path counters (thread 0's copies)
 
     while (!done) {
         const int64_t need = Leff - tot;
@@ -251,8 +252,8 @@ __global__ __launch_bounds__(NT) void k_traverse_wide(TravArgs args)
         } else {
             store = false;
             const double e = fmin(est, 4.0e15);
-            lo_t = (int64_t)(0.6 * e);
-            hi_t = (int64_t)(0.85 * e);
+            lo_t = (int64_t)(0.5 * e);
+            hi_t = (int64_t)(0.9 * e);
         }
         if (!over) {
             const int64_t room = args.max_cells - nc + 1;  // a band this large fails the capacity
@@ -263,6 +264,7 @@ __global__ __launch_bounds__(NT) void k_traverse_wide(TravArgs args)
         if (hi_t < 1) hi_t = 1;
 
         // choose the band (tcur, tnew]
+        ++n_bands;
         double tnew;
         int64_t nb;
         bool tie = false;
@@ -280,17 +282,32 @@ __global__ __launch_bounds__(NT) void k_traverse_wide(TravArgs args)
                 wl[r] = w[r];
                 wh[r] = wmax[r];
             }
-            const double tgt = 0.5 * (double)(lo_t + hi_t);
-            double fl = -tgt, fh = (double)ch - tgt;
-            int side = 0;
+            // The cell count grows about like a power of (t - tmin): interpolate
+            // log(count) against log(t - tmin) between the bracket ends; every
+            // fourth step bisects the bit range, so that tl and th meet within
+            // 256 steps
+            const double tmin = k1[0] + k2s[0];
+            const double ytg = log((double)nc + sqrt((double)lo_t * (double)hi_t));
             bool found = false;
-            // regula falsi (Illinois) on the band size, every fourth step a
-            // bisection of the bit range, so that tl and th meet within 256 steps
             for (int it = 0; it < 260; ++it) {
                 const uint64_t ol = dord(tl), oh = dord(th);
                 if (oh - ol <= 1) break;
-                double tm = tl + (th - tl) * (-fl / (fh - fl));
-                if ((it & 3) == 3 || !(tm > tl) || !(tm < th)) tm = dunord(ol + (oh - ol) / 2);
+                double tm = 0.0;
+                bool bis = (it & 3) == 3 || !(th > tmin);
+                if (!bis) {
+                    const double xh = log(th - tmin), yh = log((double)(nc + ch));
+                    double x;
+                    if (tl > tmin) {  // count at tl >= 1
+                        const double xl = log(tl - tmin), yl = log((double)(nc + cl));
+                        x = yh > yl ? xl + (ytg - yl) * (xh - xl) / (yh - yl) : 0.5 * (xl + xh);
+                    } else {
+                        x = xh + (ytg - yh) * 0.125;
+                    }
+                    tm = tmin + exp(x);
+                    bis = !(tm > tl) || !(tm < th);
+                }
+                if (bis) tm = dunord(ol + (oh - ol) / 2);
+                ++n_evals;
                 int wm[R];
                 widths_at(tm, k1r, wl, wh, wm, k2s);
                 int64_t m2 = 0;
@@ -302,17 +319,11 @@ __global__ __launch_bounds__(NT) void k_traverse_wide(TravArgs args)
                     cl = cm;
 #pragma unroll
                     for (int r = 0; r < R; ++r) wl[r] = wm[r];
-                    fl = (double)cm - tgt;
-                    if (side < 0) fh *= 0.5;
-                    side = -1;
                 } else if (cm > hi_t) {
                     th = tm;
                     ch = cm;
 #pragma unroll
                     for (int r = 0; r < R; ++r) wh[r] = wm[r];
-                    fh = (double)cm - tgt;
-                    if (side > 0) fl *= 0.5;
-                    side = 1;
                 } else {
                     tnew = tm;
 #pragma unroll
@@ -371,9 +382,24 @@ __global__ __launch_bounds__(NT) void k_traverse_wide(TravArgs args)
         }
         __syncthreads();
 
+        n_loads += nb;
         if (nb > kWCap && !tie) {
-            // summed band: accept it if it stays below min(L, N), else retry smaller
-            int64_t s = 0;
+            // Summed band, split into kSub sub-bands by threshold (th_[i], th_[i+1]]
+            // with points and cells counted per sub-band. If the band completes
+            // min(L, N), the sub-bands before the one that does are kept and
+            // the search goes on inside that one.
+            constexpr int kSub = 8;
+            double th_[kSub + 1];
+            th_[0] = tcur;
+            th_[kSub] = tnew;
+#pragma unroll
+            for (int i = 1; i < kSub; ++i) {
+                const double t = tcur + (tnew - tcur) * ((double)i / kSub);
+                th_[i] = t > th_[i - 1] ? (t < tnew ? t : tnew) : th_[i - 1];
+            }
+            int64_t sub[kSub];  // (points << 25) | cells, this thread's share
+#pragma unroll
+            for (int i = 0; i < kSub; ++i) sub[i] = 0;
             for (int64_t x0 = 0; x0 < nb; x0 += (int64_t)NT * kWPos) {
                 int xs[kWPos], as[kWPos], bs[kWPos];
                 int n = 0;
@@ -388,20 +414,69 @@ __global__ __launch_bounds__(NT) void k_traverse_wide(TravArgs args)
                 for (int e = 0; e < kWPos; ++e) {
                     if (e < n) {
                         const int64_t c = (int64_t)u[as[e]] * T + v[bs[e]];
-                        s += off[c + 1] - off[c];
+                        const int64_t cnt = off[c + 1] - off[c];
+                        const double key = k1[as[e]] + k2s[bs[e]];
+                        int js = 0;
+#pragma unroll
+                        for (int i = 1; i < kSub; ++i) js += key > th_[i];
+                        const int64_t add = (cnt << 25) | 1;
+#pragma unroll
+                        for (int i = 0; i < kSub; ++i) sub[i] += js == i ? add : 0;
                     }
                 }
             }
-            s = wg_sum<NT>(s, red);
-            rho = fmax((double)s, 0.5) / (double)nb;
-            if (tot + s < Leff) {
-                tot += s;
+            int64_t spts[kSub], scel[kSub];
+#pragma unroll
+            for (int i = 0; i < kSub; ++i) {
+                const int64_t v2 = wg_sum<NT>(sub[i], red);
+                spts[i] = v2 >> 25;
+                scel[i] = v2 & ((1ll << 25) - 1);
+            }
+            int jcut = -1;
+            int64_t pbefore = 0, cbefore = 0;
+#pragma unroll
+            for (int i = 0; i < kSub; ++i) {
+                if (jcut < 0) {
+                    if (tot + pbefore + spts[i] >= Leff) jcut = i;
+                    else {
+                        pbefore += spts[i];
+                        cbefore += scel[i];
+                    }
+                }
+            }
+            if (jcut < 0) {
+                tot += pbefore;
                 nc += nb;
                 tcur = tnew;
 #pragma unroll
                 for (int r = 0; r < R; ++r) w[r] = wn[r];
-                if (nc > args.max_cells) over = true;
+                rho = fmax((double)pbefore, 0.5) / (double)nb;
+            } else {
+                double tj = th_[0];
+#pragma unroll
+                for (int i = 1; i < kSub; ++i)
+                    if (i == jcut) tj = th_[i];
+                if (jcut > 0) {
+                    // keep the sub-bands below jcut: cells with key <= tj
+                    int wa[R];
+                    widths_at(tj, k1r, w, wn, wa, k2s);
+                    ++n_evals;
+                    tot += pbefore;
+                    nc += cbefore;
+                    tcur = tj;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) w[r] = wa[r];
+                }
+                int64_t pj = 0, cj = 1;
+#pragma unroll
+                for (int i = 0; i < kSub; ++i)
+                    if (i == jcut) {
+                        pj = spts[i];
+                        cj = scel[i] > 0 ? scel[i] : 1;
+                    }
+                rho = fmax((double)pj, 0.5) / (double)cj;
             }
+            if (nc > args.max_cells) over = true;
             continue;
         }
 
@@ -594,6 +669,11 @@ __global__ __launch_bounds__(NT) void k_traverse_wide(TravArgs args)
         }
         args.hdr[slot] = h;
         if (status != kStOk) args.fail_list[atomicAdd(args.fail_count, 1)] = (int32_t)qs;
+        if (args.stats) {
+            atomicAdd(&args.stats[kStatWideBands], (unsigned long long)n_bands);
+            atomicAdd(&args.stats[kStatWideEvals], (unsigned long long)n_evals);
+            atomicAdd(&args.stats[kStatWideLoads], (unsigned long long)n_loads);
+        }
     }
 }
 
@@ -616,9 +696,9 @@ hipError_t launch_traverse_wide(const TravArgs &a, int64_t nslots, hipStream_t s
 // ---- workgroup form of the row-major layout, for large visited sets ---------
 // Same outputs as the one-wavefront layout kernel (compacted nonempty cells in
 // row-major order, per-row and per-column starts, column lists, LUT slots),
-// with 256 threads taking kLayE consecutive cells each per step, so that a
-// query with 10^5 visited cells needs about a hundred dependent steps.
-constexpr int kLayNT = 256;
+// with 1024 threads taking kLayE consecutive cells each per step, so that a
+// query with 10^5 visited cells needs about fifty dependent steps.
+constexpr int kLayNT = 1024;
 constexpr int kLayE = 4;
 
 // exclusive prefix of x[0..n) in place (n <= kLayNT * per), returns the total

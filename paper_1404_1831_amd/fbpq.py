@@ -36,7 +36,7 @@ EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbp
 STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2",
           "traverse_wide", "scan_wide")
 STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried", "graph_replays",
-         "wide")
+         "wide", "wide_bands", "wide_evals", "wide_loads")
 
 
 class FbpqError(RuntimeError):
