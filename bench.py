@@ -33,7 +33,7 @@ WORKLOADS = {
     "plain": dict(N=100_000, T=64, M=8, nq=100, L=10_000, k=10),
     # served: Zipf(1.1) cell sizes over T^2 cells, Poisson arrivals
     "served": dict(N=1_000_000_000, T=16384, M=8, L=(10_000, 30_000, 100_000), k=10,
-                   offered=(1000, 2000, 5000, 10000, 20000)),
+                   offered=(1000, 2000, 5000, 10000, 20000, 40000, 80000)),
 }
 
 
@@ -275,8 +275,8 @@ def main() -> int:
                    "N": ix.N, "T": ix.T, "M": ix.M, "nq": nq, "L": L, "k": k},
         "kernels": prof,
         "graph_replay": {"ms_per_step": graph_ms, "value": nq / (graph_ms / 1e3)},
-        "plain_per_query": {"queries": npl, "value": npl / plain_s, "unit": "queries/s",
-                            "ms_per_query": plain_s * 1e3 / npl},
+        "plain_per_query": ({"queries": npl, "value": npl / plain_s, "unit": "queries/s",
+                             "ms_per_query": plain_s * 1e3 / npl} if npl > 0 else None),
         "scan_GBps": scan_GBps,
         "roofline": roof,
         "cpu_baseline": cpu,
