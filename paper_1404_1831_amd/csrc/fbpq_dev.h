@@ -44,7 +44,8 @@ constexpr int kNumStatSlots = 16;
 // Candidate block of the cell scan: up to kItem candidates of one nonempty cell.
 constexpr int kItem = 2048;
 constexpr int kItemMinAvg = 128;   // mean points per nonempty cell for the item scan
-constexpr int kScanWideMin = 8192; // candidates above which a sparse query keeps its sums in HBM
+constexpr int kScanWideMin = 8192; // candidates above which a query with sparse cells (fewer than
+                                   // kItemMinAvg points per nonempty cell) keeps its sums in HBM
 
 // Device view of an index and its tables.
 struct DevIndex {

@@ -441,9 +441,10 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
     for (int b = lane; b < B; b += 64) col_tot[b] = (int32_t)(colcur[b] & ((1ull << 40) - 1ull));
     if (lane == 0) {
         args.hdr[slot].nne = nerun;
-        const bool items = args.allow_items && nerun > 0 && crun >= (int64_t)kItemMinAvg * nerun;
+        const bool dense = nerun > 0 && crun >= (int64_t)kItemMinAvg * nerun;
+        const bool items = args.allow_items && dense;
         args.hdr[slot].n_items = items ? itrun : 0;
-        args.hdr[slot].gscan = !items && crun > kScanWideMin ? 1 : 0;
+        args.hdr[slot].gscan = !dense && crun > kScanWideMin ? 1 : 0;
     }
 }
 

@@ -889,9 +889,10 @@ __global__ __launch_bounds__(kLayNT) void k_layout_wide(LayoutArgs args)
     for (int b = tid; b < B; b += NT) col_tot[b] = (int32_t)(colcur[b] & ((1ull << 40) - 1ull));
     if (tid == 0) {
         args.hdr[slot].nne = (int32_t)nerun;
-        const bool items = args.allow_items && nerun > 0 && crun >= (int64_t)kItemMinAvg * nerun;
+        const bool dense = nerun > 0 && crun >= (int64_t)kItemMinAvg * nerun;
+        const bool items = args.allow_items && dense;
         args.hdr[slot].n_items = items ? (int32_t)itrun : 0;
-        args.hdr[slot].gscan = !items && crun > kScanWideMin ? 1 : 0;
+        args.hdr[slot].gscan = !dense && crun > kScanWideMin ? 1 : 0;
     }
     (void)tne;
 }
