@@ -1,7 +1,8 @@
 """FBPQ oracle -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
 
 ctypes binding of the plain FP64 C oracle in fbpq_oracle.c (Multi-D-ADC with
-explicit displacement reconstruction, Section 2.3 of the paper). Only the test
+explicit displacement reconstruction, Section 2.3 of the paper, and the same
+search with the local codebooks of HBPQ, Section 3.2). Only the test
 suite, the smoke check and the CPU-baseline leg of the benchmark may import
 this package. It never imports the GPU package.
 """
@@ -51,6 +52,11 @@ def _load():
         lib.orc_visit.restype = i64
         lib.orc_search.argtypes = ix_args + [P, i64, P, P, i32, P, P, P, P, ctypes.c_int]
         lib.orc_search.restype = ctypes.c_int
+        lix_args = [ctypes.c_int] * 4 + [i64] + [P] * 7  # QL and SL in place of R
+        lib.orc_search_local.argtypes = lix_args + [P, i64, P, P, i32, P, P, P, P, ctypes.c_int]
+        lib.orc_search_local.restype = ctypes.c_int
+        lib.orc_point_dist_local.argtypes = [ctypes.c_int] * 4 + [P, P, P, P, P, i32, i32, P]
+        lib.orc_point_dist_local.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -60,9 +66,14 @@ def _p(a: np.ndarray):
 
 
 def _ix_args(ix):
-    keep = (np.ascontiguousarray(ix.C1, np.float32), np.ascontiguousarray(ix.C2, np.float32),
-            np.ascontiguousarray(ix.R, np.float32), np.ascontiguousarray(ix.offsets, np.int64),
-            np.ascontiguousarray(ix.codes, np.uint8), np.ascontiguousarray(ix.ids, np.uint32))
+    """Arguments of the C entry points. With local codebooks (ix.QL set) the
+    codebook arguments are QL, SL (the *_local entry points), else R."""
+    local = getattr(ix, "QL", None) is not None
+    books = ((np.ascontiguousarray(ix.QL, np.float32), np.ascontiguousarray(ix.SL, np.float32)) if local
+             else (np.ascontiguousarray(ix.R, np.float32),))
+    keep = (np.ascontiguousarray(ix.C1, np.float32), np.ascontiguousarray(ix.C2, np.float32)) + books + (
+        np.ascontiguousarray(ix.offsets, np.int64), np.ascontiguousarray(ix.codes, np.uint8),
+        np.ascontiguousarray(ix.ids, np.uint32))
     return keep, [ix.D, ix.T, ix.M, ix.Kc, ix.N] + [_p(a) for a in keep]
 
 
@@ -103,8 +114,23 @@ def point_dist(ix, q: np.ndarray, i: int, j: int, code: np.ndarray) -> float:
                                   int(i), int(j), _p(code))
 
 
+def point_dist_local(ix, q: np.ndarray, i: int, j: int, code: np.ndarray) -> float:
+    """FP64 distance to the reconstruction with the local codebooks of ix."""
+    q = np.ascontiguousarray(q, np.float32)
+    code = np.ascontiguousarray(code, np.uint8)
+    C1 = np.ascontiguousarray(ix.C1, np.float32)
+    C2 = np.ascontiguousarray(ix.C2, np.float32)
+    QL = np.ascontiguousarray(ix.QL, np.float32)
+    SL = np.ascontiguousarray(ix.SL, np.float32)
+    return _load().orc_point_dist_local(ix.D, ix.T, ix.M, ix.Kc, _p(C1), _p(C2), _p(QL), _p(SL), _p(q),
+                                        int(i), int(j), _p(code))
+
+
 def visit(ix, q: np.ndarray, L: int, cells_cap: int = 1 << 20):
     """Visited cells [(cell id, points taken)] and candidate storage positions."""
+    if getattr(ix, "QL", None) is not None:
+        import dataclasses
+        ix = dataclasses.replace(ix, QL=None, SL=None)  # the traversal does not read codebooks
     keep, args = _ix_args(ix)
     q = np.ascontiguousarray(q, np.float32)
     Leff = max(0, min(int(L), ix.N))
@@ -143,8 +169,8 @@ def search(ix, Q: np.ndarray, L, k, kmax: int | None = None, nthreads: int | Non
     if nthreads is None:
         nthreads = DEFAULT_THREADS or min(16, os.cpu_count() or 1)
     nthreads = max(1, min(int(nthreads), max(nq, 1)))
-    rc = _load().orc_search(*args, _p(Q), nq, _p(L), _p(k), kmax, _p(ids), _p(d), _p(ncand),
-                            _p(ncells), nthreads)
+    fn = _load().orc_search_local if getattr(ix, "QL", None) is not None else _load().orc_search
+    rc = fn(*args, _p(Q), nq, _p(L), _p(k), kmax, _p(ids), _p(d), _p(ncand), _p(ncells), nthreads)
     if rc != 0:
         raise RuntimeError("orc_search failed")
     return ids, d, ncand, ncells

@@ -27,6 +27,13 @@
  *  - cell id = i*T + j; within a cell points keep their storage order;
  *  - results are ordered by (distance, id); missing entries are (-1, +inf);
  *  - subspace k of the PQ code covers coordinates [k*D/M, (k+1)*D/M).
+ *
+ * The same search with local codebooks (HBPQ, Section 3.2) takes, instead of
+ * the global codebooks R, one set of M/2 codebooks per first-half centroid
+ * (Q^i, coding the first half of a displacement in a cell of row i) and one
+ * per second-half centroid (S^j, the second half in a cell of column j), as in
+ * equation (residual); the traversal is unchanged and the distance is again
+ * computed by explicit reconstruction.
  */
 #include <math.h>
 #include <pthread.h>
@@ -41,6 +48,7 @@ typedef struct {
     const int64_t *offsets;
     const uint8_t *codes;
     const uint32_t *ids;
+    const float *QL, *SL; /* local codebooks [T][M/2][Kc][D/M] each, or NULL (global R) */
 } orc_ix;
 
 /* Squared distance from a query half to every half centroid (equations q1 and
@@ -226,21 +234,47 @@ static int64_t orc_collect(const orc_ix *ix, orc_work *w, const float *q, int64_
 
 /* Squared distance from q to the reconstruction of equation (approximation):
  * x ~ [c1_i; c2_j] + [R_1(b_1); ...; R_M(b_M)], computed coordinate by
- * coordinate in FP64 -- the O(D) rerank of Section 2.3.3. */
-double orc_point_dist(int D, int T, int M, int Kc, const float *C1, const float *C2,
-                      const float *R, const float *q, int32_t i, int32_t j, const uint8_t *code)
+ * coordinate in FP64 -- the O(D) rerank of Section 2.3.3. With local
+ * codebooks (QL, SL non-NULL) the codeword of subspace k < M/2 comes from
+ * Q^i_k and that of subspace M/2 + k from S^j_k (equation residual). */
+static double orc_dist(int D, int M, int Kc, const float *C1, const float *C2, const float *R,
+                       const float *QL, const float *SL, const float *q, int32_t i, int32_t j,
+                       const uint8_t *code)
 {
-    const int h = D / 2, ds = D / M;
-    (void)T;
+    const int h = D / 2, ds = D / M, mh = M / 2;
     double acc = 0.0;
     for (int t = 0; t < D; ++t) {
         const double c = t < h ? (double)C1[(int64_t)i * h + t] : (double)C2[(int64_t)j * h + (t - h)];
         const int k = t / ds;
-        const double r = (double)R[((int64_t)k * Kc + code[k]) * ds + (t - k * ds)];
+        const int64_t w = t - (int64_t)k * ds;
+        double r;
+        if (!QL) {
+            r = (double)R[((int64_t)k * Kc + code[k]) * ds + w];
+        } else if (k < mh) {
+            r = (double)QL[(((int64_t)i * mh + k) * Kc + code[k]) * ds + w];
+        } else {
+            r = (double)SL[(((int64_t)j * mh + (k - mh)) * Kc + code[k]) * ds + w];
+        }
         const double e = (double)q[t] - (c + r);
         acc += e * e;
     }
     return acc;
+}
+
+double orc_point_dist(int D, int T, int M, int Kc, const float *C1, const float *C2,
+                      const float *R, const float *q, int32_t i, int32_t j, const uint8_t *code)
+{
+    (void)T;
+    return orc_dist(D, M, Kc, C1, C2, R, NULL, NULL, q, i, j, code);
+}
+
+/* The same with local codebooks QL, SL ([T][M/2][Kc][D/M] each). */
+double orc_point_dist_local(int D, int T, int M, int Kc, const float *C1, const float *C2,
+                            const float *QL, const float *SL, const float *q, int32_t i, int32_t j,
+                            const uint8_t *code)
+{
+    (void)T;
+    return orc_dist(D, M, Kc, C1, C2, NULL, QL, SL, q, i, j, code);
 }
 
 /* Second step (Section 2.3.3): rerank the candidates by increasing distance,
@@ -250,8 +284,8 @@ static void orc_rerank(const orc_ix *ix, orc_work *w, const float *q, int64_t nc
 {
     for (int64_t p = 0; p < ncand; ++p) {
         const int64_t s = w->cand_pos[p];
-        w->dl[p].d = orc_point_dist(ix->D, ix->T, ix->M, ix->Kc, ix->C1, ix->C2, ix->R, q,
-                                    w->cand_i[p], w->cand_j[p], ix->codes + s * ix->M);
+        w->dl[p].d = orc_dist(ix->D, ix->M, ix->Kc, ix->C1, ix->C2, ix->R, ix->QL, ix->SL, q,
+                              w->cand_i[p], w->cand_j[p], ix->codes + s * ix->M);
         w->dl[p].i = (int32_t)p;
     }
     /* stable merge sort by (distance, id); ids are unique */
@@ -294,7 +328,7 @@ static orc_ix orc_make(int D, int T, int M, int Kc, int64_t N, const float *C1, 
                        const float *R, const int64_t *offsets, const uint8_t *codes,
                        const uint32_t *ids)
 {
-    orc_ix ix = { D, T, M, Kc, N, C1, C2, R, offsets, codes, ids };
+    orc_ix ix = { D, T, M, Kc, N, C1, C2, R, offsets, codes, ids, NULL, NULL };
     return ix;
 }
 
@@ -371,13 +405,9 @@ static void *orc_worker(void *arg)
 /* Full search for nq queries with per-query budgets L[q] and k[q] <= kmax,
  * queries split statically over nthreads POSIX threads. Outputs are
  * [nq][kmax]. Returns 0, or -1 on allocation failure. */
-int orc_search(int D, int T, int M, int Kc, int64_t N, const float *C1, const float *C2,
-               const float *R, const int64_t *offsets, const uint8_t *codes, const uint32_t *ids,
-               const float *Q, int64_t nq, const int64_t *L, const int32_t *k, int32_t kmax,
-               int64_t *out_ids, double *out_d, int64_t *out_ncand, int64_t *out_ncells,
-               int nthreads)
+static int orc_run(orc_ix ix, const float *Q, int64_t nq, const int64_t *L, const int32_t *k, int32_t kmax,
+                   int64_t *out_ids, double *out_d, int64_t *out_ncand, int64_t *out_ncells, int nthreads)
 {
-    orc_ix ix = orc_make(D, T, M, Kc, N, C1, C2, R, offsets, codes, ids);
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     pthread_t th[256];
@@ -401,4 +431,28 @@ int orc_search(int D, int T, int M, int Kc, int64_t N, const float *C1, const fl
         if (jobs[t].err) err = jobs[t].err;
     }
     return err;
+}
+
+int orc_search(int D, int T, int M, int Kc, int64_t N, const float *C1, const float *C2,
+               const float *R, const int64_t *offsets, const uint8_t *codes, const uint32_t *ids,
+               const float *Q, int64_t nq, const int64_t *L, const int32_t *k, int32_t kmax,
+               int64_t *out_ids, double *out_d, int64_t *out_ncand, int64_t *out_ncells,
+               int nthreads)
+{
+    orc_ix ix = orc_make(D, T, M, Kc, N, C1, C2, R, offsets, codes, ids);
+    return orc_run(ix, Q, nq, L, k, kmax, out_ids, out_d, out_ncand, out_ncells, nthreads);
+}
+
+/* The same search with local codebooks QL, SL ([T][M/2][Kc][D/M] each): the
+ * HBPQ query processing of Section 3.2 (the traversal is that of Section 2.3). */
+int orc_search_local(int D, int T, int M, int Kc, int64_t N, const float *C1, const float *C2,
+                     const float *QL, const float *SL, const int64_t *offsets, const uint8_t *codes,
+                     const uint32_t *ids, const float *Q, int64_t nq, const int64_t *L, const int32_t *k,
+                     int32_t kmax, int64_t *out_ids, double *out_d, int64_t *out_ncand,
+                     int64_t *out_ncells, int nthreads)
+{
+    orc_ix ix = orc_make(D, T, M, Kc, N, C1, C2, NULL, offsets, codes, ids);
+    ix.QL = QL;
+    ix.SL = SL;
+    return orc_run(ix, Q, nq, L, k, kmax, out_ids, out_d, out_ncand, out_ncells, nthreads);
 }

@@ -15,6 +15,8 @@ from .gen import (  # noqa: F401
     make_queries,
     draw_L_k,
     lossless_index,
+    lossless_local_index,
+    with_local_codebooks,
     random_index,
     zipf_index,
     tiny_index,

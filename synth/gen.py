@@ -42,6 +42,9 @@ class Index:
     ids:     uint32  [N]            original point id of each stored point
     base:    optional [N, D] raw vectors indexed by original id (uint8 or
              float32), kept for exact-NN recall
+    QL, SL:  optional float32 [T, M/2, Kc, D/M] local codebooks (HBPQ): QL[i]
+             codes the first half of the displacements in the cells of row i,
+             SL[j] the second half in the cells of column j; R is then unused
     """
 
     D: int
@@ -56,6 +59,12 @@ class Index:
     Kc: int = KC
     base: Optional[np.ndarray] = None
     meta: dict = field(default_factory=dict)
+    QL: Optional[np.ndarray] = None
+    SL: Optional[np.ndarray] = None
+
+    @property
+    def local(self) -> bool:
+        return self.QL is not None
 
     @property
     def N(self) -> int:
@@ -72,6 +81,11 @@ class Index:
         assert self.ids.shape == (self.N,) and self.ids.dtype == np.uint32
         assert self.offsets[0] == 0 and self.offsets[-1] == self.N
         assert np.all(np.diff(self.offsets) >= 0)
+        if self.QL is not None or self.SL is not None:
+            shp = (T, M // 2, Kc, D // M)
+            assert self.QL is not None and self.SL is not None
+            assert self.QL.shape == shp and self.QL.dtype == np.float32
+            assert self.SL.shape == shp and self.SL.dtype == np.float32
 
 
 def _gen(seed: int, device) -> torch.Generator:
@@ -243,6 +257,54 @@ def lossless_index(N: int, T: int, M: int, D: int = 16, seed: int = 7, dup: int 
         ix.ids = perm[ix.ids.astype(np.int64)].astype(np.uint32)
         ix.base = newbase
     return ix
+
+
+def lossless_local_index(N: int, T: int, M: int, D: int = 16, seed: int = 13, dup: int = 0) -> Index:
+    """Points built exactly as [c1_i + (Q^i_1(b_1), ..., Q^i_{M/2}(b_{M/2}));
+    c2_j + (S^j_1(b_{M/2+1}), ...)] with local codebooks that differ from
+    centroid to centroid (equation residual of Section 3.2). Every coordinate is
+    a small integer, so the reconstruction is exact and `base` equals it."""
+    g = _gen(seed, "cpu")
+    h, ds, mh = D // 2, D // M, M // 2
+    C1 = torch.randint(-40, 41, (T, h), generator=g).to(torch.float32).numpy()
+    C2 = torch.randint(-40, 41, (T, h), generator=g).to(torch.float32).numpy()
+    R = np.zeros((M, KC, ds), np.float32)  # unused with local codebooks
+    QL = torch.randint(-8, 9, (T, mh, KC, ds), generator=g).to(torch.float32).numpy()
+    SL = torch.randint(-8, 9, (T, mh, KC, ds), generator=g).to(torch.float32).numpy()
+    i = torch.randint(0, T, (N,), generator=g).numpy()
+    j = torch.randint(0, T, (N,), generator=g).numpy()
+    codes = torch.randint(0, KC, (N, M), generator=g).to(torch.uint8).numpy()
+    if dup:
+        src = torch.randint(0, N - dup, (dup,), generator=g).numpy()
+        i[N - dup:], j[N - dup:], codes[N - dup:] = i[src], j[src], codes[src]
+    base = np.concatenate([C1[i], C2[j]], 1)
+    for k in range(mh):
+        base[:, k * ds:(k + 1) * ds] += QL[i, k, codes[:, k]]
+        base[:, h + k * ds:h + (k + 1) * ds] += SL[j, k, codes[:, mh + k]]
+    ix = _from_cells(D, T, M, C1, C2, R, i * T + j, codes, base.astype(np.float32),
+                     dict(kind="lossless_local", seed=seed))
+    ix.QL, ix.SL = QL, SL
+    ix.check()
+    return ix
+
+
+def with_local_codebooks(ix: Index, seed: int = 17, scale: float = 0.25) -> Index:
+    """The same index with local codebooks: Q^i_k = R_k + noise and S^j_k =
+    R_{M/2+k} + noise, seeded, the noise `scale` times the codebook's standard
+    deviation. The codes stay the global encoding (the per-cell training of
+    Section 3.2 is outside this generator); the search cost does not depend on
+    how the codes were chosen."""
+    g = _gen(seed, "cpu")
+    T, M, D = ix.T, ix.M, ix.D
+    mh, ds = M // 2, D // M
+    R = torch.from_numpy(ix.R)
+    sd = float(R.std()) * scale
+    QL = (R[:mh][None] + sd * torch.randn((T, mh, KC, ds), generator=g)).to(torch.float32).numpy()
+    SL = (R[mh:][None] + sd * torch.randn((T, mh, KC, ds), generator=g)).to(torch.float32).numpy()
+    out = Index(D=D, T=T, M=M, C1=ix.C1, C2=ix.C2, R=ix.R, offsets=ix.offsets, codes=ix.codes,
+                ids=ix.ids, Kc=ix.Kc, base=ix.base, meta=dict(ix.meta, local_seed=seed), QL=QL, SL=SL)
+    out.check()
+    return out
 
 
 def random_index(N: int, T: int, M: int, D: int = 16, seed: int = 11,

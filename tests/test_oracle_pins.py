@@ -219,3 +219,58 @@ def test_empty_index_and_threads_agree():
     b = oracle.search(ix, Q, L, k, kmax=20, nthreads=4)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+# ---- local codebooks (HBPQ, Section 3.2) -----------------------------------------
+
+def test_local_lossless_equals_exact_knn():
+    """Points built from local codebooks that differ per centroid: the search
+    with those codebooks returns the exact kNN (equation residual); the same
+    index searched with the two codebook sets exchanged does not."""
+    import dataclasses
+    ix = synth.lossless_local_index(N=3000, T=8, M=4, D=16, seed=13, dup=300)
+    rng = np.random.default_rng(6)
+    Q = ix.base[ix.ids[-rng.integers(1, 300, 6)]] + rng.integers(-1, 2, (6, 16)).astype(np.float32)
+    k = 25
+    ids, d, ncand, _ = oracle.search(ix, Q, ix.N + 10, k, nthreads=2)
+    X = ix.base.astype(np.float64)
+    for r in range(Q.shape[0]):
+        dd = ((X - Q[r].astype(np.float64)) ** 2).sum(1)
+        order = np.lexsort((np.arange(ix.N), dd))[:k]
+        assert np.array_equal(ids[r], order)
+        assert np.array_equal(d[r], dd[order])
+        assert ncand[r] == ix.N
+    swapped = dataclasses.replace(ix, QL=ix.SL, SL=ix.QL)
+    s_ids, s_d, _, _ = oracle.search(swapped, Q, ix.N + 10, k, nthreads=2)
+    assert not np.array_equal(s_d, d)
+
+
+def test_local_with_global_codebooks_is_the_global_search():
+    """Local codebooks that all equal the global ones reduce the search to
+    Multi-D-ADC: same ids and bit-identical distances."""
+    import dataclasses
+    ix = synth.random_index(N=4000, T=16, M=8, D=32, seed=21)
+    mh = ix.M // 2
+    QL = np.ascontiguousarray(np.broadcast_to(ix.R[:mh][None], (ix.T,) + ix.R[:mh].shape), np.float32)
+    SL = np.ascontiguousarray(np.broadcast_to(ix.R[mh:][None], (ix.T,) + ix.R[mh:].shape), np.float32)
+    loc = dataclasses.replace(ix, QL=QL, SL=SL)
+    rng = np.random.default_rng(3)
+    Q = rng.normal(0, 30, (8, ix.D)).astype(np.float32)
+    for L in (1, 500, 3000, 10_000):
+        g_ids, g_d, g_n, _ = oracle.search(ix, Q, L, 20)
+        l_ids, l_d, l_n, _ = oracle.search(loc, Q, L, 20)
+        assert np.array_equal(g_ids, l_ids) and np.array_equal(g_d, l_d) and np.array_equal(g_n, l_n)
+
+
+def test_local_point_dist_uses_row_and_column_codebooks():
+    """One stored point of the lossless local index: its distance to itself is
+    0, and the distance to any query equals the exact Euclidean distance."""
+    ix = synth.lossless_local_index(N=500, T=6, M=4, D=16, seed=14)
+    rng = np.random.default_rng(9)
+    cells = np.repeat(np.arange(ix.T * ix.T), np.diff(ix.offsets))
+    for s in rng.integers(0, ix.N, 10):
+        i, j = divmod(int(cells[s]), ix.T)
+        x = ix.base[ix.ids[s]]
+        assert oracle.point_dist_local(ix, x, i, j, ix.codes[s]) == 0.0
+        q = rng.integers(-50, 50, ix.D).astype(np.float32)
+        assert oracle.point_dist_local(ix, q, i, j, ix.codes[s]) == float(((q.astype(np.float64) - x) ** 2).sum())
