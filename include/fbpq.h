@@ -62,7 +62,13 @@ typedef struct fbpq_index fbpq_index;
  *   R        float  [M][Kc][D/M]   displacement codebooks R_1..R_M
  *   offsets  int64  [T*T + 1]      start of each cell in storage order (Section 2.3.2)
  *   codes    uint8  [N][M]         PQ code of each stored point
- *   ids      uint32 [N]            point id of each stored point              */
+ *   ids      uint32 [N]            point id of each stored point
+ *   QL, SL   float  [T][M/2][Kc][D/M] each, or both NULL: local codebooks
+ *            (HBPQ, Section 3.2). QL[i] codes the first half of the
+ *            displacements in the cells (i, *), SL[j] the second half in the
+ *            cells (*, j) (equation residual); R is then not used. With them
+ *            the search returns the kNN of the reconstructions through the
+ *            local codebooks; without them, the FBPQ / Multi-D-ADC result. */
 typedef struct {
     int32_t D, T, M, Kc;
     int64_t N;
@@ -72,6 +78,8 @@ typedef struct {
     const int64_t *offsets;
     const uint8_t *codes;
     const uint32_t *ids;
+    const float *QL;
+    const float *SL;
 } fbpq_index_desc;
 
 typedef struct {

@@ -49,6 +49,7 @@ struct fbpq_index {
     hipStream_t stream = nullptr;
     // owned device allocations
     float *C1 = nullptr, *C2 = nullptr, *R = nullptr;
+    float *QL = nullptr, *SL = nullptr;  // local codebooks (HBPQ), or null
     int64_t *offsets = nullptr;
     uint8_t *codesA = nullptr, *codesB = nullptr;
     uint32_t *ids = nullptr;
@@ -231,6 +232,8 @@ int check_desc(const fbpq_index_desc *d)
     if (d->D > 4096) return fail(FBPQ_E_FORMAT, "D=%d too large", d->D);
     if (!d->C1 || !d->C2 || !d->R || !d->offsets || (d->N > 0 && (!d->codes || !d->ids)))
         return fail(FBPQ_E_INVALID, "null array in descriptor");
+    if ((d->QL == nullptr) != (d->SL == nullptr))
+        return fail(FBPQ_E_INVALID, "local codebooks need both QL and SL");
     const int64_t C = (int64_t)d->T * d->T;
     if (d->offsets[0] != 0 || d->offsets[C] != d->N)
         return fail(FBPQ_E_FORMAT, "offsets must start at 0 and end at N");
@@ -259,7 +262,7 @@ void free_all(fbpq_index *ix)
     (void)hipSetDevice(ix->device);
     if (ix->stream) (void)hipStreamSynchronize(ix->stream);
     void *ps[] = {ix->C1, ix->C2, ix->R, ix->offsets, ix->codesA, ix->codesB, ix->ids,
-                  ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2};
+                  ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2, ix->QL, ix->SL};
     if (!ix->shared)
         for (void *p : ps)
             if (p) (void)hipFree(p);
@@ -298,6 +301,8 @@ int create_impl(const fbpq_index_desc *d, int device, fbpq_index **out)
     if (!rc) rc = upload(ix, &ix->C2, d->C2, sizeof(float) * T * h);
     if (!rc) rc = upload(ix, &ix->R, d->R, sizeof(float) * M * FBPQ_KC * (d->D / M));
     if (!rc) rc = upload(ix, &ix->offsets, d->offsets, sizeof(int64_t) * (C + 1));
+    if (!rc && d->QL) rc = upload(ix, &ix->QL, d->QL, sizeof(float) * T * FBPQ_KC * h);
+    if (!rc && d->SL) rc = upload(ix, &ix->SL, d->SL, sizeof(float) * T * FBPQ_KC * h);
     if (!rc) rc = upload(ix, &ix->ids, d->ids, sizeof(uint32_t) * N);
     if (!rc) {
         const size_t half = (size_t)N * (M / 2);
@@ -346,6 +351,9 @@ int create_impl(const fbpq_index_desc *d, int device, fbpq_index **out)
     v.codesA = ix->codesA;
     v.codesB = ix->codesB;
     v.ids = ix->ids;
+    v.QL = ix->QL;
+    v.SL = ix->SL;
+    v.local = ix->QL ? 1 : 0;
     *out = ix;
     return FBPQ_OK;
 }
@@ -641,7 +649,8 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         ia.dbg_pos = (int64_t *)dpos;
         ia.dbg_d = (float *)ddd;
         ia.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
-        HCK(ix, timed(ix, FBPQ_STAGE_LQ, st, [&] { return launch_items_prep(ia, st); }));
+        if (!dv.local)  // local codebooks fold the query part per row and column instead
+            HCK(ix, timed(ix, FBPQ_STAGE_LQ, st, [&] { return launch_items_prep(ia, st); }));
         if (ix->items) HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_scan(ia, st); }));
         ScanArgs sa{};
         sa.ix = dv;
@@ -965,6 +974,8 @@ int lane_create(fbpq_index *src, fbpq_index **out)
     ix->codesA = src->codesA;
     ix->codesB = src->codesB;
     ix->ids = src->ids;
+    ix->QL = src->QL;
+    ix->SL = src->SL;
     ix->CR1 = src->CR1;
     ix->CR2 = src->CR2;
     ix->nR = src->nR;

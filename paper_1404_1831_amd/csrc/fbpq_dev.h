@@ -44,6 +44,7 @@ constexpr int kNumStatSlots = 16;
 // Candidate block of the cell scan: up to kItem candidates of one nonempty cell.
 constexpr int kItem = 2048;
 constexpr int kItemMinAvg = 128;   // mean points per nonempty cell for the item scan
+constexpr int kWideChunk = 2048;   // candidates of one task of the HBM two-pass scan
 constexpr int kScanWideMin = 8192; // candidates above which a query with sparse cells (fewer than
                                    // kItemMinAvg points per nonempty cell) keeps its sums in HBM
 
@@ -56,8 +57,10 @@ struct DevIndex {
     const uint8_t *codesA;  // [N][M/2] bytes of subspaces 0..M/2-1
     const uint8_t *codesB;  // [N][M/2] bytes of subspaces M/2..M-1
     const uint32_t *ids;
-    const float *CR1, *CR2, *nR, *nC1, *nC2;
+    const float *CR1, *CR2, *nR, *nC1, *nC2;  // CR1/CR2 hold CQ1/CQ2 with local codebooks
     float cmax1, cmax2;  // largest squared half-centroid norm of each half
+    const float *QL, *SL;  // local codebooks [T][M/2][Kc][D/M] (HBPQ), or null
+    int32_t local;         // 1: local codebooks
 };
 
 // Launchers (each defined next to its kernel).

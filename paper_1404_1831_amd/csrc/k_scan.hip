@@ -290,29 +290,70 @@ __global__ __launch_bounds__(512) void k_scan2(ScanArgs a)
 }
 
 // ============================ wide two-pass scan ==============================
-// Queries with more than kScanWideMin candidates in sparse cells. The partial
-// sums live in the query's HBM distance row (index = row-major candidate
-// number), so every row table LUT1_i and column table LUT2_j is folded once
-// per query however many candidates there are. Each wavefront takes whole rows
-// (then whole columns) and folds their tables in its own LDS region, without
-// workgroup barriers; the k smallest are selected afterwards from the row.
+// Queries with more than kScanWideMin candidates in sparse cells, and every
+// query of an index with local codebooks. The partial sums live in the
+// query's HBM distance row (index = row-major candidate number), so each row
+// table LUT1_i and column table LUT2_j is folded once per task. The rows
+// (then the columns) are cut into tasks of at most kWideChunk candidates;
+// wavefront w takes tasks w, w + NW, ... and folds each task's table in its
+// own LDS region, without workgroup barriers. The k smallest are selected
+// afterwards from the row.
+//
+// Folded tables: with the global codebooks LUT1_i = LQ[k<M/2] + CR1[i]; with
+// local codebooks (HBPQ, Section 3.2) LUT1_i = CQ1[i] - 2 <q1|k, Q^i_k(r)>,
+// the query part computed here from the row's own codebooks (and likewise for
+// the columns with S^j).
 // Wavefronts per query: as many as 64 KB of folded tables allow, up to 16.
 template <int MH>
 constexpr int wide_waves() { return MH <= 4 ? 16 : (MH == 8 ? 8 : 4); }
+constexpr int kWideRanks = 4097;  // task prefix entries (ranks up to 4096, plus the total)
 
-template <int MH>
+// exclusive prefix of x[0..n) in place, n <= kWideRanks; every thread calls it
+template <int NT>
+__device__ void wide_scan(int *x, int n, int *wtot)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int per = (n + NT - 1) / NT;
+    const int i0 = tid * per, i1 = i0 + per < n ? i0 + per : n;
+    int s = 0;
+    for (int i = i0; i < i1; ++i) s += x[i];
+    int v = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(v, o);
+        if (lane >= o) v += y;
+    }
+    __syncthreads();
+    if (lane == 63) wtot[wv] = v;
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wv; ++w) before += wtot[w];
+    int run = before + v - s;
+    for (int i = i0; i < i1; ++i) {
+        const int t = x[i];
+        x[i] = run;
+        run += t;
+    }
+    __syncthreads();
+}
+
+template <int MH, bool LOCAL>
 __global__ __launch_bounds__(64 * wide_waves<MH>()) void k_scan_wide(ScanArgs a)
 {
     constexpr int NW = wide_waves<MH>();
+    constexpr int NT = 64 * NW;
     constexpr int TL = MH * kKc;  // floats of one folded half table
-    extern __shared__ __align__(16) float wlut[];  // [NW][TL]
+    extern __shared__ __align__(16) float wlut[];  // [NW][TL], then the task prefix [kWideRanks], then q [D]
+    __shared__ int wtot[NW];
     const int slot = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const TravHdr h = a.hdr[slot];
     if (h.status != kStOk || !h.gscan) return;
     if (a.stats && tid == 0) atomicAdd(&a.stats[kStatTwoPass], 1ull);
     float *lut = wlut + wv * TL;
+    int *tpre = reinterpret_cast<int *>(wlut + NW * TL);
+    float *qs = reinterpret_cast<float *>(tpre + kWideRanks);
     const int P = a.P;
+    const int D = a.ix.D, ds = D / (2 * MH);
     const int64_t mc = a.max_cells;
     const int32_t *t_cs = a.ne_cs + slot * mc;
     const int64_t *t_beg = a.ne_beg + slot * mc;
@@ -329,131 +370,180 @@ __global__ __launch_bounds__(64 * wide_waves<MH>()) void k_scan_wide(ScanArgs a)
     float *dist = a.dist + (int64_t)slot * a.lcap;
     const uint64_t below_lane = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
     const int A = h.A, B = h.B;
+    if (LOCAL) {
+        const int64_t qsl = a.qlist ? a.qlist[slot] : slot;
+        for (int t = tid; t < D; t += NT) qs[t] = a.q[qsl * D + t];
+    }
 
-    // The first candidate chunk of a row (column) starts at its first cell; each
-    // next chunk starts at the cell holding the previous chunk's last candidate,
-    // or at the one after it. The folded table of the next row (column) is
-    // loaded into registers while the current one is scored.
-    constexpr int TQ = TL / 4 / 64 > 0 ? TL / 4 / 64 : 1;  // float4 of a table per lane
-    const bool tq_full = TL / 4 >= 64;
+    constexpr int TQ = TL / 4 / 64;  // float4 of a table per lane
     float4 nxt[TQ];
+    // the global-codebook fold reads the CR row prefetched into nxt
     auto fetch = [&](const float *crrow) __attribute__((always_inline)) {
+        if (LOCAL) return;
         const float4 *cr = reinterpret_cast<const float4 *>(crrow);
 #pragma unroll
-        for (int e = 0; e < TQ; ++e) {
-            const int f = lane + 64 * e;
-            if (tq_full || f < TL / 4) nxt[e] = cr[f];
-        }
+        for (int e = 0; e < TQ; ++e) nxt[e] = cr[lane + 64 * e];
     };
-    auto fold = [&](const float *lqh) __attribute__((always_inline)) {
-        const float4 *lq4 = reinterpret_cast<const float4 *>(lqh);
+    auto fold = [&](int half, int cent) __attribute__((always_inline)) {
         __builtin_amdgcn_wave_barrier();  // the previous table's lookups are done
+        if (LOCAL) {
+            // CQ[cent] - 2 <q|k, Q_k(r)> with the codebooks of this centroid
+            const float *cq = (half ? a.ix.CR2 : a.ix.CR1) + (int64_t)cent * TL;
+            const float *cb = (half ? a.ix.SL : a.ix.QL) + (int64_t)cent * TL * ds;
+            const float *qh = qs + half * (D / 2);
+            for (int f = lane; f < TL; f += 64) {
+                const int k = f >> 8;
+                const float *w = cb + (int64_t)f * ds;
+                const float *qk = qh + k * ds;
+                float acc = 0.f;
+                for (int t = 0; t < ds; ++t) acc = fmaf(qk[t], w[t], acc);
+                lut[f] = cq[f] - 2.f * acc;
+            }
+        } else {
+            const float4 *lq4 = reinterpret_cast<const float4 *>(lq + half * TL);
 #pragma unroll
-        for (int e = 0; e < TQ; ++e) {
-            const int f = lane + 64 * e;
-            if (tq_full || f < TL / 4) {
+            for (int e = 0; e < TQ; ++e) {
+                const int f = lane + 64 * e;
                 const float4 x = lq4[f], y = nxt[e];
                 reinterpret_cast<float4 *>(lut)[f] = make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
             }
         }
         __builtin_amdgcn_wave_barrier();
     };
-    auto next_row = [&](int ar) __attribute__((always_inline)) {
-        while (ar < A && row_cand[ar] >= row_cand[ar + 1]) ar += NW;
-        return ar;
-    };
-    auto next_col = [&](int b) __attribute__((always_inline)) {
-        while (b < B && col_ne[b] >= col_ne[b + 1]) b += NW;
-        return b;
-    };
 
-    // pass 1: rows, first half of the code plus the cell constant
-    int ar = next_row(wv);
-    if (ar < A) fetch(a.ix.CR1 + (int64_t)u[ar] * TL);
-    while (ar < A) {
-        fold(lq);
-        const int an = next_row(ar + NW);
-        if (an < A) fetch(a.ix.CR1 + (int64_t)u[an] * TL);
-        const int64_t rs = row_cand[ar], re = row_cand[ar + 1];
-        const int xe = row_ne[ar + 1];
-        int x0 = row_ne[ar];
-        for (int64_t t0 = rs; t0 < re; t0 += 64) {
-            const int x = x0 + lane;
-            int32_t cs = 0;
-            int64_t beg = 0;
-            float cst = 0.f;
-            bool vc = false;
-            if (x < xe) {
-                cs = t_cs[x];
-                vc = cs < t0 + 64;
-                beg = t_beg[x];
-                cst = t_cst[x];
+    // ---- pass 1: row tasks, first half of the code plus the cell constant ----
+    for (int ar = tid; ar <= A; ar += NT)
+        tpre[ar] = ar < A ? (row_cand[ar + 1] - row_cand[ar] + kWideChunk - 1) / kWideChunk : 0;
+    __syncthreads();
+    wide_scan<NT>(tpre, A + 1, wtot);
+    {
+        const int ntask = tpre[A];
+        auto task_row = [&](int tk) __attribute__((always_inline)) {
+            int lo = 0, hi = A - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (tpre[mid] <= tk) lo = mid;
+                else hi = mid - 1;
             }
-            const int sr = cs > t0 ? (int)(cs - t0) : 0;
-            const uint64_t mask = wave_or64(vc ? (1ull << sr) : 0ull);
-            const int owner = __popcll(mask & below_lane) - 1;
-            const int32_t cso = __shfl(cs, owner);
-            const int64_t bego = __shfl(beg, owner);
-            const float csto = __shfl(cst, owner);
-            const int64_t t = t0 + lane;
-            if (t < re) dist[t] = lut_sum<MH>(lut, a.ix.codesA, bego + (t - cso)) + csto;
-            // cell of candidate t0 + 64: that of lane 63's candidate, or the next
-            int xn = x0 + __shfl(owner, 63);
-            const int csn = __shfl(cs, (__shfl(owner, 63) + 1) & 63);
-            if (__shfl(owner, 63) < 63 && xn + 1 < xe && csn <= t0 + 64) ++xn;
-            else if (__shfl(owner, 63) == 63 && xn + 1 < xe && t_cs[xn + 1] <= t0 + 64) ++xn;
-            x0 = xn;
-        }
-        ar = an;
-    }
-    __syncthreads();  // every partial sum of the query is stored
-    // pass 2: columns, second half of the code
-    int b = next_col(wv);
-    if (b < B) fetch(a.ix.CR2 + (int64_t)v[b] * TL);
-    while (b < B) {
-        fold(lq + TL);
-        const int bn = next_col(b + NW);
-        if (bn < B) fetch(a.ix.CR2 + (int64_t)v[bn] * TL);
-        const int ye = col_ne[b + 1];
-        const int U = col_tot[b];
-        int y0 = col_ne[b];
-        for (int u0 = 0; u0 < U; u0 += 64) {
-            const int y = y0 + lane;
-            int32_t pre = 0, cs = 0;
-            int64_t beg = 0;
-            bool vc = false;
-            if (y < ye) {
-                pre = t_cmp[y];
-                vc = pre < u0 + 64;
-                const int e = t_cmc[y];
-                cs = t_cs[e];
-                beg = t_beg[e];
-            }
-            const int sr = pre > u0 ? pre - u0 : 0;
-            const uint64_t mask = wave_or64(vc ? (1ull << sr) : 0ull);
-            const int owner = __popcll(mask & below_lane) - 1;
-            const int32_t preo = __shfl(pre, owner);
-            const int32_t cso = __shfl(cs, owner);
-            const int64_t bego = __shfl(beg, owner);
-            const int uu = u0 + lane;
-            if (uu < U) {
-                const int64_t t = cso + (uu - preo);
-                const int64_t p = bego + (t - cso);
-                const float d = dist[t] + lut_sum<MH>(lut, a.ix.codesB, p);
-                dist[t] = d;
-                if (a.dbg_pos) {
-                    a.dbg_pos[(int64_t)slot * a.dbg_cap + t] = p;
-                    a.dbg_d[(int64_t)slot * a.dbg_cap + t] = d;
+            return lo;
+        };
+        int tk = wv;
+        int ar = tk < ntask ? task_row(tk) : 0;
+        if (tk < ntask) fetch(a.ix.CR1 + (int64_t)u[ar] * TL);
+        while (tk < ntask) {
+            const int ch = tk - tpre[ar];
+            fold(0, u[ar]);
+            const int tn = tk + NW;
+            const int an = tn < ntask ? task_row(tn) : 0;
+            if (tn < ntask) fetch(a.ix.CR1 + (int64_t)u[an] * TL);
+            const int64_t rs = row_cand[ar] + (int64_t)ch * kWideChunk;
+            const int64_t re0 = row_cand[ar + 1];
+            const int64_t re = rs + kWideChunk < re0 ? rs + kWideChunk : re0;
+            const int xe = row_ne[ar + 1];
+            int x0 = ch == 0 ? row_ne[ar] : last_le(t_cs, row_ne[ar], xe, rs);
+            for (int64_t t0 = rs; t0 < re; t0 += 64) {
+                const int x = x0 + lane;
+                int32_t cs = 0;
+                int64_t beg = 0;
+                float cst = 0.f;
+                bool vc = false;
+                if (x < xe) {
+                    cs = t_cs[x];
+                    vc = cs < t0 + 64;
+                    beg = t_beg[x];
+                    cst = t_cst[x];
                 }
+                const int sr = cs > t0 ? (int)(cs - t0) : 0;
+                const uint64_t mask = wave_or64(vc ? (1ull << sr) : 0ull);
+                const int owner = __popcll(mask & below_lane) - 1;
+                const int32_t cso = __shfl(cs, owner);
+                const int64_t bego = __shfl(beg, owner);
+                const float csto = __shfl(cst, owner);
+                const int64_t t = t0 + lane;
+                if (t < re) dist[t] = lut_sum<MH>(lut, a.ix.codesA, bego + (t - cso)) + csto;
+                // cell of candidate t0 + 64: that of lane 63's candidate, or the next
+                const int o63 = __shfl(owner, 63);
+                int xn = x0 + o63;
+                const int csn = __shfl(cs, (o63 + 1) & 63);
+                if (o63 < 63 && xn + 1 < xe && csn <= t0 + 64) ++xn;
+                else if (o63 == 63 && xn + 1 < xe && t_cs[xn + 1] <= t0 + 64) ++xn;
+                x0 = xn;
             }
-            const int o63 = __shfl(owner, 63);
-            int yn = y0 + o63;
-            const int pren = __shfl(pre, (o63 + 1) & 63);
-            if (o63 < 63 && yn + 1 < ye && pren <= u0 + 64) ++yn;
-            else if (o63 == 63 && yn + 1 < ye && t_cmp[yn + 1] <= u0 + 64) ++yn;
-            y0 = yn;
+            tk = tn;
+            ar = an;
         }
-        b = bn;
+    }
+    __syncthreads();  // every partial sum of the query is stored; tpre is free
+
+    // ---- pass 2: column tasks, second half of the code ----
+    for (int b = tid; b <= B; b += NT)
+        tpre[b] = b < B ? (col_tot[b] + kWideChunk - 1) / kWideChunk : 0;
+    __syncthreads();
+    wide_scan<NT>(tpre, B + 1, wtot);
+    {
+        const int ntask = tpre[B];
+        auto task_col = [&](int tk) __attribute__((always_inline)) {
+            int lo = 0, hi = B - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (tpre[mid] <= tk) lo = mid;
+                else hi = mid - 1;
+            }
+            return lo;
+        };
+        int tk = wv;
+        int b = tk < ntask ? task_col(tk) : 0;
+        if (tk < ntask) fetch(a.ix.CR2 + (int64_t)v[b] * TL);
+        while (tk < ntask) {
+            const int ch = tk - tpre[b];
+            fold(1, v[b]);
+            const int tn = tk + NW;
+            const int bn = tn < ntask ? task_col(tn) : 0;
+            if (tn < ntask) fetch(a.ix.CR2 + (int64_t)v[bn] * TL);
+            const int yb = col_ne[b], ye = col_ne[b + 1];
+            const int U = col_tot[b];
+            const int us = ch * kWideChunk;
+            const int ue = us + kWideChunk < U ? us + kWideChunk : U;
+            int y0 = ch == 0 ? yb : last_le(t_cmp, yb, ye, us);
+            for (int u0 = us; u0 < ue; u0 += 64) {
+                const int y = y0 + lane;
+                int32_t pre = 0, cs = 0;
+                int64_t beg = 0;
+                bool vc = false;
+                if (y < ye) {
+                    pre = t_cmp[y];
+                    vc = pre < u0 + 64;
+                    const int e = t_cmc[y];
+                    cs = t_cs[e];
+                    beg = t_beg[e];
+                }
+                const int sr = pre > u0 ? pre - u0 : 0;
+                const uint64_t mask = wave_or64(vc ? (1ull << sr) : 0ull);
+                const int owner = __popcll(mask & below_lane) - 1;
+                const int32_t preo = __shfl(pre, owner);
+                const int32_t cso = __shfl(cs, owner);
+                const int64_t bego = __shfl(beg, owner);
+                const int uu = u0 + lane;
+                if (uu < ue) {
+                    const int64_t t = cso + (uu - preo);
+                    const int64_t p = bego + (t - cso);
+                    const float d = dist[t] + lut_sum<MH>(lut, a.ix.codesB, p);
+                    dist[t] = d;
+                    if (a.dbg_pos) {
+                        a.dbg_pos[(int64_t)slot * a.dbg_cap + t] = p;
+                        a.dbg_d[(int64_t)slot * a.dbg_cap + t] = d;
+                    }
+                }
+                const int o63 = __shfl(owner, 63);
+                int yn = y0 + o63;
+                const int pren = __shfl(pre, (o63 + 1) & 63);
+                if (o63 < 63 && yn + 1 < ye && pren <= u0 + 64) ++yn;
+                else if (o63 == 63 && yn + 1 < ye && t_cmp[yn + 1] <= u0 + 64) ++yn;
+                y0 = yn;
+            }
+            tk = tn;
+            b = bn;
+        }
     }
 }
 
@@ -502,11 +592,16 @@ hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
     const dim3 g((unsigned)nslots);
+    const size_t extra = (size_t)kWideRanks * sizeof(int) + (size_t)a.ix.D * sizeof(float);
 #define FBPQ_WIDE_CASE(MH)                                                                        \
-    case MH:                                                                                      \
-        hipLaunchKernelGGL(k_scan_wide<MH>, g, dim3(64 * wide_waves<MH>()),                       \
-                           (size_t)wide_waves<MH>() * MH * kKc * sizeof(float), st, a);            \
-        break;
+    case MH: {                                                                                    \
+        const size_t lds = (size_t)wide_waves<MH>() * MH * kKc * sizeof(float) + extra;           \
+        if (a.ix.local)                                                                           \
+            hipLaunchKernelGGL((k_scan_wide<MH, true>), g, dim3(64 * wide_waves<MH>()), lds, st, a); \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_scan_wide<MH, false>), g, dim3(64 * wide_waves<MH>()), lds, st, a); \
+        break;                                                                                    \
+    }
     switch (a.ix.M / 2) {
         FBPQ_WIDE_CASE(1)
         FBPQ_WIDE_CASE(2)

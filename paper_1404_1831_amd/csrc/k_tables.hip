@@ -6,7 +6,8 @@
 //   nR[k][r]     = ||R_k(r)||^2
 //   nC1[i], nC2[j] = squared norms of the half centroids
 //
-// c|k is the k-th D/M slice of a half centroid. Accumulation is FP64, storage
+// c|k is the k-th D/M slice of a half centroid. With local codebooks the
+// CR tables hold the CQ tables below instead. Accumulation is FP64, storage
 // FP32. One thread per table entry: the inner loop is D/M long, the whole
 // build is T*Kc*D FMAs, a one-off cost next to any search.
 #include "fbpq_dev.h"
@@ -50,6 +51,31 @@ __global__ void k_norms(const float *__restrict__ R, int M, int ds, const float 
     }
 }
 
+// Local codebooks (HBPQ, Section 3.2): the query-independent part of the
+// folded table of row i,
+//   CQ[i][k][r] = ||Q^i_k(r)||^2 + 2 <c_i|k, Q^i_k(r)>,
+// so that the table of a visited row is CQ[i] - 2 <q|k, Q^i_k(r)> and the
+// distance is d1[i] + d2[j] plus one lookup per subspace (the squared norm of
+// a displacement reconstruction splits over the disjoint subspaces).
+__global__ void k_local_table(const float *__restrict__ C, const float *__restrict__ QL, int T, int h,
+                              int M, int ds, float *__restrict__ CQ)
+{
+    const int Mh = M / 2;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)T * Mh * kKc;
+    if (e >= total) return;
+    const int k = (int)((e / kKc) % Mh);
+    const int64_t i = e / ((int64_t)kKc * Mh);
+    const float *c = C + i * h + (int64_t)k * ds;
+    const float *w = QL + e * ds;  // [T][M/2][Kc][ds]: entry e is codeword (i, k, r)
+    double nn = 0.0, cr = 0.0;
+    for (int t = 0; t < ds; ++t) {
+        nn += (double)w[t] * (double)w[t];
+        cr += (double)c[t] * (double)w[t];
+    }
+    CQ[e] = (float)(nn + 2.0 * cr);
+}
+
 hipError_t launch_tables(const DevIndex &ix, float *CR1, float *CR2, float *nR, float *nC1,
                          float *nC2, hipStream_t st)
 {
@@ -57,10 +83,15 @@ hipError_t launch_tables(const DevIndex &ix, float *CR1, float *CR2, float *nR, 
     const int64_t total = (int64_t)ix.T * (ix.M / 2) * kKc;
     const int bs = 256;
     const unsigned grid = (unsigned)((total + bs - 1) / bs);
-    hipLaunchKernelGGL(k_cross_table, dim3(grid), dim3(bs), 0, st, ix.C1, ix.R, ix.T, h, ix.M, ds,
-                       0, CR1);
-    hipLaunchKernelGGL(k_cross_table, dim3(grid), dim3(bs), 0, st, ix.C2, ix.R, ix.T, h, ix.M, ds,
-                       ix.M / 2, CR2);
+    if (ix.local) {
+        hipLaunchKernelGGL(k_local_table, dim3(grid), dim3(bs), 0, st, ix.C1, ix.QL, ix.T, h, ix.M, ds, CR1);
+        hipLaunchKernelGGL(k_local_table, dim3(grid), dim3(bs), 0, st, ix.C2, ix.SL, ix.T, h, ix.M, ds, CR2);
+    } else {
+        hipLaunchKernelGGL(k_cross_table, dim3(grid), dim3(bs), 0, st, ix.C1, ix.R, ix.T, h, ix.M, ds,
+                           0, CR1);
+        hipLaunchKernelGGL(k_cross_table, dim3(grid), dim3(bs), 0, st, ix.C2, ix.R, ix.T, h, ix.M, ds,
+                           ix.M / 2, CR2);
+    }
     const int64_t nn = (int64_t)ix.M * kKc + 2 * (int64_t)ix.T;
     hipLaunchKernelGGL(k_norms, dim3((unsigned)((nn + bs - 1) / bs)), dim3(bs), 0, st, ix.R, ix.M,
                        ds, ix.C1, ix.C2, ix.T, h, nR, nC1, nC2);

@@ -49,7 +49,8 @@ class IndexDesc(ctypes.Structure):
     _fields_ = [("D", ctypes.c_int32), ("T", ctypes.c_int32), ("M", ctypes.c_int32),
                 ("Kc", ctypes.c_int32), ("N", ctypes.c_int64), ("C1", ctypes.c_void_p),
                 ("C2", ctypes.c_void_p), ("R", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
-                ("codes", ctypes.c_void_p), ("ids", ctypes.c_void_p)]
+                ("codes", ctypes.c_void_p), ("ids", ctypes.c_void_p), ("QL", ctypes.c_void_p),
+                ("SL", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -127,11 +128,16 @@ def fbpq_index_file_check(path: str) -> Info:
 
 
 def fbpq_index_create(ix, device: int = 0) -> ctypes.c_void_p:
-    """ix: any object with D, T, M, Kc, C1, C2, R, offsets, codes, ids (numpy)."""
+    """ix: any object with D, T, M, Kc, C1, C2, R, offsets, codes, ids (numpy),
+    and optionally local codebooks QL, SL ([T][M/2][Kc][D/M] float32)."""
     keep = [np.ascontiguousarray(ix.C1, np.float32), np.ascontiguousarray(ix.C2, np.float32),
             np.ascontiguousarray(ix.R, np.float32), np.ascontiguousarray(ix.offsets, np.int64),
             np.ascontiguousarray(ix.codes, np.uint8), np.ascontiguousarray(ix.ids, np.uint32)]
-    d = IndexDesc(ix.D, ix.T, ix.M, ix.Kc, keep[4].shape[0], *[_p(a) for a in keep])
+    ql, sl = getattr(ix, "QL", None), getattr(ix, "SL", None)
+    if ql is not None:
+        keep += [np.ascontiguousarray(ql, np.float32), np.ascontiguousarray(sl, np.float32)]
+    ptrs = [_p(a) for a in keep] + [None] * (8 - len(keep))
+    d = IndexDesc(ix.D, ix.T, ix.M, ix.Kc, keep[4].shape[0], *ptrs)
     h = ctypes.c_void_p()
     _check(lib.fbpq_index_create(ctypes.byref(d), device, ctypes.byref(h)))
     return h

@@ -24,13 +24,20 @@ def log(msg: str) -> None:
 
 
 def recon(ix, pos: np.ndarray) -> np.ndarray:
-    """FP64 reconstructions [len(pos), D] of stored points (equation approximation)."""
+    """FP64 reconstructions [len(pos), D] of stored points (equation
+    approximation; with local codebooks, equation residual of Section 3.2)."""
     cell = np.searchsorted(ix.offsets, pos, side="right") - 1
     i, j = cell // ix.T, cell % ix.T
     x = np.concatenate([ix.C1[i], ix.C2[j]], 1).astype(np.float64)
-    ds = ix.D // ix.M
+    ds, mh = ix.D // ix.M, ix.M // 2
     for m in range(ix.M):
-        x[:, m * ds:(m + 1) * ds] += ix.R[m][ix.codes[pos, m]]
+        if getattr(ix, "QL", None) is None:
+            w = ix.R[m][ix.codes[pos, m]]
+        elif m < mh:
+            w = ix.QL[i, m, ix.codes[pos, m]]
+        else:
+            w = ix.SL[j, m - mh, ix.codes[pos, m]]
+        x[:, m * ds:(m + 1) * ds] += w
     return x
 
 

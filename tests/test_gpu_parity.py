@@ -478,6 +478,70 @@ def test_wide_scan_sparse_cells(fb, gmm_wide, items):
     assert_topk(ix, Q[:12], k, g_ids, g_d, o_ids, o_d)
 
 
+# ---- local codebooks (HBPQ, Section 3.2) ----------------------------------------
+
+def test_local_lossless_exact_knn(fb):
+    # integer data: every table entry and distance is exact in FP32, so the
+    # top-k equals the brute-force kNN of the raw vectors bit for bit
+    ix = synth.lossless_local_index(N=3000, T=8, M=4, D=16, seed=13, dup=300)
+    rng = np.random.default_rng(6)
+    Q = ix.base[ix.ids[-rng.integers(1, 300, 8)]] + rng.integers(-1, 2, (8, 16)).astype(np.float32)
+    k = 25
+    log("local codebooks: lossless index, L >= N")
+    h = _open(fb, ix, stats=1)
+    g_ids, g_d = fb.fbpq_search(h, Q, ix.N + 10, k)
+    assert fb.fbpq_stats_read(h)["two_pass"] >= Q.shape[0]
+    fb.fbpq_free_index(h)
+    X = ix.base.astype(np.float64)
+    for r in range(Q.shape[0]):
+        dd = ((X - Q[r].astype(np.float64)) ** 2).sum(1)
+        order = np.lexsort((np.arange(ix.N), dd))[:k]
+        assert np.array_equal(g_ids[r], order), r
+        assert np.array_equal(g_d[r].astype(np.float64), dd[order]), r
+
+
+@pytest.mark.parametrize("L", [1, 777, 10000, 250000])
+def test_local_gmm_distances_and_topk(fb, gmm_small, L):
+    ix, Q = gmm_small
+    lix = synth.with_local_codebooks(ix)
+    k = 20
+    log(f"local codebooks: N=1e5 T=64 M=8 L={L}")
+    h = _open(fb, lix)
+    got = fb.fbpq_debug_dists(h, Q[:8], L, cap=min(L, lix.N))
+    for r in range(8):
+        pos, d32 = got[r]
+        _, opos = oracle.visit(lix, Q[r], L)
+        assert np.array_equal(np.sort(pos), np.sort(opos)), r
+        d64 = oracle_dists(lix, Q[r], pos)
+        err = np.abs(d32.astype(np.float64) - d64)
+        assert np.all(err <= tol(lix, Q[r], pos, d64)), (r, float((err / tol(lix, Q[r], pos, d64)).max()))
+    g_ids, g_d = fb.fbpq_search(h, Q[:40], L, k)
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(lix, Q[:40], L, k)
+    assert_topk(lix, Q[:40], k, g_ids, g_d, o_ids, o_d)
+
+
+def test_local_long_rows_in_chunks(fb):
+    # 16 cells of 1500 points over T = 4: a row holds 6000 candidates, cut
+    # into tasks of 2048; the table of each task is folded by its wavefront
+    ix = synth.with_local_codebooks(_dense_index(False), seed=5, scale=1.0)
+    rng = np.random.default_rng(8)
+    Q = rng.integers(0, 6, (16, 4)).astype(np.float32)
+    L, k = 20000, 50
+    log("local codebooks: rows of 6000 candidates")
+    h = _open(fb, ix)
+    got = fb.fbpq_debug_dists(h, Q[:4], L, cap=ix.N)
+    for r in range(4):
+        pos, d32 = got[r]
+        d64 = oracle_dists(ix, Q[r], pos)
+        assert len(pos) == min(L, ix.N)
+        assert np.all(np.abs(d32.astype(np.float64) - d64) <= tol(ix, Q[r], pos, d64)), r
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
 # ---- the selection fused into the cell scan and its fallbacks --------------------
 
 def _dense_index(const_codes: bool):
