@@ -34,6 +34,8 @@ WORKLOADS = {
     # served: Zipf(1.1) cell sizes over T^2 cells, Poisson arrivals
     "served": dict(N=1_000_000_000, T=16384, M=8, L=(10_000, 30_000, 100_000), k=10,
                    offered=(1000, 2000, 5000, 10000, 20000, 40000, 80000)),
+    # local codebooks (HBPQ): per-query L log-uniform in [L_lo, L_hi]
+    "local": dict(N=100_000_000, T=4096, M=16, nq=10_000, L_lo=10_000, L_hi=100_000, k=10),
 }
 
 
@@ -119,6 +121,8 @@ def main() -> int:
     w = dict(WORKLOADS[args.workload])
     if args.workload == "served":
         return run_served(args, w)
+    if args.workload == "local":
+        return run_local(args, w)
     if args.nq:
         w["nq"] = args.nq
     dev = torch.device("cuda:0")
@@ -278,6 +282,125 @@ def main() -> int:
         "plain_per_query": ({"queries": npl, "value": npl / plain_s, "unit": "queries/s",
                              "ms_per_query": plain_s * 1e3 / npl} if npl > 0 else None),
         "scan_GBps": scan_GBps,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def run_local(args, w) -> int:
+    """Local codebooks (HBPQ, Section 3.2): a batch with per-query L, timed
+    with the local codebooks and, on the same index and queries, with the
+    global ones (FBPQ)."""
+    import torch
+
+    import synth
+    from paper_1404_1831_amd.build import LIB
+    if not os.path.exists(LIB):
+        from paper_1404_1831_amd.build import build
+        build()
+    from paper_1404_1831_amd import fbpq
+
+    if args.nq:
+        w["nq"] = args.nq
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    means = synth.gmm_means(0)
+    base = synth.sample_points(w["N"], means, 1, dev)
+    gix = synth.build_index(base, w["T"], w["M"], keep_base=False)
+    del base
+    torch.cuda.empty_cache()
+    ix = synth.with_local_codebooks(gix)
+    nq, k = w["nq"], w["k"]
+    Q = synth.make_queries(nq, means, 2, dev)
+    Ls, _ = synth.draw_L_k(nq, 3, w["L_lo"], w["L_hi"])
+    Ls = np.ascontiguousarray(Ls, np.int64)
+    ks = np.full(nq, k, np.int32)
+    log(f"index built in {time.time() - t0:.1f}s: N={ix.N} T={ix.T} M={ix.M}, local codebooks "
+        f"{2 * ix.QL.nbytes / 2**20:.0f} MiB; mean L {Ls.mean():.0f}")
+    d_q = torch.from_numpy(Q).to(dev).contiguous()
+    d_ids = torch.empty(nq, k, dtype=torch.int64, device=dev)
+    d_d = torch.empty(nq, k, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    ncand = int(np.minimum(Ls, ix.N).sum())
+
+    def timed(h, label):
+        for i in range(args.warmup):
+            fbpq.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, stream)
+        torch.cuda.synchronize()
+        fbpq.fbpq_set_option(h, "profile", 1)
+        fbpq.fbpq_set_option(h, "profile_mask", -1)
+        for s_ in range(len(fbpq.STAGES)):
+            fbpq.fbpq_profile_read(h, s_, reset=True)
+        for _ in range(args.profile_steps):
+            fbpq.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, stream)
+        torch.cuda.synchronize()
+        prof = {}
+        for s_, name in enumerate(fbpq.STAGES):
+            ms, n = fbpq.fbpq_profile_read(h, s_, reset=True)
+            prof[name] = {"ms_per_launch": ms / n if n else None, "launches": n}
+        log(f"{label} kernels: " + ", ".join(f"{n}={v['ms_per_launch']:.4f}" for n, v in prof.items()
+                                              if v["ms_per_launch"]))
+        fbpq.fbpq_set_option(h, "profile_mask", 1 << fbpq.STAGES.index("scan_wide"))
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.steps):
+            fbpq.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - a) * 1e3 / args.steps
+        sw_ms, sw_n = fbpq.fbpq_profile_read(h, fbpq.STAGES.index("scan_wide"), reset=True)
+        fbpq.fbpq_set_option(h, "profile", 0)
+        log(f"{label}: {ms:.3f} ms per batch")
+        return ms, prof, (sw_ms / sw_n if sw_n else None), sw_n
+
+    h = fbpq.fbpq_index_create(ix, 0)
+    fbpq.fbpq_build_tables(h)
+    ms, prof, sw_ms, sw_n = timed(h, "local")
+    res_ids, res_d = d_ids.cpu().numpy(), d_d.cpu().numpy()
+    fbpq.fbpq_free_index(h)
+    hg = fbpq.fbpq_index_create(gix, 0)
+    fbpq.fbpq_build_tables(hg)
+    g_ms, g_prof, _, _ = timed(hg, "global")
+    fbpq.fbpq_free_index(hg)
+
+    # the scan with local codebooks: M code bytes per candidate over its time
+    achieved = ncand * ix.M / (sw_ms * 1e-3) / 1e9 if sw_ms else None
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": None,
+            "kernel": "k_scan_wide", "algorithmic_per_launch": ncand * ix.M, "what": "code bytes",
+            "ms_per_launch": sw_ms, "launches": sw_n}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        n0 = min(nq, threads)
+        a = time.perf_counter()
+        o_ids, o_d, _, _ = oracle.search(ix, Q[:n0], Ls[:n0], k, nthreads=threads)
+        t_first = time.perf_counter() - a
+        n1 = int(min(nq, max(n0, n0 * args.cpu_seconds / max(t_first, 1e-3))))
+        if n1 > n0:
+            a = time.perf_counter()
+            o_ids, o_d, _, _ = oracle.search(ix, Q[:n1], Ls[:n1], k, nthreads=threads)
+            t_cpu = time.perf_counter() - a
+        else:
+            n1, t_cpu = n0, t_first
+        overlap = float(np.mean([len(set(res_ids[r]) & set(o_ids[r])) / k for r in range(n1)]))
+        rel = np.abs(res_d[:n1].astype(np.float64) - o_d) / np.maximum(o_d, 1.0)
+        cpu = {"value": n1 / t_cpu, "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {n1} of the {nq} queries, same index and local codebooks, their own L, k={k}",
+               "topk_overlap_with_gpu": overlap, "max_rel_dist_diff": float(rel.max())}
+        log(f"cpu oracle: {n1} queries in {t_cpu:.1f}s on {threads} threads")
+    out = {
+        "metric": "queries/s at fixed L, Recall@10 = oracle, 1 GPU; p50/p99 latency; scan GB/s",
+        "value": nq / (ms / 1e3), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"local codebooks (HBPQ): N={ix.N}, T={ix.T} per half, M={ix.M}, nq={nq} per batch, "
+                               f"L log-uniform in [{w['L_lo']}, {w['L_hi']}], k={k}",
+                   "N": ix.N, "T": ix.T, "M": ix.M, "nq": nq, "k": k, "mean_L": float(Ls.mean())},
+        "kernels": prof,
+        "global_codebooks_same_L": {"ms_per_step": g_ms, "value": nq / (g_ms / 1e3), "kernels": g_prof},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -304,9 +304,32 @@ __global__ __launch_bounds__(512) void k_scan2(ScanArgs a)
 // the query part computed here from the row's own codebooks (and likewise for
 // the columns with S^j).
 // Wavefronts per query: as many as 64 KB of folded tables allow, up to 16.
+template <int MH, bool LOCAL>
+constexpr int wide_waves() { return LOCAL && MH <= 8 ? 16 : (MH <= 4 ? 16 : (MH == 8 ? 8 : 4)); }
+// With local codebooks, a query with at most this many distinct row and column
+// tables folds each of them once into LDS, shared by all its tasks.
 template <int MH>
-constexpr int wide_waves() { return MH <= 4 ? 16 : (MH == 8 ? 8 : 4); }
+constexpr int wide_tables() { return MH <= 8 ? 16 : 8; }
+template <int MH, bool LOCAL>
+constexpr int wide_regions()
+{
+    return LOCAL && wide_tables<MH>() > wide_waves<MH, LOCAL>() ? wide_tables<MH>() : wide_waves<MH, LOCAL>();
+}
 constexpr int kWideRanks = 4097;  // task prefix entries (ranks up to 4096, plus the total)
+constexpr int kWideU = 4;         // 64-candidate chunks a wavefront has in flight
+
+// the last lane o < n whose start v (held by lane o, ascending over lanes) is <= x
+__device__ __forceinline__ int lane_owner(int32_t v, int n, int32_t x)
+{
+    int lo = 0, hi = n - 1;
+    for (int it = 0; it < 6; ++it) {
+        const int mid = (lo + hi + 1) >> 1;
+        const bool le = __shfl(v, mid) <= x;
+        lo = lo < hi && le ? mid : lo;
+        hi = lo < hi && !le ? mid - 1 : hi;
+    }
+    return lo;
+}
 
 // exclusive prefix of x[0..n) in place, n <= kWideRanks; every thread calls it
 template <int NT>
@@ -337,12 +360,13 @@ __device__ void wide_scan(int *x, int n, int *wtot)
 }
 
 template <int MH, bool LOCAL>
-__global__ __launch_bounds__(64 * wide_waves<MH>()) void k_scan_wide(ScanArgs a)
+__global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(ScanArgs a)
 {
-    constexpr int NW = wide_waves<MH>();
+    constexpr int NW = wide_waves<MH, LOCAL>();
     constexpr int NT = 64 * NW;
     constexpr int TL = MH * kKc;  // floats of one folded half table
-    extern __shared__ __align__(16) float wlut[];  // [NW][TL], then the task prefix [kWideRanks], then q [D]
+    constexpr int NREG = wide_regions<MH, LOCAL>();
+    extern __shared__ __align__(16) float wlut[];  // [NREG][TL], then the task prefix [kWideRanks], then q [D]
     __shared__ int wtot[NW];
     const int slot = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -350,7 +374,7 @@ __global__ __launch_bounds__(64 * wide_waves<MH>()) void k_scan_wide(ScanArgs a)
     if (h.status != kStOk || !h.gscan) return;
     if (a.stats && tid == 0) atomicAdd(&a.stats[kStatTwoPass], 1ull);
     float *lut = wlut + wv * TL;
-    int *tpre = reinterpret_cast<int *>(wlut + NW * TL);
+    int *tpre = reinterpret_cast<int *>(wlut + NREG * TL);
     float *qs = reinterpret_cast<float *>(tpre + kWideRanks);
     const int P = a.P;
     const int D = a.ix.D, ds = D / (2 * MH);
@@ -384,7 +408,7 @@ __global__ __launch_bounds__(64 * wide_waves<MH>()) void k_scan_wide(ScanArgs a)
 #pragma unroll
         for (int e = 0; e < TQ; ++e) nxt[e] = cr[lane + 64 * e];
     };
-    auto fold = [&](int half, int cent) __attribute__((always_inline)) {
+    auto fold = [&](int half, int cent, float *lut) __attribute__((always_inline)) {
         __builtin_amdgcn_wave_barrier();  // the previous table's lookups are done
         if (LOCAL) {
             // CQ[cent] - 2 <q|k, Q_k(r)> with the codebooks of this centroid
@@ -411,6 +435,18 @@ __global__ __launch_bounds__(64 * wide_waves<MH>()) void k_scan_wide(ScanArgs a)
         __builtin_amdgcn_wave_barrier();
     };
 
+    // Local codebooks and few distinct tables: fold each table once, shared.
+    // Table s < a_ne belongs to row centroid slot_ij[s], the others to columns;
+    // a cell's ne_slot holds its row table | (its column table << 16).
+    const int nsl = h.a_ne + h.b_ne;
+    const bool shared_tab = LOCAL && nsl <= wide_tables<MH>();
+    const int32_t *sij = a.slot_ij + (int64_t)slot * 2 * P;
+    const int32_t *t_nsl = a.ne_slot + slot * mc;
+    if (shared_tab) {
+        __syncthreads();  // the query vector is staged
+        for (int sidx = wv; sidx < nsl; sidx += NW) fold(sidx < h.a_ne ? 0 : 1, sij[sidx], wlut + sidx * TL);
+    }
+
     // ---- pass 1: row tasks, first half of the code plus the cell constant ----
     for (int ar = tid; ar <= A; ar += NT)
         tpre[ar] = ar < A ? (row_cand[ar + 1] - row_cand[ar] + kWideChunk - 1) / kWideChunk : 0;
@@ -432,7 +468,8 @@ __global__ __launch_bounds__(64 * wide_waves<MH>()) void k_scan_wide(ScanArgs a)
         if (tk < ntask) fetch(a.ix.CR1 + (int64_t)u[ar] * TL);
         while (tk < ntask) {
             const int ch = tk - tpre[ar];
-            fold(0, u[ar]);
+            if (shared_tab) lut = wlut + (t_nsl[row_ne[ar]] & 0xffff) * TL;
+            else fold(0, u[ar], lut);
             const int tn = tk + NW;
             const int an = tn < ntask ? task_row(tn) : 0;
             if (tn < ntask) fetch(a.ix.CR1 + (int64_t)u[an] * TL);
@@ -440,6 +477,40 @@ __global__ __launch_bounds__(64 * wide_waves<MH>()) void k_scan_wide(ScanArgs a)
             const int64_t re0 = row_cand[ar + 1];
             const int64_t re = rs + kWideChunk < re0 ? rs + kWideChunk : re0;
             const int xe = row_ne[ar + 1];
+            if (xe - row_ne[ar] <= 64) {
+                // the row's cells sit one per lane; a candidate's cell is found
+                // by a binary search over the lanes, kWideU chunks in flight
+                const int xb = row_ne[ar], ncell = xe - xb;
+                int32_t ccs = 0x7fffffff;
+                int64_t cbeg = 0;
+                float ccst = 0.f;
+                if (lane < ncell) {
+                    ccs = t_cs[xb + lane];
+                    cbeg = t_beg[xb + lane];
+                    ccst = t_cst[xb + lane];
+                }
+                for (int64_t t0 = rs; t0 < re; t0 += 64 * kWideU) {
+                    typename CodeT<MH>::T cv[kWideU];
+                    float cst_[kWideU];
+#pragma unroll
+                    for (int j = 0; j < kWideU; ++j) {
+                        const int64_t t = t0 + 64 * j + lane;
+                        const int o = lane_owner(ccs, ncell, (int32_t)(t < re ? t : re - 1));
+                        const int32_t cso = __shfl(ccs, o);
+                        const int64_t bego = __shfl(cbeg, o);
+                        cst_[j] = __shfl(ccst, o);
+                        if (t < re) cv[j] = load_code<MH>(a.ix.codesA, bego + (t - cso));
+                    }
+#pragma unroll
+                    for (int j = 0; j < kWideU; ++j) {
+                        const int64_t t = t0 + 64 * j + lane;
+                        if (t < re) dist[t] = lut_sum_c<MH>(lut, cv[j]) + cst_[j];
+                    }
+                }
+                tk = tn;
+                ar = an;
+                continue;
+            }
             int x0 = ch == 0 ? row_ne[ar] : last_le(t_cs, row_ne[ar], xe, rs);
             for (int64_t t0 = rs; t0 < re; t0 += 64) {
                 const int x = x0 + lane;
@@ -496,7 +567,8 @@ __global__ __launch_bounds__(64 * wide_waves<MH>()) void k_scan_wide(ScanArgs a)
         if (tk < ntask) fetch(a.ix.CR2 + (int64_t)v[b] * TL);
         while (tk < ntask) {
             const int ch = tk - tpre[b];
-            fold(1, v[b]);
+            if (shared_tab) lut = wlut + (t_nsl[t_cmc[col_ne[b]]] >> 16) * TL;
+            else fold(1, v[b], lut);
             const int tn = tk + NW;
             const int bn = tn < ntask ? task_col(tn) : 0;
             if (tn < ntask) fetch(a.ix.CR2 + (int64_t)v[bn] * TL);
@@ -504,6 +576,47 @@ __global__ __launch_bounds__(64 * wide_waves<MH>()) void k_scan_wide(ScanArgs a)
             const int U = col_tot[b];
             const int us = ch * kWideChunk;
             const int ue = us + kWideChunk < U ? us + kWideChunk : U;
+            if (ye - yb <= 64) {
+                const int ny = ye - yb;
+                int32_t cpre = 0x7fffffff, ccs = 0;
+                int64_t cbeg = 0;
+                if (lane < ny) {
+                    cpre = t_cmp[yb + lane];
+                    const int e = t_cmc[yb + lane];
+                    ccs = t_cs[e];
+                    cbeg = t_beg[e];
+                }
+                for (int u0 = us; u0 < ue; u0 += 64 * kWideU) {
+                    typename CodeT<MH>::T cv[kWideU];
+                    int64_t tt[kWideU], pp[kWideU];
+#pragma unroll
+                    for (int j = 0; j < kWideU; ++j) {
+                        const int uu = u0 + 64 * j + lane;
+                        const int o = lane_owner(cpre, ny, uu < ue ? uu : ue - 1);
+                        const int32_t preo = __shfl(cpre, o);
+                        const int32_t cso = __shfl(ccs, o);
+                        const int64_t bego = __shfl(cbeg, o);
+                        tt[j] = cso + (uu - preo);
+                        pp[j] = bego + (uu - preo);
+                        if (uu < ue) cv[j] = load_code<MH>(a.ix.codesB, pp[j]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < kWideU; ++j) {
+                        const int uu = u0 + 64 * j + lane;
+                        if (uu < ue) {
+                            const float d = dist[tt[j]] + lut_sum_c<MH>(lut, cv[j]);
+                            dist[tt[j]] = d;
+                            if (a.dbg_pos) {
+                                a.dbg_pos[(int64_t)slot * a.dbg_cap + tt[j]] = pp[j];
+                                a.dbg_d[(int64_t)slot * a.dbg_cap + tt[j]] = d;
+                            }
+                        }
+                    }
+                }
+                tk = tn;
+                b = bn;
+                continue;
+            }
             int y0 = ch == 0 ? yb : last_le(t_cmp, yb, ye, us);
             for (int u0 = us; u0 < ue; u0 += 64) {
                 const int y = y0 + lane;
@@ -595,11 +708,14 @@ hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st)
     const size_t extra = (size_t)kWideRanks * sizeof(int) + (size_t)a.ix.D * sizeof(float);
 #define FBPQ_WIDE_CASE(MH)                                                                        \
     case MH: {                                                                                    \
-        const size_t lds = (size_t)wide_waves<MH>() * MH * kKc * sizeof(float) + extra;           \
+        const size_t tab = (size_t)MH * kKc * sizeof(float);                                      \
+        constexpr int reg_l = wide_regions<MH, true>(), reg_g = wide_regions<MH, false>();         \
+        const size_t lds_l = reg_l * tab + extra, lds_g = reg_g * tab + extra;                    \
+        constexpr int nt_l = 64 * wide_waves<MH, true>(), nt_g = 64 * wide_waves<MH, false>();   \
         if (a.ix.local)                                                                           \
-            hipLaunchKernelGGL((k_scan_wide<MH, true>), g, dim3(64 * wide_waves<MH>()), lds, st, a); \
+            hipLaunchKernelGGL((k_scan_wide<MH, true>), g, dim3(nt_l), lds_l, st, a);                  \
         else                                                                                      \
-            hipLaunchKernelGGL((k_scan_wide<MH, false>), g, dim3(64 * wide_waves<MH>()), lds, st, a); \
+            hipLaunchKernelGGL((k_scan_wide<MH, false>), g, dim3(nt_g), lds_g, st, a);                 \
         break;                                                                                    \
     }
     switch (a.ix.M / 2) {
