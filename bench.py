@@ -356,7 +356,10 @@ def run_local(args, w) -> int:
 
     h = fbpq.fbpq_index_create(ix, 0)
     fbpq.fbpq_build_tables(h)
+    fbpq.fbpq_set_option(h, "stats", 1)
     ms, prof, sw_ms, sw_n = timed(h, "local")
+    stats = fbpq.fbpq_stats_read(h)
+    log(f"local path counters: {stats}")
     res_ids, res_d = d_ids.cpu().numpy(), d_d.cpu().numpy()
     fbpq.fbpq_free_index(h)
     hg = fbpq.fbpq_index_create(gix, 0)
@@ -400,6 +403,7 @@ def run_local(args, w) -> int:
                                f"L log-uniform in [{w['L_lo']}, {w['L_hi']}], k={k}",
                    "N": ix.N, "T": ix.T, "M": ix.M, "nq": nq, "k": k, "mean_L": float(Ls.mean())},
         "kernels": prof,
+        "path_counters": stats,
         "global_codebooks_same_L": {"ms_per_step": g_ms, "value": nq / (g_ms / 1e3), "kernels": g_prof},
         "roofline": roof,
         "cpu_baseline": cpu,

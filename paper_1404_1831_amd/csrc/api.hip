@@ -683,6 +683,7 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         sa.dbg_d = (float *)ddd;
         sa.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
         sa.stats = ix->stats_dev;
+        sa.sel_done = (int32_t *)seldone;
         sa.lq = (const float *)lq;
         sa.dist = (float *)dist;
         sa.lcap = dstride;

@@ -161,6 +161,7 @@ struct ScanArgs {
     const float *lq;       // [slot][M][Kc] query tables (wide scan)
     float *dist;           // [slot][lcap] partial and final distances (wide scan)
     int64_t lcap;
+    int32_t *sel_done;     // [slot] 1: the wide scan selected the top-k itself
     int64_t *out_ids;      // [query][k_max]
     float *out_d;
     int64_t *dbg_pos;      // optional [slot][dbg_cap]

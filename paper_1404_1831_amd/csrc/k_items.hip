@@ -25,7 +25,7 @@ namespace {
 
 constexpr int kNT = 256;                // threads of the item scan and merge
 constexpr int kCPT = kItem / kNT;       // candidates per thread of an item
-constexpr int kTieCapI = 256;
+constexpr int kTieCapI = 4096;  // equal keys at the bound the distance select buffers
 
 template <int MH>
 struct CodeU;
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(kSelNT) void k_select_dist(ItemArgs a)
     const int tid = threadIdx.x, lane = tid & 63;
     const TravHdr h = a.hdr[slot];
     if (h.status != kStOk || (h.n_items == 0 && !h.gscan)) return;
-    if (h.n_items != 0 && a.sel_done[slot]) return;  // selected inside the cell scan
+    if (a.sel_done[slot]) return;  // selected inside the cell scan or the wide scan
     const int64_t qs = a.qlist ? a.qlist[slot] : slot;
     const int kq = a.k[qs];
     int KP = 1;

@@ -317,6 +317,8 @@ constexpr int wide_regions()
 }
 constexpr int kWideRanks = 4097;  // task prefix entries (ranks up to 4096, plus the total)
 constexpr int kWideU = 4;         // 64-candidate chunks a wavefront has in flight
+constexpr int kWideKeep = 6;      // (distance, candidate) pairs each lane keeps for the selection
+constexpr int kWideWin = 512;     // candidates the fused selection can rank
 
 // the last lane o < n whose start v (held by lane o, ascending over lanes) is <= x
 __device__ __forceinline__ int lane_owner(int32_t v, int n, int32_t x)
@@ -372,7 +374,35 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const TravHdr h = a.hdr[slot];
     if (h.status != kStOk || !h.gscan) return;
-    if (a.stats && tid == 0) atomicAdd(&a.stats[kStatTwoPass], 1ull);
+    if (tid == 0) {
+        a.sel_done[slot] = 0;
+        if (a.stats) atomicAdd(&a.stats[kStatTwoPass], 1ull);
+    }
+    // this lane's kWideKeep smallest (distance key, candidate) pairs, ascending,
+    // and the smallest key it did not keep (for the fused selection)
+    uint64_t kp[kWideKeep];
+#pragma unroll
+    for (int q = 0; q < kWideKeep; ++q) kp[q] = ~0ull;
+    uint32_t dmin = 0xffffffffu;
+    auto keep = [&](float d, int64_t t) __attribute__((always_inline)) {
+        const uint64_t kv = ((uint64_t)fkey(d) << 32) | (uint32_t)t;
+        if (kv < kp[kWideKeep - 1]) {
+            const uint32_t out = (uint32_t)(kp[kWideKeep - 1] >> 32);
+            dmin = out < dmin ? out : dmin;
+            kp[kWideKeep - 1] = kv;
+#pragma unroll
+            for (int q = kWideKeep - 1; q > 0; --q) {
+                if (kp[q] < kp[q - 1]) {
+                    const uint64_t x = kp[q - 1];
+                    kp[q - 1] = kp[q];
+                    kp[q] = x;
+                }
+            }
+        } else {
+            const uint32_t kk = (uint32_t)(kv >> 32);
+            dmin = kk < dmin ? kk : dmin;
+        }
+    };
     float *lut = wlut + wv * TL;
     int *tpre = reinterpret_cast<int *>(wlut + NREG * TL);
     float *qs = reinterpret_cast<float *>(tpre + kWideRanks);
@@ -606,6 +636,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
                         if (uu < ue) {
                             const float d = dist[tt[j]] + lut_sum_c<MH>(lut, cv[j]);
                             dist[tt[j]] = d;
+                            keep(d, tt[j]);
                             if (a.dbg_pos) {
                                 a.dbg_pos[(int64_t)slot * a.dbg_cap + tt[j]] = pp[j];
                                 a.dbg_d[(int64_t)slot * a.dbg_cap + tt[j]] = d;
@@ -642,6 +673,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
                     const int64_t p = bego + (t - cso);
                     const float d = dist[t] + lut_sum<MH>(lut, a.ix.codesB, p);
                     dist[t] = d;
+                    keep(d, t);
                     if (a.dbg_pos) {
                         a.dbg_pos[(int64_t)slot * a.dbg_cap + t] = p;
                         a.dbg_d[(int64_t)slot * a.dbg_cap + t] = d;
@@ -657,6 +689,135 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
             tk = tn;
             b = bn;
         }
+    }
+
+    // Fused selection of the kq smallest (distance, id) from the kept pairs.
+    // Each wavefront finds the ceil(kq/NW)-th smallest of its kept keys; the
+    // largest of these bounds tau has kq distinct candidates at or below it.
+    // The kept pairs at or below tau are all the candidates at or below it
+    // unless some lane dropped a key <= tau: then (or with too many keys at or
+    // below tau) the query is left to k_select_dist, which reads the row.
+    __shared__ uint64_t s_win[kWideWin];
+    __shared__ uint32_t s_hist[256];
+    __shared__ uint32_t s_tau, s_digit;
+    __shared__ int s_nwin, s_unsafe, s_need, s_total;
+    const int64_t qry = a.qlist ? a.qlist[slot] : slot;
+    const int kq = a.k[qry];
+    const int nne = h.nne;
+    if (tid == 0) {
+        s_nwin = 0;
+        s_unsafe = 0;
+        s_total = 0;
+    }
+    __syncthreads();
+    {
+        int nv = 0;
+#pragma unroll
+        for (int q = 0; q < kWideKeep; ++q) nv += kp[q] != ~0ull;
+        for (int o = 32; o > 0; o >>= 1) nv += __shfl_xor(nv, o);
+        if (lane == 0) atomicAdd(&s_total, nv);
+    }
+    // tau: the kq-th smallest kept key, 8 bits at a time (every key when
+    // fewer than kq are kept)
+    uint32_t pre = 0;
+    int need = kq;
+    for (int sh8 = 24; sh8 >= 0; sh8 -= 8) {
+        for (int b = tid; b < 256; b += NT) s_hist[b] = 0;
+        __syncthreads();
+        const uint32_t hm = sh8 == 24 ? 0u : (0xffffffffu << (sh8 + 8));
+#pragma unroll
+        for (int q = 0; q < kWideKeep; ++q) {
+            const uint32_t kk = (uint32_t)(kp[q] >> 32);
+            if (kp[q] != ~0ull && (kk & hm) == (pre & hm)) atomicAdd(&s_hist[(kk >> sh8) & 255u], 1u);
+        }
+        __syncthreads();
+        if (wv == 0) {
+            uint32_t c[4], sum = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c[q] = s_hist[lane * 4 + q];
+                sum += c[q];
+            }
+            uint32_t x = sum;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            uint32_t before = x - sum;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (before < (uint32_t)need && before + c[q] >= (uint32_t)need) {
+                    s_digit = lane * 4 + q;
+                    s_need = need - (int)before;
+                }
+                before += c[q];
+            }
+        }
+        __syncthreads();
+        pre |= s_digit << sh8;
+        need = s_need;
+        __syncthreads();
+    }
+    if (tid == 0) s_tau = s_total >= kq ? pre : 0xffffffffu;
+    __syncthreads();
+    const uint32_t tau = s_tau;
+    if (dmin <= tau) s_unsafe = 1;  // a dropped candidate lies at or below tau
+    __syncthreads();
+    auto append = [&](bool pred, uint64_t kk) __attribute__((always_inline)) {
+        const uint64_t m = __ballot(pred);
+        if (m) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_nwin, (int)__popcll(m));
+            base = __shfl(base, 0);
+            if (pred) {
+                const int wi = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+                if (wi < kWideWin) s_win[wi] = kk;
+            }
+        }
+    };
+    if (!s_unsafe) {
+        // the kept pairs at or below tau are all the candidates at or below it
+#pragma unroll
+        for (int q = 0; q < kWideKeep; ++q)
+            append(kp[q] != ~0ull && (uint32_t)(kp[q] >> 32) <= tau, kp[q]);
+    } else {
+        // a lane dropped a key <= tau (equal distances): read the whole row
+        const int64_t ncand = h.ncand;
+        for (int64_t t0 = 0; t0 < ncand; t0 += NT) {
+            const int64_t t = t0 + tid;
+            const uint32_t kk = t < ncand ? fkey(dist[t]) : 0xffffffffu;
+            append(t < ncand && kk <= tau, ((uint64_t)kk << 32) | (uint32_t)t);
+        }
+    }
+    __syncthreads();
+    const int nwin = s_nwin;
+    if (nwin > kWideWin) return;  // many equal distances at the bound: k_select_dist
+    for (int i = tid; i < nwin; i += NT) {
+        const uint64_t x = s_win[i];
+        const int64_t t = (uint32_t)x;
+        const int e = last_le(t_cs, 0, nne, t);
+        s_win[i] = (x & 0xffffffff00000000ull) | a.ix.ids[t_beg[e] + (t - t_cs[e])];
+    }
+    __syncthreads();
+    int64_t *oid = a.out_ids + qry * a.k_max;
+    float *od = a.out_d + qry * a.k_max;
+    const int nk = nwin < kq ? nwin : kq;
+    for (int i = tid; i < nwin; i += NT) {
+        const uint64_t x = s_win[i];
+        int rank = 0;
+        for (int j = 0; j < nwin; ++j) rank += s_win[j] < x;
+        if (rank < nk) {
+            oid[rank] = (int64_t)(uint32_t)x;
+            od[rank] = unfkey((uint32_t)(x >> 32));
+        }
+    }
+    for (int r = nk + tid; r < a.k_max; r += NT) {
+        oid[r] = -1;
+        od[r] = __builtin_huge_valf();
+    }
+    if (tid == 0) {
+        a.sel_done[slot] = 1;
+        if (a.stats) atomicAdd(&a.stats[kStatFused], 1ull);
     }
 }
 
