@@ -99,6 +99,8 @@ def main() -> int:
     ap.add_argument("--served-batch", type=int, default=512)
     ap.add_argument("--plain-queries", type=int, default=200,
                     help="queries searched one launch sequence at a time, for the per-query comparison")
+    ap.add_argument("--adc-steps", type=int, default=3,
+                    help="batches searched with the O(D) Multi-D-ADC rerank, for the comparison (0: skip)")
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="untimed steps with every kernel timed, for the per-kernel breakdown")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -248,6 +250,23 @@ def main() -> int:
                "topk_overlap_with_gpu": overlap, "max_rel_dist_diff": float(rel.max())}
         log(f"cpu oracle: {n1} queries in {t_cpu:.1f}s on {threads} threads")
 
+    # the Multi-D-ADC baseline on the GPU: the same search with every candidate
+    # scored by explicit O(D) reconstruction instead of the FBPQ tables
+    adc = None
+    if args.adc_steps > 0:
+        fbpq.fbpq_set_option(h, "adc_od", 1)
+        for _ in range(2):
+            fbpq.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, stream)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.adc_steps):
+            fbpq.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, stream)
+        torch.cuda.synchronize()
+        adc_ms = (time.perf_counter() - a) * 1e3 / args.adc_steps
+        fbpq.fbpq_set_option(h, "adc_od", 0)
+        adc = {"ms_per_step": adc_ms, "value": nq / (adc_ms / 1e3), "fbpq_speedup": adc_ms / ms_per_step}
+        log(f"Multi-D-ADC O(D) baseline: {adc_ms:.3f} ms per batch (FBPQ {ms_per_step:.3f} ms)")
+
     if args.calibrate_copy_mib > 0:
         nel = args.calibrate_copy_mib * (1 << 20) // 4
         x = torch.ones(nel, dtype=torch.float32, device=dev)
@@ -279,6 +298,7 @@ def main() -> int:
                    "N": ix.N, "T": ix.T, "M": ix.M, "nq": nq, "L": L, "k": k},
         "kernels": prof,
         "graph_replay": {"ms_per_step": graph_ms, "value": nq / (graph_ms / 1e3)},
+        "multi_d_adc_baseline": adc,
         "plain_per_query": ({"queries": npl, "value": npl / plain_s, "unit": "queries/s",
                              "ms_per_query": plain_s * 1e3 / npl} if npl > 0 else None),
         "scan_GBps": scan_GBps,

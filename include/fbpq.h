@@ -182,7 +182,10 @@ int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int
  * with fbpq_stats_read), "pop_budget" (cells the traversal visits one at a
  * time before it switches to threshold steps, which load the point counts of
  * many cells at once; 0 switches at once; default 512; the visited cells are
- * the same either way), "graph" (0/1: the first traversal round of a search
+ * the same either way), "adc_od" (0/1: score every candidate by explicit
+ * reconstruction, O(D) per candidate -- the Multi-D-ADC rerank of Section
+ * 2.3.3 -- instead of the FBPQ tables; same visited cells and, up to FP32
+ * rounding, the same distances; a baseline for comparison), "graph" (0/1: the first traversal round of a search
  * is captured once into a HIP graph and replayed on later searches with the
  * same queries buffer, result buffers, nq, k_max, min(L, N) and options;
  * retry rounds and profiled or debug searches run eagerly). Errors: INVALID,

@@ -649,7 +649,7 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         ia.dbg_pos = (int64_t *)dpos;
         ia.dbg_d = (float *)ddd;
         ia.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
-        if (!dv.local)  // local codebooks fold the query part per row and column instead
+        if (!dv.local && !dv.od)  // local codebooks and the O(D) scan do not use LQ
             HCK(ix, timed(ix, FBPQ_STAGE_LQ, st, [&] { return launch_items_prep(ia, st); }));
         if (ix->items) HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_scan(ia, st); }));
         ScanArgs sa{};
@@ -1259,6 +1259,14 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
             HCK(ix, hipDeviceSynchronize());
             (void)hipFree(ix->stats_dev);
             ix->stats_dev = nullptr;
+        }
+    } else if (!strcmp(key, "adc_od")) {
+        // score every candidate by explicit reconstruction (the Multi-D-ADC baseline)
+        ix->dv.od = value != 0 ? 1 : 0;
+        if (ix->gexec) {
+            HCK(ix, hipDeviceSynchronize());
+            (void)hipGraphExecDestroy(ix->gexec);
+            ix->gexec = nullptr;
         }
     } else if (!strcmp(key, "pop_budget")) {
         if (value < 0 || value > ((int64_t)1 << 26)) return fail(FBPQ_E_INVALID, "pop_budget out of range");

@@ -61,6 +61,7 @@ struct DevIndex {
     float cmax1, cmax2;  // largest squared half-centroid norm of each half
     const float *QL, *SL;  // local codebooks [T][M/2][Kc][D/M] (HBPQ), or null
     int32_t local;         // 1: local codebooks
+    int32_t od;            // 1: candidates scored by explicit O(D) reconstruction (Multi-D-ADC baseline)
 };
 
 // Launchers (each defined next to its kernel).

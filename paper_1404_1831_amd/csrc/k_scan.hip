@@ -304,16 +304,28 @@ __global__ __launch_bounds__(512) void k_scan2(ScanArgs a)
 // the query part computed here from the row's own codebooks (and likewise for
 // the columns with S^j).
 // Wavefronts per query: as many as 64 KB of folded tables allow, up to 16.
-template <int MH, bool LOCAL>
-constexpr int wide_waves() { return LOCAL && MH <= 8 ? 16 : (MH <= 4 ? 16 : (MH == 8 ? 8 : 4)); }
+// Scan modes: the FBPQ tables of the global codebooks, the tables of local
+// codebooks, or (the Multi-D-ADC baseline) the explicit O(D) reconstruction.
+enum : int { kWideFbpq = 0, kWideLocal = 1, kWideOD = 2 };
+template <int MH, int MODE>
+constexpr int wide_waves() { return MODE != kWideFbpq && MH <= 8 ? 16 : (MH <= 4 ? 16 : (MH == 8 ? 8 : 4)); }
 // With local codebooks, a query with at most this many distinct row and column
 // tables folds each of them once into LDS, shared by all its tasks.
 template <int MH>
 constexpr int wide_tables() { return MH <= 8 ? 16 : 8; }
-template <int MH, bool LOCAL>
+template <int MH, int MODE>
 constexpr int wide_regions()
 {
-    return LOCAL && wide_tables<MH>() > wide_waves<MH, LOCAL>() ? wide_tables<MH>() : wide_waves<MH, LOCAL>();
+    return MODE == kWideLocal && wide_tables<MH>() > wide_waves<MH, MODE>() ? wide_tables<MH>()
+                                                                            : wide_waves<MH, MODE>();
+}
+// floats before the task prefix: folded tables, or (O(D) mode) one half of the
+// codebooks [M/2][Kc][D/M] and each wavefront's q - c of its task
+template <int MH, int MODE>
+__host__ __device__ constexpr int64_t wide_region_floats(int D)
+{
+    return MODE == kWideOD ? (int64_t)MH * kKc * (D / (2 * MH)) + (int64_t)wide_waves<MH, MODE>() * (D / 2)
+                           : (int64_t)wide_regions<MH, MODE>() * MH * kKc;
 }
 constexpr int kWideRanks = 4097;  // task prefix entries (ranks up to 4096, plus the total)
 constexpr int kWideU = 4;         // 64-candidate chunks a wavefront has in flight
@@ -361,13 +373,15 @@ __device__ void wide_scan(int *x, int n, int *wtot)
     __syncthreads();
 }
 
-template <int MH, bool LOCAL>
-__global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(ScanArgs a)
+template <int MH, int MODE>
+__global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(ScanArgs a)
 {
-    constexpr int NW = wide_waves<MH, LOCAL>();
+    constexpr bool LOCAL = MODE == kWideLocal;
+    constexpr bool OD = MODE == kWideOD;
+    constexpr int NW = wide_waves<MH, MODE>();
     constexpr int NT = 64 * NW;
     constexpr int TL = MH * kKc;  // floats of one folded half table
-    constexpr int NREG = wide_regions<MH, LOCAL>();
+    constexpr int NREG = wide_regions<MH, MODE>();
     extern __shared__ __align__(16) float wlut[];  // [NREG][TL], then the task prefix [kWideRanks], then q [D]
     __shared__ int wtot[NW];
     const int slot = blockIdx.x;
@@ -404,7 +418,9 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
         }
     };
     float *lut = wlut + wv * TL;
-    int *tpre = reinterpret_cast<int *>(wlut + NREG * TL);
+    int *tpre = reinterpret_cast<int *>(wlut + wide_region_floats<MH, MODE>(a.ix.D));
+    float *cbh = wlut;                                  // O(D): the codebook half of the pass
+    float *qcw = wlut + (int64_t)TL * (a.ix.D / (2 * MH)) + wv * (a.ix.D / 2);  // O(D): this wave's q - c
     float *qs = reinterpret_cast<float *>(tpre + kWideRanks);
     const int P = a.P;
     const int D = a.ix.D, ds = D / (2 * MH);
@@ -424,16 +440,46 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
     float *dist = a.dist + (int64_t)slot * a.lcap;
     const uint64_t below_lane = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
     const int A = h.A, B = h.B;
-    if (LOCAL) {
+    if (LOCAL || OD) {
         const int64_t qsl = a.qlist ? a.qlist[slot] : slot;
         for (int t = tid; t < D; t += NT) qs[t] = a.q[qsl * D + t];
     }
+    // O(D): stage the codebooks R_k, k in [half*M/2, half*M/2 + M/2), in LDS
+    auto stage_half = [&](int half) __attribute__((always_inline)) {
+        if (!OD) return;
+        const int64_t n = (int64_t)TL * ds;
+        const float *src = a.ix.R + (int64_t)half * n;
+        for (int64_t e = tid; e < n; e += NT) cbh[e] = src[e];
+    };
+    // O(D): this wavefront's q_h - c for its current task
+    auto set_qc = [&](int half, int cent) __attribute__((always_inline)) {
+        const float *c = (half ? a.ix.C2 : a.ix.C1) + (int64_t)cent * (D / 2);
+        __builtin_amdgcn_wave_barrier();
+        for (int t = lane; t < D / 2; t += 64) qcw[t] = qs[half * (D / 2) + t] - c[t];
+        __builtin_amdgcn_wave_barrier();
+    };
+    // O(D): sum over the half's subspaces of ||(q - c)|k - R_k(b_k)||^2
+    auto od_sum = [&](typename CodeT<MH>::T code) __attribute__((always_inline)) {
+        uint8_t bytes[MH];
+        __builtin_memcpy(bytes, &code, MH);
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < MH; ++k) {
+            const float *w = cbh + ((int64_t)k * kKc + bytes[k]) * ds;
+            const float *qk = qcw + k * ds;
+            for (int t = 0; t < ds; ++t) {
+                const float e = qk[t] - w[t];
+                acc = fmaf(e, e, acc);
+            }
+        }
+        return acc;
+    };
 
     constexpr int TQ = TL / 4 / 64;  // float4 of a table per lane
     float4 nxt[TQ];
     // the global-codebook fold reads the CR row prefetched into nxt
     auto fetch = [&](const float *crrow) __attribute__((always_inline)) {
-        if (LOCAL) return;
+        if (LOCAL || OD) return;
         const float4 *cr = reinterpret_cast<const float4 *>(crrow);
 #pragma unroll
         for (int e = 0; e < TQ; ++e) nxt[e] = cr[lane + 64 * e];
@@ -478,6 +524,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
     }
 
     // ---- pass 1: row tasks, first half of the code plus the cell constant ----
+    stage_half(0);
     for (int ar = tid; ar <= A; ar += NT)
         tpre[ar] = ar < A ? (row_cand[ar + 1] - row_cand[ar] + kWideChunk - 1) / kWideChunk : 0;
     __syncthreads();
@@ -498,7 +545,8 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
         if (tk < ntask) fetch(a.ix.CR1 + (int64_t)u[ar] * TL);
         while (tk < ntask) {
             const int ch = tk - tpre[ar];
-            if (shared_tab) lut = wlut + (t_nsl[row_ne[ar]] & 0xffff) * TL;
+            if (OD) set_qc(0, u[ar]);
+            else if (shared_tab) lut = wlut + (t_nsl[row_ne[ar]] & 0xffff) * TL;
             else fold(0, u[ar], lut);
             const int tn = tk + NW;
             const int an = tn < ntask ? task_row(tn) : 0;
@@ -534,7 +582,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
 #pragma unroll
                     for (int j = 0; j < kWideU; ++j) {
                         const int64_t t = t0 + 64 * j + lane;
-                        if (t < re) dist[t] = lut_sum_c<MH>(lut, cv[j]) + cst_[j];
+                        if (t < re) dist[t] = OD ? od_sum(cv[j]) : lut_sum_c<MH>(lut, cv[j]) + cst_[j];
                     }
                 }
                 tk = tn;
@@ -561,7 +609,10 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
                 const int64_t bego = __shfl(beg, owner);
                 const float csto = __shfl(cst, owner);
                 const int64_t t = t0 + lane;
-                if (t < re) dist[t] = lut_sum<MH>(lut, a.ix.codesA, bego + (t - cso)) + csto;
+                if (t < re) {
+                    const auto code = load_code<MH>(a.ix.codesA, bego + (t - cso));
+                    dist[t] = OD ? od_sum(code) : lut_sum_c<MH>(lut, code) + csto;
+                }
                 // cell of candidate t0 + 64: that of lane 63's candidate, or the next
                 const int o63 = __shfl(owner, 63);
                 int xn = x0 + o63;
@@ -577,6 +628,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
     __syncthreads();  // every partial sum of the query is stored; tpre is free
 
     // ---- pass 2: column tasks, second half of the code ----
+    stage_half(1);
     for (int b = tid; b <= B; b += NT)
         tpre[b] = b < B ? (col_tot[b] + kWideChunk - 1) / kWideChunk : 0;
     __syncthreads();
@@ -597,7 +649,8 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
         if (tk < ntask) fetch(a.ix.CR2 + (int64_t)v[b] * TL);
         while (tk < ntask) {
             const int ch = tk - tpre[b];
-            if (shared_tab) lut = wlut + (t_nsl[t_cmc[col_ne[b]]] >> 16) * TL;
+            if (OD) set_qc(1, v[b]);
+            else if (shared_tab) lut = wlut + (t_nsl[t_cmc[col_ne[b]]] >> 16) * TL;
             else fold(1, v[b], lut);
             const int tn = tk + NW;
             const int bn = tn < ntask ? task_col(tn) : 0;
@@ -634,7 +687,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
                     for (int j = 0; j < kWideU; ++j) {
                         const int uu = u0 + 64 * j + lane;
                         if (uu < ue) {
-                            const float d = dist[tt[j]] + lut_sum_c<MH>(lut, cv[j]);
+                            const float d = dist[tt[j]] + (OD ? od_sum(cv[j]) : lut_sum_c<MH>(lut, cv[j]));
                             dist[tt[j]] = d;
                             keep(d, tt[j]);
                             if (a.dbg_pos) {
@@ -671,7 +724,8 @@ __global__ __launch_bounds__((64 * wide_waves<MH, LOCAL>())) void k_scan_wide(Sc
                 if (uu < ue) {
                     const int64_t t = cso + (uu - preo);
                     const int64_t p = bego + (t - cso);
-                    const float d = dist[t] + lut_sum<MH>(lut, a.ix.codesB, p);
+                    const auto code = load_code<MH>(a.ix.codesB, p);
+                    const float d = dist[t] + (OD ? od_sum(code) : lut_sum_c<MH>(lut, code));
                     dist[t] = d;
                     keep(d, t);
                     if (a.dbg_pos) {
@@ -867,18 +921,20 @@ hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st)
     if (nslots == 0) return hipSuccess;
     const dim3 g((unsigned)nslots);
     const size_t extra = (size_t)kWideRanks * sizeof(int) + (size_t)a.ix.D * sizeof(float);
-#define FBPQ_WIDE_CASE(MH)                                                                        \
-    case MH: {                                                                                    \
-        const size_t tab = (size_t)MH * kKc * sizeof(float);                                      \
-        constexpr int reg_l = wide_regions<MH, true>(), reg_g = wide_regions<MH, false>();         \
-        const size_t lds_l = reg_l * tab + extra, lds_g = reg_g * tab + extra;                    \
-        constexpr int nt_l = 64 * wide_waves<MH, true>(), nt_g = 64 * wide_waves<MH, false>();   \
-        if (a.ix.local)                                                                           \
-            hipLaunchKernelGGL((k_scan_wide<MH, true>), g, dim3(nt_l), lds_l, st, a);                  \
-        else                                                                                      \
-            hipLaunchKernelGGL((k_scan_wide<MH, false>), g, dim3(nt_g), lds_g, st, a);                 \
-        break;                                                                                    \
+    const int mode = a.ix.od ? kWideOD : (a.ix.local ? kWideLocal : kWideFbpq);
+#define FBPQ_WIDE_MODE(MH, MODE)                                                                  \
+    {                                                                                             \
+        constexpr int nt = 64 * wide_waves<MH, MODE>();                                           \
+        const size_t lds = (size_t)wide_region_floats<MH, MODE>(a.ix.D) * sizeof(float) + extra;  \
+        if (lds > 160 * 1024) return hipErrorInvalidValue;                                       \
+        hipLaunchKernelGGL((k_scan_wide<MH, MODE>), g, dim3(nt), lds, st, a);                     \
     }
+#define FBPQ_WIDE_CASE(MH)                                                                        \
+    case MH:                                                                                      \
+        if (mode == kWideOD) FBPQ_WIDE_MODE(MH, kWideOD)                                          \
+        else if (mode == kWideLocal) FBPQ_WIDE_MODE(MH, kWideLocal)                               \
+        else FBPQ_WIDE_MODE(MH, kWideFbpq)                                                        \
+        break;
     switch (a.ix.M / 2) {
         FBPQ_WIDE_CASE(1)
         FBPQ_WIDE_CASE(2)
@@ -888,6 +944,7 @@ hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st)
     default: return hipErrorInvalidValue;
     }
 #undef FBPQ_WIDE_CASE
+#undef FBPQ_WIDE_MODE
     return hipGetLastError();
 }
 

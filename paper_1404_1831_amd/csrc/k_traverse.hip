@@ -442,9 +442,9 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
     if (lane == 0) {
         args.hdr[slot].nne = nerun;
         const bool dense = nerun > 0 && crun >= (int64_t)kItemMinAvg * nerun;
-        const bool items = args.allow_items && dense && !args.ix.local;
+        const bool items = args.allow_items && dense && !args.ix.local && !args.ix.od;
         args.hdr[slot].n_items = items ? itrun : 0;
-        args.hdr[slot].gscan = args.ix.local || (!dense && crun > kScanWideMin) ? 1 : 0;
+        args.hdr[slot].gscan = args.ix.local || args.ix.od || (!dense && crun > kScanWideMin) ? 1 : 0;
     }
 }
 

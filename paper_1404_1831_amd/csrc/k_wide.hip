@@ -890,9 +890,9 @@ __global__ __launch_bounds__(kLayNT) void k_layout_wide(LayoutArgs args)
     if (tid == 0) {
         args.hdr[slot].nne = (int32_t)nerun;
         const bool dense = nerun > 0 && crun >= (int64_t)kItemMinAvg * nerun;
-        const bool items = args.allow_items && dense && !args.ix.local;
+        const bool items = args.allow_items && dense && !args.ix.local && !args.ix.od;
         args.hdr[slot].n_items = items ? (int32_t)itrun : 0;
-        args.hdr[slot].gscan = args.ix.local || (!dense && crun > kScanWideMin) ? 1 : 0;
+        args.hdr[slot].gscan = args.ix.local || args.ix.od || (!dense && crun > kScanWideMin) ? 1 : 0;
     }
     (void)tne;
 }

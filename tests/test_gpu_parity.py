@@ -542,6 +542,28 @@ def test_local_long_rows_in_chunks(fb):
     assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
 
 
+# ---- the Multi-D-ADC baseline: explicit O(D) reconstruction on the GPU -----------
+
+@pytest.mark.parametrize("which,L", [("small", 777), ("small", 10000), ("m16", 5000)])
+def test_adc_od_baseline_matches_oracle(fb, gmm_small, gmm_m16, which, L):
+    ix, Q = gmm_small if which == "small" else gmm_m16
+    k = 20
+    log(f"O(D) baseline: {which} L={L}")
+    h = _open(fb, ix, adc_od=1, stats=1)
+    got = fb.fbpq_debug_dists(h, Q[:6], L, cap=min(L, ix.N))
+    for r in range(6):
+        pos, d32 = got[r]
+        _, opos = oracle.visit(ix, Q[r], L)
+        assert np.array_equal(np.sort(pos), np.sort(opos)), r
+        d64 = oracle_dists(ix, Q[r], pos)
+        assert np.all(np.abs(d32.astype(np.float64) - d64) <= tol(ix, Q[r], pos, d64)), r
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    assert fb.fbpq_stats_read(h)["two_pass"] >= Q.shape[0]
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
 # ---- the selection fused into the cell scan and its fallbacks --------------------
 
 def _dense_index(const_codes: bool):
