@@ -25,120 +25,194 @@ namespace fbpq {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // ---- step 1: approximate keys on the matrix cores ---------------------------
-// Block tile: 64 queries x 128 centroids of one half, 4 wavefronts; wavefront w
-// owns queries [16w, 16w+16) and all 128 centroids (8 blocks of 16x16). Each
-// v_mfma_f32_16x16x4f32 takes A[i][k] from lane i + 16k and B[k][j] from lane
-// j + 16k and leaves D[4*(lane/16) + r][lane % 16] in accumulator r.
-constexpr int kAQ = 64, kAC = 128, kAS = 68;  // LDS row stride 68 floats: conflict-free reads
+// A wavefront owns kQT tiles of 16 rows (query halves of one half) and a chunk
+// of kCT centroids, which it takes 16 at a time. The dot product runs over the
+// D/2 coordinates in slabs of 64; inside a slab, coordinate 16k + s feeds step
+// s of v_mfma_f32_16x16x4f32 from lane i + 16k (A: row i) and lane j + 16k
+// (B: centroid j), so each lane reads 16 consecutive floats of its own row and
+// the operands need no LDS. The instruction leaves D[4*(lane/16) + r][lane % 16]
+// in accumulator r. The summation order differs from a plain loop, which the
+// error bound of step 2 allows (it holds for any order). One tile holds only
+// 64 bytes of each output row, so the keys of four tiles are staged in LDS and
+// written as 256-byte runs: the key array is the kernel's dominant traffic.
+constexpr int kQT = 2;    // 16-row query tiles per wavefront
+constexpr int kCT = 256;  // centroids per wavefront (a multiple of 64)
+constexpr int kStgLd = 68;  // LDS row stride of the staged keys (floats): 64 keys + 4
 
+// v[s] = row[t + s] for t + s < h, 0 beyond h or when the row is absent
+__device__ __forceinline__ void load_strip(const float *__restrict__ row, bool ok, int t, int h, bool vec,
+                                           float v[16])
+{
+    if (ok && vec && t + 16 <= h) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float4 x = *reinterpret_cast<const float4 *>(row + t + 4 * u);
+            v[4 * u] = x.x;
+            v[4 * u + 1] = x.y;
+            v[4 * u + 2] = x.z;
+            v[4 * u + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = (ok && t + u < h) ? row[t + u] : 0.f;
+    }
+}
+
+// ONE: D/2 <= 64, so the query rows are loaded once and stay in registers
+template <bool ONE>
 __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q, int64_t nq, int D,
                                                      const int32_t *__restrict__ qlist,
                                                      const float *__restrict__ C1,
                                                      const float *__restrict__ C2,
                                                      const float *__restrict__ nC1,
-                                                     const float *__restrict__ nC2, int T,
+                                                     const float *__restrict__ nC2, int T, int nchunk,
                                                      float *__restrict__ ka)
 {
     // rows are slots 0..nq-1; slot s holds query qlist[s] (or s); ka is [slot][2][T]
-    __shared__ __align__(16) float qs[kAQ * kAS];
-    __shared__ __align__(16) float cs[kAC * kAS];
-    __shared__ float qn[kAQ];
-    const int half = blockIdx.z;
+    __shared__ __align__(16) float stage[4][16 * kQT * kStgLd];  // per wavefront: 16 kQT rows x 64 keys
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    // the wavefront index, in a scalar register so that everything derived from
+    // it (and every branch on it) is uniform
+    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t ngrp = (nq + 16 * kQT - 1) / (16 * kQT);
+    const int64_t g = w / nchunk;
+    if (g >= 2 * ngrp) return;  // no barriers below: a wavefront may leave alone
+    const int chunk = (int)(w - g * nchunk);
+    const int half = (int)(g / ngrp);
+    const int64_t s0 = (g - half * ngrp) * 16 * kQT;
     const int h = D / 2;
+    const bool vec = ((h | D) & 3) == 0;
     const float *C = half ? C2 : C1;
     const float *nC = half ? nC2 : nC1;
-    const int64_t q0 = (int64_t)blockIdx.y * kAQ;
-    const int c0 = blockIdx.x * kAC;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-
-    floatx4 acc[8];
+    const float *qrow[kQT];
+    bool qok[kQT];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float qnorm = 0.f;  // thread tid < 64 accumulates ||q_tid||^2 over the slabs
-
-    const bool vec = (h & 3) == 0;
-    for (int t0 = 0; t0 < h; t0 += 64) {
-        const int tn = min(64, h - t0);
-        __syncthreads();
-        if (vec) {
-            // 16-byte loads, all issued before the LDS stores: 4 of the query
-            // slab and 8 of the centroid slab per thread
-            float4 qv[4], cv[8];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int e = tid + 256 * i, row = e >> 4, t = 4 * (e & 15);
-                const int64_t qi = q0 + row;
-                const int64_t qr = qi < nq ? (qlist ? qlist[qi] : qi) : 0;
-                qv[i] = (qi < nq && t < tn)
-                            ? *reinterpret_cast<const float4 *>(Q + qr * D + half * h + t0 + t)
-                            : float4{0.f, 0.f, 0.f, 0.f};
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int e = tid + 256 * i, row = e >> 4, t = 4 * (e & 15);
-                const int ci = c0 + row;
-                cv[i] = (ci < T && t < tn) ? *reinterpret_cast<const float4 *>(C + (int64_t)ci * h + t0 + t)
-                                           : float4{0.f, 0.f, 0.f, 0.f};
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int e = tid + 256 * i;
-                *reinterpret_cast<float4 *>(&qs[(e >> 4) * kAS + 4 * (e & 15)]) = qv[i];
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int e = tid + 256 * i;
-                *reinterpret_cast<float4 *>(&cs[(e >> 4) * kAS + 4 * (e & 15)]) = cv[i];
-            }
-        } else {
-            for (int e = tid; e < kAQ * 64; e += 256) {
-                const int qq = e >> 6, t = e & 63;
-                const int64_t qi = q0 + qq;
-                const int64_t qr = qi < nq ? (qlist ? qlist[qi] : qi) : 0;
-                qs[qq * kAS + t] = (qi < nq && t < tn) ? Q[qr * D + half * h + t0 + t] : 0.f;
-            }
-            for (int e = tid; e < kAC * 64; e += 256) {
-                const int cc = e >> 6, t = e & 63;
-                const int ci = c0 + cc;
-                cs[cc * kAS + t] = (ci < T && t < tn) ? C[(int64_t)ci * h + t0 + t] : 0.f;
-            }
-        }
-        __syncthreads();
-        if (tid < kAQ) {
-            // any summation order suits the error bound: four partial sums
-            float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-            for (int t = 0; t < 64; t += 4) {
-                const float4 x = *reinterpret_cast<const float4 *>(&qs[tid * kAS + t]);  // zero beyond tn
-                p0 = fmaf(x.x, x.x, p0);
-                p1 = fmaf(x.y, x.y, p1);
-                p2 = fmaf(x.z, x.z, p2);
-                p3 = fmaf(x.w, x.w, p3);
-            }
-            qnorm += (p0 + p1) + (p2 + p3);
-        }
-        for (int s = 0; s < 16; ++s) {
-            const float a = qs[(wv * 16 + li) * kAS + 4 * s + lk];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float b = cs[(j * 16 + li) * kAS + 4 * s + lk];
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[j], 0, 0, 0);
-            }
-        }
+    for (int a = 0; a < kQT; ++a) {
+        const int64_t slot = s0 + 16 * a + li;
+        qok[a] = slot < nq;
+        const int64_t qr = qok[a] ? (qlist ? qlist[slot] : slot) : 0;
+        qrow[a] = Q + qr * D + (int64_t)half * h;
     }
-    if (tid < kAQ) qn[tid] = qnorm;
-    __syncthreads();
+    const int nsl = (h + 63) / 64;
+    float av[kQT][16];
+    float qn[kQT];  // ||q_h||^2 of row 16a + li
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int ci = c0 + j * 16 + li;
-        if (ci >= T) continue;
-        const float nc = nC[ci];
+    for (int a = 0; a < kQT; ++a) {
+        // ||q_h||^2 of row 16a + li: this lane's 16 coordinates of each slab,
+        // then the four lanes of the row (any order suits the bound)
+        float p = 0.f;
+        for (int sl = 0; sl < (ONE ? 1 : nsl); ++sl) {
+            load_strip(qrow[a], qok[a], 64 * sl + 16 * lk, h, vec, av[a]);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int qq = wv * 16 + 4 * lk + r;
-            const int64_t qi = q0 + qq;
-            if (qi < nq) ka[(qi * 2 + half) * (int64_t)T + ci] = (qn[qq] + nc) - 2.f * acc[j][r];
+            for (int u = 0; u < 16; ++u) p = fmaf(av[a][u], av[a][u], p);
         }
+        p += __shfl_xor(p, 16);
+        p += __shfl_xor(p, 32);
+        qn[a] = p;
+    }
+    const int cb = chunk * kCT, ce = min(T, cb + kCT);
+    float *kout = ka + (s0 * 2 + half) * (int64_t)T;  // row s0 + q of this half at kout[2 q T]
+    if (ONE && vec && h == 64 && s0 + 16 * kQT <= nq && ce - cb == kCT) {
+        // every row and centroid present: the next centroid strip is loaded
+        // before this tile's products, and the stores are unconditional, so
+        // waiting for the strip does not wait for the stores
+        const int64_t ldq = 2 * (int64_t)T;
+        float nq4[kQT][4];
+#pragma unroll
+        for (int a = 0; a < kQT; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) nq4[a][r] = __shfl(qn[a], 4 * lk + r);
+        // Centroid strips alternate between two register sets, a set loaded
+        // one tile before its products. Four tiles (64 centroids) are staged
+        // in this wavefront's LDS slot and written as 256-byte runs of each
+        // row, 16 bytes per lane: whole cache lines instead of the 64-byte
+        // pieces one tile holds per row.
+        float *stg = stage[threadIdx.x >> 6];
+        float b0[16], b1[16];
+        float n0, n1;
+        auto tile = [&](const float (&bv)[16], float nc, int col) __attribute__((always_inline)) {
+            floatx4 acc[kQT];
+#pragma unroll
+            for (int a = 0; a < kQT; ++a) acc[a] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+#pragma unroll
+                for (int a = 0; a < kQT; ++a)
+                    acc[a] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][u], bv[u], acc[a], 0, 0, 0);
+#pragma unroll
+            for (int a = 0; a < kQT; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    stg[(16 * a + 4 * lk + r) * kStgLd + col + li] = (nq4[a][r] + nc) - 2.f * acc[a][r];
+        };
+        // LDS executes a wavefront's instructions in issue order: the staged
+        // keys are visible to the other lanes once the writes have completed
+        // (lgkmcnt 0, vector memory counters untouched); the empty asm keeps
+        // the compiler from moving LDS accesses across
+        auto lds_order = [&]() __attribute__((always_inline)) {
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0) only
+            __builtin_amdgcn_wave_barrier();
+            __asm__ __volatile__("" ::: "memory");
+        };
+        auto flush = [&](int c0) __attribute__((always_inline)) {
+            lds_order();
+#pragma unroll
+            for (int i = 0; i < 16 * kQT / 4; ++i) {
+                const int row = 4 * i + (lane >> 4), col = 4 * (lane & 15);
+                const float4 v = *reinterpret_cast<const float4 *>(stg + row * kStgLd + col);
+                *reinterpret_cast<float4 *>(kout + row * ldq + c0 + col) = v;
+            }
+            lds_order();
+        };
+        load_strip(C + (int64_t)(cb + li) * h, true, 16 * lk, h, true, b0);
+        n0 = nC[cb + li];
+#pragma unroll
+        for (int t = 0; t < kCT / 16; ++t) {  // straight-line code: exact wait counts
+            const int c0 = cb + 16 * t;
+            if (t + 1 < kCT / 16) {
+                if (t & 1) {
+                    load_strip(C + (int64_t)(c0 + 16 + li) * h, true, 16 * lk, h, true, b0);
+                    n0 = nC[c0 + 16 + li];
+                } else {
+                    load_strip(C + (int64_t)(c0 + 16 + li) * h, true, 16 * lk, h, true, b1);
+                    n1 = nC[c0 + 16 + li];
+                }
+            }
+            if (t & 1) tile(b1, n1, 16 * (t & 3));
+            else tile(b0, n0, 16 * (t & 3));
+            if ((t & 3) == 3) flush(c0 - 48);
+        }
+        return;
+    }
+    for (int c0 = cb; c0 < ce; c0 += 16) {
+        const int c = c0 + li;
+        const bool cok = c < ce;
+        const float *crow = C + (int64_t)(cok ? c : 0) * h;
+        floatx4 acc[kQT];
+#pragma unroll
+        for (int a = 0; a < kQT; ++a) acc[a] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int sl = 0; sl < (ONE ? 1 : nsl); ++sl) {
+            float bv[16];
+            load_strip(crow, cok, 64 * sl + 16 * lk, h, vec, bv);
+            if constexpr (!ONE) {
+#pragma unroll
+                for (int a = 0; a < kQT; ++a) load_strip(qrow[a], qok[a], 64 * sl + 16 * lk, h, vec, av[a]);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+#pragma unroll
+                for (int a = 0; a < kQT; ++a)
+                    acc[a] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][u], bv[u], acc[a], 0, 0, 0);
+        }
+        const float nc = cok ? nC[c] : 0.f;
+#pragma unroll
+        for (int a = 0; a < kQT; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t slot = s0 + 16 * a + 4 * lk + r;
+                const float n = __shfl(qn[a], 4 * lk + r);  // the norm of this output's row
+                if (slot < nq && cok) ka[(slot * 2 + half) * (int64_t)T + c] = (n + nc) - 2.f * acc[a][r];
+            }
     }
 }
 
@@ -146,9 +220,15 @@ hipError_t launch_half_approx(const DevIndex &ix, const float *q, const int32_t 
                               float *ka, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
-    dim3 grid((unsigned)((ix.T + kAC - 1) / kAC), (unsigned)((nslots + kAQ - 1) / kAQ), 2);
-    hipLaunchKernelGGL(k_half_approx, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2, ix.nC1,
-                       ix.nC2, ix.T, ka);
+    const int nchunk = (ix.T + kCT - 1) / kCT;
+    const int64_t waves = 2 * ((nslots + 16 * kQT - 1) / (16 * kQT)) * nchunk;
+    const dim3 grid((unsigned)((waves + 3) / 4));
+    if (ix.D / 2 <= 64)
+        hipLaunchKernelGGL(k_half_approx<true>, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2,
+                           ix.nC1, ix.nC2, ix.T, nchunk, ka);
+    else
+        hipLaunchKernelGGL(k_half_approx<false>, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2,
+                           ix.nC1, ix.nC2, ix.T, nchunk, ka);
     return hipGetLastError();
 }
 
@@ -616,7 +696,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
 // sample (found bit by bit with ballot counts) bounds kP from above, as P
 // distinct centroids lie at or below it.
 // Survivors (ka <= bound + 2e) are compacted with ballots, get their exact
-// FP64 keys and are ranked by (key, index) inside the wave. When more than
+// FP64 keys and are sorted by (key, index) inside the wave. When more than
 // kWaveS survive, pstat keeps the pair for the workgroup kernel.
 constexpr int kWPB = 4;  // wavefronts (query halves) per workgroup
 
@@ -629,6 +709,80 @@ __device__ __forceinline__ uint32_t okey(float f)
 __device__ __forceinline__ float unokey(uint32_t k)
 {
     return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
+}
+
+// Exact keys of the n survivors sidx[0..n) and their ranking by (key, centroid
+// index): element i = 64 r + lane sits in register r of its lane, padded with
+// (~0, INT_MAX) to 64 E elements, and a bitonic network sorts them (strides
+// below 64 across lanes with shuffles, larger ones between registers). Position
+// i of the sorted sequence is rank i; ranks below P are written.
+template <int E>
+__device__ __forceinline__ void rank_survivors(const float *qh, const float *__restrict__ C, int h,
+                                               const int32_t *sidx, int n, int P, int lane,
+                                               double *__restrict__ ok, int32_t *__restrict__ oi)
+{
+    uint64_t k[E];
+    int32_t x[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int i = 64 * r + lane;
+        if (i < n) {
+            x[r] = sidx[i];
+            k[r] = dkey(exact_key(qh, C + (int64_t)x[r] * h, h));
+        } else {
+            x[r] = 0x7fffffff;
+            k[r] = ~0ull;
+        }
+    }
+    constexpr int N = 64 * E;
+#pragma unroll
+    for (int kk = 2; kk <= N; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const int rp = r ^ (j >> 6);
+                    if (rp > r) {
+                        const bool asc = ((64 * r + lane) & kk) == 0;
+                        const bool gt = k[r] > k[rp] || (k[r] == k[rp] && x[r] > x[rp]);
+                        if (gt == asc) {
+                            const uint64_t tk = k[r];
+                            k[r] = k[rp];
+                            k[rp] = tk;
+                            const int32_t tx = x[r];
+                            x[r] = x[rp];
+                            x[rp] = tx;
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const uint64_t ko = __shfl_xor(k[r], j);
+                    const int32_t xo = __shfl_xor(x[r], j);
+                    const bool asc = ((64 * r + lane) & kk) == 0;
+                    const bool lower = (lane & j) == 0;  // this element comes first in the pair
+                    const bool olt = ko < k[r] || (ko == k[r] && xo < x[r]);
+                    // the first of an ascending pair (or the second of a
+                    // descending one) keeps the smaller element
+                    if ((lower == asc) ? olt : !olt) {
+                        k[r] = ko;
+                        x[r] = xo;
+                    }
+                }
+            }
+        }
+    }
+    const int m = n < P ? n : P;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const int i = 64 * r + lane;
+        if (i < m) {
+            ok[i] = __longlong_as_double((long long)k[r]);
+            oi[i] = x[r];
+        }
+    }
 }
 
 template <int SPL>
@@ -648,10 +802,6 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
     float *qh = reinterpret_cast<float *>(smem) + (size_t)wv * hpad;
     int32_t *sidx = reinterpret_cast<int32_t *>(reinterpret_cast<float *>(smem) + (size_t)kWPB * hpad) +
                     (size_t)wv * kWaveS;
-    uint64_t *skey = reinterpret_cast<uint64_t *>(reinterpret_cast<int32_t *>(reinterpret_cast<float *>(smem) +
-                                                                              (size_t)kWPB * hpad) +
-                                                  (size_t)kWPB * kWaveS) +
-                     (size_t)wv * kWaveS;
     const int64_t qs = qlist ? qlist[slot] : slot;
     const float *C = half ? C2 : C1;
     const float cmax = half ? cmax2 : cmax1;
@@ -749,25 +899,12 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int i = lane; i < n; i += 64) skey[i] = dkey(exact_key(qh, C + (int64_t)sidx[i] * h, h));
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double *ok = lkey + (slot * 2 + half) * (int64_t)P;
     int32_t *oi = lidx + (slot * 2 + half) * (int64_t)P;
-    for (int i = lane; i < n; i += 64) {
-        const uint64_t k = skey[i];
-        const int x = sidx[i];
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const uint64_t kj = skey[j];
-            rank += (kj < k) | ((kj == k) & (sidx[j] < x));
-        }
-        if (rank < P) {
-            ok[rank] = __longlong_as_double((long long)k);
-            oi[rank] = x;
-        }
-    }
+    if (n <= 64) rank_survivors<1>(qh, C, h, sidx, n, P, lane, ok, oi);
+    else if (n <= 128) rank_survivors<2>(qh, C, h, sidx, n, P, lane, ok, oi);
+    else if (n <= 256) rank_survivors<4>(qh, C, h, sidx, n, P, lane, ok, oi);
+    else rank_survivors<8>(qh, C, h, sidx, n, P, lane, ok, oi);
     if (lane == 0) {
         pstat[pair] = 0;
         if (stats) atomicAdd(&stats[kStatPrefixWave], 1ull);
@@ -802,7 +939,7 @@ hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *k
     if (nslots == 0) return hipSuccess;
     if (!prefix_wave_ok(ix, P) || !pstat) return hipErrorInvalidValue;
     const int hpad = (ix.D / 2 + 3) & ~3;
-    const size_t lds = (size_t)kWPB * ((size_t)hpad * 4 + (size_t)kWaveS * 12);
+    const size_t lds = (size_t)kWPB * ((size_t)hpad * 4 + (size_t)kWaveS * 4);
     const int64_t pairs = nslots * 2;
     const dim3 g((unsigned)((pairs + kWPB - 1) / kWPB)), b(kWPB * 64);
     if (P <= 128)
