@@ -786,7 +786,7 @@ __device__ __forceinline__ void rank_survivors(const float *qh, const float *__r
 }
 
 template <int SPL>
-__global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
+__global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_prefix_wave(
     const float *__restrict__ kapprox, const float *__restrict__ Q, int D,
     const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, int T,
     const int32_t *qlist, int64_t nslots, int P, double *__restrict__ lkey, int32_t *__restrict__ lidx,
@@ -802,6 +802,10 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
     float *qh = reinterpret_cast<float *>(smem) + (size_t)wv * hpad;
     int32_t *sidx = reinterpret_cast<int32_t *>(reinterpret_cast<float *>(smem) + (size_t)kWPB * hpad) +
                     (size_t)wv * kWaveS;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(reinterpret_cast<int32_t *>(reinterpret_cast<float *>(smem) +
+                                                                              (size_t)kWPB * hpad) +
+                                                  (size_t)kWPB * kWaveS) +
+                     (size_t)wv * 256;
     const int64_t qs = qlist ? qlist[slot] : slot;
     const float *C = half ? C2 : C1;
     const float cmax = half ? cmax2 : cmax1;
@@ -848,19 +852,52 @@ __global__ __launch_bounds__(kWPB * 64) void k_prefix_wave(
     uint32_t u[SPL];
 #pragma unroll
     for (int q = 0; q < SPL; ++q) u[q] = okey(smp[q]);
-    // the P-th smallest sample key, one bit at a time from the top
-    uint32_t pre = 0;
-    int need = P;
-    for (int b = 31; b >= 0; --b) {
-        const uint32_t hm = b == 31 ? 0u : (0xffffffffu << (b + 1));
-        int cnt = 0;
+    // The P-th smallest sample key, one byte at a time from the top: a 256-bin
+    // histogram of the samples that match the bytes found so far, a scan over
+    // the lanes (four bins each), and the bin where the running count reaches
+    // the rank still needed. LDS executes a wavefront's instructions in issue
+    // order, so waiting for them (lgkmcnt 0) orders the clear, the atomic adds
+    // and the reads; the empty asm keeps the compiler from moving them.
+    auto lds_order = [&]() __attribute__((always_inline)) {
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0) only
+        __builtin_amdgcn_wave_barrier();
+        __asm__ __volatile__("" ::: "memory");
+    };
+    uint32_t pre = 0, hm = 0;
+    int need = P;  // at most the 64 SPL samples, so a bin always reaches it
+    for (int sh = 24; sh >= 0; sh -= 8) {
+        reinterpret_cast<uint4 *>(hist)[lane] = uint4{0u, 0u, 0u, 0u};
+        lds_order();
 #pragma unroll
         for (int q = 0; q < SPL; ++q)
-            cnt += __popcll(__ballot(((u[q] & hm) == pre) && !((u[q] >> b) & 1u)));
-        if (cnt < need) {
-            pre |= 1u << b;
-            need -= cnt;
+            if ((u[q] & hm) == pre) atomicAdd(&hist[(u[q] >> sh) & 255u], 1u);
+        lds_order();
+        const uint4 hb = reinterpret_cast<const uint4 *>(hist)[lane];  // bins 4 lane .. 4 lane + 3
+        const uint32_t s4 = hb.x + hb.y + hb.z + hb.w;
+        uint32_t inc = s4;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o);
+            if (lane >= o) inc += t;
         }
+        const uint32_t exc = inc - s4;
+        const int L = __ffsll(__ballot(exc < (uint32_t)need && (uint32_t)need <= inc)) - 1;
+        int bin = 0;
+        uint32_t low = 0;
+        if (lane == L) {
+            const uint32_t v[4] = {hb.x, hb.y, hb.z, hb.w};
+            uint32_t c = exc;
+            int j = 0;
+            while (j < 3 && c + v[j] < (uint32_t)need) c += v[j++];
+            bin = 4 * L + j;
+            low = c;
+        }
+        bin = __shfl(bin, L);
+        low = __shfl(low, L);
+        pre |= (uint32_t)bin << sh;
+        hm |= 255u << sh;
+        need -= (int)low;
+        lds_order();  // the reads are done before the next clear
     }
     // error bound of the approximate keys (any summation order, FP32)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -939,7 +976,7 @@ hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *k
     if (nslots == 0) return hipSuccess;
     if (!prefix_wave_ok(ix, P) || !pstat) return hipErrorInvalidValue;
     const int hpad = (ix.D / 2 + 3) & ~3;
-    const size_t lds = (size_t)kWPB * ((size_t)hpad * 4 + (size_t)kWaveS * 4);
+    const size_t lds = (size_t)kWPB * ((size_t)hpad * 4 + (size_t)kWaveS * 4 + 256 * 4);
     const int64_t pairs = nslots * 2;
     const dim3 g((unsigned)((pairs + kWPB - 1) / kWPB)), b(kWPB * 64);
     if (P <= 128)
