@@ -36,6 +36,8 @@ WORKLOADS = {
                    offered=(1000, 2000, 5000, 10000, 20000, 40000, 80000)),
     # local codebooks (HBPQ): per-query L log-uniform in [L_lo, L_hi]
     "local": dict(N=100_000_000, T=4096, M=16, nq=10_000, L_lo=10_000, L_hi=100_000, k=10),
+    # GIST-like width: D = 384 at the same 8-byte codes, FBPQ against the O(D) scan at each L
+    "gist": dict(N=50_000_000, D=384, T=1024, M=8, nq=10_000, L=(10_000, 30_000, 100_000), k=10),
 }
 
 
@@ -125,6 +127,8 @@ def main() -> int:
         return run_served(args, w)
     if args.workload == "local":
         return run_local(args, w)
+    if args.workload == "gist":
+        return run_gist(args, w)
     if args.nq:
         w["nq"] = args.nq
     dev = torch.device("cuda:0")
@@ -425,6 +429,126 @@ def run_local(args, w) -> int:
         "kernels": prof,
         "path_counters": stats,
         "global_codebooks_same_L": {"ms_per_step": g_ms, "value": nq / (g_ms / 1e3), "kernels": g_prof},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def run_gist(args, w) -> int:
+    """The GIST-like width (D = 384, T = 1024, M = 8 bytes of code): FBPQ and the
+    Multi-D-ADC O(D) scan on the same index and batch at each L. The FBPQ scan
+    costs M lookups per candidate whatever D is, the O(D) scan D/2 multiply-adds
+    per half, so the ratio grows with D at fixed M (Section 3.1, Table 2)."""
+    import torch
+
+    import synth
+    from paper_1404_1831_amd.build import LIB
+    if not os.path.exists(LIB):
+        from paper_1404_1831_amd.build import build
+        build()
+    from paper_1404_1831_amd import fbpq
+
+    if args.nq:
+        w["nq"] = args.nq
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    means = synth.gmm_means(0, D=w["D"])
+    base = synth.sample_points(w["N"], means, 1, dev)
+    ix = synth.build_index(base, w["T"], w["M"], keep_base=False)
+    del base
+    torch.cuda.empty_cache()
+    nq, k = w["nq"], w["k"]
+    Q = synth.make_queries(nq, means, 2, dev)
+    log(f"index built in {time.time() - t0:.1f}s: N={ix.N} D={ix.D} T={ix.T} M={ix.M} "
+        f"nonempty cells={int((np.diff(ix.offsets) > 0).sum())}")
+    d_q = torch.from_numpy(Q).to(dev).contiguous()
+    d_ids = torch.empty(nq, k, dtype=torch.int64, device=dev)
+    d_d = torch.empty(nq, k, dtype=torch.float32, device=dev)
+    ks = np.full(nq, k, np.int32)
+    stream = torch.cuda.current_stream(dev)
+    h = fbpq.fbpq_index_create(ix, 0)
+    fbpq.fbpq_build_tables(h)
+
+    def timed(Ls, od):
+        fbpq.fbpq_set_option(h, "adc_od", od)
+        for _ in range(args.warmup):
+            fbpq.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, stream)
+        torch.cuda.synchronize()
+        fbpq.fbpq_set_option(h, "profile", 1)
+        fbpq.fbpq_set_option(h, "profile_mask", -1)
+        for s_ in range(len(fbpq.STAGES)):
+            fbpq.fbpq_profile_read(h, s_, reset=True)
+        a = time.perf_counter()
+        for _ in range(args.steps):
+            fbpq.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - a) * 1e3 / args.steps
+        prof = {}
+        for s_, name in enumerate(fbpq.STAGES):
+            t, n = fbpq.fbpq_profile_read(h, s_, reset=True)
+            prof[name] = {"ms_per_launch": t / n if n else None, "launches": n}
+        fbpq.fbpq_set_option(h, "profile", 0)
+        return ms, prof
+
+    legs = []
+    first = None
+    for L in w["L"]:
+        Ls = np.full(nq, L, np.int64)
+        f_ms, f_prof = timed(Ls, 0)
+        if first is None:
+            first = (L, f_ms, f_prof, d_ids.cpu().numpy(), d_d.cpu().numpy())
+        o_ms, o_prof = timed(Ls, 1) if args.adc_steps > 0 else (None, None)
+        legs.append({"L": L, "fbpq_ms_per_batch": f_ms, "fbpq_queries_per_s": nq / (f_ms / 1e3),
+                     "od_ms_per_batch": o_ms, "fbpq_speedup": (o_ms / f_ms) if o_ms else None,
+                     "fbpq_kernels": f_prof, "od_kernels": o_prof})
+        log(f"L={L}: FBPQ {f_ms:.3f} ms per batch, O(D) " + (f"{o_ms:.3f} ms, {o_ms / f_ms:.1f}x" if o_ms else "skipped"))
+    fbpq.fbpq_free_index(h)
+
+    L0, ms0, prof0, res_ids, res_d = first
+    # the dominant scan kernel of the FBPQ search at the first L: M code bytes per candidate
+    scans = {"score": "k_score_query", "scan_wide": "k_scan_wide", "scan2": "k_scan2"}
+    dom = max(scans, key=lambda s_: (prof0[s_]["ms_per_launch"] or 0.0) * (prof0[s_]["launches"] or 0))
+    ncand = nq * min(L0, ix.N)
+    d_ms = prof0[dom]["ms_per_launch"]
+    achieved = ncand * ix.M / (d_ms * 1e-3) / 1e9 if d_ms else None
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": None,
+            "kernel": scans[dom], "algorithmic_per_launch": ncand * ix.M, "what": "code bytes",
+            "ms_per_launch": d_ms, "launches": prof0[dom]["launches"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        Ls0 = np.full(nq, L0, np.int64)
+        n0 = min(nq, threads)
+        a = time.perf_counter()
+        o_ids, o_d, _, _ = oracle.search(ix, Q[:n0], Ls0[:n0], k, nthreads=threads)
+        t_first = time.perf_counter() - a
+        n1 = int(min(nq, max(n0, n0 * args.cpu_seconds / max(t_first, 1e-3))))
+        if n1 > n0:
+            a = time.perf_counter()
+            o_ids, o_d, _, _ = oracle.search(ix, Q[:n1], Ls0[:n1], k, nthreads=threads)
+            t_cpu = time.perf_counter() - a
+        else:
+            n1, t_cpu = n0, t_first
+        overlap = float(np.mean([len(set(res_ids[r]) & set(o_ids[r])) / k for r in range(n1)]))
+        rel = np.abs(res_d[:n1].astype(np.float64) - o_d) / np.maximum(o_d, 1.0)
+        cpu = {"value": n1 / t_cpu, "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {n1} of the {nq} queries, same index, L={L0}, k={k}",
+               "topk_overlap_with_gpu": overlap, "max_rel_dist_diff": float(rel.max())}
+        log(f"cpu oracle: {n1} queries in {t_cpu:.1f}s on {threads} threads")
+    out = {
+        "metric": "queries/s at fixed L, Recall@10 = oracle, 1 GPU; p50/p99 latency; scan GB/s",
+        "value": nq / (ms0 / 1e3), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"GIST-like FBPQ: N={ix.N}, D={ix.D}, T={ix.T} per half, M={ix.M}, "
+                               f"nq={nq} per batch, L={L0} (and {', '.join(str(x) for x in w['L'][1:])} "
+                               f"in legs), k={k}",
+                   "N": ix.N, "D": ix.D, "T": ix.T, "M": ix.M, "nq": nq, "k": k},
+        "legs": legs,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -163,6 +163,7 @@ struct ScanArgs {
     float *dist;           // [slot][lcap] partial and final distances (wide scan)
     int64_t lcap;
     int32_t *sel_done;     // [slot] 1: the wide scan selected the top-k itself
+    int32_t od_group;      // O(D) scan: subspaces whose codebooks are staged per group (set by the launcher)
     int64_t *out_ids;      // [query][k_max]
     float *out_d;
     int64_t *dbg_pos;      // optional [slot][dbg_cap]

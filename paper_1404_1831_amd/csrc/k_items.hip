@@ -126,12 +126,27 @@ __global__ __launch_bounds__(256) void k_lq(ItemArgs a)
                 a.lq[slots[i] * M * kKc + e] = nr - 2.f * acc;
             }
         } else {
-            for (int i = 0; i < n; ++i) {
-                const float *qk = qv + i * D + k * ds;
-                float acc = 0.f;
-                for (int t = 0; t < ds; ++t) acc = fmaf(qk[t], rw[t], acc);
-                a.lq[slots[i] * M * kKc + e] = nr - 2.f * acc;
+            // any width: the codeword passes through registers 16 floats at a
+            // time, against every query of the group (same order of sums)
+            float acc[kLqQ];
+#pragma unroll
+            for (int i = 0; i < kLqQ; ++i) acc[i] = 0.f;
+            for (int t0 = 0; t0 < ds; t0 += 16) {
+                float r[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) r[u] = t0 + u < ds ? rw[t0 + u] : 0.f;
+                const int tn = ds - t0 < 16 ? ds - t0 : 16;
+#pragma unroll
+                for (int i = 0; i < kLqQ; ++i) {
+                    if (i < n) {
+                        const float *qk = qv + i * D + k * ds + t0;
+                        for (int u = 0; u < tn; ++u) acc[i] = fmaf(qk[u], r[u], acc[i]);
+                    }
+                }
             }
+#pragma unroll
+            for (int i = 0; i < kLqQ; ++i)
+                if (i < n) a.lq[slots[i] * M * kKc + e] = nr - 2.f * acc[i];
         }
     }
 }

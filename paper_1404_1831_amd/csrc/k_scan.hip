@@ -319,12 +319,14 @@ constexpr int wide_regions()
     return MODE == kWideLocal && wide_tables<MH>() > wide_waves<MH, MODE>() ? wide_tables<MH>()
                                                                             : wide_waves<MH, MODE>();
 }
-// floats before the task prefix: folded tables, or (O(D) mode) one half of the
-// codebooks [M/2][Kc][D/M] and each wavefront's q - c of its task
+// floats before the task prefix: folded tables, or (O(D) mode) the codebooks of
+// `group` subspaces of the current half [group][Kc][D/M] and each wavefront's
+// q - c of its task. A half whose codebooks do not fit in LDS at once (large D)
+// is scanned in several groups of subspaces; group 0 reads them from memory.
 template <int MH, int MODE>
-__host__ __device__ constexpr int64_t wide_region_floats(int D)
+__host__ __device__ constexpr int64_t wide_region_floats(int D, int group = MH)
 {
-    return MODE == kWideOD ? (int64_t)MH * kKc * (D / (2 * MH)) + (int64_t)wide_waves<MH, MODE>() * (D / 2)
+    return MODE == kWideOD ? (int64_t)group * kKc * (D / (2 * MH)) + (int64_t)wide_waves<MH, MODE>() * (D / 2)
                            : (int64_t)wide_regions<MH, MODE>() * MH * kKc;
 }
 constexpr int kWideRanks = 4097;  // task prefix entries (ranks up to 4096, plus the total)
@@ -418,9 +420,11 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
         }
     };
     float *lut = wlut + wv * TL;
-    int *tpre = reinterpret_cast<int *>(wlut + wide_region_floats<MH, MODE>(a.ix.D));
-    float *cbh = wlut;                                  // O(D): the codebook half of the pass
-    float *qcw = wlut + (int64_t)TL * (a.ix.D / (2 * MH)) + wv * (a.ix.D / 2);  // O(D): this wave's q - c
+    const int og = OD ? a.od_group : MH;  // O(D): subspaces staged per group (0: none, read from memory)
+    int *tpre = reinterpret_cast<int *>(wlut + wide_region_floats<MH, MODE>(a.ix.D, og));
+    const float *cbh = wlut;  // O(D): codebooks of subspaces [k0, k1) of the pass (LDS or memory)
+    int k0 = 0, k1 = MH;
+    float *qcw = wlut + (int64_t)og * kKc * (a.ix.D / (2 * MH)) + wv * (a.ix.D / 2);  // O(D): q - c
     float *qs = reinterpret_cast<float *>(tpre + kWideRanks);
     const int P = a.P;
     const int D = a.ix.D, ds = D / (2 * MH);
@@ -444,12 +448,24 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
         const int64_t qsl = a.qlist ? a.qlist[slot] : slot;
         for (int t = tid; t < D; t += NT) qs[t] = a.q[qsl * D + t];
     }
-    // O(D): stage the codebooks R_k, k in [half*M/2, half*M/2 + M/2), in LDS
-    auto stage_half = [&](int half) __attribute__((always_inline)) {
+    // O(D): the codebooks of group g of the half (subspaces [k0, k1) of the
+    // half's M/2), staged in LDS, or all of them in memory when og is 0
+    const int ng = OD && og > 0 ? (MH + og - 1) / og : 1;
+    auto stage_half = [&](int half, int g) __attribute__((always_inline)) {
         if (!OD) return;
-        const int64_t n = (int64_t)TL * ds;
-        const float *src = a.ix.R + (int64_t)half * n;
-        for (int64_t e = tid; e < n; e += NT) cbh[e] = src[e];
+        const float *src = a.ix.R + (int64_t)half * TL * ds;
+        if (og == 0) {
+            cbh = src;
+            k0 = 0;
+            k1 = MH;
+            return;
+        }
+        k0 = g * og;
+        k1 = k0 + og < MH ? k0 + og : MH;
+        const int64_t n = (int64_t)(k1 - k0) * kKc * ds;
+        src += (int64_t)k0 * kKc * ds;
+        for (int64_t e = tid; e < n; e += NT) wlut[e] = src[e];
+        cbh = wlut;
     };
     // O(D): this wavefront's q_h - c for its current task
     auto set_qc = [&](int half, int cent) __attribute__((always_inline)) {
@@ -465,11 +481,25 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < MH; ++k) {
-            const float *w = cbh + ((int64_t)k * kKc + bytes[k]) * ds;
+            if (k < k0 || k >= k1) continue;
+            const float *w = cbh + ((int64_t)(k - k0) * kKc + bytes[k]) * ds;
             const float *qk = qcw + k * ds;
-            for (int t = 0; t < ds; ++t) {
-                const float e = qk[t] - w[t];
-                acc = fmaf(e, e, acc);
+            if ((ds & 3) == 0) {
+                // 16-byte reads of the codeword and of q - c (both 16-byte aligned)
+                for (int t = 0; t < ds; t += 4) {
+                    const float4 wv4 = *reinterpret_cast<const float4 *>(w + t);
+                    const float4 qv4 = *reinterpret_cast<const float4 *>(qk + t);
+                    const float e0 = qv4.x - wv4.x, e1 = qv4.y - wv4.y, e2 = qv4.z - wv4.z, e3 = qv4.w - wv4.w;
+                    acc = fmaf(e0, e0, acc);
+                    acc = fmaf(e1, e1, acc);
+                    acc = fmaf(e2, e2, acc);
+                    acc = fmaf(e3, e3, acc);
+                }
+            } else {
+                for (int t = 0; t < ds; ++t) {
+                    const float e = qk[t] - w[t];
+                    acc = fmaf(e, e, acc);
+                }
             }
         }
         return acc;
@@ -524,12 +554,17 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
     }
 
     // ---- pass 1: row tasks, first half of the code plus the cell constant ----
-    stage_half(0);
+    stage_half(0, 0);
     for (int ar = tid; ar <= A; ar += NT)
         tpre[ar] = ar < A ? (row_cand[ar + 1] - row_cand[ar] + kWideChunk - 1) / kWideChunk : 0;
     __syncthreads();
     wide_scan<NT>(tpre, A + 1, wtot);
-    {
+    for (int g = 0; g < ng; ++g) {
+        if (g > 0) {
+            __syncthreads();  // every wavefront is done with the previous group's codebooks
+            stage_half(0, g);
+            __syncthreads();
+        }
         const int ntask = tpre[A];
         auto task_row = [&](int tk) __attribute__((always_inline)) {
             int lo = 0, hi = A - 1;
@@ -582,7 +617,9 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
 #pragma unroll
                     for (int j = 0; j < kWideU; ++j) {
                         const int64_t t = t0 + 64 * j + lane;
-                        if (t < re) dist[t] = OD ? od_sum(cv[j]) : lut_sum_c<MH>(lut, cv[j]) + cst_[j];
+                        if (t < re)
+                            dist[t] = OD ? (g == 0 ? 0.f : dist[t]) + od_sum(cv[j])
+                                         : lut_sum_c<MH>(lut, cv[j]) + cst_[j];
                     }
                 }
                 tk = tn;
@@ -611,7 +648,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
                 const int64_t t = t0 + lane;
                 if (t < re) {
                     const auto code = load_code<MH>(a.ix.codesA, bego + (t - cso));
-                    dist[t] = OD ? od_sum(code) : lut_sum_c<MH>(lut, code) + csto;
+                    dist[t] = OD ? (g == 0 ? 0.f : dist[t]) + od_sum(code) : lut_sum_c<MH>(lut, code) + csto;
                 }
                 // cell of candidate t0 + 64: that of lane 63's candidate, or the next
                 const int o63 = __shfl(owner, 63);
@@ -628,12 +665,18 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
     __syncthreads();  // every partial sum of the query is stored; tpre is free
 
     // ---- pass 2: column tasks, second half of the code ----
-    stage_half(1);
+    stage_half(1, 0);
     for (int b = tid; b <= B; b += NT)
         tpre[b] = b < B ? (col_tot[b] + kWideChunk - 1) / kWideChunk : 0;
     __syncthreads();
     wide_scan<NT>(tpre, B + 1, wtot);
-    {
+    for (int g = 0; g < ng; ++g) {
+        if (g > 0) {
+            __syncthreads();  // every wavefront is done with the previous group's codebooks
+            stage_half(1, g);
+            __syncthreads();
+        }
+        const bool last = g == ng - 1;  // the distances are complete: keep them for the selection
         const int ntask = tpre[B];
         auto task_col = [&](int tk) __attribute__((always_inline)) {
             int lo = 0, hi = B - 1;
@@ -689,6 +732,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
                         if (uu < ue) {
                             const float d = dist[tt[j]] + (OD ? od_sum(cv[j]) : lut_sum_c<MH>(lut, cv[j]));
                             dist[tt[j]] = d;
+                            if (!last) continue;
                             keep(d, tt[j]);
                             if (a.dbg_pos) {
                                 a.dbg_pos[(int64_t)slot * a.dbg_cap + tt[j]] = pp[j];
@@ -727,8 +771,8 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
                     const auto code = load_code<MH>(a.ix.codesB, p);
                     const float d = dist[t] + (OD ? od_sum(code) : lut_sum_c<MH>(lut, code));
                     dist[t] = d;
-                    keep(d, t);
-                    if (a.dbg_pos) {
+                    if (last) keep(d, t);
+                    if (last && a.dbg_pos) {
                         a.dbg_pos[(int64_t)slot * a.dbg_cap + t] = p;
                         a.dbg_d[(int64_t)slot * a.dbg_cap + t] = d;
                     }
@@ -925,9 +969,16 @@ hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st)
 #define FBPQ_WIDE_MODE(MH, MODE)                                                                  \
     {                                                                                             \
         constexpr int nt = 64 * wide_waves<MH, MODE>();                                           \
-        const size_t lds = (size_t)wide_region_floats<MH, MODE>(a.ix.D) * sizeof(float) + extra;  \
+        ScanArgs b = a;                                                                           \
+        b.od_group = MH; /* O(D): the most subspaces whose codebooks fit in LDS at once */        \
+        while (b.od_group > 0 &&                                                                  \
+               (size_t)wide_region_floats<MH, MODE>(a.ix.D, b.od_group) * sizeof(float) + extra > \
+                   160 * 1024)                                                                    \
+            --b.od_group;                                                                         \
+        const size_t lds =                                                                        \
+            (size_t)wide_region_floats<MH, MODE>(a.ix.D, b.od_group) * sizeof(float) + extra;     \
         if (lds > 160 * 1024) return hipErrorInvalidValue;                                       \
-        hipLaunchKernelGGL((k_scan_wide<MH, MODE>), g, dim3(nt), lds, st, a);                     \
+        hipLaunchKernelGGL((k_scan_wide<MH, MODE>), g, dim3(nt), lds, st, b);                     \
     }
 #define FBPQ_WIDE_CASE(MH)                                                                        \
     case MH:                                                                                      \

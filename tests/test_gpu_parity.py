@@ -564,6 +564,76 @@ def test_adc_od_baseline_matches_oracle(fb, gmm_small, gmm_m16, which, L):
     assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
 
 
+# ---- D = 384, the GIST-like width: wider halves, the same code length -------------
+
+@pytest.fixture(scope="module")
+def gmm_d384():
+    # 40k mixture points of D = 384 with T = 256 per half and M = 8 (48
+    # coordinates per subspace): the half keys take the multi-slab path (D/2 =
+    # 192 coordinates), the prefixes the wavefront select, and the O(D) scan
+    # reads its codebooks from memory (one half of them is 196 KB, beyond LDS)
+    means = synth.gmm_means(0, D=384)
+    base = synth.sample_points(40000, means, 1)
+    ix = synth.build_index(base, 256, 8, train_n=10000)
+    Q = synth.make_queries(30, means, 2)
+    return ix, Q
+
+
+@pytest.mark.parametrize("P", [64, 200])
+def test_d384_rank_prefix_bitexact(fb, gmm_d384, P):
+    ix, Q = gmm_d384
+    log(f"rank prefix: D=384 T=256 P={P}")
+    h = _open(fb, ix, stats=1)
+    keys, idx = fb.fbpq_debug_rank(h, Q, P)
+    st = fb.fbpq_stats_read(h)
+    fb.fbpq_free_index(h)
+    assert st["prefix_wave"] > 0
+    for r in range(Q.shape[0]):
+        d1, d2, u, v = oracle.rank_lists(ix, Q[r])
+        assert np.array_equal(idx[r, 0], u[:P]) and np.array_equal(idx[r, 1], v[:P]), r
+        assert np.array_equal(keys[r, 0], d1[u[:P]]) and np.array_equal(keys[r, 1], d2[v[:P]]), r
+
+
+@pytest.mark.parametrize("adc_od,L", [(0, 3000), (0, 20000), (1, 3000), (1, 20000)])
+def test_d384_search_matches_oracle(fb, gmm_d384, adc_od, L):
+    ix, Q = gmm_d384
+    k = 20
+    log(f"D=384 search: adc_od={adc_od} L={L}")
+    h = _open(fb, ix, adc_od=adc_od)
+    got = fb.fbpq_debug_dists(h, Q[:6], L, cap=min(L, ix.N))
+    for r in range(6):
+        pos, d32 = got[r]
+        _, opos = oracle.visit(ix, Q[r], L)
+        assert np.array_equal(np.sort(pos), np.sort(opos)), r
+        d64 = oracle_dists(ix, Q[r], pos)
+        assert np.all(np.abs(d32.astype(np.float64) - d64) <= tol(ix, Q[r], pos, d64)), r
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
+def test_d320_adc_od_uneven_groups(fb):
+    # D = 320, M = 8: three of the four subspaces of a half fit in LDS at once,
+    # so the O(D) scan takes each half in groups {0, 1, 2} and {3}
+    means = synth.gmm_means(0, D=320)
+    ix = synth.build_index(synth.sample_points(20000, means, 1), 64, 8, train_n=8000)
+    Q = synth.make_queries(16, means, 2)
+    L, k = 4000, 20
+    log("O(D) baseline: D=320, uneven subspace groups")
+    h = _open(fb, ix, adc_od=1)
+    got = fb.fbpq_debug_dists(h, Q[:4], L, cap=L)
+    for r in range(4):
+        pos, d32 = got[r]
+        d64 = oracle_dists(ix, Q[r], pos)
+        assert len(pos) == L
+        assert np.all(np.abs(d32.astype(np.float64) - d64) <= tol(ix, Q[r], pos, d64)), r
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
 # ---- the selection fused into the cell scan and its fallbacks --------------------
 
 def _dense_index(const_codes: bool):
