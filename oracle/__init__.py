@@ -2,7 +2,10 @@
 
 ctypes binding of the plain FP64 C oracle in fbpq_oracle.c (Multi-D-ADC with
 explicit displacement reconstruction, Section 2.3 of the paper, and the same
-search with the local codebooks of HBPQ, Section 3.2). Only the test
+search with the local codebooks of HBPQ, Section 3.2). An index with an OPQ
+rotation (`Rot`, Section 2.1) lives in the rotated space: every function that
+takes queries rotates them first (`rotate`), so they take queries in the
+original space. Only the test
 suite, the smoke check and the CPU-baseline leg of the benchmark may import
 this package. It never imports the GPU package.
 """
@@ -50,6 +53,8 @@ def _load():
         ix_args = [ctypes.c_int] * 4 + [i64, P, P, P, P, P, P]
         lib.orc_visit.argtypes = ix_args + [P, i64, P, i64, P, P, i64]
         lib.orc_visit.restype = i64
+        lib.orc_rotate.argtypes = [ctypes.c_int, P, P, i64, P]
+        lib.orc_rotate.restype = None
         lib.orc_search.argtypes = ix_args + [P, i64, P, P, i32, P, P, P, P, ctypes.c_int]
         lib.orc_search.restype = ctypes.c_int
         lix_args = [ctypes.c_int] * 4 + [i64] + [P] * 7  # QL and SL in place of R
@@ -77,6 +82,25 @@ def _ix_args(ix):
     return keep, [ix.D, ix.T, ix.M, ix.Kc, ix.N] + [_p(a) for a in keep]
 
 
+def rotate(Rot: np.ndarray, Q: np.ndarray) -> np.ndarray:
+    """Queries in the rotated space of an OPQ index: q' = Rot q per row, each
+    coordinate an FP64 fused multiply-add chain over b = 0..D-1, rounded to FP32."""
+    Rot = np.ascontiguousarray(Rot, np.float32)
+    Q = np.ascontiguousarray(Q, np.float32)
+    D = Rot.shape[0]
+    assert Rot.shape == (D, D) and Q.shape[-1] == D
+    flat = Q.reshape(-1, D)
+    out = np.empty_like(flat)
+    _load().orc_rotate(D, _p(Rot), _p(flat), flat.shape[0], _p(out))
+    return out.reshape(Q.shape)
+
+
+def _in_space(ix, Q: np.ndarray) -> np.ndarray:
+    """Queries in the index's space: rotated when the index has an OPQ rotation."""
+    Rot = getattr(ix, "Rot", None)
+    return np.ascontiguousarray(Q, np.float32) if Rot is None else rotate(Rot, Q)
+
+
 def half_dists(q: np.ndarray, Ch: np.ndarray) -> np.ndarray:
     q = np.ascontiguousarray(q, np.float32)
     Ch = np.ascontiguousarray(Ch, np.float32)
@@ -94,7 +118,7 @@ def rank(d: np.ndarray) -> np.ndarray:
 
 def rank_lists(ix, q: np.ndarray):
     """(d1, d2, u, v) of one query: FP64 half distances and rank lists."""
-    q = np.ascontiguousarray(q, np.float32)
+    q = _in_space(ix, q)
     T = ix.T
     d1, d2 = np.empty(T), np.empty(T)
     u, v = np.empty(T, np.int32), np.empty(T, np.int32)
@@ -105,7 +129,7 @@ def rank_lists(ix, q: np.ndarray):
 
 
 def point_dist(ix, q: np.ndarray, i: int, j: int, code: np.ndarray) -> float:
-    q = np.ascontiguousarray(q, np.float32)
+    q = _in_space(ix, q)
     code = np.ascontiguousarray(code, np.uint8)
     C1 = np.ascontiguousarray(ix.C1, np.float32)
     C2 = np.ascontiguousarray(ix.C2, np.float32)
@@ -116,7 +140,7 @@ def point_dist(ix, q: np.ndarray, i: int, j: int, code: np.ndarray) -> float:
 
 def point_dist_local(ix, q: np.ndarray, i: int, j: int, code: np.ndarray) -> float:
     """FP64 distance to the reconstruction with the local codebooks of ix."""
-    q = np.ascontiguousarray(q, np.float32)
+    q = _in_space(ix, q)
     code = np.ascontiguousarray(code, np.uint8)
     C1 = np.ascontiguousarray(ix.C1, np.float32)
     C2 = np.ascontiguousarray(ix.C2, np.float32)
@@ -132,7 +156,7 @@ def visit(ix, q: np.ndarray, L: int, cells_cap: int = 1 << 20):
         import dataclasses
         ix = dataclasses.replace(ix, QL=None, SL=None)  # the traversal does not read codebooks
     keep, args = _ix_args(ix)
-    q = np.ascontiguousarray(q, np.float32)
+    q = _in_space(ix, q)
     Leff = max(0, min(int(L), ix.N))
     cells = np.zeros((cells_cap, 2), np.int64)
     nc = np.zeros(1, np.int64)
@@ -156,7 +180,7 @@ def search(ix, Q: np.ndarray, L, k, kmax: int | None = None, nthreads: int | Non
     L and k are scalars or per-query arrays; outputs are [nq][kmax] padded with
     (-1, +inf)."""
     keep, args = _ix_args(ix)
-    Q = np.ascontiguousarray(Q, np.float32).reshape(-1, ix.D)
+    Q = _in_space(ix, np.asarray(Q, np.float32).reshape(-1, ix.D))
     nq = Q.shape[0]
     L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, np.int64), (nq,)))
     k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))

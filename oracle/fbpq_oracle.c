@@ -34,6 +34,12 @@
  * per second-half centroid (S^j, the second half in a cell of column j), as in
  * equation (residual); the traversal is unchanged and the distance is again
  * computed by explicit reconstruction.
+ *
+ * With optimized product quantization (OPQ, Section 2.1; the optimized
+ * variants of Section 3.2) the index lives in a rotated space: a query q
+ * enters it as q' = Rot q, Rot an orthogonal D x D matrix. Reading: each
+ * coordinate of q' is the FP64 sum over b = 0..D-1 in that order, one fused
+ * multiply-add per term, rounded once to FP32 (the search takes FP32 queries).
  */
 #include <math.h>
 #include <pthread.h>
@@ -53,6 +59,17 @@ typedef struct {
 
 /* Squared distance from a query half to every half centroid (equations q1 and
  * q2, Section 2.3.1): d[i] = sum_t (q[t] - C[i][t])^2, t in increasing order. */
+/* q' = Rot q for nq queries (OPQ): Rot row-major [D][D], Q and out [nq][D]. */
+void orc_rotate(int D, const float *Rot, const float *Q, int64_t nq, float *out)
+{
+    for (int64_t r = 0; r < nq; ++r)
+        for (int a = 0; a < D; ++a) {
+            double acc = 0.0;
+            for (int b = 0; b < D; ++b) acc = fma((double)Rot[(int64_t)a * D + b], (double)Q[r * D + b], acc);
+            out[r * D + a] = (float)acc;
+        }
+}
+
 void orc_half_dists(const float *qh, const float *Ch, int T, int h, double *d)
 {
     for (int i = 0; i < T; ++i) {

@@ -13,6 +13,7 @@ from .gen import (  # noqa: F401
     sample_points,
     build_index,
     make_queries,
+    random_rotation,
     draw_L_k,
     lossless_index,
     lossless_local_index,

@@ -45,6 +45,8 @@ class Index:
     QL, SL:  optional float32 [T, M/2, Kc, D/M] local codebooks (HBPQ): QL[i]
              codes the first half of the displacements in the cells of row i,
              SL[j] the second half in the cells of column j; R is then unused
+    Rot:     optional float32 [D, D] orthogonal rotation (OPQ): the index lives
+             in the rotated space and a query q enters it as Rot q
     """
 
     D: int
@@ -61,6 +63,7 @@ class Index:
     meta: dict = field(default_factory=dict)
     QL: Optional[np.ndarray] = None
     SL: Optional[np.ndarray] = None
+    Rot: Optional[np.ndarray] = None
 
     @property
     def local(self) -> bool:
@@ -86,6 +89,8 @@ class Index:
             assert self.QL is not None and self.SL is not None
             assert self.QL.shape == shp and self.QL.dtype == np.float32
             assert self.SL.shape == shp and self.SL.dtype == np.float32
+        if self.Rot is not None:
+            assert self.Rot.shape == (D, D) and self.Rot.dtype == np.float32
 
 
 def _gen(seed: int, device) -> torch.Generator:
@@ -196,6 +201,16 @@ def build_index(base: torch.Tensor, T: int, M: int, seed: int = 0, train_n: int 
                meta=dict(kind="gmm", seed=seed, train_n=ntr, iters=iters))
     ix.check()
     return ix
+
+
+def random_rotation(D: int, seed: int = 23) -> np.ndarray:
+    """A seeded orthogonal D x D matrix (float32): the Q factor of a Gaussian
+    matrix, columns signed so that R's diagonal is positive (a unique choice)."""
+    g = _gen(seed, "cpu")
+    a = torch.randn(D, D, generator=g, dtype=torch.float64)
+    q, r = torch.linalg.qr(a)
+    q = q * torch.sign(torch.diagonal(r))[None, :]
+    return q.to(torch.float32).numpy()
 
 
 def make_queries(nq: int, means: torch.Tensor, seed: int = 2, device="cpu") -> np.ndarray:

@@ -274,3 +274,60 @@ def test_local_point_dist_uses_row_and_column_codebooks():
         assert oracle.point_dist_local(ix, x, i, j, ix.codes[s]) == 0.0
         q = rng.integers(-50, 50, ix.D).astype(np.float32)
         assert oracle.point_dist_local(ix, q, i, j, ix.codes[s]) == float(((q.astype(np.float64) - x) ** 2).sum())
+
+
+# ---- OPQ rotation of the queries (Section 2.1; the optimized variants) --------------
+
+def test_rotation_identity_is_the_plain_search():
+    """An identity rotation leaves every query bit-identical, so the search is
+    the unrotated one to the last bit."""
+    import dataclasses
+    ix = synth.random_index(N=3000, T=16, M=4, D=16, seed=11)
+    Q = np.random.default_rng(3).normal(0, 20, (8, 16)).astype(np.float32)
+    rix = dataclasses.replace(ix, Rot=np.eye(16, dtype=np.float32))
+    a = oracle.search(ix, Q, 700, 15, nthreads=2)
+    b = oracle.search(rix, Q, 700, 15, nthreads=2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_rotation_by_permutation_permutes_the_query():
+    """Rot[a][b] = 1 where b = p(a): coordinate a of the rotated query is
+    coordinate p(a) of the query, exactly (this fixes q' = Rot q, not Rot^T q)."""
+    import dataclasses
+    ix = synth.random_index(N=3000, T=16, M=4, D=16, seed=12)
+    rng = np.random.default_rng(4)
+    Q = rng.normal(0, 20, (8, 16)).astype(np.float32)
+    p = rng.permutation(16)
+    P = np.zeros((16, 16), np.float32)
+    P[np.arange(16), p] = 1.0
+    assert np.array_equal(oracle.rotate(P, Q), Q[:, p])
+    a = oracle.search(dataclasses.replace(ix, Rot=P), Q, 900, 12, nthreads=2)
+    b = oracle.search(ix, Q[:, p], 900, 12, nthreads=2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert not np.array_equal(oracle.rotate(P.T.copy(), Q), Q[:, p])
+
+
+def test_rotated_lossless_index_is_exact_knn_in_the_original_space():
+    """A lossless index in the rotated space holds x' = Rot x; searched with
+    queries of the original space and L >= N it returns the exact kNN of the
+    original points x = Rot^T x' (a rotation keeps distances)."""
+    import dataclasses
+    ix = synth.lossless_index(N=3000, T=8, M=4, D=16, seed=9, dup=200)
+    Rot = synth.random_rotation(16, seed=5)
+    rix = dataclasses.replace(ix, Rot=Rot)
+    X = ix.base.astype(np.float64) @ Rot.astype(np.float64)  # rows x = Rot^T x'
+    rng = np.random.default_rng(7)
+    Q = (X[rng.integers(0, ix.N, 6)] + rng.normal(0, 1.5, (6, 16))).astype(np.float32)
+    k = 20
+    ids, d, ncand, _ = oracle.search(rix, Q, ix.N + 5, k, nthreads=2)
+    for r in range(Q.shape[0]):
+        dd = ((X - Q[r].astype(np.float64)) ** 2).sum(1)
+        order = np.lexsort((np.arange(ix.N), dd))[:k]
+        assert np.array_equal(ids[r], order), r
+        assert np.allclose(d[r], dd[order], rtol=1e-5, atol=1e-3), r
+        assert ncand[r] == ix.N
+    # the transposed rotation is a different search
+    wrong = oracle.search(dataclasses.replace(ix, Rot=Rot.T.copy()), Q, ix.N + 5, k, nthreads=2)[0]
+    assert not np.array_equal(wrong, ids)
