@@ -68,7 +68,14 @@ typedef struct fbpq_index fbpq_index;
  *            displacements in the cells (i, *), SL[j] the second half in the
  *            cells (*, j) (equation residual); R is then not used. With them
  *            the search returns the kNN of the reconstructions through the
- *            local codebooks; without them, the FBPQ / Multi-D-ADC result. */
+ *            local codebooks; without them, the FBPQ / Multi-D-ADC result.
+ *   Rot      float  [D][D] row-major, or NULL: the orthogonal rotation of
+ *            optimized product quantization (OPQ, Section 2.1; the optimized
+ *            variants of Sections 3.1-3.2). The index lives in the rotated
+ *            space and every search first maps its queries there: coordinate
+ *            a of q' = Rot q is the FP64 sum over b = 0..D-1 in that order (one
+ *            fused multiply-add per term) rounded once to FP32. Queries and
+ *            results are otherwise unchanged. */
 typedef struct {
     int32_t D, T, M, Kc;
     int64_t N;
@@ -80,6 +87,7 @@ typedef struct {
     const uint32_t *ids;
     const float *QL;
     const float *SL;
+    const float *Rot;
 } fbpq_index_desc;
 
 typedef struct {
@@ -205,7 +213,8 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 #define FBPQ_STAGE_SCAN2 8     /* two-pass scan (queries whose cells hold few points) */
 #define FBPQ_STAGE_TRAVERSE_WIDE 9 /* threshold-stepping traversal (queries with many visited cells) */
 #define FBPQ_STAGE_SCAN_WIDE 10 /* two-pass scan with sums in HBM (many candidates in sparse cells) */
-#define FBPQ_NUM_STAGES 11
+#define FBPQ_STAGE_ROTATE 11 /* OPQ rotation of the queries (indexes with Rot) */
+#define FBPQ_NUM_STAGES 12
 
 /* ---- served form: continuous batching (Section 4 measures per-query time;
  * a server keeps the GPU busy with overlapping batches of arriving queries) --

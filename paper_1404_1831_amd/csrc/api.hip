@@ -50,6 +50,7 @@ struct fbpq_index {
     // owned device allocations
     float *C1 = nullptr, *C2 = nullptr, *R = nullptr;
     float *QL = nullptr, *SL = nullptr;  // local codebooks (HBPQ), or null
+    float *Rot = nullptr;                // OPQ rotation, or null
     int64_t *offsets = nullptr;
     uint8_t *codesA = nullptr, *codesB = nullptr;
     uint32_t *ids = nullptr;
@@ -113,7 +114,7 @@ enum WsSlot {
     W_Q, W_KEYS, W_LKEY, W_LIDX, W_HDR, W_W, W_ROWNE, W_ROWCAND, W_COLNE, W_COLTOT, W_NECS,
     W_NECNT, W_NEBEG, W_NECST, W_CMCELL, W_CMPRE, W_L, W_K, W_QLIST, W_FAIL, W_IDS, W_D,
     W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NESLOT, W_SLOTIJ, W_COUNTER,
-    W_LQ, W_ITEMN, W_PSTAT, W_SELDONE, W_NSLOTS
+    W_LQ, W_ITEMN, W_PSTAT, W_SELDONE, W_QROT, W_NSLOTS
 };
 constexpr int kWsSet = 40;  // slots per workspace set
 static_assert(W_NSLOTS <= kWsSet, "workspace slots");
@@ -234,6 +235,7 @@ int check_desc(const fbpq_index_desc *d)
         return fail(FBPQ_E_INVALID, "null array in descriptor");
     if ((d->QL == nullptr) != (d->SL == nullptr))
         return fail(FBPQ_E_INVALID, "local codebooks need both QL and SL");
+    if (d->Rot && d->D > 1024) return fail(FBPQ_E_INVALID, "an OPQ rotation needs D <= 1024");
     const int64_t C = (int64_t)d->T * d->T;
     if (d->offsets[0] != 0 || d->offsets[C] != d->N)
         return fail(FBPQ_E_FORMAT, "offsets must start at 0 and end at N");
@@ -262,7 +264,7 @@ void free_all(fbpq_index *ix)
     (void)hipSetDevice(ix->device);
     if (ix->stream) (void)hipStreamSynchronize(ix->stream);
     void *ps[] = {ix->C1, ix->C2, ix->R, ix->offsets, ix->codesA, ix->codesB, ix->ids,
-                  ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2, ix->QL, ix->SL};
+                  ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2, ix->QL, ix->SL, ix->Rot};
     if (!ix->shared)
         for (void *p : ps)
             if (p) (void)hipFree(p);
@@ -303,6 +305,7 @@ int create_impl(const fbpq_index_desc *d, int device, fbpq_index **out)
     if (!rc) rc = upload(ix, &ix->offsets, d->offsets, sizeof(int64_t) * (C + 1));
     if (!rc && d->QL) rc = upload(ix, &ix->QL, d->QL, sizeof(float) * T * FBPQ_KC * h);
     if (!rc && d->SL) rc = upload(ix, &ix->SL, d->SL, sizeof(float) * T * FBPQ_KC * h);
+    if (!rc && d->Rot) rc = upload(ix, &ix->Rot, d->Rot, sizeof(float) * d->D * d->D);
     if (!rc) rc = upload(ix, &ix->ids, d->ids, sizeof(uint32_t) * N);
     if (!rc) {
         const size_t half = (size_t)N * (M / 2);
@@ -353,6 +356,7 @@ int create_impl(const fbpq_index_desc *d, int device, fbpq_index **out)
     v.ids = ix->ids;
     v.QL = ix->QL;
     v.SL = ix->SL;
+    v.Rot = ix->Rot;
     v.local = ix->QL ? 1 : 0;
     *out = ix;
     return FBPQ_OK;
@@ -756,6 +760,21 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
     return FBPQ_OK;
 }
 
+// An index with an OPQ rotation searches q' = Rot q: the rotated queries go
+// to their own workspace slot (same address while nq stays, so a captured
+// first round stays valid) and replace the caller's for the whole search.
+int rotate_queries(fbpq_index *ix, const float **d_q, int64_t nq, hipStream_t st)
+{
+    if (!ix->dv.Rot) return FBPQ_OK;
+    void *qr;
+    TRY(ws_get(ix, W_QROT, sizeof(float) * (size_t)nq * ix->dv.D, &qr));
+    const float *src = *d_q;
+    HCK(ix, timed(ix, FBPQ_STAGE_ROTATE, st,
+                  [&] { return launch_rotate(src, nq, ix->dv.D, ix->dv.Rot, (float *)qr, st); }));
+    *d_q = (const float *)qr;
+    return FBPQ_OK;
+}
+
 int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
                 int32_t k_max, int64_t *d_ids, float *d_d, hipStream_t st, const DebugOut *dbg)
 {
@@ -786,6 +805,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     HCK(ix, hipMemcpyAsync(dL, stage, sizeof(int64_t) * nq, hipMemcpyHostToDevice, st));
     HCK(ix, hipMemcpyAsync(dk, stage + sizeof(int64_t) * nq, sizeof(int32_t) * nq,
                            hipMemcpyHostToDevice, st));
+    TRY(rotate_queries(ix, &d_q, nq, st));
     const int T = ix->dv.T;
     int32_t P = std::min<int32_t>(std::max<int32_t>(ix->prefix, 1), T);
     P = std::min<int32_t>(P, kMaxPrefix);
@@ -977,6 +997,7 @@ int lane_create(fbpq_index *src, fbpq_index **out)
     ix->ids = src->ids;
     ix->QL = src->QL;
     ix->SL = src->SL;
+    ix->Rot = src->Rot;
     ix->CR1 = src->CR1;
     ix->CR2 = src->CR2;
     ix->nR = src->nR;
@@ -1197,7 +1218,9 @@ int fbpq_debug_rank(fbpq_index *ix, const float *q, int64_t nq, int32_t P, doubl
     TRY(ws_get(ix, W_LKEY, sizeof(double) * nq * 2 * P, &lkey));
     TRY(ws_get(ix, W_LIDX, sizeof(int32_t) * nq * 2 * P, &lidx));
     HCK(ix, hipMemcpyAsync(dq, q, sizeof(float) * nq * ix->dv.D, hipMemcpyHostToDevice, ix->stream));
-    TRY(first_layer(ix, (const float *)dq, nq, nullptr, P, (double *)lkey, (int32_t *)lidx, ix->stream));
+    const float *qin = (const float *)dq;
+    TRY(rotate_queries(ix, &qin, nq, ix->stream));
+    TRY(first_layer(ix, qin, nq, nullptr, P, (double *)lkey, (int32_t *)lidx, ix->stream));
     HCK(ix, hipMemcpyAsync(keys, lkey, sizeof(double) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
     HCK(ix, hipMemcpyAsync(idx, lidx, sizeof(int32_t) * nq * 2 * P, hipMemcpyDeviceToHost, ix->stream));
     HCK(ix, hipStreamSynchronize(ix->stream));

@@ -60,6 +60,7 @@ struct DevIndex {
     const float *CR1, *CR2, *nR, *nC1, *nC2;  // CR1/CR2 hold CQ1/CQ2 with local codebooks
     float cmax1, cmax2;  // largest squared half-centroid norm of each half
     const float *QL, *SL;  // local codebooks [T][M/2][Kc][D/M] (HBPQ), or null
+    const float *Rot;      // OPQ rotation [D][D] row-major, or null
     int32_t local;         // 1: local codebooks
     int32_t od;            // 1: candidates scored by explicit O(D) reconstruction (Multi-D-ADC baseline)
 };
@@ -75,6 +76,8 @@ hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, 
 
 // Approximate half keys ||q||^2 + ||c||^2 - 2 <q, c> into ka [slot][2][T]
 // (slot s holds query qlist[s], or s when qlist is null).
+// q' = Rot q for nq queries of dimension D (OPQ), FP64 chains rounded to FP32
+hipError_t launch_rotate(const float *q, int64_t nq, int D, const float *Rot, float *out, hipStream_t st);
 hipError_t launch_half_approx(const DevIndex &ix, const float *q, const int32_t *qlist, int64_t nslots,
                               float *ka, hipStream_t st);
 

@@ -24,6 +24,49 @@ namespace fbpq {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// ---- OPQ: queries into the index's rotated space -----------------------------
+// q' = Rot q (optimized product quantization, Section 2.1). Coordinate a is
+// the FP64 fused multiply-add chain over b = 0..D-1 in that order, rounded
+// once to FP32, so the rotated query is a single defined value whatever the
+// launch shape. A workgroup stages kRotQ queries in LDS; a thread owns output
+// coordinates a and runs the kRotQ chains of its row of Rot side by side.
+constexpr int kRotQ = 16;
+
+__global__ __launch_bounds__(256) void k_rotate(const float *__restrict__ Q, int64_t nq, int D,
+                                                const float *__restrict__ Rot, float *__restrict__ out)
+{
+    extern __shared__ __align__(16) float qs[];  // [kRotQ][D]
+    const int64_t q0 = (int64_t)blockIdx.x * kRotQ;
+    const int nr = (int)(nq - q0 < kRotQ ? nq - q0 : kRotQ);
+    for (int e = threadIdx.x; e < nr * D; e += blockDim.x) qs[e] = Q[q0 * D + e];
+    __syncthreads();
+    for (int a = threadIdx.x; a < D; a += blockDim.x) {
+        const float *row = Rot + (int64_t)a * D;
+        double acc[kRotQ];
+#pragma unroll
+        for (int r = 0; r < kRotQ; ++r) acc[r] = 0.0;
+        for (int b = 0; b < D; ++b) {
+            const double w = (double)row[b];
+#pragma unroll
+            for (int r = 0; r < kRotQ; ++r)
+                if (r < nr) acc[r] = __builtin_fma(w, (double)qs[r * D + b], acc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < kRotQ; ++r)
+            if (r < nr) out[(q0 + r) * D + a] = (float)acc[r];
+    }
+}
+
+hipError_t launch_rotate(const float *q, int64_t nq, int D, const float *Rot, float *out, hipStream_t st)
+{
+    if (nq == 0) return hipSuccess;
+    const size_t lds = (size_t)kRotQ * D * sizeof(float);
+    if (lds > 64 * 1024) return hipErrorInvalidValue;  // D above 1024
+    hipLaunchKernelGGL(k_rotate, dim3((unsigned)((nq + kRotQ - 1) / kRotQ)), dim3(256), lds, st, q, nq, D, Rot,
+                       out);
+    return hipGetLastError();
+}
+
 // ---- step 1: approximate keys on the matrix cores ---------------------------
 // A wavefront owns kQT tiles of 16 rows (query halves of one half) and a chunk
 // of kCT centroids, which it takes 16 at a time. The dot product runs over the

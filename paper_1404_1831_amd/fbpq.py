@@ -34,7 +34,7 @@ EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbp
            "fbpq_free_index", "fbpq_last_error", "fbpq_server_create", "fbpq_server_submit",
            "fbpq_server_poll", "fbpq_server_counts", "fbpq_server_first_error", "fbpq_server_destroy")
 STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2",
-          "traverse_wide", "scan_wide")
+          "traverse_wide", "scan_wide", "rotate")
 STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried", "graph_replays",
          "wide", "wide_bands", "wide_evals", "wide_loads")
 
@@ -50,7 +50,7 @@ class IndexDesc(ctypes.Structure):
                 ("Kc", ctypes.c_int32), ("N", ctypes.c_int64), ("C1", ctypes.c_void_p),
                 ("C2", ctypes.c_void_p), ("R", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
                 ("codes", ctypes.c_void_p), ("ids", ctypes.c_void_p), ("QL", ctypes.c_void_p),
-                ("SL", ctypes.c_void_p)]
+                ("SL", ctypes.c_void_p), ("Rot", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -129,14 +129,19 @@ def fbpq_index_file_check(path: str) -> Info:
 
 def fbpq_index_create(ix, device: int = 0) -> ctypes.c_void_p:
     """ix: any object with D, T, M, Kc, C1, C2, R, offsets, codes, ids (numpy),
-    and optionally local codebooks QL, SL ([T][M/2][Kc][D/M] float32)."""
+    optionally local codebooks QL, SL ([T][M/2][Kc][D/M] float32) and an OPQ
+    rotation Rot ([D][D] float32)."""
     keep = [np.ascontiguousarray(ix.C1, np.float32), np.ascontiguousarray(ix.C2, np.float32),
             np.ascontiguousarray(ix.R, np.float32), np.ascontiguousarray(ix.offsets, np.int64),
             np.ascontiguousarray(ix.codes, np.uint8), np.ascontiguousarray(ix.ids, np.uint32)]
-    ql, sl = getattr(ix, "QL", None), getattr(ix, "SL", None)
-    if ql is not None:
-        keep += [np.ascontiguousarray(ql, np.float32), np.ascontiguousarray(sl, np.float32)]
-    ptrs = [_p(a) for a in keep] + [None] * (8 - len(keep))
+    ql, sl, rot = getattr(ix, "QL", None), getattr(ix, "SL", None), getattr(ix, "Rot", None)
+    ptrs = [_p(a) for a in keep]
+    for a in (ql, sl, rot):
+        if a is not None:
+            keep.append(np.ascontiguousarray(a, np.float32))
+            ptrs.append(_p(keep[-1]))
+        else:
+            ptrs.append(None)
     d = IndexDesc(ix.D, ix.T, ix.M, ix.Kc, keep[4].shape[0], *ptrs)
     h = ctypes.c_void_p()
     _check(lib.fbpq_index_create(ctypes.byref(d), device, ctypes.byref(h)))

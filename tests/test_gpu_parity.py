@@ -634,6 +634,58 @@ def test_d320_adc_od_uneven_groups(fb):
     assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
 
 
+# ---- OPQ: queries rotated into the index's space ------------------------------
+
+def _rotated(ix, Q, seed=23):
+    # the index's space is the rotated one; queries arrive in the original
+    # space, Q_orig = Rot^T Q (so that Rot Q_orig falls back near the data)
+    import dataclasses
+    Rot = synth.random_rotation(ix.D, seed=seed)
+    Qo = (Q.astype(np.float64) @ Rot.astype(np.float64)).astype(np.float32)
+    return dataclasses.replace(ix, Rot=Rot), Qo
+
+
+@pytest.mark.parametrize("L", [777, 10000])
+def test_rotation_prefix_visit_dists_topk(fb, gmm_small, L):
+    ix0, Q0 = gmm_small
+    ix, Q = _rotated(ix0, Q0[:30])
+    Qr = oracle.rotate(ix.Rot, Q)  # the queries the index sees
+    k = 20
+    log(f"OPQ rotation: T=64 D=128 L={L}")
+    h = _open(fb, ix)
+    keys, idx = fb.fbpq_debug_rank(h, Q[:10], 64)
+    for r in range(10):
+        d1, d2, u, v = oracle.rank_lists(ix, Q[r])
+        assert np.array_equal(idx[r, 0], u[:64]) and np.array_equal(idx[r, 1], v[:64]), r
+        assert np.array_equal(keys[r, 0], d1[u[:64]]) and np.array_equal(keys[r, 1], d2[v[:64]]), r
+    _check_visit(fb, h, ix, Q[:6], L)
+    got = fb.fbpq_debug_dists(h, Q[:6], L, cap=min(L, ix.N))
+    for r in range(6):
+        pos, d32 = got[r]
+        d64 = oracle_dists(ix, Qr[r], pos)
+        assert np.all(np.abs(d32.astype(np.float64) - d64) <= tol(ix, Qr[r], pos, d64)), r
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Qr, k, g_ids, g_d, o_ids, o_d)
+    # device entry point with a captured first round: every replay sees the
+    # rotated queries at the same address
+    import torch
+    fb.fbpq_set_option(h, "graph", 1)
+    dev = torch.device("cuda:0")
+    d_q = torch.from_numpy(Q).to(dev)
+    Ls, ks = np.full(Q.shape[0], L, np.int64), np.full(Q.shape[0], k, np.int32)
+    d_ids = torch.empty((Q.shape[0], k), dtype=torch.int64, device=dev)
+    d_d = torch.empty((Q.shape[0], k), dtype=torch.float32, device=dev)
+    for rep in range(3):  # the same buffers: the second and third calls replay
+        d_ids.fill_(-7)
+        d_d.zero_()
+        fb.fbpq_search_device(h, d_q, Ls, ks, k, d_ids, d_d, torch.cuda.current_stream(dev))
+        torch.cuda.synchronize()
+        assert np.array_equal(d_ids.cpu().numpy(), g_ids), rep
+        assert np.array_equal(d_d.cpu().numpy(), g_d), rep
+    fb.fbpq_free_index(h)
+
+
 # ---- the selection fused into the cell scan and its fallbacks --------------------
 
 def _dense_index(const_codes: bool):
