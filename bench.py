@@ -271,6 +271,34 @@ def main() -> int:
         adc = {"ms_per_step": adc_ms, "value": nq / (adc_ms / 1e3), "fbpq_speedup": adc_ms / ms_per_step}
         log(f"Multi-D-ADC O(D) baseline: {adc_ms:.3f} ms per batch (FBPQ {ms_per_step:.3f} ms)")
 
+    # OPQ: the same index declared to live in a rotated space, searched with the
+    # batch expressed in the original space (Rot^T q), so the rotation kernel
+    # maps it back: the cost of the query rotation inside a full search
+    opq = None
+    if args.adc_steps > 0:
+        import dataclasses
+        Rot = synth.random_rotation(ix.D, seed=23)
+        rix = dataclasses.replace(ix, Rot=Rot)
+        hr = fbpq.fbpq_index_create(rix, 0)
+        fbpq.fbpq_build_tables(hr)
+        d_qo = (d_q.double() @ torch.from_numpy(Rot).to(dev).double()).float().contiguous()
+        for _ in range(2):
+            fbpq.fbpq_search_device(hr, d_qo, Ls, ks, k, d_ids, d_d, stream)
+        torch.cuda.synchronize()
+        fbpq.fbpq_set_option(hr, "profile", 1)
+        fbpq.fbpq_set_option(hr, "profile_mask", 1 << fbpq.STAGES.index("rotate"))
+        a = time.perf_counter()
+        for _ in range(args.adc_steps):
+            fbpq.fbpq_search_device(hr, d_qo, Ls, ks, k, d_ids, d_d, stream)
+        torch.cuda.synchronize()
+        opq_ms = (time.perf_counter() - a) * 1e3 / args.adc_steps
+        rot_ms, rot_n = fbpq.fbpq_profile_read(hr, fbpq.STAGES.index("rotate"), reset=True)
+        fbpq.fbpq_free_index(hr)
+        opq = {"ms_per_step": opq_ms, "value": nq / (opq_ms / 1e3),
+               "rotate_ms_per_launch": rot_ms / rot_n if rot_n else None}
+        log(f"OPQ rotation: {opq_ms:.3f} ms per batch, rotation kernel "
+            f"{(rot_ms / rot_n if rot_n else float('nan')):.4f} ms")
+
     if args.calibrate_copy_mib > 0:
         nel = args.calibrate_copy_mib * (1 << 20) // 4
         x = torch.ones(nel, dtype=torch.float32, device=dev)
@@ -303,6 +331,7 @@ def main() -> int:
         "kernels": prof,
         "graph_replay": {"ms_per_step": graph_ms, "value": nq / (graph_ms / 1e3)},
         "multi_d_adc_baseline": adc,
+        "opq_rotation": opq,
         "plain_per_query": ({"queries": npl, "value": npl / plain_s, "unit": "queries/s",
                              "ms_per_query": plain_s * 1e3 / npl} if npl > 0 else None),
         "scan_GBps": scan_GBps,

@@ -30,22 +30,38 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // once to FP32, so the rotated query is a single defined value whatever the
 // launch shape. A workgroup stages kRotQ queries in LDS; a thread owns output
 // coordinates a and runs the kRotQ chains of its row of Rot side by side.
-constexpr int kRotQ = 16;
+constexpr int kRotQ = 8;    // queries per workgroup
+constexpr int kRotNT = 128;  // threads per workgroup
 
-__global__ __launch_bounds__(256) void k_rotate(const float *__restrict__ Q, int64_t nq, int D,
-                                                const float *__restrict__ Rot, float *__restrict__ out)
+__global__ __launch_bounds__(kRotNT) void k_rotate(const float *__restrict__ Q, int64_t nq, int D,
+                                                   const float *__restrict__ Rot, float *__restrict__ out)
 {
     extern __shared__ __align__(16) float qs[];  // [kRotQ][D]
     const int64_t q0 = (int64_t)blockIdx.x * kRotQ;
     const int nr = (int)(nq - q0 < kRotQ ? nq - q0 : kRotQ);
-    for (int e = threadIdx.x; e < nr * D; e += blockDim.x) qs[e] = Q[q0 * D + e];
+    for (int e = threadIdx.x; e < nr * D; e += kRotNT) qs[e] = Q[q0 * D + e];
     __syncthreads();
-    for (int a = threadIdx.x; a < D; a += blockDim.x) {
+    const bool v4 = (D & 3) == 0;
+    for (int a = threadIdx.x; a < D; a += kRotNT) {
         const float *row = Rot + (int64_t)a * D;
         double acc[kRotQ];
 #pragma unroll
         for (int r = 0; r < kRotQ; ++r) acc[r] = 0.0;
-        for (int b = 0; b < D; ++b) {
+        int b = 0;
+        if (v4) {
+            // 16-byte reads of the row, four terms at a time in increasing b
+#pragma unroll 4
+            for (; b < D; b += 4) {
+                const float4 w4 = *reinterpret_cast<const float4 *>(row + b);
+                const float w[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int r = 0; r < kRotQ; ++r)
+                        if (r < nr) acc[r] = __builtin_fma((double)w[u], (double)qs[r * D + b + u], acc[r]);
+            }
+        }
+        for (; b < D; ++b) {
             const double w = (double)row[b];
 #pragma unroll
             for (int r = 0; r < kRotQ; ++r)
@@ -61,8 +77,8 @@ hipError_t launch_rotate(const float *q, int64_t nq, int D, const float *Rot, fl
 {
     if (nq == 0) return hipSuccess;
     const size_t lds = (size_t)kRotQ * D * sizeof(float);
-    if (lds > 64 * 1024) return hipErrorInvalidValue;  // D above 1024
-    hipLaunchKernelGGL(k_rotate, dim3((unsigned)((nq + kRotQ - 1) / kRotQ)), dim3(256), lds, st, q, nq, D, Rot,
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rotate, dim3((unsigned)((nq + kRotQ - 1) / kRotQ)), dim3(kRotNT), lds, st, q, nq, D, Rot,
                        out);
     return hipGetLastError();
 }
