@@ -22,7 +22,52 @@
 // flagged for a longer prefix when the next pop reaches that bound.
 #include "fbpq_dev.h"
 
+#include <type_traits>
+
 namespace fbpq {
+
+// Wave-wide minimum of (key, a), ties to the smaller a; every lane gets it.
+// Keys are non-negative doubles or +inf, so their bit patterns order as the
+// values do. Within each row of 16 lanes the pairs are exchanged with DPP moves
+// (lane xor 1, xor 2, then the mirrors of 8 and of 16 lanes: each step pairs
+// every lane with one holding a disjoint set), and the four rows are combined
+// through lanes 0, 16, 32 and 48. The minimum of a total order does not depend
+// on the order of combination, so the result is the same as any other reduction.
+__device__ __forceinline__ void wave_argmin(double &key, int &a)
+{
+    uint64_t kb = (uint64_t)__double_as_longlong(key);
+    int ab = a;
+    auto step = [&](auto ctrl) __attribute__((always_inline)) {
+        constexpr int c = decltype(ctrl)::value;
+        const uint32_t lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)kb, c, 0xf, 0xf, false);
+        const uint32_t hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(kb >> 32), c, 0xf, 0xf, false);
+        const int oa = __builtin_amdgcn_update_dpp(0, ab, c, 0xf, 0xf, false);
+        const uint64_t ok = ((uint64_t)hi << 32) | lo;
+        if (ok < kb || (ok == kb && oa < ab)) {
+            kb = ok;
+            ab = oa;
+        }
+    };
+    step(std::integral_constant<int, 0xb1>{});   // quad_perm [1,0,3,2]: lane xor 1
+    step(std::integral_constant<int, 0x4e>{});   // quad_perm [2,3,0,1]: lane xor 2
+    step(std::integral_constant<int, 0x141>{});  // row_half_mirror: 7 - lane within 8
+    step(std::integral_constant<int, 0x140>{});  // row_mirror: 15 - lane within 16
+    uint64_t best = ~0ull;
+    int besta = 0x7fffffff;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)kb, 16 * r);
+        const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(kb >> 32), 16 * r);
+        const int ra = __builtin_amdgcn_readlane(ab, 16 * r);
+        const uint64_t rk = ((uint64_t)hi << 32) | lo;
+        if (rk < best || (rk == best && ra < besta)) {
+            best = rk;
+            besta = ra;
+        }
+    }
+    key = __longlong_as_double((long long)best);
+    a = besta;
+}
 
 template <int RPL>
 __global__ __launch_bounds__(64) void k_traverse(TravArgs args)
@@ -85,14 +130,7 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs args)
                     bk = nk[r];
                     ba = lane + 64 * r;
                 }
-            for (int o = 32; o > 0; o >>= 1) {
-                const double ok = __shfl_xor(bk, o);
-                const int oa = __shfl_xor(ba, o);
-                if (ok < bk || (ok == bk && oa < ba)) {
-                    bk = ok;
-                    ba = oa;
-                }
-            }
+            wave_argmin(bk, ba);
             if (bk == INF) {
                 exhausted = true;
                 break;
@@ -106,7 +144,7 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs args)
 #pragma unroll
             for (int r = 0; r < RPL; ++r)
                 if (r == ro) wsel = w[r];
-            const int bb = __shfl(wsel, lo);
+            const int bb = __builtin_amdgcn_readlane(wsel, lo);  // lo is the same on every lane
             if (lane == j) {
                 pa = ba;
                 pb = bb;
