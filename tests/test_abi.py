@@ -113,3 +113,32 @@ def test_invalid_arguments_without_gpu(fb):
     with pytest.raises(fb.FbpqError) as e:
         fb.fbpq_set_option(None, "prefix", 4)
     assert e.value.code == fb.FBPQ_E_INVALID
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of fbpq_index_desc and fbpq_info_t have the C
+    layout: a small C program built against include/fbpq.h prints sizeof and
+    every field's offset, and the binding must agree field by field."""
+    import ctypes
+    import subprocess
+
+    from paper_1404_1831_amd import fbpq as fbm
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"fbpq_index_desc": fbm.IndexDesc, "fbpq_info_t": fbm.Info}
+    body = []
+    for cname, py in structs.items():
+        body.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            body.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "fbpq.h"\nint main(void) {\n'
+                   + "\n".join(body) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (ln.split() for ln in out if ln)}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
