@@ -78,8 +78,10 @@ int items_wcap(int k_max)
 
 // LQ[k][r] = ||R_k(r)||^2 - 2 <q|k, R_k(r)> for kLqQ queries per workgroup:
 // each thread reads one codeword R_k(r) and scores it against every query of
-// the group, so the codebooks are read once per kLqQ queries.
+// the group, so the codebooks are read once per kLqQ queries. The M*Kc entries
+// are split into chunks of kLqE over blockIdx.y, for enough workgroups.
 constexpr int kLqQ = 16;
+constexpr int kLqE = 1024;
 
 // DS > 0: the subspace width, codeword held in registers; DS == 0: any width.
 template <int DS>
@@ -110,7 +112,8 @@ __global__ __launch_bounds__(256) void k_lq(ItemArgs a)
         qv[i * D + t] = a.q[qs * D + t];
     }
     __syncthreads();
-    for (int e = tid; e < M * kKc; e += 256) {
+    const int e1 = (int)(blockIdx.y + 1) * kLqE < M * kKc ? (int)(blockIdx.y + 1) * kLqE : M * kKc;
+    for (int e = (int)blockIdx.y * kLqE + tid; e < e1; e += 256) {
         const int k = e / kKc;
         const float *rw = a.ix.R + (int64_t)e * ds;
         const float nr = a.ix.nR[e];
@@ -610,7 +613,7 @@ hipError_t launch_items_prep(const ItemArgs &a, hipStream_t st)
 {
     if (a.nslots == 0) return hipSuccess;
     if (a.ix.D > 1024) return hipErrorInvalidValue;
-    const dim3 g((unsigned)((a.nslots + kLqQ - 1) / kLqQ)), b(256);
+    const dim3 g((unsigned)((a.nslots + kLqQ - 1) / kLqQ), (unsigned)((a.ix.M * kKc + kLqE - 1) / kLqE)), b(256);
     const size_t lds = (size_t)kLqQ * a.ix.D * sizeof(float);
     switch (a.ix.D / a.ix.M) {
     case 2: hipLaunchKernelGGL(k_lq<2>, g, b, lds, st, a); break;
