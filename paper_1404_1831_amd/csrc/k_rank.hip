@@ -818,8 +818,25 @@ __device__ __forceinline__ void rank_survivors(const float *qh, const float *__r
             } else {
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
-                    const uint64_t ko = __shfl_xor(k[r], j);
-                    const int32_t xo = __shfl_xor(x[r], j);
+                    uint64_t ko;
+                    int32_t xo;
+                    if (j <= 2) {
+                        // lane xor 1 / xor 2 inside each quad: DPP moves, no LDS
+                        // (j is a constant once the loops are unrolled)
+                        constexpr int kX1 = 0xb1, kX2 = 0x4e;  // quad_perm [1,0,3,2], [2,3,0,1]
+                        const uint32_t lo = j == 1
+                            ? __builtin_amdgcn_update_dpp(0, (int)(uint32_t)k[r], kX1, 0xf, 0xf, false)
+                            : __builtin_amdgcn_update_dpp(0, (int)(uint32_t)k[r], kX2, 0xf, 0xf, false);
+                        const uint32_t hi = j == 1
+                            ? __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(k[r] >> 32), kX1, 0xf, 0xf, false)
+                            : __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(k[r] >> 32), kX2, 0xf, 0xf, false);
+                        xo = j == 1 ? __builtin_amdgcn_update_dpp(0, x[r], kX1, 0xf, 0xf, false)
+                                    : __builtin_amdgcn_update_dpp(0, x[r], kX2, 0xf, 0xf, false);
+                        ko = ((uint64_t)hi << 32) | lo;
+                    } else {
+                        ko = __shfl_xor(k[r], j);
+                        xo = __shfl_xor(x[r], j);
+                    }
                     const bool asc = ((64 * r + lane) & kk) == 0;
                     const bool lower = (lane & j) == 0;  // this element comes first in the pair
                     const bool olt = ko < k[r] || (ko == k[r] && xo < x[r]);
