@@ -105,9 +105,12 @@ typedef struct {
  * On success *out owns the device copy. Errors: INVALID, FORMAT, OOM, DEVICE. */
 int fbpq_index_create(const fbpq_index_desc *desc, int device, fbpq_index **out);
 
-/* Read an index file (layout: 64-byte header "FBPQIDX1", six section records
- * with CRC-32, then C1, C2, R, offsets, codes, ids), validate it and upload it.
- * Errors: INVALID, IO, FORMAT (magic, version, sizes, CRC, offsets), OOM, DEVICE. */
+/* Read an index file (layout: 64-byte header "FBPQIDX1", six to nine section
+ * records with CRC-32, then the payloads: C1, C2, R, offsets, codes, ids,
+ * required once each, and optionally QL and SL (local codebooks, both or
+ * neither) and Rot (OPQ rotation), as in fbpq_index_desc), validate it and
+ * upload it. Errors: INVALID, IO, FORMAT (magic, version, section set, sizes,
+ * CRC, offsets), OOM, DEVICE. */
 int fbpq_load_index(const char *path, int device, fbpq_index **out);
 
 /* Validate an index file on the host only (no device work). Same checks and

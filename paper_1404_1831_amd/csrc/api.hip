@@ -396,12 +396,18 @@ struct FileSec {
 static_assert(sizeof(FileHdr) == 64, "header layout");
 static_assert(sizeof(FileSec) == 32, "section layout");
 
+// Sections 1-6 (C1, C2, R, offsets, codes, ids) are required; 7 and 8 (the
+// local codebooks QL, SL, together) and 9 (the OPQ rotation) are optional.
+constexpr int kSecReq = 6, kSecMax = 9;
+
 struct FileData {
     FileHdr h;
     std::vector<float> C1, C2, R;
     std::vector<int64_t> offsets;
     std::vector<uint8_t> codes;
     std::vector<uint32_t> ids;
+    std::vector<float> QL, SL, Rot;
+    bool has[kSecMax] = {};
 };
 
 int read_file(const char *path, FileData *fd, bool keep)
@@ -417,16 +423,28 @@ int read_file(const char *path, FileData *fd, bool keep)
     if (fread(&h, sizeof h, 1, f) != 1) return fail(FBPQ_E_FORMAT, "%s: short header", path);
     if (memcmp(h.magic, "FBPQIDX1", 8) != 0) return fail(FBPQ_E_FORMAT, "%s: bad magic", path);
     if (h.version != 1) return fail(FBPQ_E_FORMAT, "%s: unsupported version %u", path, h.version);
-    if (h.nsect != 6) return fail(FBPQ_E_FORMAT, "%s: expected 6 sections", path);
+    if (h.nsect < (uint32_t)kSecReq || h.nsect > (uint32_t)kSecMax)
+        return fail(FBPQ_E_FORMAT, "%s: expected 6 to 9 sections", path);
     if (h.D == 0 || h.D % 2 || h.M == 0 || h.M % 2 || h.D % h.M || h.Kc != FBPQ_KC || h.T == 0 ||
         h.T > (1u << 20) || h.D > 4096 || h.N > 0xffffffffull)
         return fail(FBPQ_E_FORMAT, "%s: bad geometry", path);
-    FileSec sec[6];
-    if (fread(sec, sizeof(FileSec), 6, f) != 6) return fail(FBPQ_E_FORMAT, "%s: short section table", path);
+    const int nsect = (int)h.nsect;
+    FileSec sec[kSecMax];
+    if (fread(sec, sizeof(FileSec), nsect, f) != (size_t)nsect)
+        return fail(FBPQ_E_FORMAT, "%s: short section table", path);
+    for (int s = 0; s < nsect; ++s) {
+        if (sec[s].kind < 1 || sec[s].kind > (uint32_t)kSecMax) return fail(FBPQ_E_FORMAT, "%s: bad section kind", path);
+        if (fd->has[sec[s].kind - 1]) return fail(FBPQ_E_FORMAT, "%s: section %u twice", path, sec[s].kind);
+        fd->has[sec[s].kind - 1] = true;
+    }
+    for (int k = 0; k < kSecReq; ++k)
+        if (!fd->has[k]) return fail(FBPQ_E_FORMAT, "%s: section %d missing", path, k + 1);
+    if (fd->has[6] != fd->has[7]) return fail(FBPQ_E_FORMAT, "%s: local codebooks need both QL and SL", path);
     const uint64_t T = h.T, half = h.D / 2;
-    const uint64_t want[6] = {4 * T * half, 4 * T * half, 4ull * h.M * h.Kc * (h.D / h.M),
-                              8 * (T * T + 1), h.N * h.M, 4 * h.N};
-    void *dst[6] = {nullptr};
+    const uint64_t want[kSecMax] = {4 * T * half, 4 * T * half, 4ull * h.M * h.Kc * (h.D / h.M),
+                                    8 * (T * T + 1), h.N * h.M, 4 * h.N,
+                                    4 * T * h.Kc * half, 4 * T * h.Kc * half, 4ull * h.D * h.D};
+    void *dst[kSecMax] = {nullptr};
     if (keep) {
         fd->C1.resize(T * half);
         fd->C2.resize(T * half);
@@ -434,15 +452,17 @@ int read_file(const char *path, FileData *fd, bool keep)
         fd->offsets.resize(T * T + 1);
         fd->codes.resize(h.N * h.M);
         fd->ids.resize(h.N);
-        void *d[6] = {fd->C1.data(), fd->C2.data(), fd->R.data(), fd->offsets.data(), fd->codes.data(),
-                      fd->ids.data()};
+        if (fd->has[6]) fd->QL.resize(T * h.Kc * half);
+        if (fd->has[7]) fd->SL.resize(T * h.Kc * half);
+        if (fd->has[8]) fd->Rot.resize((size_t)h.D * h.D);
+        void *d[kSecMax] = {fd->C1.data(), fd->C2.data(), fd->R.data(), fd->offsets.data(), fd->codes.data(),
+                            fd->ids.data(), fd->QL.data(), fd->SL.data(), fd->Rot.data()};
         memcpy(dst, d, sizeof d);
     }
     std::vector<unsigned char> tmp;
     std::vector<int64_t> offs_check;
-    for (int s = 0; s < 6; ++s) {
+    for (int s = 0; s < nsect; ++s) {
         const FileSec &r = sec[s];
-        if (r.kind < 1 || r.kind > 6) return fail(FBPQ_E_FORMAT, "%s: bad section kind", path);
         const int k = (int)r.kind - 1;
         if (r.bytes != want[k]) return fail(FBPQ_E_FORMAT, "%s: section %d has %llu bytes, want %llu", path,
                                             k + 1, (unsigned long long)r.bytes, (unsigned long long)want[k]);
@@ -1074,6 +1094,9 @@ int fbpq_load_index(const char *path, int device, fbpq_index **out)
     d.offsets = fd.offsets.data();
     d.codes = fd.codes.data();
     d.ids = fd.ids.data();
+    d.QL = fd.has[6] ? fd.QL.data() : nullptr;
+    d.SL = fd.has[7] ? fd.SL.data() : nullptr;
+    d.Rot = fd.has[8] ? fd.Rot.data() : nullptr;
     return create_impl(&d, device, out);
 }
 

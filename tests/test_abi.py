@@ -106,6 +106,56 @@ def test_index_file_errors(fb, tmp_path):
     assert "offsets" in str(e.value)
 
 
+def _write_sections(path, ix, sections):
+    """A file with the given (kind, array) sections in that order, CRCs valid."""
+    import zlib
+    from synth.indexfile import HDR, SEC, MAGIC, _align
+    pos = _align(HDR.size + SEC.size * len(sections))
+    recs = []
+    for kind, a in sections:
+        a = np.ascontiguousarray(a)
+        recs.append((kind, zlib.crc32(a.tobytes()) & 0xFFFFFFFF, pos, a.nbytes, 0))
+        pos = _align(pos + a.nbytes)
+    with open(path, "wb") as f:
+        f.write(HDR.pack(MAGIC, 1, ix.D, ix.T, ix.M, ix.Kc, len(sections), ix.N, b"\0" * 24))
+        for r in recs:
+            f.write(SEC.pack(*r))
+        for r, (_, a) in zip(recs, sections):
+            f.seek(r[2])
+            np.ascontiguousarray(a).tofile(f)
+
+
+def test_index_file_optional_sections(fb, tmp_path):
+    """Local codebooks (QL, SL) and the OPQ rotation travel in optional
+    sections: written, read back and checked natively; QL without SL, a
+    repeated kind and a corrupt optional section are format errors."""
+    import dataclasses
+    base = synth.random_index(N=400, T=8, M=4, D=16, seed=3)
+    ix = dataclasses.replace(synth.with_local_codebooks(base, seed=4), Rot=synth.random_rotation(16, seed=6))
+    p = _write(tmp_path, ix)
+    info = fb.fbpq_index_file_check(p)
+    assert (info.D, info.T, info.M, info.N) == (16, 8, 4, 400)
+    back = synth.read_index(p)
+    for a in ("C1", "C2", "R", "offsets", "codes", "ids", "QL", "SL", "Rot"):
+        assert np.array_equal(getattr(back, a), getattr(ix, a)), a
+    req = [(1, ix.C1), (2, ix.C2), (3, ix.R), (4, ix.offsets), (5, ix.codes), (6, ix.ids)]
+    cases = {"ql_only.bin": req + [(7, ix.QL)],
+             "twice.bin": req + [(9, ix.Rot), (9, ix.Rot)],
+             "missing.bin": req[:5] + [(9, ix.Rot)],
+             "rot_shape.bin": req + [(9, ix.Rot[:8])]}
+    for name, secs in cases.items():
+        _write_sections(str(tmp_path / name), ix, secs)
+        with pytest.raises(fb.FbpqError) as e:
+            fb.fbpq_index_file_check(str(tmp_path / name))
+        assert e.value.code == fb.FBPQ_E_FORMAT, name
+    raw = bytearray(open(p, "rb").read())
+    raw[-3] ^= 0x40  # a payload byte of the rotation, the last section
+    (tmp_path / "rot_crc.bin").write_bytes(bytes(raw))
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_index_file_check(str(tmp_path / "rot_crc.bin"))
+    assert e.value.code == fb.FBPQ_E_FORMAT
+
+
 def test_invalid_arguments_without_gpu(fb):
     with pytest.raises(fb.FbpqError) as e:
         fb.fbpq_table_bytes(0, 8, 256)

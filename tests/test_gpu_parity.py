@@ -686,6 +686,30 @@ def test_rotation_prefix_visit_dists_topk(fb, gmm_small, L):
     fb.fbpq_free_index(h)
 
 
+def test_load_index_with_local_codebooks_and_rotation(fb, tmp_path):
+    # the optional file sections reach the device: a file index searches bit
+    # for bit like the same arrays given to fbpq_index_create, and both match
+    # the oracle (local codebooks and an OPQ rotation together)
+    import dataclasses
+    base = synth.random_index(N=3000, T=16, M=4, D=16, seed=21)
+    ix = dataclasses.replace(synth.with_local_codebooks(base, seed=8), Rot=synth.random_rotation(16, seed=9))
+    path = str(tmp_path / "ix.bin")
+    synth.write_index(path, ix)
+    Q = np.random.default_rng(2).normal(0, 20, (12, 16)).astype(np.float32)
+    L, k = 900, 10
+    log("file index with local codebooks and a rotation")
+    h1 = _open(fb, ix)
+    a_ids, a_d = fb.fbpq_search(h1, Q, L, k)
+    fb.fbpq_free_index(h1)
+    h2 = fb.fbpq_load_index(path, 0)
+    fb.fbpq_build_tables(h2)
+    b_ids, b_d = fb.fbpq_search(h2, Q, L, k)
+    fb.fbpq_free_index(h2)
+    assert np.array_equal(a_ids, b_ids) and np.array_equal(a_d, b_d)
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, oracle.rotate(ix.Rot, Q), k, b_ids, b_d, o_ids, o_d)
+
+
 # ---- the selection fused into the cell scan and its fallbacks --------------------
 
 def _dense_index(const_codes: bool):
