@@ -870,16 +870,21 @@ def test_full_uneven_100M_sampled(fb):
 
 # ---- served form ----------------------------------------------------------------
 
-def test_server_continuous_batching(fb, gmm_small):
+@pytest.mark.parametrize("rot", [False, True])
+def test_server_continuous_batching(fb, gmm_small, rot):
+    # rot: the index lives in a rotated space (OPQ) and the serving lanes share
+    # its rotation; requests arrive in the original space
     import time
     ix, Q0 = gmm_small
     means = synth.gmm_means(0)
-    nreq, kmax = 300, 100
+    nreq, kmax = (120 if rot else 300), 100
     Q = synth.make_queries(nreq, means, 7)
+    if rot:
+        ix, Q = _rotated(ix, Q)
     rng = np.random.default_rng(31)
     L = rng.integers(1, 30000, nreq)
     k = rng.choice([1, 10, 100], nreq).astype(np.int32)
-    log(f"server: N=1e5 T=64 M=8, {nreq} requests, 2 lanes, batches of at most 64")
+    log(f"server: N=1e5 T=64 M=8, {nreq} requests, 2 lanes, batches of at most 64, rotation={rot}")
     h = _open(fb, ix)
     s = fb.fbpq_server_create(h, 64, 2, kmax)
     got = {}
@@ -905,4 +910,4 @@ def test_server_continuous_batching(fb, gmm_small):
     g_ids = np.stack([got[i][0] for i in range(nreq)])
     g_d = np.stack([got[i][1] for i in range(nreq)])
     o_ids, o_d, _, _ = oracle.search(ix, Q, L, k, kmax=kmax)
-    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+    assert_topk(ix, oracle.rotate(ix.Rot, Q) if rot else Q, k, g_ids, g_d, o_ids, o_d)
