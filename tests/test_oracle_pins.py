@@ -331,3 +331,13 @@ def test_rotated_lossless_index_is_exact_knn_in_the_original_space():
     # the transposed rotation is a different search
     wrong = oracle.search(dataclasses.replace(ix, Rot=Rot.T.copy()), Q, ix.N + 5, k, nthreads=2)[0]
     assert not np.array_equal(wrong, ids)
+
+
+def test_random_rotation_is_orthogonal_and_seeded():
+    """The generator's rotation is orthogonal (to FP32 rounding) and fixed by its seed."""
+    R = synth.random_rotation(128, seed=23)
+    assert R.shape == (128, 128) and R.dtype == np.float32
+    G = R.astype(np.float64) @ R.T.astype(np.float64)
+    assert np.abs(G - np.eye(128)).max() < 1e-5
+    assert np.array_equal(R, synth.random_rotation(128, seed=23))
+    assert not np.array_equal(R, synth.random_rotation(128, seed=24))
