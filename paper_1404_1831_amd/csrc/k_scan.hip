@@ -383,8 +383,9 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
     constexpr int NW = wide_waves<MH, MODE>();
     constexpr int NT = 64 * NW;
     constexpr int TL = MH * kKc;  // floats of one folded half table
-    constexpr int NREG = wide_regions<MH, MODE>();
-    extern __shared__ __align__(16) float wlut[];  // [NREG][TL], then the task prefix [kWideRanks], then q [D]
+    // the regions (wide_regions of them: folded tables, or the O(D) codebooks and
+    // q - c), then the task prefix [kWideRanks], then q [D]
+    extern __shared__ __align__(16) float wlut[];
     __shared__ int wtot[NW];
     const int slot = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;

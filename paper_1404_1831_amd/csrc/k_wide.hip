@@ -243,14 +243,11 @@ __global__ __launch_bounds__(NT) void k_traverse_wide(TravArgs args)
         // band size window [lo_t, hi_t]
         const double est = rho > 0.0 ? (double)need / rho : 384.0;
         const double e125 = est * 1.25 + 32.0;
-        bool store;
         int64_t lo_t, hi_t;
         if (dbg || e125 <= (double)kWCap) {
-            store = true;
             lo_t = (int64_t)fmin(e125, 0.75 * kWCap);
             hi_t = lo_t * 2 < kWCap ? lo_t * 2 : kWCap;
         } else {
-            store = false;
             const double e = fmin(est, 4.0e15);
             lo_t = (int64_t)(0.5 * e);
             hi_t = (int64_t)(0.9 * e);
