@@ -235,7 +235,7 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = oracle.host_threads()
         n0 = min(nq, 2 * threads)
         a = time.perf_counter()
         o_ids, o_d, _, _ = oracle.search(ix, Q[:n0], L, k, nthreads=threads)
@@ -429,7 +429,7 @@ def run_local(args, w) -> int:
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = oracle.host_threads()
         n0 = min(nq, threads)
         a = time.perf_counter()
         o_ids, o_d, _, _ = oracle.search(ix, Q[:n0], Ls[:n0], k, nthreads=threads)
@@ -549,7 +549,7 @@ def run_gist(args, w) -> int:
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = oracle.host_threads()
         Ls0 = np.full(nq, L0, np.int64)
         n0 = min(nq, threads)
         a = time.perf_counter()

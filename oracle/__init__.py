@@ -45,9 +45,9 @@ def _load():
         lib.orc_half_dists.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P]
         lib.orc_half_dists.restype = None
         lib.orc_rank.argtypes = [P, ctypes.c_int, P]
-        lib.orc_rank.restype = None
+        lib.orc_rank.restype = ctypes.c_int
         lib.orc_rank_lists.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P]
-        lib.orc_rank_lists.restype = None
+        lib.orc_rank_lists.restype = ctypes.c_int
         lib.orc_point_dist.argtypes = [ctypes.c_int] * 4 + [P, P, P, P, i32, i32, P]
         lib.orc_point_dist.restype = ctypes.c_double
         ix_args = [ctypes.c_int] * 4 + [i64, P, P, P, P, P, P]
@@ -112,7 +112,8 @@ def half_dists(q: np.ndarray, Ch: np.ndarray) -> np.ndarray:
 def rank(d: np.ndarray) -> np.ndarray:
     d = np.ascontiguousarray(d, np.float64)
     o = np.empty(d.size, np.int32)
-    _load().orc_rank(_p(d), d.size, _p(o))
+    if _load().orc_rank(_p(d), d.size, _p(o)) != 0:
+        raise MemoryError("orc_rank: no memory for the sort")
     return o
 
 
@@ -124,7 +125,8 @@ def rank_lists(ix, q: np.ndarray):
     u, v = np.empty(T, np.int32), np.empty(T, np.int32)
     C1 = np.ascontiguousarray(ix.C1, np.float32)
     C2 = np.ascontiguousarray(ix.C2, np.float32)
-    _load().orc_rank_lists(ix.D, T, _p(C1), _p(C2), _p(q), _p(d1), _p(d2), _p(u), _p(v))
+    if _load().orc_rank_lists(ix.D, T, _p(C1), _p(C2), _p(q), _p(d1), _p(d2), _p(u), _p(v)) != 0:
+        raise MemoryError("orc_rank_lists: no memory for the sort")
     return d1, d2, u, v
 
 
@@ -170,7 +172,18 @@ def visit(ix, q: np.ndarray, L: int, cells_cap: int = 1 << 20):
     return cells[:ncell].copy(), pos[:n].copy()
 
 
-# threads of `search` when the caller names none (None: up to 16 host threads)
+def host_threads() -> int:
+    """Host cores this process may run on (its CPU affinity), at most 16: the
+    share of host cores that goes with one GPU on the machines the GPU runs
+    use, and enough for every oracle workload here."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+# threads of `search` when the caller names none (None: host_threads())
 DEFAULT_THREADS = None
 
 
@@ -191,7 +204,7 @@ def search(ix, Q: np.ndarray, L, k, kmax: int | None = None, nthreads: int | Non
     ncand = np.empty(nq, np.int64)
     ncells = np.empty(nq, np.int64)
     if nthreads is None:
-        nthreads = DEFAULT_THREADS or min(16, os.cpu_count() or 1)
+        nthreads = DEFAULT_THREADS or host_threads()
     nthreads = max(1, min(int(nthreads), max(nq, 1)))
     fn = _load().orc_search_local if getattr(ix, "QL", None) is not None else _load().orc_search
     rc = fn(*args, _p(Q), nq, _p(L), _p(k), kmax, _p(ids), _p(d), _p(ncand), _p(ncells), nthreads)

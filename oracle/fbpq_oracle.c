@@ -93,13 +93,16 @@ static int orc_cmp_di(const void *x, const void *y)
     return (a->i > b->i) - (a->i < b->i);
 }
 
-void orc_rank(const double *d, int T, int32_t *order)
+/* Returns 0, or -1 when its scratch cannot be allocated (order untouched). */
+int orc_rank(const double *d, int T, int32_t *order)
 {
-    orc_di *tmp = (orc_di *)malloc(sizeof(orc_di) * (size_t)T);
+    orc_di *tmp = (orc_di *)malloc(sizeof(orc_di) * (size_t)(T > 0 ? T : 1));
+    if (!tmp) return -1;
     for (int i = 0; i < T; ++i) { tmp[i].d = d[i]; tmp[i].i = i; }
     qsort(tmp, (size_t)T, sizeof(orc_di), orc_cmp_di);
     for (int i = 0; i < T; ++i) order[i] = tmp[i].i;
     free(tmp);
+    return 0;
 }
 
 /* ---- multi-sequence traversal (Section 2.3.3) ----------------------------
@@ -108,7 +111,12 @@ void orc_rank(const double *d, int T, int32_t *order)
  * (a+1, b) is pushed once its other predecessor (a+1, b-1) has been popped
  * (or b = 0), and (a, b+1) once (a-1, b+1) has been popped (or a = 0). Since
  * the key grows along both grid directions, cells leave the queue in
- * ascending (key, a, b). */
+ * ascending (key, a, b).
+ * The popped cells always form a staircase (a cell enters the queue only
+ * after both its predecessors left it, and the cells of one row leave it in
+ * column order), so "was (a, b) popped" is b < width[a], width[a] being the
+ * number of cells of row a popped so far: T counters per query instead of a
+ * T x T flag array. */
 typedef struct { double key; int32_t a, b; } orc_ent;
 
 static int orc_less(const orc_ent *x, const orc_ent *y)
@@ -155,7 +163,8 @@ typedef struct {
     double *d1, *d2;
     int32_t *u, *v;
     orc_ent *heap;
-    uint8_t *popped; /* T*T flags, rows [0, max_row] are dirty after a query */
+    int32_t *width;  /* popped cells per row of the rank grid; rows [0, max_row] dirty after a query */
+    orc_di *sort_tmp; /* cap_cand entries: merge-sort scratch of the rerank */
     int64_t cap_cand;
     int64_t *cand_pos;
     int32_t *cand_i, *cand_j;
@@ -171,41 +180,44 @@ static int orc_work_init(orc_work *w, const orc_ix *ix)
     w->u = (int32_t *)malloc(sizeof(int32_t) * T);
     w->v = (int32_t *)malloc(sizeof(int32_t) * T);
     w->heap = (orc_ent *)malloc(sizeof(orc_ent) * ((size_t)T + 2));
-    w->popped = (uint8_t *)calloc((size_t)T * (size_t)T, 1);
-    return (w->d1 && w->d2 && w->u && w->v && w->heap && w->popped) ? 0 : -1;
+    w->width = (int32_t *)calloc((size_t)T, sizeof(int32_t));
+    return (w->d1 && w->d2 && w->u && w->v && w->heap && w->width) ? 0 : -1;
 }
 
 static int orc_work_cand(orc_work *w, int64_t n)
 {
     if (n <= w->cap_cand) return 0;
-    free(w->cand_pos); free(w->cand_i); free(w->cand_j); free(w->dl);
+    free(w->cand_pos); free(w->cand_i); free(w->cand_j); free(w->dl); free(w->sort_tmp);
     w->cap_cand = n;
     w->cand_pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     w->cand_i = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     w->cand_j = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     w->dl = (orc_di *)malloc(sizeof(orc_di) * (size_t)n);
-    return (w->cand_pos && w->cand_i && w->cand_j && w->dl) ? 0 : -1;
+    w->sort_tmp = (orc_di *)malloc(sizeof(orc_di) * (size_t)n);
+    if (w->cand_pos && w->cand_i && w->cand_j && w->dl && w->sort_tmp) return 0;
+    w->cap_cand = 0; /* a failed growth leaves no capacity claimed */
+    return -1;
 }
 
 static void orc_work_free(orc_work *w)
 {
-    free(w->d1); free(w->d2); free(w->u); free(w->v); free(w->heap); free(w->popped);
-    free(w->cand_pos); free(w->cand_i); free(w->cand_j); free(w->dl);
+    free(w->d1); free(w->d2); free(w->u); free(w->v); free(w->heap); free(w->width);
+    free(w->cand_pos); free(w->cand_i); free(w->cand_j); free(w->dl); free(w->sort_tmp);
 }
 
 /* First step of the search (Section 2.3.3): visit cells in ascending order and
  * collect the points they hold until min(L, N) are collected.
  * Writes candidate storage positions and their cells (i, j) into w; optionally
  * records the visited cells (cell id, points taken). Returns the number of
- * candidates, and the number of visited cells in *ncells. */
+ * candidates, and the number of visited cells in *ncells; -1 when the rank
+ * lists cannot be sorted (no memory). */
 static int64_t orc_collect(const orc_ix *ix, orc_work *w, const float *q, int64_t L,
                            int64_t *cells_out, int64_t cells_cap, int64_t *ncells)
 {
     const int T = ix->T, h = ix->D / 2;
     orc_half_dists(q, ix->C1, T, h, w->d1);
     orc_half_dists(q + h, ix->C2, T, h, w->d2);
-    orc_rank(w->d1, T, w->u);
-    orc_rank(w->d2, T, w->v);
+    if (orc_rank(w->d1, T, w->u) || orc_rank(w->d2, T, w->v)) return -1;
 
     const int64_t Leff = L < ix->N ? L : ix->N;
     int64_t total = 0, nc = 0;
@@ -218,13 +230,13 @@ static int64_t orc_collect(const orc_ix *ix, orc_work *w, const float *q, int64_
     while (total < Leff && hp.n > 0) {
         orc_ent e = orc_pop(&hp);
         const int a = e.a, b = e.b;
-        w->popped[(int64_t)a * T + b] = 1;
+        w->width[a] = b + 1; /* cells of a row leave the queue in column order */
         if (a > max_row) max_row = a;
-        if (a + 1 < T && (b == 0 || w->popped[(int64_t)(a + 1) * T + (b - 1)])) {
+        if (a + 1 < T && (b == 0 || b - 1 < w->width[a + 1])) {
             orc_ent n1 = { w->d1[w->u[a + 1]] + w->d2[w->v[b]], a + 1, b };
             orc_push(&hp, n1);
         }
-        if (b + 1 < T && (a == 0 || w->popped[(int64_t)(a - 1) * T + (b + 1)])) {
+        if (b + 1 < T && (a == 0 || b + 1 < w->width[a - 1])) {
             orc_ent n2 = { w->d1[w->u[a]] + w->d2[w->v[b + 1]], a, b + 1 };
             orc_push(&hp, n2);
         }
@@ -244,7 +256,7 @@ static int64_t orc_collect(const orc_ix *ix, orc_work *w, const float *q, int64_
         ++nc;
         total += take;
     }
-    memset(w->popped, 0, (size_t)(max_row + 1) * (size_t)T);
+    memset(w->width, 0, sizeof(int32_t) * (size_t)(max_row + 1));
     if (ncells) *ncells = nc;
     return total;
 }
@@ -309,7 +321,7 @@ static void orc_rerank(const orc_ix *ix, orc_work *w, const float *q, int64_t nc
     {
         int64_t n = ncand;
         orc_di *a = w->dl;
-        orc_di *tmp = (orc_di *)malloc(sizeof(orc_di) * (size_t)(n > 0 ? n : 1));
+        orc_di *tmp = w->sort_tmp; /* ncand entries, allocated with the candidate arrays */
         for (int64_t width = 1; width < n; width *= 2) {
             for (int64_t lo = 0; lo < n; lo += 2 * width) {
                 int64_t mid = lo + width < n ? lo + width : n;
@@ -326,7 +338,6 @@ static void orc_rerank(const orc_ix *ix, orc_work *w, const float *q, int64_t nc
             }
             memcpy(a, tmp, sizeof(orc_di) * (size_t)n);
         }
-        free(tmp);
     }
     for (int32_t r = 0; r < k; ++r) {
         if (r < ncand) {
@@ -363,21 +374,22 @@ int64_t orc_visit(int D, int T, int M, int Kc, int64_t N, const float *C1, const
     const int64_t Leff = L < N ? L : N;
     if (orc_work_cand(&w, Leff > 0 ? Leff : 1)) { orc_work_free(&w); return -1; }
     int64_t n = orc_collect(&ix, &w, q, L, cells, cells_cap, ncells);
+    if (n < 0) { orc_work_free(&w); return -1; }
     if (n > pos_cap) { orc_work_free(&w); return -2; }
     memcpy(pos, w.cand_pos, sizeof(int64_t) * (size_t)n);
     orc_work_free(&w);
     return n;
 }
 
-/* FP64 rank lists of one query: d1, d2 (T each) and u, v (T each). */
-void orc_rank_lists(int D, int T, const float *C1, const float *C2, const float *q,
-                    double *d1, double *d2, int32_t *u, int32_t *v)
+/* FP64 rank lists of one query: d1, d2 (T each) and u, v (T each). Returns 0,
+ * or -1 when the sort scratch cannot be allocated. */
+int orc_rank_lists(int D, int T, const float *C1, const float *C2, const float *q,
+                   double *d1, double *d2, int32_t *u, int32_t *v)
 {
     const int h = D / 2;
     orc_half_dists(q, C1, T, h, d1);
     orc_half_dists(q + h, C2, T, h, d2);
-    orc_rank(d1, T, u);
-    orc_rank(d2, T, v);
+    return (orc_rank(d1, T, u) || orc_rank(d2, T, v)) ? -1 : 0;
 }
 
 typedef struct {
@@ -407,6 +419,7 @@ static void *orc_worker(void *arg)
         const float *q = j->Q + qi * ix->D;
         int64_t nc = 0;
         int64_t n = orc_collect(ix, &w, q, L, NULL, 0, &nc);
+        if (n < 0) { j->err = -1; break; }
         orc_rerank(ix, &w, q, n, j->k[qi], j->out_ids + qi * j->kmax, j->out_d + qi * j->kmax);
         for (int32_t r = j->k[qi]; r < j->kmax; ++r) {
             j->out_ids[qi * j->kmax + r] = -1;

@@ -14,9 +14,6 @@ from parity import assert_topk, log, oracle_dists, tol
 
 pytestmark = pytest.mark.gpu
 
-# the oracle runs in the calling thread inside the GPU test process
-oracle.DEFAULT_THREADS = 1
-
 
 @pytest.fixture(scope="module")
 def fb():
