@@ -49,7 +49,10 @@ extern "C" {
 #define FBPQ_E_OOM (-4)      /* host or device allocation failed */
 #define FBPQ_E_DEVICE (-5)   /* a HIP call failed, or the handle was poisoned by one */
 #define FBPQ_E_STATE (-6)    /* call out of order (e.g. search before fbpq_build_tables) */
-#define FBPQ_E_CAPACITY (-7) /* a query needs more traversal depth than the library supports */
+#define FBPQ_E_CAPACITY (-7) /* a query needs more traversal depth than the library supports, or a
+                                server's admission limits refuse a request */
+#define FBPQ_E_TIMEOUT (-8)   /* served request still queued at its deadline (not searched) */
+#define FBPQ_E_CANCELLED (-9) /* served request taken out of the queue by fbpq_server_cancel */
 
 #define FBPQ_KC 256
 #define FBPQ_K_MAX 1024 /* largest k per query */
@@ -222,30 +225,81 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 /* ---- served form: continuous batching (Section 4 measures per-query time;
  * a server keeps the GPU busy with overlapping batches of arriving queries) --
  *
- * fbpq_server_create: a server over a handle whose tables are built. It owns
- *   nlanes (1..16) lanes, each with its own HIP stream and workspace over the
- *   handle's index arrays, and one host worker thread per lane. A lane that is
- *   free takes every pending request, up to max_batch, and searches them as one
- *   batch; the lanes' batches overlap on the GPU. Results have k_max columns.
+ * fbpq_server_create2: a server over a handle whose tables are built. It owns
+ *   cfg->nlanes (1..16) lanes, each with its own HIP stream and workspace over
+ *   the handle's index arrays, and one host worker thread per lane. A lane
+ *   that is free takes the oldest queued request and, in arrival order, the
+ *   queued requests of the same candidate-budget class (floor(log2(min(L, N))))
+ *   up to cfg->max_batch, and searches them as one batch; the lanes' batches
+ *   overlap on the GPU. Results have cfg->k_max columns.
+ *   Admission: each request reserves an estimate of its search workspace
+ *   (bytes per query plus bytes per candidate); one lane's batch reserves at
+ *   most cfg->ws_budget / nlanes (ws_budget 0: 16 GiB), so the lanes'
+ *   workspace stays within ws_budget. A request whose own reservation exceeds
+ *   a lane's share, or that arrives while cfg->max_pending requests are queued
+ *   (0: 2^20), is refused by fbpq_server_submit with FBPQ_E_CAPACITY. A
+ *   request still queued cfg->timeout_s seconds after its submission (0: no
+ *   limit) completes with status FBPQ_E_TIMEOUT without being searched.
+ *   Test backend: with ix NULL, cfg->D > 0 and cfg->fake_ns_per_cand > 0 the
+ *   lanes run on the host instead: a batch sleeps fake_ns_per_cand per
+ *   candidate (sum of L) and answers request (q, k) with ids
+ *   j + 1000 * round(q[0]) and distances q[1] + j for j < k. The scheduler
+ *   (batching, admission, timeouts, cancellation) is the same.
  *   The handle must outlive the server and must not be searched directly while
  *   the server runs. Errors: INVALID, STATE, DEVICE.
+ * fbpq_server_create: fbpq_server_create2 with max_batch, nlanes and k_max
+ *   given and every other field 0 (the defaults).
  * fbpq_server_submit: queues one query (host, D floats, copied), its L >= 1 and
- *   1 <= k <= k_max, under a caller tag. Thread-safe. Errors: INVALID, STATE.
+ *   1 <= k <= k_max, under a caller tag. Thread-safe. Errors: INVALID, STATE
+ *   (server stopping), CAPACITY (refused by admission; nothing is queued).
+ * fbpq_server_cancel: completes the queued request of that tag with status
+ *   FBPQ_E_CANCELLED. Errors: STATE (no such request is queued: it runs,
+ *   finished or never existed), INVALID.
  * fbpq_server_poll: moves up to max_n finished requests out, waiting up to
  *   wait_s seconds for the first: tags[n], ids/dists [n][k_max] (padded with
  *   -1 / +inf past k), times[n][3] = submit, batch start, batch end (seconds on
- *   the host steady clock), status[n] = the batch's return code. Writes the
- *   count to *n_out. Errors: INVALID.
+ *   the host steady clock), status[n] = FBPQ_OK, the batch's error code,
+ *   FBPQ_E_CAPACITY for a row the traversal could not serve (ids -2),
+ *   FBPQ_E_TIMEOUT or FBPQ_E_CANCELLED. Writes the count to *n_out. Errors:
+ *   INVALID.
  * fbpq_server_counts: requests still queued, batches run, requests batched.
+ * fbpq_server_stats: copies min(n, FBPQ_SERVER_NUM_STATS) counters to out[].
  * fbpq_server_first_error: message of the first failed batch ("" if none).
  * fbpq_server_destroy: finishes every queued request, then frees the lanes;
  *   results not polled are dropped. */
 typedef struct fbpq_server fbpq_server;
+typedef struct {
+    int32_t max_batch;       /* requests per batch, >= 1 */
+    int32_t nlanes;          /* concurrent batches, 1..16 */
+    int32_t k_max;           /* result columns, 1..FBPQ_K_MAX */
+    int32_t D;               /* query dimension: test backend only (taken from the index otherwise) */
+    int64_t ws_budget;       /* workspace bytes all lanes together may reserve (0: 16 GiB) */
+    int64_t max_pending;     /* queued requests above which submit refuses (0: 2^20) */
+    double timeout_s;        /* queueing deadline per request in seconds (0: none) */
+    double fake_ns_per_cand; /* > 0 with a NULL index: host test backend */
+} fbpq_server_config;
+#define FBPQ_SERVER_STAT_SUBMITTED 0   /* requests queued */
+#define FBPQ_SERVER_STAT_COMPLETED 1   /* ... finished with FBPQ_OK */
+#define FBPQ_SERVER_STAT_FAILED 2      /* ... finished by a batch with an error (CAPACITY rows included) */
+#define FBPQ_SERVER_STAT_TIMEOUT 3     /* ... completed with FBPQ_E_TIMEOUT */
+#define FBPQ_SERVER_STAT_CANCELLED 4   /* ... completed with FBPQ_E_CANCELLED */
+#define FBPQ_SERVER_STAT_REJECTED 5    /* submissions refused with FBPQ_E_CAPACITY */
+#define FBPQ_SERVER_STAT_BATCHES 6     /* batches run */
+#define FBPQ_SERVER_STAT_BATCHED 7     /* requests in them */
+#define FBPQ_SERVER_STAT_PEAK_RESERVED 8 /* largest workspace reserved at once by running batches */
+#define FBPQ_SERVER_STAT_PEAK_BATCH_RESERVED 9 /* largest reservation of one batch */
+#define FBPQ_SERVER_STAT_BUDGET 10     /* ws_budget in effect */
+#define FBPQ_SERVER_STAT_LANE_BUDGET 11 /* a lane's share of it */
+#define FBPQ_SERVER_STAT_PENDING 12    /* requests queued now */
+#define FBPQ_SERVER_NUM_STATS 13
+int fbpq_server_create2(fbpq_index *ix, const fbpq_server_config *cfg, fbpq_server **out);
 int fbpq_server_create(fbpq_index *ix, int32_t max_batch, int32_t nlanes, int32_t k_max, fbpq_server **out);
 int fbpq_server_submit(fbpq_server *s, const float *q, int64_t L, int32_t k, int64_t tag);
+int fbpq_server_cancel(fbpq_server *s, int64_t tag);
 int fbpq_server_poll(fbpq_server *s, int32_t max_n, double wait_s, int64_t *tags, int64_t *ids, float *dists,
                      double *times, int32_t *status, int32_t *n_out);
 int fbpq_server_counts(fbpq_server *s, int64_t *pending, int64_t *batches, int64_t *batched);
+int fbpq_server_stats(fbpq_server *s, int64_t *out, int32_t n);
 const char *fbpq_server_first_error(fbpq_server *s);
 void fbpq_server_destroy(fbpq_server *s);
 

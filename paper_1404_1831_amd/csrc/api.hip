@@ -47,6 +47,7 @@ struct fbpq_index {
     bool tables = false;
     DevIndex dv{};
     hipStream_t stream = nullptr;
+    hipStream_t cur = nullptr;  // stream of the search in progress (workspace growth is ordered on it)
     // owned device allocations
     float *C1 = nullptr, *C2 = nullptr, *R = nullptr;
     float *QL = nullptr, *SL = nullptr;  // local codebooks (HBPQ), or null
@@ -128,20 +129,23 @@ static_assert(W_NSLOTS <= kWsSet, "workspace slots");
         }                                                                                       \
     } while (0)
 
+// Workspace buffers grow with stream-ordered frees and allocations on the
+// stream of the search in progress, so that growing one lane's buffer never
+// waits for the work of other streams (hipFree would synchronize the device).
 int ws_get(fbpq_index *ix, int slot, size_t bytes, void **out)
 {
     DevBuf &b = ix->ws[slot + ix->ws_base];
     if (bytes == 0) bytes = 8;
     if (b.cap < bytes) {
+        hipStream_t st = ix->cur ? ix->cur : ix->stream;
         if (b.p) {
-            HCK(ix, hipStreamSynchronize(ix->stream));
-            HCK(ix, hipFree(b.p));
+            HCK(ix, hipFreeAsync(b.p, st));
             b.p = nullptr;
             b.cap = 0;
         }
         const size_t nb = std::max(bytes, b.cap + b.cap / 2);
         if (ix->ws_base == 0) ++ix->ws_gen;  // a buffer a captured round may use moved
-        hipError_t e = hipMalloc(&b.p, nb);
+        hipError_t e = hipMallocAsync(&b.p, nb, st);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             b.p = nullptr;
@@ -293,7 +297,8 @@ int create_impl(const fbpq_index_desc *d, int device, fbpq_index **out)
     }
     fbpq_index *ix = new fbpq_index();
     ix->device = device;
-    if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&ix->stream) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess ||
+        hipStreamCreateWithFlags(&ix->stream, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
         delete ix;
         return fail(FBPQ_E_DEVICE, "cannot initialise device %d", device);
@@ -735,10 +740,11 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
             std::vector<int32_t> ab((size_t)2 * nslots * max_cells);
             std::vector<int64_t> take((size_t)nslots * max_cells), beg((size_t)nslots * max_cells);
             std::vector<int32_t> li((size_t)nslots * 2 * P);
-            HCK(ix, hipMemcpy(ab.data(), dab, ab.size() * 4, hipMemcpyDeviceToHost));
-            HCK(ix, hipMemcpy(take.data(), dtake, take.size() * 8, hipMemcpyDeviceToHost));
-            HCK(ix, hipMemcpy(beg.data(), dbeg, beg.size() * 8, hipMemcpyDeviceToHost));
-            HCK(ix, hipMemcpy(li.data(), lidx, li.size() * 4, hipMemcpyDeviceToHost));
+            HCK(ix, hipMemcpyAsync(ab.data(), dab, ab.size() * 4, hipMemcpyDeviceToHost, st));
+            HCK(ix, hipMemcpyAsync(take.data(), dtake, take.size() * 8, hipMemcpyDeviceToHost, st));
+            HCK(ix, hipMemcpyAsync(beg.data(), dbeg, beg.size() * 8, hipMemcpyDeviceToHost, st));
+            HCK(ix, hipMemcpyAsync(li.data(), lidx, li.size() * 4, hipMemcpyDeviceToHost, st));
+            HCK(ix, hipStreamSynchronize(st));
             for (int64_t s = 0; s < nslots; ++s) {
                 if (hh[s].status != kStOk) continue;
                 const int64_t q = ql[s];
@@ -761,8 +767,9 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         if (dbg->dists) {
             std::vector<int64_t> pp((size_t)nslots * dbg->dcap);
             std::vector<float> dd((size_t)nslots * dbg->dcap);
-            HCK(ix, hipMemcpy(pp.data(), dpos, pp.size() * 8, hipMemcpyDeviceToHost));
-            HCK(ix, hipMemcpy(dd.data(), ddd, dd.size() * 4, hipMemcpyDeviceToHost));
+            HCK(ix, hipMemcpyAsync(pp.data(), dpos, pp.size() * 8, hipMemcpyDeviceToHost, st));
+            HCK(ix, hipMemcpyAsync(dd.data(), ddd, dd.size() * 4, hipMemcpyDeviceToHost, st));
+            HCK(ix, hipStreamSynchronize(st));
             for (int64_t s = 0; s < nslots; ++s) {
                 if (hh[s].status != kStOk) continue;
                 const int64_t q = ql[s];
@@ -799,6 +806,11 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
                 int32_t k_max, int64_t *d_ids, float *d_d, hipStream_t st, const DebugOut *dbg)
 {
     TRY(check_handle(ix));
+    struct CurStream {
+        fbpq_index *ix;
+        ~CurStream() { ix->cur = nullptr; }
+    } cur_reset{ix};
+    ix->cur = st;
     if (!ix->tables) return fail(FBPQ_E_STATE, "fbpq_build_tables has not been called");
     if (nq < 0) return fail(FBPQ_E_INVALID, "nq < 0");
     if (nq == 0) return FBPQ_OK;
@@ -908,8 +920,9 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     for (int round = 1; nfail > 0; ++round) {
         ix->stat_retried += nfail;
         std::vector<TravHdr> hh(nslots);
-        HCK(ix, hipMemcpy(hh.data(), ix->ws[W_HDR + ix->ws_base].p, sizeof(TravHdr) * nslots,
-                          hipMemcpyDeviceToHost));
+        HCK(ix, hipMemcpyAsync(hh.data(), ix->ws[W_HDR + ix->ws_base].p, sizeof(TravHdr) * nslots,
+                               hipMemcpyDeviceToHost, st));
+        HCK(ix, hipStreamSynchronize(st));
         std::vector<int32_t> retry, terminal;
         bool grow_p = false, grow_c = false;
         int64_t need_cells = 0;  // cells a failed query is known to need (threshold kernel)
@@ -963,7 +976,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
         ix->ws_base = kWsSet;
         void *ql;
         TRY(ws_get(ix, W_QLIST, sizeof(int32_t) * retry.size(), &ql));
-        HCK(ix, hipMemcpy(ql, retry.data(), sizeof(int32_t) * retry.size(), hipMemcpyHostToDevice));
+        HCK(ix, hipMemcpyAsync(ql, retry.data(), sizeof(int32_t) * retry.size(), hipMemcpyHostToDevice, st));
         qlist = (const int32_t *)ql;
         nslots = (int64_t)retry.size();
         cur.swap(retry);
@@ -974,8 +987,9 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
         if (nfail == 0) {
             // every query of this retry round succeeded at P
             std::vector<TravHdr> hl(nslots);
-            HCK(ix, hipMemcpy(hl.data(), ix->ws[W_HDR + ix->ws_base].p, sizeof(TravHdr) * nslots,
-                              hipMemcpyDeviceToHost));
+            HCK(ix, hipMemcpyAsync(hl.data(), ix->ws[W_HDR + ix->ws_base].p, sizeof(TravHdr) * nslots,
+                                   hipMemcpyDeviceToHost, st));
+            HCK(ix, hipStreamSynchronize(st));
             for (int64_t sl = 0; sl < nslots; ++sl) record_hint(cur[sl], P, hl[sl].ncells);
         }
     }
@@ -1001,7 +1015,8 @@ int lane_create(fbpq_index *src, fbpq_index **out)
     fbpq_index *ix = new fbpq_index();
     ix->device = src->device;
     ix->shared = true;
-    if (hipSetDevice(src->device) != hipSuccess || hipStreamCreate(&ix->stream) != hipSuccess) {
+    if (hipSetDevice(src->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&ix->stream, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
         delete ix;
         return fail(FBPQ_E_DEVICE, "cannot create a stream on device %d", src->device);
@@ -1034,6 +1049,24 @@ int lane_create(fbpq_index *src, fbpq_index **out)
 
 int lane_device(const fbpq_index *ix) { return ix->device; }
 int lane_dim(const fbpq_index *ix) { return ix->dv.D; }
+int64_t lane_points(const fbpq_index *ix) { return ix->dv.N; }
+
+int64_t search_ws_estimate(const fbpq_index *ix, int64_t L, int32_t k)
+{
+    const int64_t Leff = std::max<int64_t>(1, std::min(L, ix->dv.N));
+    const int b = 63 - __builtin_clzll((unsigned long long)Leff);
+    const int64_t T = ix->dv.T, M = ix->dv.M, D = ix->dv.D;
+    const int64_t P = std::max<int64_t>(ix->prefix, ix->p_hint[b]);
+    const int64_t cells = std::max<int64_t>(std::max<int64_t>(ix->max_cells, ix->c_hint[b]), 2 * Leff);
+    // first round: keys, prefixes, per-rank arrays, cell lists, LQ, distance
+    // row (a batch's stride is its largest min(L, N): at most 2 Leff within a
+    // budget class), query, results
+    const int64_t per_rank = 2 * P * 12 + 6 * (P + 1) * 4;
+    const int64_t per_cell = 32;
+    const int64_t once = 2 * T * 4 + M * kKc * 4 + D * 4 + (int64_t)k * 12 + 256;
+    const int64_t round = per_rank + per_cell * cells;
+    return once + 8 * Leff + 2 * round;  // the retry round has its own workspace set
+}
 
 }  // namespace fbpq
 

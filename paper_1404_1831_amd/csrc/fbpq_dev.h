@@ -216,5 +216,10 @@ size_t select_dist_lds(int k_max);
 int lane_create(fbpq_index *src, fbpq_index **out);
 int lane_device(const fbpq_index *ix);
 int lane_dim(const fbpq_index *ix);
+int64_t lane_points(const fbpq_index *ix);
+// Workspace bytes one query of budget L and k may need in a search on ix (a
+// fixed part per query plus bytes per candidate and per visited cell, from the
+// buffer sizes of the search pipeline, with room for its retry round).
+int64_t search_ws_estimate(const fbpq_index *ix, int64_t L, int32_t k);
 
 }  // namespace fbpq

@@ -24,6 +24,8 @@ FBPQ_E_OOM = -4
 FBPQ_E_DEVICE = -5
 FBPQ_E_STATE = -6
 FBPQ_E_CAPACITY = -7
+FBPQ_E_TIMEOUT = -8
+FBPQ_E_CANCELLED = -9
 FBPQ_KC = 256
 FBPQ_K_MAX = 1024
 
@@ -31,10 +33,13 @@ EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbp
            "fbpq_search", "fbpq_search_uneven", "fbpq_search_device", "fbpq_debug_visit",
            "fbpq_debug_dists", "fbpq_debug_tables", "fbpq_debug_rank", "fbpq_info",
            "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_stats_read", "fbpq_autotune",
-           "fbpq_free_index", "fbpq_last_error", "fbpq_server_create", "fbpq_server_submit",
-           "fbpq_server_poll", "fbpq_server_counts", "fbpq_server_first_error", "fbpq_server_destroy")
+           "fbpq_free_index", "fbpq_last_error", "fbpq_server_create", "fbpq_server_create2",
+           "fbpq_server_submit", "fbpq_server_cancel", "fbpq_server_poll", "fbpq_server_counts",
+           "fbpq_server_stats", "fbpq_server_first_error", "fbpq_server_destroy")
 STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2",
           "traverse_wide", "scan_wide", "rotate")
+SERVER_STATS = ("submitted", "completed", "failed", "timeout", "cancelled", "rejected", "batches", "batched",
+                "peak_reserved", "peak_batch_reserved", "budget", "lane_budget", "pending")
 STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried", "graph_replays",
          "wide", "wide_bands", "wide_evals", "wide_loads")
 
@@ -58,6 +63,12 @@ class Info(ctypes.Structure):
                 ("Kc", ctypes.c_int32), ("N", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("norm_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("tables_ready", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("nlanes", ctypes.c_int32), ("k_max", ctypes.c_int32),
+                ("D", ctypes.c_int32), ("ws_budget", ctypes.c_int64), ("max_pending", ctypes.c_int64),
+                ("timeout_s", ctypes.c_double), ("fake_ns_per_cand", ctypes.c_double)]
 
 
 def _load():
@@ -85,7 +96,10 @@ def _load():
         "fbpq_autotune": ([P, P, i64, P, P, i32, P, P, P, i32, P], ctypes.c_int),
         "fbpq_free_index": ([P], None),
         "fbpq_server_create": ([P, i32, i32, i32, P], ctypes.c_int),
+        "fbpq_server_create2": ([P, P, P], ctypes.c_int),
         "fbpq_server_submit": ([P, P, i64, i32, i64], ctypes.c_int),
+        "fbpq_server_cancel": ([P, i64], ctypes.c_int),
+        "fbpq_server_stats": ([P, P, i32], ctypes.c_int),
         "fbpq_server_poll": ([P, i32, ctypes.c_double, P, P, P, P, P, P], ctypes.c_int),
         "fbpq_server_counts": ([P, P, P, P], ctypes.c_int),
         "fbpq_server_first_error": ([P], ctypes.c_char_p),
@@ -283,9 +297,36 @@ def fbpq_server_create(h, max_batch: int, nlanes: int, k_max: int) -> ctypes.c_v
     return s
 
 
-def fbpq_server_submit(s, q: np.ndarray, L: int, k: int, tag: int) -> None:
+def fbpq_server_create2(h, max_batch: int, nlanes: int, k_max: int, D: int = 0, ws_budget: int = 0,
+                        max_pending: int = 0, timeout_s: float = 0.0, fake_ns_per_cand: float = 0.0):
+    """Server with admission limits; h None with fake_ns_per_cand > 0: host test backend."""
+    cfg = ServerConfig(int(max_batch), int(nlanes), int(k_max), int(D), int(ws_budget), int(max_pending),
+                       float(timeout_s), float(fake_ns_per_cand))
+    s = ctypes.c_void_p()
+    rc = lib.fbpq_server_create2(h, ctypes.byref(cfg), ctypes.byref(s))
+    if rc != FBPQ_OK:
+        raise FbpqError(rc, "fbpq_server_create2 failed: " + lib.fbpq_last_error().decode())
+    return s
+
+
+def fbpq_server_submit(s, q: np.ndarray, L: int, k: int, tag: int) -> int:
+    """Queues a request; returns FBPQ_OK, or FBPQ_E_CAPACITY when admission refuses it."""
     q = np.ascontiguousarray(q, np.float32)
-    _check(lib.fbpq_server_submit(s, _p(q), int(L), int(k), int(tag)))
+    rc = lib.fbpq_server_submit(s, _p(q), int(L), int(k), int(tag))
+    if rc not in (FBPQ_OK, FBPQ_E_CAPACITY):
+        _check(rc)
+    return rc
+
+
+def fbpq_server_cancel(s, tag: int) -> int:
+    """FBPQ_OK if the queued request was taken out, FBPQ_E_STATE if none is queued under tag."""
+    return lib.fbpq_server_cancel(s, int(tag))
+
+
+def fbpq_server_stats(s) -> dict:
+    out = np.zeros(len(SERVER_STATS), np.int64)
+    _check(lib.fbpq_server_stats(s, _p(out), out.size))
+    return dict(zip(SERVER_STATS, (int(x) for x in out)))
 
 
 def fbpq_server_poll(s, max_n: int, k_max: int, D: int = 0, wait_s: float = 0.0):

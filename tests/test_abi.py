@@ -25,7 +25,7 @@ def fb():
 
 def test_exports_match_header(fb):
     hdr = open(os.path.join(ROOT, "include", "fbpq.h")).read()
-    declared = set(re.findall(r"\b(fbpq_[a-z_]+)\s*\(", hdr))
+    declared = set(re.findall(r"\b(fbpq_[a-z_0-9]+)\s*\(", hdr))
     assert declared == set(fb.EXPORTS)
     for name in declared:
         assert hasattr(fb.lib, name)
