@@ -132,7 +132,8 @@ int fbpq_build_tables(fbpq_index *ix);
  * 1 <= k <= FBPQ_K_MAX; writes host ids [nq][k] and dists [nq][k].
  * nq == 0 is a no-op. Errors: INVALID, STATE, CAPACITY, OOM, DEVICE.
  * CAPACITY (for every search entry point): some queries need more than the
- * traversal supports (4096 ranks of a half list, or 2^26 visited cells);
+ * traversal supports (min(T, prefix_cap) ranks of a half list, at most 16384,
+ * or 2^26 visited cells);
  * their rows hold id -2 and NaN distances, every other row is complete. */
 int fbpq_search(fbpq_index *ix, const float *q, int64_t nq, int64_t L, int32_t k,
                 int64_t *ids, float *dists);
@@ -187,7 +188,11 @@ int fbpq_info(const fbpq_index *ix, fbpq_info_t *out);
 int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int64_t *norm_bytes);
 
 /* Tuning knobs (autotuner and tests). Keys: "prefix" (initial sorted-list
- * length P), "max_cells" (initial per-query visited-cell capacity), "chunk"
+ * length P, 1..16384), "prefix_cap" (longest sorted-list length a retry round
+ * may take, 1..16384, default 16384; a query whose traversal needs more ranks
+ * of a half list than min(T, prefix_cap) ends with its row (-2, NaN) and the
+ * search returns FBPQ_E_CAPACITY, the other rows being complete), "max_cells"
+ * (initial per-query visited-cell capacity), "chunk"
  * (candidates per scan chunk), "items" (0/1: use the cell scan for
  * queries whose visited cells hold many points; 0 sends every query to the
  * two-pass scan), "profile" (0/1: time kernel launches with HIP events,

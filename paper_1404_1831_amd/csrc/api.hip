@@ -76,6 +76,7 @@ struct fbpq_index {
     int64_t prof_n[FBPQ_NUM_STAGES] = {0};
     // options
     int32_t prefix = 128;
+    int32_t prefix_cap = kMaxPrefix;  // longest prefix a retry round may take
     int64_t max_cells = 4096;
     int32_t chunk = 8192;
     bool items = true;
@@ -115,7 +116,7 @@ enum WsSlot {
     W_Q, W_KEYS, W_LKEY, W_LIDX, W_HDR, W_W, W_ROWNE, W_ROWCAND, W_COLNE, W_COLTOT, W_NECS,
     W_NECNT, W_NEBEG, W_NECST, W_CMCELL, W_CMPRE, W_L, W_K, W_QLIST, W_FAIL, W_IDS, W_D,
     W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NESLOT, W_SLOTIJ, W_COUNTER,
-    W_LQ, W_ITEMN, W_PSTAT, W_SELDONE, W_QROT, W_NSLOTS
+    W_LQ, W_ITEMN, W_PSTAT, W_SELDONE, W_QROT, W_PSORT, W_BIG, W_LAYSCR, W_NSLOTS
 };
 constexpr int kWsSet = 40;  // slots per workspace set
 static_assert(W_NSLOTS <= kWsSet, "workspace slots");
@@ -134,8 +135,8 @@ static_assert(W_NSLOTS <= kWsSet, "workspace slots");
 // waits for the work of other streams (hipFree would synchronize the device).
 int ws_get(fbpq_index *ix, int slot, size_t bytes, void **out)
 {
-    DevBuf &b = ix->ws[slot + ix->ws_base];
     if (bytes == 0) bytes = 8;
+    DevBuf &b = ix->ws[slot + ix->ws_base];
     if (b.cap < bytes) {
         hipStream_t st = ix->cur ? ix->cur : ix->stream;
         if (b.p) {
@@ -551,7 +552,10 @@ int first_layer(fbpq_index *ix, const float *d_q, int64_t nslots, const int32_t 
     const bool pwave = prefix_wave_ok(dv, P);
     if (pwave)
         HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_wave(dv, d_q, (const float *)keys, nslots, d_qlist, P, lkey, lidx, (int32_t *)pstat, ix->stats_dev, st); }));
-    HCK(ix, timed(ix, pwave ? FBPQ_STAGE_PREFIX_FB : FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_block(dv, d_q, (const float *)keys, nslots, d_qlist, P, lkey, lidx, pwave ? (const int32_t *)pstat : nullptr, ix->stats_dev, st); }));
+    void *gsort = nullptr;  // long prefixes: the workgroup select sorts in HBM
+    const size_t sort_bytes = prefix_sort_bytes(dv, P);
+    if (sort_bytes) TRY(ws_get(ix, W_PSORT, sort_bytes * 2 * (size_t)nslots, &gsort));
+    HCK(ix, timed(ix, pwave ? FBPQ_STAGE_PREFIX_FB : FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_block(dv, d_q, (const float *)keys, nslots, d_qlist, P, lkey, lidx, pwave ? (const int32_t *)pstat : nullptr, ix->stats_dev, (unsigned char *)gsort, st); }));
     return FBPQ_OK;
 }
 
@@ -617,8 +621,19 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
     const bool pop = P <= kMaxPopPrefix && ix->pop_budget > 0;
     ta.pop_budget = pop ? ix->pop_budget : 0;
     ta.wide_all = pop ? 0 : 1;
+    // prefixes longer than the LDS-resident kernels hold keep their per-rank state in HBM
+    const bool big = P > kMaxFastPrefix;
+    void *bigw = nullptr, *layscr = nullptr;
+    if (big) {
+        TRY(ws_get(ix, W_BIG, sizeof(int32_t) * (size_t)big_trav_ints(P) * nslots, &bigw));
+        TRY(ws_get(ix, W_LAYSCR, layout_rank_bytes(P) * (size_t)nslots, &layscr));
+        ta.big = (int32_t *)bigw;
+    }
     if (pop) HCK(ix, timed(ix, FBPQ_STAGE_TRAVERSE, st, [&] { return launch_traverse(ta, nslots, st); }));
-    HCK(ix, timed(ix, FBPQ_STAGE_TRAVERSE_WIDE, st, [&] { return launch_traverse_wide(ta, nslots, st); }));
+    if (big)
+        HCK(ix, timed(ix, FBPQ_STAGE_TRAVERSE_WIDE, st, [&] { return launch_traverse_big(ta, nslots, st); }));
+    else
+        HCK(ix, timed(ix, FBPQ_STAGE_TRAVERSE_WIDE, st, [&] { return launch_traverse_wide(ta, nslots, st); }));
     if (!(dbg && dbg->visit)) {
         LayoutArgs la{};
         la.ix = dv;
@@ -641,6 +656,7 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         la.ne_slot = (int32_t *)neslot;
         la.slot_ij = (int32_t *)slotij;
         la.allow_items = ix->items ? 1 : 0;
+        la.gscr = (unsigned char *)layscr;
         HCK(ix, timed(ix, FBPQ_STAGE_LAYOUT, st, [&] { return launch_layout(la, nslots, st); }));
         HCK(ix, timed(ix, FBPQ_STAGE_LAYOUT, st, [&] { return launch_layout_wide(la, nslots, st); }));
         // query tables and per-candidate distance rows: the cell scan and the
@@ -740,6 +756,8 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
             std::vector<int32_t> ab((size_t)2 * nslots * max_cells);
             std::vector<int64_t> take((size_t)nslots * max_cells), beg((size_t)nslots * max_cells);
             std::vector<int32_t> li((size_t)nslots * 2 * P);
+            std::vector<double> lk(P > kMaxFastPrefix ? (size_t)nslots * 2 * P : 0);
+            if (!lk.empty()) HCK(ix, hipMemcpyAsync(lk.data(), lkey, lk.size() * 8, hipMemcpyDeviceToHost, st));
             HCK(ix, hipMemcpyAsync(ab.data(), dab, ab.size() * 4, hipMemcpyDeviceToHost, st));
             HCK(ix, hipMemcpyAsync(take.data(), dtake, take.size() * 8, hipMemcpyDeviceToHost, st));
             HCK(ix, hipMemcpyAsync(beg.data(), dbeg, beg.size() * 8, hipMemcpyDeviceToHost, st));
@@ -751,9 +769,24 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
                 const int64_t nc = hh[s].ncells;
                 if (nc > dbg->cells_cap || hh[s].ncand > dbg->pos_cap)
                     return fail(FBPQ_E_CAPACITY, "debug buffers too small for query %lld", (long long)q);
+                // the long-prefix traversal lists its cells row-major: order them
+                // by (key, a, b), the traversal order
+                std::vector<int64_t> order((size_t)nc);
+                for (int64_t c = 0; c < nc; ++c) order[c] = c;
+                if (!lk.empty()) {
+                    const double *k1 = lk.data() + (size_t)s * 2 * P, *k2 = k1 + P;
+                    const int32_t *abs = ab.data() + (size_t)2 * s * max_cells;
+                    std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+                        const int32_t ax = abs[2 * x], bx = abs[2 * x + 1], ay = abs[2 * y], by = abs[2 * y + 1];
+                        const double kx = k1[ax] + k2[bx], ky = k1[ay] + k2[by];
+                        if (kx != ky) return kx < ky;
+                        return ax != ay ? ax < ay : bx < by;
+                    });
+                }
                 int64_t np = 0;
-                for (int64_t c = 0; c < nc; ++c) {
-                    const size_t o = (size_t)s * max_cells + c;
+                for (int64_t ci = 0; ci < nc; ++ci) {
+                    const int64_t c = ci;
+                    const size_t o = (size_t)s * max_cells + order[ci];
                     const int32_t a = ab[2 * o], b = ab[2 * o + 1];
                     const int64_t cell = (int64_t)li[(size_t)s * 2 * P + a] * dv.T + li[(size_t)s * 2 * P + P + b];
                     dbg->cells[(q * dbg->cells_cap + c) * 2] = cell;
@@ -894,7 +927,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     // capacity is searched again with 4x the ranks or 8x the cells; one that
     // already had the most the traversal supports is a terminal failure: its
     // result row is filled with (-2, NaN) and the others complete.
-    const int32_t Pcap = std::min<int32_t>(T, kMaxPrefix);
+    const int32_t Pcap = std::min<int32_t>(std::min<int32_t>(T, kMaxPrefix), std::max<int32_t>(P, ix->prefix_cap));
     const int64_t ccap = ((int64_t)1 << 31) / 32;
     std::vector<int32_t> cur;  // query of each slot of the last round (empty: slot = query)
     int64_t nterminal = 0;
@@ -1307,6 +1340,9 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
     if (!strcmp(key, "prefix")) {
         if (value < 1 || value > kMaxPrefix) return fail(FBPQ_E_INVALID, "prefix out of [1, %d]", kMaxPrefix);
         ix->prefix = (int32_t)value;
+    } else if (!strcmp(key, "prefix_cap")) {
+        if (value < 1 || value > kMaxPrefix) return fail(FBPQ_E_INVALID, "prefix_cap out of [1, %d]", kMaxPrefix);
+        ix->prefix_cap = (int32_t)value;
     } else if (!strcmp(key, "max_cells")) {
         if (value < 64 || value > ((int64_t)1 << 26)) return fail(FBPQ_E_INVALID, "max_cells out of range");
         ix->max_cells = value;

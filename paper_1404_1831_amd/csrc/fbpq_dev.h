@@ -10,7 +10,9 @@ namespace fbpq {
 
 constexpr int kWave = 64;
 constexpr int kKc = 256;
-constexpr int kMaxPrefix = 4096;  // longest sorted half list the traversal tracks
+constexpr int kMaxPrefix = 16384;     // longest sorted half list the traversal tracks (row and column LUT slots,
+                                      // fewer than 2 * kMaxPrefix, pack into the 16-bit halves of an int32)
+constexpr int kMaxFastPrefix = 4096;  // longest one the LDS-resident traversal and layouts hold
 constexpr int kMaxPopPrefix = 2048;  // longest one the one-cell-at-a-time traversal holds
 constexpr int kMaxK = 1024;
 
@@ -94,7 +96,11 @@ hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *k
                               int32_t *pstat, unsigned long long *stats, hipStream_t st);
 hipError_t launch_prefix_block(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
                                const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
-                               const int32_t *pstat, unsigned long long *stats, hipStream_t st);
+                               const int32_t *pstat, unsigned long long *stats, unsigned char *gsort,
+                               hipStream_t st);
+// Bytes per (slot, half) of the HBM sort buffer gsort that the workgroup
+// select needs at prefix length P (0: its sort buffer fits in LDS).
+size_t prefix_sort_bytes(const DevIndex &ix, int32_t P);
 
 struct TravArgs {
     DevIndex ix;
@@ -114,10 +120,15 @@ struct TravArgs {
     int32_t pop_budget;    // pops before a query is left to the threshold kernel (0: none)
     int32_t wide_all;      // threshold kernel: take every slot, not only deferred ones
     unsigned long long *stats;  // optional path counters
+    int32_t *big;          // long prefixes: [slot][big_trav_ints(P)] per-row state in HBM
 };
 hipError_t launch_traverse(const TravArgs &a, int64_t nslots, hipStream_t st);
 hipError_t launch_traverse_wide(const TravArgs &a, int64_t nslots, hipStream_t st);
 size_t wide_lds_bytes(int P);
+// Traversal for prefixes longer than kMaxFastPrefix: the same visited cells
+// and cut, with its per-row state in HBM (args.big).
+hipError_t launch_traverse_big(const TravArgs &a, int64_t nslots, hipStream_t st);
+__host__ __device__ inline int64_t big_trav_ints(int P) { return 4 * (int64_t)P + 4; }
 
 struct LayoutArgs {
     DevIndex ix;
@@ -140,7 +151,14 @@ struct LayoutArgs {
     int32_t *ne_slot;      // [slot][max_cells] LUT slots of the cell: row slot | (col slot << 16)
     int32_t *slot_ij;      // [slot][2P] centroid of each LUT slot: rows, then columns
     int32_t allow_items;   // 0: every query goes to the two-pass scan
+    unsigned char *gscr;   // long prefixes: [slot][layout_rank_bytes(P)] per-rank arrays in HBM, else null (LDS)
 };
+// Bytes of the layouts' per-rank arrays (column cursors, row and column
+// starts, LUT slots) at prefix length P, rounded to 16.
+__host__ __device__ inline size_t layout_rank_bytes(int P)
+{
+    return (((size_t)P * 8 + (size_t)3 * (P + 1) * 4 + (size_t)2 * P * 4) + 15) & ~(size_t)15;
+}
 hipError_t launch_layout(const LayoutArgs &a, int64_t nslots, hipStream_t st);
 hipError_t launch_layout_wide(const LayoutArgs &a, int64_t nslots, hipStream_t st);
 constexpr int64_t kLayoutWaveMax = 4096;  // visited cells above which the workgroup layout runs

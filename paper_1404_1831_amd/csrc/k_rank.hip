@@ -468,7 +468,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     const float *__restrict__ kapprox, const float *__restrict__ Q, int D,
     const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, int T,
     const int32_t *qlist, int P, int S, int stage_ka, double *__restrict__ lkey, int32_t *__restrict__ lidx,
-    const int32_t *__restrict__ pstat, unsigned long long *stats)
+    const int32_t *__restrict__ pstat, unsigned long long *stats, unsigned char *__restrict__ gsort)
 {
     if (pstat && pstat[(int64_t)blockIdx.x * 2 + blockIdx.y] == 0) return;  // done by the wave select
     if (stats && threadIdx.x == 0) atomicAdd(&stats[kStatPrefixWG], 1ull);
@@ -491,7 +491,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     float *qh = reinterpret_cast<float *>(smem);
     const int hpad = (h + 3) & ~3;
     float *kal = qh + hpad;
-    uint64_t *sk = reinterpret_cast<uint64_t *>(kal + (lds_ka ? ((T + 1) & ~1) : 0));
+    // sort buffer: in LDS, or (long prefixes) in this pair's slice of gsort
+    uint64_t *sk = gsort ? reinterpret_cast<uint64_t *>(gsort + ((int64_t)slot * 2 + half) * (int64_t)S * 12)
+                         : reinterpret_cast<uint64_t *>(kal + (lds_ka ? ((T + 1) & ~1) : 0));
     int32_t *si = reinterpret_cast<int32_t *>(sk + S);
     const float *kg = have_ka ? kapprox + ((int64_t)slot * 2 + half) * (int64_t)T : nullptr;
 
@@ -1035,12 +1037,22 @@ int select_sort_size(int P, int T)
     return S < 64 ? 64 : S;
 }
 
-// Dynamic LDS of the workgroup select, with or without the staged key row.
-size_t select_lds_bytes(int D, int T, int S, bool stage_ka)
+// Dynamic LDS of the workgroup select, with or without the staged key row
+// and with or without the sort buffer.
+size_t select_lds_bytes(int D, int T, int S, bool stage_ka, bool sort_in_lds = true)
 {
     const int h = D / 2;
     const size_t f = (size_t)((h + 3) & ~3) + (stage_ka ? (size_t)((T + 1) & ~1) : 0);
-    return f * 4 + (size_t)S * (sizeof(uint64_t) + sizeof(int32_t));
+    return f * 4 + (sort_in_lds ? (size_t)S * (sizeof(uint64_t) + sizeof(int32_t)) : 0);
+}
+
+constexpr size_t kSelLdsMax = 144 * 1024;  // static LDS of the kernel is about 6 KB of the 160 KB
+
+size_t prefix_sort_bytes(const DevIndex &ix, int32_t P)
+{
+    const int S = select_sort_size(P, ix.T);
+    if (select_lds_bytes(ix.D, ix.T, S, false) <= kSelLdsMax) return 0;
+    return (size_t)S * (sizeof(uint64_t) + sizeof(int32_t));
 }
 
 bool prefix_wave_ok(const DevIndex &ix, int32_t P) { return ix.T >= 256 && P <= 256 && P < ix.T; }
@@ -1066,18 +1078,20 @@ hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *k
 
 hipError_t launch_prefix_block(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
                                const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
-                               const int32_t *pstat, unsigned long long *stats, hipStream_t st)
+                               const int32_t *pstat, unsigned long long *stats, unsigned char *gsort,
+                               hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
     const int S = select_sort_size(P, ix.T);
-    // stage the key row in LDS when it and the sort buffer fit (static LDS of
-    // the kernel is about 6 KB; the device offers 160 KB per workgroup)
-    const bool stage = ka && ix.T <= kApproxLds && select_lds_bytes(ix.D, ix.T, S, true) <= 144 * 1024;
-    const size_t lds = select_lds_bytes(ix.D, ix.T, S, stage);
-    if (lds > 144 * 1024) return hipErrorInvalidValue;
+    const bool glob = prefix_sort_bytes(ix, P) > 0;  // sort buffer in HBM (long prefixes)
+    if (glob && !gsort) return hipErrorInvalidValue;
+    // stage the key row in LDS when it and the sort buffer fit
+    const bool stage = ka && ix.T <= kApproxLds && select_lds_bytes(ix.D, ix.T, S, true, !glob) <= kSelLdsMax;
+    const size_t lds = select_lds_bytes(ix.D, ix.T, S, stage, !glob);
+    if (lds > kSelLdsMax) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_select_prefix, dim3((unsigned)nslots, 2), dim3(kSelThreads), lds, st, ka,
                        q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist, P, S, stage ? 1 : 0, lkey, lidx,
-                       pstat, stats);
+                       pstat, stats, glob ? gsort : nullptr);
     return hipGetLastError();
 }
 

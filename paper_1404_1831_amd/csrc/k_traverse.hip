@@ -290,8 +290,10 @@ hipError_t launch_traverse(const TravArgs &a, int64_t nslots, hipStream_t st)
 // order) with a running candidate prefix inside the column.
 __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(16) unsigned char lds[];
     const int P = args.P;
+    // per-rank arrays in LDS, or (long prefixes) in this slot's slice of HBM
+    unsigned char *smem = args.gscr ? args.gscr + (size_t)blockIdx.x * layout_rank_bytes(P) : lds;
     unsigned long long *colcur = reinterpret_cast<unsigned long long *>(smem);  // [P] cells | candidates
     int *rc = reinterpret_cast<int *>(colcur + P);      // [P + 1] first diagram cell of each row
     int *rowcnt = rc + (P + 1);                         // [P + 1] nonempty cells per row
@@ -489,7 +491,8 @@ __global__ __launch_bounds__(64) void k_layout(LayoutArgs args)
 hipError_t launch_layout(const LayoutArgs &a, int64_t nslots, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
-    const size_t lds = (size_t)a.P * 8 + (size_t)3 * (a.P + 1) * 4 + (size_t)2 * a.P * 4;
+    const size_t lds = a.gscr ? 0 : layout_rank_bytes(a.P);
+    if (lds > 144 * 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_layout, dim3((unsigned)nslots), dim3(64), lds, st, a);
     return hipGetLastError();
 }

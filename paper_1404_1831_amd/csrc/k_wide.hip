@@ -690,6 +690,326 @@ hipError_t launch_traverse_wide(const TravArgs &a, int64_t nslots, hipStream_t s
     return hipGetLastError();
 }
 
+// ---- traversal for long prefixes (P > kMaxFastPrefix) -----------------------
+// The same visited cells, order and cut as the kernels above, for prefixes
+// whose per-rank arrays do not fit in LDS. Per-row state lives in this slot's
+// slice of HBM (args.big): wlo, the row widths of the cells with key <= lo
+// (the visited part so far); whi, the widths at hi; wm, the widths at a probe
+// threshold t; pre, the exclusive prefix over rows of a band's lengths.
+//
+// Invariants: the cells with key <= lo hold C_lo < min(L, N) points; once
+// hi_ok is set, the cells with key <= hi hold at least min(L, N). A step takes
+// a threshold t in (lo, hi]: before hi_ok the largest whose band (lo, t] has at
+// most kBigBand cells (searched on cell counts, which need no loads), after it
+// the midpoint of (lo, hi) in the order of doubles. The band's point counts
+// are loaded and summed: below the target the band is accepted (lo = t),
+// otherwise hi = t. When t is the next double after lo, every cell of the band
+// has key t and the band is walked in (a, b) order, chunk by chunk, up to the
+// cell that completes min(L, N). Each step after hi_ok halves the range of
+// doubles, so at most 64 follow.
+constexpr int kBigNT = 1024;
+constexpr int64_t kBigBand = 1 << 16;  // cells of a band searched by threshold
+constexpr int kBigPos = 4;             // band positions per thread per step
+
+// first b in [lo, hi) with k1a + k2[b] > t, hi if none
+__device__ __forceinline__ int width_at(double t, double k1a, const double *k2, int lo, int hi)
+{
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (k1a + k2[mid] <= t) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// largest a in [0, P) with pre[a] <= x (x < pre[P])
+__device__ __forceinline__ int row_of(const int32_t *pre, int P, int64_t x)
+{
+    int lo = 0, hi = P - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_traverse_big(TravArgs args)
+{
+    __shared__ int64_t red[NT / 64];
+    __shared__ int64_t s_take;
+    const int P = args.P;
+    const int slot = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (!args.wide_all && args.hdr[slot].status != kStDefer) return;
+    int32_t *wlo = args.big + (int64_t)slot * big_trav_ints(P);
+    int32_t *whi = wlo + P;
+    int32_t *wm = whi + P;
+    int32_t *pre = wm + P;  // [P + 1]
+
+    const int64_t qs = args.qlist ? args.qlist[slot] : slot;
+    const int T = args.ix.T;
+    const double *k1 = args.lkey + (int64_t)slot * 2 * P;
+    const double *k2 = k1 + P;
+    const int32_t *u = args.lidx + (int64_t)slot * 2 * P;
+    const int32_t *v = u + P;
+    const int64_t *off = args.ix.offsets;
+    if (args.stats && tid == 0) atomicAdd(&args.stats[kStatWide], 1ull);
+
+    const int64_t L = args.L[qs];
+    const int64_t Leff = L < args.ix.N ? L : args.ix.N;
+    const double INF = __builtin_huge_val();
+    const double DMAX = 1.7976931348623157e308;
+    // every visited cell has key <= tmax (as in the kernels above)
+    double tmax;
+    if (P >= T) {
+        tmax = k1[P - 1] + k2[P - 1];
+    } else {
+        const double kb = fmin(k1[P - 1] + k2[0], k1[0] + k2[P - 1]);
+        tmax = dunord(dord(kb) - 1);
+    }
+    if (!(tmax < INF)) tmax = DMAX;
+    for (int a = tid; a < P; a += NT) {
+        wlo[a] = 0;
+        whi[a] = width_at(tmax, k1[a], k2, 0, P);
+    }
+    __syncthreads();
+
+    double lo = dunord(dord(k1[0] + k2[0]) - 1);  // below every key: nothing visited
+    double hi = tmax;
+    bool hi_ok = false;
+    int64_t C_lo = 0;
+    int status = kStOk;
+    int cut_a = -1, cut_b = -1;
+    int64_t cut_take = 0;
+    bool found = Leff <= 0;
+    int64_t n_bands = 0, n_evals = 1, n_loads = 0;
+    const int RP = (P + NT - 1) / NT;  // rows per thread in the prefix over rows
+
+    // band lengths wm - wlo: their exclusive prefix over rows into pre, returns the total
+    auto band_prefix = [&]() -> int64_t {
+        const int a0 = tid * RP, a1 = a0 + RP < P ? a0 + RP : P;
+        int64_t s = 0;
+        for (int a = a0; a < a1; ++a) s += wm[a] - wlo[a];
+        int64_t tot;
+        int64_t run = wg_scan<NT>(s, red, &tot);
+        for (int a = a0; a < a1; ++a) {
+            pre[a] = (int32_t)run;
+            run += wm[a] - wlo[a];
+        }
+        if (tid == 0) pre[P] = (int32_t)tot;
+        __syncthreads();
+        return tot;
+    };
+    // widths at t into wm (rows searched between wlo and whi); returns the band's cell count
+    auto widths = [&](double t) -> int64_t {
+        int64_t s = 0;
+        for (int a = tid; a < P; a += NT) {
+            const int w = width_at(t, k1[a], k2, wlo[a], whi[a]);
+            wm[a] = w;
+            s += w - wlo[a];
+        }
+        ++n_evals;
+        return wg_sum<NT>(s, red);
+    };
+    auto count_at = [&](int64_t x) -> int64_t {
+        const int a = row_of(pre, P, x);
+        const int b = wlo[a] + (int)(x - pre[a]);
+        const int64_t c = (int64_t)u[a] * T + v[b];
+        return off[c + 1] - off[c];
+    };
+
+    while (!found && status == kStOk) {
+        const uint64_t ol = dord(lo), oh = dord(hi);
+        double t;
+        int64_t nb;
+        ++n_bands;
+        if (hi_ok) {
+            if (oh - ol <= 1) {
+                t = hi;
+                for (int a = tid; a < P; a += NT) wm[a] = whi[a];
+                __syncthreads();
+                nb = -1;
+            } else {
+                t = dunord(ol + (oh - ol) / 2);
+                nb = widths(t);
+            }
+        } else {
+            for (int a = tid; a < P; a += NT) wm[a] = whi[a];
+            int64_t s = 0;
+            for (int a = tid; a < P; a += NT) s += whi[a] - wlo[a];
+            nb = wg_sum<NT>(s, red);
+            t = hi;
+            if (nb > kBigBand) {
+                // the largest t with a band of at most kBigBand cells, bisecting the doubles
+                uint64_t tl = ol, th = oh;
+                int64_t nl = 0;
+                while (th - tl > 1) {
+                    const uint64_t tm = tl + (th - tl) / 2;
+                    const int64_t nm = widths(dunord(tm));
+                    if (nm <= kBigBand) {
+                        tl = tm;
+                        nl = nm;
+                        if (nm >= kBigBand / 4) break;
+                    } else {
+                        th = tm;
+                    }
+                }
+                if (tl > ol) {
+                    t = dunord(tl);
+                    if (nl >= 0) nb = widths(t);
+                } else {
+                    t = dunord(th);  // the next double: one key, more than kBigBand cells
+                    nb = widths(t);
+                }
+            }
+        }
+        const bool tie = dord(t) - ol <= 1;
+        nb = band_prefix();
+        n_loads += nb;
+        if (tie) {
+            // one key value: walk the band in (a, b) order up to the cell that completes min(L, N)
+            int64_t run = C_lo;
+            for (int64_t x0 = 0; x0 < nb && !found; x0 += (int64_t)NT * kBigPos) {
+                int64_t c[kBigPos];
+                int64_t s = 0;
+#pragma unroll
+                for (int e = 0; e < kBigPos; ++e) {
+                    const int64_t x = x0 + (int64_t)tid * kBigPos + e;
+                    c[e] = x < nb ? count_at(x) : 0;
+                    s += c[e];
+                }
+                int64_t tot;
+                const int64_t ex = wg_scan<NT>(s, red, &tot);
+                int64_t r = run + ex, xmine = INT64_MAX, take = 0;
+#pragma unroll
+                for (int e = 0; e < kBigPos; ++e) {
+                    const int64_t x = x0 + (int64_t)tid * kBigPos + e;
+                    if (xmine == INT64_MAX && x < nb && r + c[e] >= Leff) {
+                        xmine = x;
+                        take = Leff - r;
+                    }
+                    r += c[e];
+                }
+                const int64_t xcut = wg_min<NT>(xmine, red);
+                if (xcut != INT64_MAX) {
+                    if (xmine == xcut) s_take = take;
+                    __syncthreads();
+                    cut_a = row_of(pre, P, xcut);
+                    cut_b = wlo[cut_a] + (int)(xcut - pre[cut_a]);
+                    cut_take = s_take;
+                    found = true;
+                } else {
+                    run += tot;
+                }
+            }
+            if (found) {
+                // rows before the cut row take their whole band, the cut row up to the cut
+                for (int a = tid; a < P; a += NT) {
+                    if (a < cut_a) wlo[a] = wm[a];
+                    else if (a == cut_a) wlo[a] = cut_b + 1;
+                }
+                __syncthreads();
+                C_lo = Leff;
+            } else {
+                C_lo = run;
+                lo = t;
+                for (int a = tid; a < P; a += NT) wlo[a] = wm[a];
+                __syncthreads();
+                if (t == hi) status = kStNeedPrefix;  // every cell up to tmax taken, min(L, N) not reached
+            }
+            continue;
+        }
+        // sum the band's points
+        int64_t s = 0;
+        for (int64_t x = tid; x < nb; x += NT) s += count_at(x);
+        const int64_t S = wg_sum<NT>(s, red);
+        if (C_lo + S < Leff) {
+            C_lo += S;
+            lo = t;
+            for (int a = tid; a < P; a += NT) wlo[a] = wm[a];
+            __syncthreads();
+            if (t == hi) status = kStNeedPrefix;
+        } else {
+            hi = t;
+            hi_ok = true;
+            for (int a = tid; a < P; a += NT) whi[a] = wm[a];
+            __syncthreads();
+        }
+    }
+
+    // outputs: final widths (wlo), as the kernels above write them
+    int64_t myc = 0;
+    int myA = 0;
+    for (int a = tid; a < P; a += NT) {
+        const int w = wlo[a];
+        args.w[(int64_t)slot * P + a] = w;
+        myc += w;
+        myA += w > 0;
+    }
+    const int64_t nc = wg_sum<NT>(myc, red);
+    const int64_t A = wg_sum<NT>(myA, red);
+    if (status == kStOk && Leff > 0 && nc > args.max_cells) status = kStNeedCells;
+    if (args.dbg_ab && status == kStOk && Leff > 0) {
+        // visited cells in row-major order (the host orders them by (key, a, b))
+        for (int a = tid; a < P; a += NT) pre[a] = wlo[a];
+        __syncthreads();
+        const int a0 = tid * RP, a1 = a0 + RP < P ? a0 + RP : P;
+        int64_t s2 = 0;
+        for (int a = a0; a < a1; ++a) s2 += pre[a];
+        int64_t tot;
+        int64_t o = wg_scan<NT>(s2, red, &tot);
+        for (int a = a0; a < a1; ++a) {
+            for (int b = 0; b < pre[a]; ++b, ++o) {
+                const int64_t cell = (int64_t)u[a] * T + v[b];
+                const int64_t so = (int64_t)slot * args.max_cells + o;
+                args.dbg_ab[2 * so] = a;
+                args.dbg_ab[2 * so + 1] = b;
+                args.dbg_take[so] = (a == cut_a && b == cut_b) ? cut_take : off[cell + 1] - off[cell];
+                args.dbg_beg[so] = off[cell];
+            }
+        }
+    }
+    if (tid == 0) {
+        TravHdr h;
+        h.status = status;
+        h.A = (int32_t)A;
+        h.B = args.w[(int64_t)slot * P];
+        h.cut_a = cut_a;
+        h.cut_b = cut_b;
+        h.nne = 0;
+        h.a_ne = 0;
+        h.b_ne = 0;
+        h.n_items = 0;
+        h.gscan = 0;
+        h.ncells = nc;
+        h.ncand = status == kStOk ? Leff : C_lo;
+        h.cut_take = cut_take;
+        if (Leff <= 0) {
+            h.A = 0;
+            h.B = 0;
+            h.ncells = 0;
+            h.ncand = 0;
+        }
+        args.hdr[slot] = h;
+        if (status != kStOk) args.fail_list[atomicAdd(args.fail_count, 1)] = (int32_t)qs;
+        if (args.stats) {
+            atomicAdd(&args.stats[kStatWideBands], (unsigned long long)n_bands);
+            atomicAdd(&args.stats[kStatWideEvals], (unsigned long long)n_evals);
+            atomicAdd(&args.stats[kStatWideLoads], (unsigned long long)n_loads);
+        }
+    }
+}
+
+hipError_t launch_traverse_big(const TravArgs &a, int64_t nslots, hipStream_t st)
+{
+    if (nslots == 0) return hipSuccess;
+    if (!a.big || a.P > kMaxPrefix) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_traverse_big<kBigNT>, dim3((unsigned)nslots), dim3(kBigNT), 0, st, a);
+    return hipGetLastError();
+}
+
 // ---- workgroup form of the row-major layout, for large visited sets ---------
 // Same outputs as the one-wavefront layout kernel (compacted nonempty cells in
 // row-major order, per-row and per-column starts, column lists, LUT slots),
@@ -720,9 +1040,11 @@ __device__ __forceinline__ int64_t wg_scan_array(int *x, int n, int64_t *red)
 __global__ __launch_bounds__(kLayNT) void k_layout_wide(LayoutArgs args)
 {
     constexpr int NT = kLayNT, E = kLayE;
-    extern __shared__ __align__(16) unsigned char smem[];
+    extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int64_t red[NT / 64];
     const int P = args.P;
+    // per-rank arrays in LDS, or (long prefixes) in this slot's slice of HBM
+    unsigned char *smem = args.gscr ? args.gscr + (size_t)blockIdx.x * layout_rank_bytes(P) : lds;
     unsigned long long *colcur = reinterpret_cast<unsigned long long *>(smem);  // [P] cells | candidates
     int *rc = reinterpret_cast<int *>(colcur + P);      // [P + 1] first diagram cell of each row
     int *rowcnt = rc + (P + 1);                         // [P + 1] nonempty cells per row, then starts
@@ -897,7 +1219,8 @@ __global__ __launch_bounds__(kLayNT) void k_layout_wide(LayoutArgs args)
 hipError_t launch_layout_wide(const LayoutArgs &a, int64_t nslots, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
-    const size_t lds = (size_t)a.P * 8 + (size_t)3 * (a.P + 1) * 4 + (size_t)2 * a.P * 4;
+    const size_t lds = a.gscr ? 0 : layout_rank_bytes(a.P);
+    if (lds > 144 * 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_layout_wide, dim3((unsigned)nslots), dim3(kLayNT), lds, st, a);
     return hipGetLastError();
 }

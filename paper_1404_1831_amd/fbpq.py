@@ -221,6 +221,17 @@ def fbpq_search(h, q: np.ndarray, L: int, k: int):
     return ids, d
 
 
+def fbpq_search_rc(h, q: np.ndarray, L: int, k: int):
+    """fbpq_search returning (code, ids, dists) instead of raising: with
+    FBPQ_E_CAPACITY the rows it could not serve hold (-2, NaN), the others are complete."""
+    q = np.ascontiguousarray(q, np.float32)
+    nq = q.shape[0]
+    ids = np.empty((nq, k), np.int64)
+    d = np.empty((nq, k), np.float32)
+    rc = lib.fbpq_search(h, _p(q), nq, int(L), int(k), _p(ids), _p(d))
+    return rc, ids, d
+
+
 def fbpq_search_uneven(h, q: np.ndarray, L, k, k_max: int):
     q = np.ascontiguousarray(q, np.float32)
     nq = q.shape[0]

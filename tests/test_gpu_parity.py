@@ -100,7 +100,7 @@ def _check_visit(fb, h, ix, Q, L, cap=1 << 16):
     cap = min(ix.T * ix.T + 1, cap)
     got = fb.fbpq_debug_visit(h, Q, L, cells_cap=cap, pos_cap=max(1, min(L, ix.N)))
     for r in range(Q.shape[0]):
-        cells, pos = oracle.visit(ix, Q[r], L)
+        cells, pos = oracle.visit(ix, Q[r], L, cells_cap=max(cap, 1 << 20))
         gc, gp = got[r]
         assert np.array_equal(gc, cells), (r, L, gc.shape, cells.shape)
         assert np.array_equal(gp, pos), (r, L)
@@ -908,3 +908,89 @@ def test_server_continuous_batching(fb, gmm_small, rot):
     g_d = np.stack([got[i][1] for i in range(nreq)])
     o_ids, o_d, _, _ = oracle.search(ix, Q, L, k, kmax=kmax)
     assert_topk(ix, oracle.rotate(ix.Rot, Q) if rot else Q, k, g_ids, g_d, o_ids, o_d)
+
+
+@pytest.fixture(scope="module")
+def sparse_t8192():
+    """3000 points in random cells of a T = 8192 multi-index (6.7e7 cells): a
+    query with L = 50 visits about 1.3e6 cells, and most of them need more than
+    4096 ranks of one half list (prefixes beyond what the LDS-resident
+    traversal and layouts hold)."""
+    ix = synth.random_index(N=3000, T=8192, M=4, D=16, seed=21)
+    rng = np.random.default_rng(5)
+    Q = (rng.random((8, 16)) * 100).astype(np.float32)
+    return ix, Q
+
+
+def _cut_needs_ranks(ix, q, L, P):
+    """True when the oracle's traversal of q needs cells outside the P x P
+    window of the sorted half lists: its last visited cell's key reaches the
+    smallest key outside the window."""
+    cells, _ = oracle.visit(ix, q, L, cells_cap=1 << 22)
+    d1, d2, u, v = oracle.rank_lists(ix, q)
+    last = int(cells[-1, 0])
+    cut_key = d1[last // ix.T] + d2[last % ix.T]
+    kb = min(d1[u[P - 1]] + d2[v[0]], d1[u[0]] + d2[v[P - 1]])
+    return cut_key >= kb
+
+
+def test_long_prefix_beyond_lds_visit_and_topk(fb, sparse_t8192):
+    ix, Q = sparse_t8192
+    L, k = 50, 10
+    log(f"long prefix in HBM: N=3000 T=8192 M=4 L={L} (retry rounds up to P=8192)")
+    need = [_cut_needs_ranks(ix, Q[r], L, 4096) for r in range(Q.shape[0])]
+    log(f"  queries needing more than 4096 ranks: {sum(need)} of {len(need)}")
+    assert sum(need) >= 2
+    h = _open(fb, ix, stats=1)
+    _check_visit(fb, h, ix, Q[:4], L, cap=1 << 22)
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    st = fb.fbpq_stats_read(h)
+    log(f"  counters {st}")
+    fb.fbpq_free_index(h)
+    assert st["retried"] > 0
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
+@pytest.mark.parametrize("L", [1, 20, 200])
+def test_full_prefix_in_hbm(fb, sparse_t8192, L):
+    # P = T = 8192 from the first round: the complete sorted lists, every query
+    # traversed by the long-prefix kernel
+    ix, Q = sparse_t8192
+    k = 10
+    log(f"full prefix in HBM: N=3000 T=8192 P=8192 L={L}")
+    h = _open(fb, ix, prefix=8192, stats=1)
+    keys, idx = fb.fbpq_debug_rank(h, Q[:2], 8192)
+    for r in range(2):
+        d1, d2, u, v = oracle.rank_lists(ix, Q[r])
+        assert np.array_equal(idx[r, 0], u) and np.array_equal(idx[r, 1], v), r
+        assert np.array_equal(keys[r, 0], d1[u]) and np.array_equal(keys[r, 1], d2[v]), r
+    if L <= 50:
+        _check_visit(fb, h, ix, Q[:2], L, cap=1 << 22)
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    st = fb.fbpq_stats_read(h)
+    fb.fbpq_free_index(h)
+    assert st["wide"] >= Q.shape[0]
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
+def test_capacity_rows_contract(fb, sparse_t8192):
+    """With the prefix capped at 4096 ranks, exactly the queries whose
+    traversal needs a longer prefix end with (-2, NaN) and the search returns
+    FBPQ_E_CAPACITY; every other row equals the oracle's."""
+    ix, Q = sparse_t8192
+    L, k, cap = 50, 10, 4096
+    need = np.array([_cut_needs_ranks(ix, Q[r], L, cap) for r in range(Q.shape[0])])
+    log(f"capacity contract: T=8192 prefix_cap={cap}, {int(need.sum())} of {need.size} queries over the cap")
+    assert 0 < need.sum() < need.size
+    h = _open(fb, ix, prefix_cap=cap)
+    rc, g_ids, g_d = fb.fbpq_search_rc(h, Q, L, k)
+    fb.fbpq_free_index(h)
+    assert rc == fb.FBPQ_E_CAPACITY
+    failed = np.all(g_ids == -2, axis=1)
+    assert np.array_equal(failed, need)
+    assert np.all(np.isnan(g_d[failed]))
+    ok = ~failed
+    o_ids, o_d, _, _ = oracle.search(ix, Q[ok], L, k)
+    assert_topk(ix, Q[ok], k, g_ids[ok], g_d[ok], o_ids, o_d)
