@@ -153,6 +153,24 @@ int fbpq_search_device(fbpq_index *ix, const float *d_q, int64_t nq, const int64
                        const int32_t *k, int32_t k_max, int64_t *d_ids, float *d_dists,
                        void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * search as fbpq_search_device, same arguments and results, but every
+ * workspace buffer (both traversal rounds included) is carved from a static
+ * scratch array of 128 MiB that the library holds on each device it runs on
+ * until the process ends, and host staging uses pageable memory. It calls no
+ * hipMalloc, hipFree, hipHostMalloc or other allocating routine; graph replay
+ * and profiling are off for it. A search whose workspace exceeds the 128 MiB
+ * returns FBPQ_E_CAPACITY, its result rows undefined (about 230 KB per query at
+ * T = 4096, M = 16, L = 10^4; workspace grows with nq, T, L and the visited
+ * cells). Every call on a device shares that device's array: calls that
+ * overlap on one device (two host threads, or two handles) race and must be
+ * serialized by the caller. Errors: as fbpq_search_device, plus CAPACITY for
+ * the scratch limit. */
+int fbpq_search_device_noalloc(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L,
+                               const int32_t *k, int32_t k_max, int64_t *d_ids, float *d_dists,
+                               void *hip_stream);
+
 /* Parity/debug: the visited cells and candidate positions of each query, in
  * traversal order, produced by the GPU traversal. Host buffers:
  *   cells [nq][cells_cap][2]  (cell id, points taken from it)

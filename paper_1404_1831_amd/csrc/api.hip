@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,13 @@
 using namespace fbpq;
 
 static constexpr size_t kScanLdsLimit = 74 * 1024;  // two scan workgroups per CU (160 KB LDS)
+
+// Scratch of the no-allocation search (fbpq_search_device_noalloc): one copy
+// per device, resident while the process lives. Host code never uses the
+// array's name as an address; it looks up each device's copy once with
+// hipGetSymbolAddress and passes that pointer on.
+static constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -63,6 +71,16 @@ struct fbpq_index {
     int ws_base = 0;
     void *pinned = nullptr;
     size_t pinned_cap = 0;
+    // no-allocation searches: workspace carved from the device's static scratch
+    // array for the duration of one call, host staging in pageable memory
+    struct Arena {
+        unsigned char *base = nullptr;  // this device's scratch array (device address)
+        size_t cap = 0, used = 0;
+        void *slot[80] = {};
+        size_t bytes[80] = {};
+    } arena;
+    bool use_arena = false;
+    std::vector<char> host_stage;
     // profiler: events recorded around launches while `profile` is on
     bool profile = false;
     int64_t prof_mask = -1;  // stages timed while profiling
@@ -136,6 +154,21 @@ static_assert(W_NSLOTS <= kWsSet, "workspace slots");
 int ws_get(fbpq_index *ix, int slot, size_t bytes, void **out)
 {
     if (bytes == 0) bytes = 8;
+    if (ix->use_arena) {
+        fbpq_index::Arena &ar = ix->arena;
+        const int i = slot + ix->ws_base;
+        if (!ar.slot[i] || ar.bytes[i] < bytes) {
+            const size_t at = (ar.used + 255) & ~(size_t)255;
+            if (at > ar.cap || bytes > ar.cap - at)
+                return fail(FBPQ_E_CAPACITY, "the search needs more than the %zu bytes of no-allocation scratch",
+                            ar.cap);
+            ar.slot[i] = ar.base + at;
+            ar.bytes[i] = bytes;
+            ar.used = at + bytes;
+        }
+        *out = ar.slot[i];
+        return FBPQ_OK;
+    }
     DevBuf &b = ix->ws[slot + ix->ws_base];
     if (b.cap < bytes) {
         hipStream_t st = ix->cur ? ix->cur : ix->stream;
@@ -158,8 +191,19 @@ int ws_get(fbpq_index *ix, int slot, size_t bytes, void **out)
     return FBPQ_OK;
 }
 
+// Buffer of a workspace slot obtained earlier in this search.
+void *ws_ptr(fbpq_index *ix, int slot)
+{
+    return ix->use_arena ? ix->arena.slot[slot + ix->ws_base] : ix->ws[slot + ix->ws_base].p;
+}
+
 int pinned_get(fbpq_index *ix, size_t bytes, void **out)
 {
+    if (ix->use_arena) {  // no-allocation searches stage through pageable host memory
+        if (ix->host_stage.size() < bytes) ix->host_stage.resize(std::max<size_t>(bytes, 4096));
+        *out = ix->host_stage.data();
+        return FBPQ_OK;
+    }
     if (ix->pinned_cap < bytes) {
         if (ix->pinned) {
             HCK(ix, hipStreamSynchronize(ix->stream));
@@ -198,7 +242,7 @@ hipEvent_t ev_take(fbpq_index *ix)
 template <typename F>
 hipError_t timed(fbpq_index *ix, int stage, hipStream_t st, F &&launch)
 {
-    if (!ix->profile || !((ix->prof_mask >> stage) & 1)) return launch();
+    if (!ix->profile || ix->use_arena || !((ix->prof_mask >> stage) & 1)) return launch();
     hipEvent_t a = ev_take(ix), b = ev_take(ix);
     if (a) (void)hipEventRecord(a, st);
     const hipError_t e = launch();
@@ -222,6 +266,29 @@ void prof_collect(fbpq_index *ix)
         ix->ev_pool.push_back(e.b);
     }
     ix->ev_live.clear();
+}
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[64] = {};  // device address of each device's scratch array
+
+// The device address of `scratch` on `device`, which must be current; looked
+// up on the first call for each device and kept.
+int scratch_addr(int device, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= 64) return fail(FBPQ_E_DEVICE, "device %d out of range", device);
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(FBPQ_E_DEVICE, "address of the scratch array on device %d: %s", device,
+                        hipGetErrorString(e));
+        }
+        g_scratch_dev[device] = p;
+    }
+    *out = g_scratch_dev[device];
+    return FBPQ_OK;
 }
 
 int check_desc(const fbpq_index_desc *d)
@@ -303,6 +370,17 @@ int create_impl(const fbpq_index_desc *d, int device, fbpq_index **out)
         (void)hipGetLastError();
         delete ix;
         return fail(FBPQ_E_DEVICE, "cannot initialise device %d", device);
+    }
+    {
+        void *sp = nullptr;
+        rc = scratch_addr(device, &sp);
+        if (rc) {
+            (void)hipStreamDestroy(ix->stream);
+            delete ix;
+            return rc;
+        }
+        ix->arena.base = (unsigned char *)sp;
+        ix->arena.cap = kScratchBytes;
     }
     const int64_t T = d->T, h = d->D / 2, C = T * T, N = d->N, M = d->M;
     rc = upload(ix, &ix->C1, d->C1, sizeof(float) * T * h);
@@ -882,7 +960,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
 
     // first round: replay the captured graph when the launch sequence is the
     // same, else run it eagerly (and capture it for the next call)
-    const bool use_graph = ix->graph && !dbg && !ix->profile;
+    const bool use_graph = ix->graph && !dbg && !ix->profile && !ix->use_arena;
     fbpq_index::GraphKey key{d_q, nq, lcap, max_cells, ix->ws_gen, d_ids, d_d, k_max, P, ix->chunk, ix->pop_budget,
                              ix->items,
                              ix->stats_dev};
@@ -953,7 +1031,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     for (int round = 1; nfail > 0; ++round) {
         ix->stat_retried += nfail;
         std::vector<TravHdr> hh(nslots);
-        HCK(ix, hipMemcpyAsync(hh.data(), ix->ws[W_HDR + ix->ws_base].p, sizeof(TravHdr) * nslots,
+        HCK(ix, hipMemcpyAsync(hh.data(), ws_ptr(ix, W_HDR), sizeof(TravHdr) * nslots,
                                hipMemcpyDeviceToHost, st));
         HCK(ix, hipStreamSynchronize(st));
         std::vector<int32_t> retry, terminal;
@@ -1020,7 +1098,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
         if (nfail == 0) {
             // every query of this retry round succeeded at P
             std::vector<TravHdr> hl(nslots);
-            HCK(ix, hipMemcpyAsync(hl.data(), ix->ws[W_HDR + ix->ws_base].p, sizeof(TravHdr) * nslots,
+            HCK(ix, hipMemcpyAsync(hl.data(), ws_ptr(ix, W_HDR), sizeof(TravHdr) * nslots,
                                    hipMemcpyDeviceToHost, st));
             HCK(ix, hipStreamSynchronize(st));
             for (int64_t sl = 0; sl < nslots; ++sl) record_hint(cur[sl], P, hl[sl].ncells);
@@ -1055,6 +1133,8 @@ int lane_create(fbpq_index *src, fbpq_index **out)
         return fail(FBPQ_E_DEVICE, "cannot create a stream on device %d", src->device);
     }
     ix->tables = true;
+    ix->arena.base = src->arena.base;
+    ix->arena.cap = src->arena.cap;
     ix->dv = src->dv;
     ix->C1 = src->C1;
     ix->C2 = src->C2;
@@ -1201,6 +1281,24 @@ int fbpq_build_tables(fbpq_index *ix)
 int fbpq_search_device(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
                        int32_t k_max, int64_t *d_ids, float *d_dists, void *hip_stream)
 {
+    return search_impl(ix, d_q, nq, L, k, k_max, d_ids, d_dists, (hipStream_t)hip_stream, nullptr);
+}
+
+int fbpq_search_device_noalloc(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
+                               int32_t k_max, int64_t *d_ids, float *d_dists, void *hip_stream)
+{
+    TRY(check_handle(ix));
+    if (!ix->arena.base) return fail(FBPQ_E_STATE, "no scratch array on device %d", ix->device);
+    struct ArenaOff {
+        fbpq_index *ix;
+        ~ArenaOff() { ix->use_arena = false; }
+    } arena_off{ix};
+    ix->arena.used = 0;
+    for (int i = 0; i < 80; ++i) {
+        ix->arena.slot[i] = nullptr;
+        ix->arena.bytes[i] = 0;
+    }
+    ix->use_arena = true;
     return search_impl(ix, d_q, nq, L, k, k_max, d_ids, d_dists, (hipStream_t)hip_stream, nullptr);
 }
 

@@ -30,7 +30,8 @@ FBPQ_KC = 256
 FBPQ_K_MAX = 1024
 
 EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbpq_build_tables",
-           "fbpq_search", "fbpq_search_uneven", "fbpq_search_device", "fbpq_debug_visit",
+           "fbpq_search", "fbpq_search_uneven", "fbpq_search_device", "fbpq_search_device_noalloc",
+           "fbpq_debug_visit",
            "fbpq_debug_dists", "fbpq_debug_tables", "fbpq_debug_rank", "fbpq_info",
            "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_stats_read", "fbpq_autotune",
            "fbpq_free_index", "fbpq_last_error", "fbpq_server_create", "fbpq_server_create2",
@@ -84,6 +85,7 @@ def _load():
         "fbpq_search": ([P, P, i64, i64, i32, P, P], ctypes.c_int),
         "fbpq_search_uneven": ([P, P, i64, P, P, i32, P, P], ctypes.c_int),
         "fbpq_search_device": ([P, P, i64, P, P, i32, P, P, P], ctypes.c_int),
+        "fbpq_search_device_noalloc": ([P, P, i64, P, P, i32, P, P, P], ctypes.c_int),
         "fbpq_debug_visit": ([P, P, i64, i64, P, i64, P, P, i64, P], ctypes.c_int),
         "fbpq_debug_dists": ([P, P, i64, i64, P, P, i64, P], ctypes.c_int),
         "fbpq_debug_tables": ([P, P, P, P, P, P], ctypes.c_int),
@@ -255,6 +257,24 @@ def fbpq_search_device(h, d_q, L: np.ndarray, k: np.ndarray, k_max: int, d_ids, 
     _check(lib.fbpq_search_device(h, ctypes.c_void_p(d_q.data_ptr()), nq, _p(L), _p(k), int(k_max),
                                   ctypes.c_void_p(d_ids.data_ptr()), ctypes.c_void_p(d_dists.data_ptr()),
                                   st))
+
+
+def fbpq_search_device_noalloc(h, d_q, L: np.ndarray, k: np.ndarray, k_max: int, d_ids, d_dists,
+                               stream=None) -> int:
+    """fbpq_search_device with every workspace buffer in the library's static
+    scratch array (no device allocation); returns the code (FBPQ_E_CAPACITY:
+    the search needs more than the scratch holds)."""
+    nq = d_q.shape[0]
+    assert d_q.is_contiguous() and d_ids.is_contiguous() and d_dists.is_contiguous()
+    L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, np.int64), (nq,)))
+    k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
+    st = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+    rc = lib.fbpq_search_device_noalloc(h, ctypes.c_void_p(d_q.data_ptr()), nq, _p(L), _p(k), int(k_max),
+                                        ctypes.c_void_p(d_ids.data_ptr()), ctypes.c_void_p(d_dists.data_ptr()),
+                                        st)
+    if rc not in (FBPQ_OK, FBPQ_E_CAPACITY):
+        _check(rc)
+    return rc
 
 
 def fbpq_debug_visit(h, q: np.ndarray, L: int, cells_cap: int, pos_cap: int):
