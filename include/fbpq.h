@@ -354,7 +354,11 @@ int fbpq_autotune(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L
 #define FBPQ_STAT_WIDE_BANDS 8  /* ... bands of cells they took (dropped ones included) */
 #define FBPQ_STAT_WIDE_EVALS 9  /* ... row widths evaluated at a threshold (per query) */
 #define FBPQ_STAT_WIDE_LOADS 10 /* ... cell point counts they loaded */
-#define FBPQ_NUM_STATS 11
+#define FBPQ_STAT_CAND_CELL_SCAN 11 /* candidates scored by the cell scan */
+#define FBPQ_STAT_CAND_TWO_PASS 12  /* candidates scored by the two-pass scan in LDS */
+#define FBPQ_STAT_CAND_WIDE 13      /* candidates scored by the two-pass scan with sums in HBM
+                                       (once per pass group with adc_od) */
+#define FBPQ_NUM_STATS 14
 int fbpq_stats_read(fbpq_index *ix, int64_t *out, int32_t n, int32_t reset);
 
 /* Device time per kernel stage, measured with HIP events recorded on the
@@ -362,6 +366,13 @@ int fbpq_stats_read(fbpq_index *ix, int64_t *out, int32_t n, int32_t reset);
  * = 1). Writes the accumulated milliseconds and launch count of `stage` and,
  * if reset != 0, clears that stage's counters. Errors: INVALID. */
 int fbpq_profile_read(fbpq_index *ix, int32_t stage, int32_t reset, double *ms, int64_t *launches);
+
+/* Measurement probe (no index needed): the chip-wide rate of random 4-byte
+ * LDS reads from 256-entry tables, the access pattern of the scans' table
+ * lookups (16 tables, random code bytes, 8 workgroups of 256 threads per
+ * compute unit), in lookups per second. A denominator for the scans' LDS
+ * roof. Errors: INVALID, DEVICE. */
+int fbpq_probe_lds_gather(int device, double *lookups_per_s);
 
 /* Release the handle and all device memory it holds. Null is a no-op. */
 void fbpq_free_index(fbpq_index *ix);

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfbpq.so")
-SOURCES = ["api.hip", "k_tables.hip", "k_rank.hip", "k_traverse.hip", "k_wide.hip", "k_scan.hip", "k_items.hip", "serve.hip"]
+SOURCES = ["api.hip", "k_tables.hip", "k_rank.hip", "k_traverse.hip", "k_wide.hip", "k_scan.hip", "k_items.hip", "serve.hip", "k_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

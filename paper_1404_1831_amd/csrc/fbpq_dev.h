@@ -41,6 +41,7 @@ struct TravHdr {
 // Path counters (slots of FBPQ_STAT_*), incremented when the pointer is set.
 constexpr int kStatCellScan = 0, kStatFused = 1, kStatTwoPass = 2, kStatPrefixWave = 3, kStatPrefixWG = 4;
 constexpr int kStatWide = 7, kStatWideBands = 8, kStatWideEvals = 9, kStatWideLoads = 10;
+constexpr int kStatCandCell = 11, kStatCandTwoPass = 12, kStatCandWide = 13;  // candidates each scan scored
 constexpr int kNumStatSlots = 16;
 
 // Candidate block of the cell scan: up to kItem candidates of one nonempty cell.

@@ -181,7 +181,10 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
     const int tid = threadIdx.x, lane = tid & 63;
     if (tid == 0) {
         a.sel_done[slot] = 0;
-        if (a.stats) atomicAdd(&a.stats[kStatCellScan], 1ull);
+        if (a.stats) {
+            atomicAdd(&a.stats[kStatCellScan], 1ull);
+            atomicAdd(&a.stats[kStatCandCell], (unsigned long long)h.ncand);
+        }
     }
     const int64_t mc = a.max_cells;
     const int32_t *g_cs = a.ne_cs + slot * mc, *g_cnt = a.ne_cnt + slot * mc;

@@ -111,7 +111,10 @@ __global__ __launch_bounds__(512) void k_scan2(ScanArgs a)
     const TravHdr h = a.hdr[slot];
     if (h.status != kStOk || h.n_items != 0 || h.gscan) return;
     if (TAB_LDS != (h.nne <= kScanCellsLds)) return;
-    if (a.stats && tid == 0) atomicAdd(&a.stats[kStatTwoPass], 1ull);
+    if (a.stats && tid == 0) {
+        atomicAdd(&a.stats[kStatTwoPass], 1ull);
+        atomicAdd(&a.stats[kStatCandTwoPass], (unsigned long long)h.ncand);
+    }
     const int D = a.ix.D, ds = D / M, P = a.P;
     const int kq = a.k[qs];
     int KP = 1;
@@ -393,7 +396,10 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
     if (h.status != kStOk || !h.gscan) return;
     if (tid == 0) {
         a.sel_done[slot] = 0;
-        if (a.stats) atomicAdd(&a.stats[kStatTwoPass], 1ull);
+        if (a.stats) {
+            atomicAdd(&a.stats[kStatTwoPass], 1ull);
+            atomicAdd(&a.stats[kStatCandWide], (unsigned long long)h.ncand);
+        }
     }
     // this lane's kWideKeep smallest (distance key, candidate) pairs, ascending,
     // and the smallest key it did not keep (for the fused selection)

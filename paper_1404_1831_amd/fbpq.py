@@ -36,13 +36,13 @@ EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbp
            "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_stats_read", "fbpq_autotune",
            "fbpq_free_index", "fbpq_last_error", "fbpq_server_create", "fbpq_server_create2",
            "fbpq_server_submit", "fbpq_server_cancel", "fbpq_server_poll", "fbpq_server_counts",
-           "fbpq_server_stats", "fbpq_server_first_error", "fbpq_server_destroy")
+           "fbpq_server_stats", "fbpq_server_first_error", "fbpq_server_destroy", "fbpq_probe_lds_gather")
 STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score", "select", "scan2",
           "traverse_wide", "scan_wide", "rotate")
 SERVER_STATS = ("submitted", "completed", "failed", "timeout", "cancelled", "rejected", "batches", "batched",
                 "peak_reserved", "peak_batch_reserved", "budget", "lane_budget", "pending")
 STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried", "graph_replays",
-         "wide", "wide_bands", "wide_evals", "wide_loads")
+         "wide", "wide_bands", "wide_evals", "wide_loads", "cand_cell_scan", "cand_two_pass", "cand_wide")
 
 
 class FbpqError(RuntimeError):
@@ -107,6 +107,7 @@ def _load():
         "fbpq_server_first_error": ([P], ctypes.c_char_p),
         "fbpq_server_destroy": ([P], None),
         "fbpq_last_error": ([], ctypes.c_char_p),
+        "fbpq_probe_lds_gather": ([ctypes.c_int, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -234,6 +235,18 @@ def fbpq_search_rc(h, q: np.ndarray, L: int, k: int):
     return rc, ids, d
 
 
+def fbpq_search_uneven_rc(h, q: np.ndarray, L, k, k_max: int):
+    """fbpq_search_uneven returning (code, ids, dists) instead of raising."""
+    q = np.ascontiguousarray(q, np.float32)
+    nq = q.shape[0]
+    L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, np.int64), (nq,)))
+    k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
+    ids = np.empty((nq, k_max), np.int64)
+    d = np.empty((nq, k_max), np.float32)
+    rc = lib.fbpq_search_uneven(h, _p(q), nq, _p(L), _p(k), int(k_max), _p(ids), _p(d))
+    return rc, ids, d
+
+
 def fbpq_search_uneven(h, q: np.ndarray, L, k, k_max: int):
     q = np.ascontiguousarray(q, np.float32)
     nq = q.shape[0]
@@ -320,6 +333,13 @@ def fbpq_debug_rank(h, q: np.ndarray, P: int):
     idx = np.empty((nq, 2, P), np.int32)
     _check(lib.fbpq_debug_rank(h, _p(q), nq, int(P), _p(keys), _p(idx)))
     return keys, idx
+
+
+def fbpq_probe_lds_gather(device: int = 0) -> float:
+    """Chip-wide random 4-byte LDS reads per second (the scans' lookup pattern)."""
+    r = ctypes.c_double()
+    _check(lib.fbpq_probe_lds_gather(int(device), ctypes.byref(r)))
+    return r.value
 
 
 def fbpq_server_create(h, max_batch: int, nlanes: int, k_max: int) -> ctypes.c_void_p:
