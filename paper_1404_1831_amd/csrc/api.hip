@@ -98,6 +98,7 @@ struct fbpq_index {
     int64_t max_cells = 4096;
     int32_t chunk = 8192;
     bool items = true;
+    bool block_min = true;  // the wave prefix select samples the key kernel's block minima
     int32_t pop_budget = 512;  // cells popped one at a time before the threshold kernel takes over
     // per floor(log2(min(L, N))): the prefix length at which retried queries of
     // that budget last succeeded; retry rounds start there instead of at 4P
@@ -116,13 +117,14 @@ struct fbpq_index {
         int64_t *d_ids;
         float *d_d;
         int32_t k_max, P, chunk, pop_budget;
-        bool items;
+        bool items, block_min;
         unsigned long long *stats;
         bool operator==(const GraphKey &o) const
         {
             return d_q == o.d_q && nq == o.nq && lcap == o.lcap && max_cells == o.max_cells &&
                    ws_gen == o.ws_gen && d_ids == o.d_ids && d_d == o.d_d && k_max == o.k_max && P == o.P &&
-                   chunk == o.chunk && pop_budget == o.pop_budget && items == o.items && stats == o.stats;
+                   chunk == o.chunk && pop_budget == o.pop_budget && items == o.items &&
+                   block_min == o.block_min && stats == o.stats;
         }
     } gkey{};
     int64_t graph_replays = 0;
@@ -134,7 +136,7 @@ enum WsSlot {
     W_Q, W_KEYS, W_LKEY, W_LIDX, W_HDR, W_W, W_ROWNE, W_ROWCAND, W_COLNE, W_COLTOT, W_NECS,
     W_NECNT, W_NEBEG, W_NECST, W_CMCELL, W_CMPRE, W_L, W_K, W_QLIST, W_FAIL, W_IDS, W_D,
     W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NESLOT, W_SLOTIJ, W_COUNTER,
-    W_LQ, W_ITEMN, W_PSTAT, W_SELDONE, W_QROT, W_PSORT, W_BIG, W_LAYSCR, W_NSLOTS
+    W_LQ, W_ITEMN, W_PSTAT, W_SELDONE, W_QROT, W_PSORT, W_BIG, W_LAYSCR, W_KMIN, W_NSLOTS
 };
 constexpr int kWsSet = 40;  // slots per workspace set
 static_assert(W_NSLOTS <= kWsSet, "workspace slots");
@@ -626,10 +628,13 @@ int first_layer(fbpq_index *ix, const float *d_q, int64_t nslots, const int32_t 
     TRY(ws_get(ix, W_PSTAT, sizeof(int32_t) * nslots * 2, &pstat));
     void *keys;
     TRY(ws_get(ix, W_KEYS, sizeof(float) * nslots * 2 * dv.T, &keys));
-    HCK(ix, timed(ix, FBPQ_STAGE_HALF_KEYS, st, [&] { return launch_half_approx(dv, d_q, d_qlist, nslots, (float *)keys, st); }));
     const bool pwave = prefix_wave_ok(dv, P);
+    void *kmin = nullptr;  // block minima: the wave select reads only the blocks that can hold survivors
+    if (pwave && ix->block_min && prefix_blocks_ok(dv, P))
+        TRY(ws_get(ix, W_KMIN, sizeof(float) * nslots * 2 * (size_t)((dv.T + 15) / 16), &kmin));
+    HCK(ix, timed(ix, FBPQ_STAGE_HALF_KEYS, st, [&] { return launch_half_approx(dv, d_q, d_qlist, nslots, (float *)keys, (float *)kmin, st); }));
     if (pwave)
-        HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_wave(dv, d_q, (const float *)keys, nslots, d_qlist, P, lkey, lidx, (int32_t *)pstat, ix->stats_dev, st); }));
+        HCK(ix, timed(ix, FBPQ_STAGE_PREFIX, st, [&] { return launch_prefix_wave(dv, d_q, (const float *)keys, (const float *)kmin, nslots, d_qlist, P, lkey, lidx, (int32_t *)pstat, ix->stats_dev, st); }));
     void *gsort = nullptr;  // long prefixes: the workgroup select sorts in HBM
     const size_t sort_bytes = prefix_sort_bytes(dv, P);
     if (sort_bytes) TRY(ws_get(ix, W_PSORT, sort_bytes * 2 * (size_t)nslots, &gsort));
@@ -962,8 +967,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     // same, else run it eagerly (and capture it for the next call)
     const bool use_graph = ix->graph && !dbg && !ix->profile && !ix->use_arena;
     fbpq_index::GraphKey key{d_q, nq, lcap, max_cells, ix->ws_gen, d_ids, d_d, k_max, P, ix->chunk, ix->pop_budget,
-                             ix->items,
-                             ix->stats_dev};
+                             ix->items, ix->block_min, ix->stats_dev};
     if (use_graph && ix->gexec && ix->gkey == key) {
         HCK(ix, hipGraphLaunch(ix->gexec, st));
         ++ix->graph_replays;
@@ -1155,6 +1159,7 @@ int lane_create(fbpq_index *src, fbpq_index **out)
     ix->max_cells = src->max_cells;
     ix->chunk = src->chunk;
     ix->items = src->items;
+    ix->block_min = src->block_min;
     ix->pop_budget = src->pop_budget;
     *out = ix;
     return FBPQ_OK;
@@ -1444,6 +1449,8 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
     } else if (!strcmp(key, "max_cells")) {
         if (value < 64 || value > ((int64_t)1 << 26)) return fail(FBPQ_E_INVALID, "max_cells out of range");
         ix->max_cells = value;
+    } else if (!strcmp(key, "block_min")) {
+        ix->block_min = value != 0;
     } else if (!strcmp(key, "items")) {
         ix->items = value != 0;
     } else if (!strcmp(key, "profile")) {

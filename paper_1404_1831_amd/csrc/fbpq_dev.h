@@ -81,8 +81,10 @@ hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, 
 // (slot s holds query qlist[s], or s when qlist is null).
 // q' = Rot q for nq queries of dimension D (OPQ), FP64 chains rounded to FP32
 hipError_t launch_rotate(const float *q, int64_t nq, int D, const float *Rot, float *out, hipStream_t st);
+// kmin (optional) [slot][2][ceil(T/16)]: the smallest approximate key of each
+// block of 16 consecutive centroids.
 hipError_t launch_half_approx(const DevIndex &ix, const float *q, const int32_t *qlist, int64_t nslots,
-                              float *ka, hipStream_t st);
+                              float *ka, float *kmin, hipStream_t st);
 
 constexpr int kWaveS = 512;  // survivors a wavefront select ranks
 
@@ -92,8 +94,11 @@ constexpr int kWaveS = 512;  // survivors a wavefront select ranks
 // takes the pairs left over (every pair when pstat is null), from ka, or by
 // an exact radix select alone when ka is null.
 bool prefix_wave_ok(const DevIndex &ix, int32_t P);
-hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
-                              const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
+// The wave select can take its samples from the block minima (and read only
+// the blocks that can hold survivors) at this geometry.
+bool prefix_blocks_ok(const DevIndex &ix, int32_t P);
+hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *ka, const float *kmin,
+                              int64_t nslots, const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
                               int32_t *pstat, unsigned long long *stats, hipStream_t st);
 hipError_t launch_prefix_block(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
                                const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,

@@ -125,10 +125,13 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
                                                      const float *__restrict__ C2,
                                                      const float *__restrict__ nC1,
                                                      const float *__restrict__ nC2, int T, int nchunk,
-                                                     float *__restrict__ ka)
+                                                     float *__restrict__ ka, float *__restrict__ kmin)
 {
     // rows are slots 0..nq-1; slot s holds query qlist[s] (or s); ka is [slot][2][T]
+    // and kmin (when set) [slot][2][ceil(T/16)]: the smallest key of each
+    // block of 16 consecutive centroids, one per 16x16 tile column group
     __shared__ __align__(16) float stage[4][16 * kQT * kStgLd];  // per wavefront: 16 kQT rows x 64 keys
+    __shared__ __align__(16) float smin[4][16 * kQT][kCT / 16];  // per wavefront: block minima of its chunk
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     // the wavefront index, in a scalar register so that everything derived from
     // it (and every branch on it) is uniform
@@ -189,7 +192,8 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         float *stg = stage[threadIdx.x >> 6];
         float b0[16], b1[16];
         float n0, n1;
-        auto tile = [&](const float (&bv)[16], float nc, int col) __attribute__((always_inline)) {
+        float(*mn)[kCT / 16] = smin[threadIdx.x >> 6];
+        auto tile = [&](const float (&bv)[16], float nc, int col, int t) __attribute__((always_inline)) {
             floatx4 acc[kQT];
 #pragma unroll
             for (int a = 0; a < kQT; ++a) acc[a] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -201,8 +205,19 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
 #pragma unroll
             for (int a = 0; a < kQT; ++a)
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    stg[(16 * a + 4 * lk + r) * kStgLd + col + li] = (nq4[a][r] + nc) - 2.f * acc[a][r];
+                for (int r = 0; r < 4; ++r) {
+                    const float key = (nq4[a][r] + nc) - 2.f * acc[a][r];
+                    stg[(16 * a + 4 * lk + r) * kStgLd + col + li] = key;
+                    if (kmin) {
+                        // the tile's 16 columns of this row sit in the 16 lanes of its lane group
+                        float m = key;
+                        m = fminf(m, __shfl_xor(m, 1));
+                        m = fminf(m, __shfl_xor(m, 2));
+                        m = fminf(m, __shfl_xor(m, 4));
+                        m = fminf(m, __shfl_xor(m, 8));
+                        if (li == 0) mn[16 * a + 4 * lk + r][t] = m;
+                    }
+                }
         };
         // LDS executes a wavefront's instructions in issue order: the staged
         // keys are visible to the other lanes once the writes have completed
@@ -237,9 +252,20 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
                     n1 = nC[c0 + 16 + li];
                 }
             }
-            if (t & 1) tile(b1, n1, 16 * (t & 3));
-            else tile(b0, n0, 16 * (t & 3));
+            if (t & 1) tile(b1, n1, 16 * (t & 3), t);
+            else tile(b0, n0, 16 * (t & 3), t);
             if ((t & 3) == 3) flush(c0 - 48);
+        }
+        if (kmin) {
+            // 16 block minima per row of the chunk: 64 contiguous bytes of each row
+            const int64_t G = (T + 15) / 16;
+            float *mout = kmin + (s0 * 2 + half) * G + cb / 16;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int row = (lane >> 2) + 16 * i, part = lane & 3;
+                const float4 v = *reinterpret_cast<const float4 *>(&mn[row][4 * part]);
+                *reinterpret_cast<float4 *>(mout + row * 2 * G + 4 * part) = v;
+            }
         }
         return;
     }
@@ -270,13 +296,24 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
             for (int r = 0; r < 4; ++r) {
                 const int64_t slot = s0 + 16 * a + 4 * lk + r;
                 const float n = __shfl(qn[a], 4 * lk + r);  // the norm of this output's row
-                if (slot < nq && cok) ka[(slot * 2 + half) * (int64_t)T + c] = (n + nc) - 2.f * acc[a][r];
+                const float key = (n + nc) - 2.f * acc[a][r];
+                if (slot < nq && cok) ka[(slot * 2 + half) * (int64_t)T + c] = key;
+                if (kmin) {
+                    // block minimum over the tile's present columns (c0 is a multiple of 16)
+                    float m = cok ? key : __builtin_huge_valf();
+                    m = fminf(m, __shfl_xor(m, 1));
+                    m = fminf(m, __shfl_xor(m, 2));
+                    m = fminf(m, __shfl_xor(m, 4));
+                    m = fminf(m, __shfl_xor(m, 8));
+                    const int64_t G = (T + 15) / 16;
+                    if (li == 0 && slot < nq) kmin[(slot * 2 + half) * G + c0 / 16] = m;
+                }
             }
     }
 }
 
 hipError_t launch_half_approx(const DevIndex &ix, const float *q, const int32_t *qlist, int64_t nslots,
-                              float *ka, hipStream_t st)
+                              float *ka, float *kmin, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
     const int nchunk = (ix.T + kCT - 1) / kCT;
@@ -284,10 +321,10 @@ hipError_t launch_half_approx(const DevIndex &ix, const float *q, const int32_t 
     const dim3 grid((unsigned)((waves + 3) / 4));
     if (ix.D / 2 <= 64)
         hipLaunchKernelGGL(k_half_approx<true>, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2,
-                           ix.nC1, ix.nC2, ix.T, nchunk, ka);
+                           ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin);
     else
         hipLaunchKernelGGL(k_half_approx<false>, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2,
-                           ix.nC1, ix.nC2, ix.T, nchunk, ka);
+                           ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin);
     return hipGetLastError();
 }
 
@@ -863,9 +900,17 @@ __device__ __forceinline__ void rank_survivors(const float *qh, const float *__r
     }
 }
 
-template <int SPL>
+// BLK: the samples are the block minima kmin [slot][2][T/16] of the key kernel
+// (64 SPL of them per pair, SPL per lane), and only the blocks whose minimum
+// is at or below the threshold are read for survivors. The P-th smallest
+// block minimum bounds kP from above like any P-th smallest sample (the
+// blocks are disjoint), and a centroid with ka <= thr lies in a block whose
+// minimum is <= thr.
+constexpr int kBlkCap = 512;  // blocks a wavefront reads for survivors
+
+template <int SPL, bool BLK>
 __global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_prefix_wave(
-    const float *__restrict__ kapprox, const float *__restrict__ Q, int D,
+    const float *__restrict__ kapprox, const float *__restrict__ kmin, const float *__restrict__ Q, int D,
     const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, int T,
     const int32_t *qlist, int64_t nslots, int P, double *__restrict__ lkey, int32_t *__restrict__ lidx,
     int32_t *__restrict__ pstat, unsigned long long *stats)
@@ -914,18 +959,31 @@ __global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) 
         }
     };
     float smp[SPL];
-#pragma unroll
-    for (int q = 0; q < SPL; ++q) smp[q] = __builtin_huge_valf();
     const int nch = (T + kChunk - 1) / kChunk;
-    for (int ch = 0; ch < nch; ++ch) {
-        load_chunk(ch * kChunk);
+    if constexpr (BLK) {
+        // this lane's SPL consecutive block minima (T = 1024 SPL)
+        const float *mg = kmin + (slot * 2 + half) * (int64_t)(T / 16) + lane * SPL;
 #pragma unroll
-        for (int m = 0; m < kF4; ++m)
+        for (int q = 0; q < SPL; q += 4) {
+            const float4 f = *reinterpret_cast<const float4 *>(mg + q);
+            smp[q] = f.x;
+            smp[q + 1] = f.y;
+            smp[q + 2] = f.z;
+            smp[q + 3] = f.w;
+        }
+    } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int q = j + 4 * (m % (SPL / 4));
-                smp[q] = x[4 * m + j] < smp[q] ? x[4 * m + j] : smp[q];
-            }
+        for (int q = 0; q < SPL; ++q) smp[q] = __builtin_huge_valf();
+        for (int ch = 0; ch < nch; ++ch) {
+            load_chunk(ch * kChunk);
+#pragma unroll
+            for (int m = 0; m < kF4; ++m)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int q = j + 4 * (m % (SPL / 4));
+                    smp[q] = x[4 * m + j] < smp[q] ? x[4 * m + j] : smp[q];
+                }
+        }
     }
     uint32_t u[SPL];
 #pragma unroll
@@ -991,21 +1049,55 @@ __global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) 
     // survivors (ka <= thr), compacted with ballots
     const uint64_t below = (1ull << lane) - 1ull;
     int n = 0;
-    for (int ch = 0; ch < nch; ++ch) {
-        if (nch > 1) load_chunk(ch * kChunk);
+    if constexpr (BLK) {
+        // the blocks that can hold a survivor, listed in LDS ...
+        // (after the kWPB histograms: this wavefront's kBlkCap entries)
+        int32_t *blk = reinterpret_cast<int32_t *>(hist - (size_t)wv * 256 + (size_t)kWPB * 256) + (size_t)wv * kBlkCap;
+        int nb = 0;
 #pragma unroll
-        for (int m = 0; m < kF4; ++m)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = ch * kChunk + 4 * (lane + 64 * m) + j;
-                const bool sv = c < T && x[4 * m + j] <= thr;
-                const uint64_t bm = __ballot(sv);
-                if (sv) {
-                    const int w = n + __popcll(bm & below);
-                    if (w < kWaveS) sidx[w] = c;
-                }
-                n += __popcll(bm);
+        for (int q = 0; q < SPL; ++q) {
+            const bool cand = smp[q] <= thr;
+            const uint64_t bm = __ballot(cand);
+            if (cand) {
+                const int w = nb + __popcll(bm & below);
+                if (w < kBlkCap) blk[w] = lane * SPL + q;
             }
+            nb += __popcll(bm);
+        }
+        if (nb > kBlkCap) {
+            if (lane == 0) pstat[pair] = 1;
+            return;
+        }
+        lds_order();
+        // ... then read four blocks (16 keys each) per step
+        for (int b0 = 0; b0 < nb; b0 += 4) {
+            const int bi = b0 + (lane >> 4);
+            const int c = bi < nb ? blk[bi] * 16 + (lane & 15) : T;
+            const bool sv = c < T && kg[c] <= thr;
+            const uint64_t bm = __ballot(sv);
+            if (sv) {
+                const int w = n + __popcll(bm & below);
+                if (w < kWaveS) sidx[w] = c;
+            }
+            n += __popcll(bm);
+        }
+    } else {
+        for (int ch = 0; ch < nch; ++ch) {
+            if (nch > 1) load_chunk(ch * kChunk);
+#pragma unroll
+            for (int m = 0; m < kF4; ++m)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int c = ch * kChunk + 4 * (lane + 64 * m) + j;
+                    const bool sv = c < T && x[4 * m + j] <= thr;
+                    const uint64_t bm = __ballot(sv);
+                    if (sv) {
+                        const int w = n + __popcll(bm & below);
+                        if (w < kWaveS) sidx[w] = c;
+                    }
+                    n += __popcll(bm);
+                }
+        }
     }
     if (n > kWaveS) {
         if (lane == 0) pstat[pair] = 1;
@@ -1057,22 +1149,42 @@ size_t prefix_sort_bytes(const DevIndex &ix, int32_t P)
 
 bool prefix_wave_ok(const DevIndex &ix, int32_t P) { return ix.T >= 256 && P <= 256 && P < ix.T; }
 
-hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *ka, int64_t nslots,
-                              const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
+bool prefix_blocks_ok(const DevIndex &ix, int32_t P)
+{
+    // 64 SPL block minima per pair, SPL a power of two from 4 to 64, at least 2P of them
+    const int spl = ix.T / 1024;
+    return prefix_wave_ok(ix, P) && ix.T % 1024 == 0 && spl >= 4 && spl <= 64 && (spl & (spl - 1)) == 0 &&
+           ix.T / 16 >= 2 * P;
+}
+
+hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *ka, const float *kmin,
+                              int64_t nslots, const int32_t *qlist, int32_t P, double *lkey, int32_t *lidx,
                               int32_t *pstat, unsigned long long *stats, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
     if (!prefix_wave_ok(ix, P) || !pstat) return hipErrorInvalidValue;
+    const bool blk = kmin && prefix_blocks_ok(ix, P);
     const int hpad = (ix.D / 2 + 3) & ~3;
-    const size_t lds = (size_t)kWPB * ((size_t)hpad * 4 + (size_t)kWaveS * 4 + 256 * 4);
+    const size_t lds = (size_t)kWPB * ((size_t)hpad * 4 + (size_t)kWaveS * 4 + 256 * 4 + (blk ? kBlkCap * 4 : 0));
     const int64_t pairs = nslots * 2;
     const dim3 g((unsigned)((pairs + kWPB - 1) / kWPB)), b(kWPB * 64);
-    if (P <= 128)
-        hipLaunchKernelGGL(k_prefix_wave<4>, g, b, lds, st, ka, q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T,
-                           qlist, nslots, P, lkey, lidx, pstat, stats);
-    else
-        hipLaunchKernelGGL(k_prefix_wave<8>, g, b, lds, st, ka, q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T,
-                           qlist, nslots, P, lkey, lidx, pstat, stats);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, g, b, lds, st, ka, kmin, q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist,
+                           nslots, P, lkey, lidx, pstat, stats);
+    };
+    if (blk) {
+        switch (ix.T / 1024) {
+        case 4: go(k_prefix_wave<4, true>); break;
+        case 8: go(k_prefix_wave<8, true>); break;
+        case 16: go(k_prefix_wave<16, true>); break;
+        case 32: go(k_prefix_wave<32, true>); break;
+        default: go(k_prefix_wave<64, true>); break;
+        }
+    } else if (P <= 128) {
+        go(k_prefix_wave<4, false>);
+    } else {
+        go(k_prefix_wave<8, false>);
+    }
     return hipGetLastError();
 }
 

@@ -96,6 +96,31 @@ def test_rank_prefix_ties(fb):
     fb.fbpq_free_index(h)
 
 
+@pytest.mark.parametrize("block_min", [1, 0])
+def test_rank_prefix_block_minima_ties(fb, block_min):
+    # T = 4096 and 8192 integer centroids, 2048 of them copies of others (their
+    # keys tied with another centroid's, in other blocks): prefixes from the
+    # block minima of the key kernel (4 and 8 samples per lane) equal the
+    # oracle's, ties ordered by index
+    for T in (4096, 8192):
+        ix = synth.random_index(N=3000, T=T, M=4, D=16, seed=3, int_valued=True)
+        ix.C1[2048:4096] = ix.C1[:2048]
+        ix.C2[1024:2048] = ix.C2[:1024]
+        rng = np.random.default_rng(6)
+        Q = rng.integers(0, 32, (24, 16)).astype(np.float32)
+        log(f"rank prefix from block minima: T={T} duplicated centroids block_min={block_min}")
+        h = _open(fb, ix, block_min=block_min, stats=1)
+        for P in (128, 64, 7):
+            keys, idx = fb.fbpq_debug_rank(h, Q, P)
+            for r in range(Q.shape[0]):
+                d1, d2, u, v = oracle.rank_lists(ix, Q[r])
+                assert np.array_equal(idx[r, 0], u[:P]) and np.array_equal(idx[r, 1], v[:P]), (T, P, r)
+                assert np.array_equal(keys[r, 0], d1[u[:P]]) and np.array_equal(keys[r, 1], d2[v[:P]])
+        st = fb.fbpq_stats_read(h)
+        fb.fbpq_free_index(h)
+        assert st["prefix_wave"] > 0
+
+
 def _check_visit(fb, h, ix, Q, L, cap=1 << 16):
     cap = min(ix.T * ix.T + 1, cap)
     got = fb.fbpq_debug_visit(h, Q, L, cells_cap=cap, pos_cap=max(1, min(L, ix.N)))
