@@ -318,6 +318,8 @@ def main() -> int:
                     help="batches searched with the O(D) Multi-D-ADC rerank, for the comparison (0: skip)")
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="untimed steps with every kernel timed, for the per-kernel breakdown")
+    ap.add_argument("--option", action="append", default=[],
+                    help="library option key=value set on the search handle (repeatable)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (read once, written once), "
                          "the reference dispatch for scaling HBM traffic counters")
@@ -383,6 +385,9 @@ def run_batch(args, w) -> int:
 
     h = fbpq.fbpq_index_create(ix, 0)
     fbpq.fbpq_build_tables(h)
+    for kv in args.option:
+        key, val = kv.split("=")
+        fbpq.fbpq_set_option(h, key, int(val))
     d_q = torch.from_numpy(Q).to(dev).contiguous()
     d_ids = torch.empty(nq, k, dtype=torch.int64, device=dev)
     d_d = torch.empty(nq, k, dtype=torch.float32, device=dev)
@@ -396,10 +401,16 @@ def run_batch(args, w) -> int:
         log(f"warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
 
-    # per-kernel breakdown and path counters (untimed): HIP events around every launch
+    # path counters (untimed steps of their own: their atomics would slow the kernels)
+    fbpq.fbpq_set_option(h, "stats", 1)
+    for _ in range(args.profile_steps):
+        search()
+    torch.cuda.synchronize()
+    stats = fbpq.fbpq_stats_read(h)
+    fbpq.fbpq_set_option(h, "stats", 0)
+    # per-kernel breakdown (untimed): HIP events around every launch
     fbpq.fbpq_set_option(h, "profile", 1)
     fbpq.fbpq_set_option(h, "profile_mask", -1)
-    fbpq.fbpq_set_option(h, "stats", 1)
     for s in range(len(fbpq.STAGES)):
         fbpq.fbpq_profile_read(h, s, reset=True)
     for _ in range(args.profile_steps):
@@ -409,8 +420,6 @@ def run_batch(args, w) -> int:
     for s, name in enumerate(fbpq.STAGES):
         ms, n = fbpq.fbpq_profile_read(h, s, reset=True)
         prof[name] = {"ms_per_launch": ms / n if n else None, "launches": n}
-    stats = fbpq.fbpq_stats_read(h)
-    fbpq.fbpq_set_option(h, "stats", 0)
     log("kernels: " + ", ".join(f"{n}={v['ms_per_launch']:.4f}" for n, v in prof.items() if v["ms_per_launch"]))
     log(f"path counters over {args.profile_steps} steps: {stats}")
 
@@ -578,7 +587,8 @@ def run_batch(args, w) -> int:
         "data": "synthetic",
         "config": {"workload": f"{args.workload} FBPQ: N={ix.N}, T={ix.T} per half, M={ix.M}, "
                                f"nq={nq} per batch, {lk_desc}",
-                   "N": ix.N, "T": ix.T, "M": ix.M, "nq": nq, "k_max": k, "mean_L": float(Ls.mean())},
+                   "N": ix.N, "T": ix.T, "M": ix.M, "nq": nq, "k_max": k, "mean_L": float(Ls.mean()),
+                   "options": args.option},
         "kernels": prof,
         "path_counters": stats,
         "recall": recall,

@@ -153,6 +153,29 @@ int fbpq_search_device(fbpq_index *ix, const float *d_q, int64_t nq, const int64
                        const int32_t *k, int32_t k_max, int64_t *d_ids, float *d_dists,
                        void *hip_stream);
 
+/* Device-resident form that does not wait for the device (the survey's
+ * fbpq_search_device contract): queries d_q [nq][D], budgets d_L [nq] (int64)
+ * and d_k [nq] (int32), results d_ids / d_dists [nq][k_max] are all device
+ * pointers on the index's device; the call queues the search on hip_stream
+ * and returns without synchronizing. L_max is a host upper bound on the
+ * budgets (it sizes the distance rows); an entry of d_L outside [1, L_max] or
+ * of d_k outside [1, k_max] is clamped into range and counted. d_pending
+ * [2] (device, written on the stream): [0] = the queries whose traversal
+ * needs a longer sorted prefix or more visited cells than the first round
+ * provided (their rows are not final yet), [1] = the clamped entries. When
+ * [0] is not zero, fbpq_search_device_finish (or the next search on the
+ * handle, which calls it first) runs the deeper rounds on the same stream and
+ * synchronizes; when it is zero, the results are complete once the stream
+ * reaches them. The first round replays a captured HIP graph when option
+ * "graph" is on and a search of the same shape was captured. Inputs and
+ * outputs must stay valid until the stream has passed the search (and its
+ * finish, when [0] is not zero). Errors: INVALID, STATE, DEVICE, OOM; from
+ * finish, also CAPACITY (rows (-2, NaN) as for the other entries). */
+int fbpq_search_device_async(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *d_L,
+                             const int32_t *d_k, int64_t L_max, int32_t k_max, int64_t *d_ids,
+                             float *d_dists, int32_t *d_pending, void *hip_stream);
+int fbpq_search_device_finish(fbpq_index *ix);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * search as fbpq_search_device, same arguments and results, but every

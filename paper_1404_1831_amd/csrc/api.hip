@@ -81,6 +81,21 @@ struct fbpq_index {
     } arena;
     bool use_arena = false;
     std::vector<char> host_stage;
+    // the last fbpq_search_device_async, while its retry rounds (if any) are
+    // still to run: finished by fbpq_search_device_finish or the next search
+    bool async_open = false;
+    hipEvent_t async_ev = nullptr;      // recorded after its first round
+    int32_t *async_count = nullptr;     // pinned: queries its first round left over
+    struct AsyncState {
+        const float *d_q;
+        int64_t nq;
+        int32_t P;
+        int64_t max_cells, lcap;
+        int32_t k_max;
+        int64_t *d_ids;
+        float *d_d;
+        hipStream_t st;
+    } async{};
     // profiler: events recorded around launches while `profile` is on
     bool profile = false;
     int64_t prof_mask = -1;  // stages timed while profiling
@@ -346,6 +361,8 @@ void free_all(fbpq_index *ix)
     for (auto &b : ix->ws)
         if (b.p) (void)hipFree(b.p);
     if (ix->pinned) (void)hipHostFree(ix->pinned);
+    if (ix->async_count) (void)hipHostFree(ix->async_count);
+    if (ix->async_ev) (void)hipEventDestroy(ix->async_ev);
     for (auto &e : ix->ev_live) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -918,9 +935,28 @@ int rotate_queries(fbpq_index *ix, const float **d_q, int64_t nq, hipStream_t st
     return FBPQ_OK;
 }
 
+// What the retry rounds of a search need from its first round.
+struct RoundCtx {
+    const float *d_q;  // queries in the index's space
+    int64_t nq;
+    int32_t P;
+    int64_t max_cells, lcap;
+    const int64_t *dL;
+    const int32_t *dk;
+    int32_t *dfail;  // [0]: queries left for another round, then their ids
+    int32_t k_max;
+    int64_t *d_ids;
+    float *d_d;
+    hipStream_t st;
+    const DebugOut *dbg;
+};
+int retry_rounds(fbpq_index *ix, RoundCtx &c, const int64_t *L, int64_t nfail);
+int async_finish(fbpq_index *ix);
+
 int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
                 int32_t k_max, int64_t *d_ids, float *d_d, hipStream_t st, const DebugOut *dbg)
 {
+    if (ix && ix->async_open) TRY(async_finish(ix));
     TRY(check_handle(ix));
     struct CurStream {
         fbpq_index *ix;
@@ -1005,10 +1041,34 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
             ix->gkey.ws_gen = ix->ws_gen;
         }
     }
-    // Retry rounds. A query whose traversal ran out of prefix ranks or cell
-    // capacity is searched again with 4x the ranks or 8x the cells; one that
-    // already had the most the traversal supports is a terminal failure: its
-    // result row is filled with (-2, NaN) and the others complete.
+    RoundCtx c{d_q, nq, P, max_cells, lcap, (const int64_t *)dL, (const int32_t *)dk, (int32_t *)dfail, k_max,
+               d_ids, d_d, st, dbg};
+    return retry_rounds(ix, c, L, nfail);
+}
+
+// Retry rounds. A query whose traversal ran out of prefix ranks or cell
+// capacity is searched again with 4x the ranks or 8x the cells; one that
+// already had the most the traversal supports is a terminal failure: its
+// result row is filled with (-2, NaN) and the others complete. The first
+// round left nfail such queries (their list at c.dfail + 1); L holds the host
+// copy of every query's budget.
+int retry_rounds(fbpq_index *ix, RoundCtx &c, const int64_t *L, int64_t nfail)
+{
+    const float *d_q = c.d_q;
+    const int64_t nq = c.nq;
+    int32_t P = c.P;
+    int64_t max_cells = c.max_cells;
+    const int64_t lcap = c.lcap;
+    const int32_t k_max = c.k_max;
+    int64_t *d_ids = c.d_ids;
+    float *d_d = c.d_d;
+    hipStream_t st = c.st;
+    const DebugOut *dbg = c.dbg;
+    const void *dL = c.dL, *dk = c.dk;
+    void *dfail = c.dfail;
+    const int T = ix->dv.T;
+    int64_t nslots = nq;
+    const int32_t *qlist = nullptr;
     const int32_t Pcap = std::min<int32_t>(std::min<int32_t>(T, kMaxPrefix), std::max<int32_t>(P, ix->prefix_cap));
     const int64_t ccap = ((int64_t)1 << 31) / 32;
     std::vector<int32_t> cur;  // query of each slot of the last round (empty: slot = query)
@@ -1113,6 +1173,30 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
                     "%lld queries need more than %d ranks per half list or %lld cells (their rows are -2 / NaN)",
                     (long long)nterminal, Pcap, (long long)ccap);
     return FBPQ_OK;
+}
+
+// Completes the handle's open asynchronous search: waits for its first
+// round, and runs its retry rounds on its stream if that round left queries.
+int async_finish(fbpq_index *ix)
+{
+    if (!ix->async_open) return FBPQ_OK;
+    ix->async_open = false;
+    fbpq_index::AsyncState &a = ix->async;
+    HCK(ix, hipEventSynchronize(ix->async_ev));
+    const int64_t nfail = ix->async_count[0];
+    if (nfail == 0) return FBPQ_OK;
+    struct CurStream {
+        fbpq_index *ix;
+        ~CurStream() { ix->cur = nullptr; }
+    } cur_reset{ix};
+    ix->cur = a.st;
+    void *dL = ws_ptr(ix, W_L), *dk = ws_ptr(ix, W_K), *dfail = ws_ptr(ix, W_FAIL);
+    std::vector<int64_t> L((size_t)a.nq);
+    HCK(ix, hipMemcpyAsync(L.data(), dL, sizeof(int64_t) * a.nq, hipMemcpyDeviceToHost, a.st));
+    HCK(ix, hipStreamSynchronize(a.st));
+    RoundCtx c{a.d_q, a.nq, a.P, a.max_cells, a.lcap, (const int64_t *)dL, (const int32_t *)dk, (int32_t *)dfail,
+               a.k_max, a.d_ids, a.d_d, a.st, nullptr};
+    return retry_rounds(ix, c, L.data(), nfail);
 }
 
 }  // namespace
@@ -1287,6 +1371,72 @@ int fbpq_search_device(fbpq_index *ix, const float *d_q, int64_t nq, const int64
                        int32_t k_max, int64_t *d_ids, float *d_dists, void *hip_stream)
 {
     return search_impl(ix, d_q, nq, L, k, k_max, d_ids, d_dists, (hipStream_t)hip_stream, nullptr);
+}
+
+int fbpq_search_device_async(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *d_L, const int32_t *d_k,
+                             int64_t L_max, int32_t k_max, int64_t *d_ids, float *d_dists, int32_t *d_pending,
+                             void *hip_stream)
+{
+    TRY(check_handle(ix));
+    if (!ix->tables) return fail(FBPQ_E_STATE, "fbpq_build_tables has not been called");
+    if (nq < 0 || nq > 0x7fffffff) return fail(FBPQ_E_INVALID, "nq out of range");
+    if (L_max < 1) return fail(FBPQ_E_INVALID, "L_max < 1");
+    if (k_max < 1 || k_max > FBPQ_K_MAX) return fail(FBPQ_E_INVALID, "k_max out of range");
+    if (!d_pending || (nq > 0 && (!d_q || !d_L || !d_k || !d_ids || !d_dists)))
+        return fail(FBPQ_E_INVALID, "null pointer");
+    if (std::min<int64_t>(L_max, ix->dv.N) > 0x7fffffffLL)
+        return fail(FBPQ_E_INVALID, "min(L_max, N) must stay below 2^31 candidates per query");
+    TRY(async_finish(ix));  // the previous asynchronous search's retry rounds use the workspace
+    hipStream_t st = (hipStream_t)hip_stream;
+    struct CurStream {
+        fbpq_index *ix;
+        ~CurStream() { ix->cur = nullptr; }
+    } cur_reset{ix};
+    ix->cur = st;
+    if (!ix->async_ev) {
+        HCK(ix, hipEventCreateWithFlags(&ix->async_ev, hipEventDisableTiming));
+        void *p = nullptr;
+        if (hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(FBPQ_E_OOM, "pinned host allocation failed");
+        }
+        ix->async_count = (int32_t *)p;
+    }
+    HCK(ix, launch_fill_i32(d_pending, 0, 2, st));
+    if (nq == 0) return FBPQ_OK;
+    void *dL, *dk, *dfail;
+    TRY(ws_get(ix, W_L, sizeof(int64_t) * nq, &dL));
+    TRY(ws_get(ix, W_K, sizeof(int32_t) * nq, &dk));
+    TRY(ws_get(ix, W_FAIL, sizeof(int32_t) * (nq + 1), &dfail));
+    HCK(ix, launch_sanitize(d_L, d_k, nq, L_max, k_max, (int64_t *)dL, (int32_t *)dk, d_pending + 1, st));
+    TRY(rotate_queries(ix, &d_q, nq, st));
+    const int T = ix->dv.T;
+    const int32_t P = std::min<int32_t>(std::min<int32_t>(std::max<int32_t>(ix->prefix, 1), T), kMaxPrefix);
+    const int64_t max_cells = std::max<int64_t>(ix->max_cells, 64);
+    const int64_t lcap = std::max<int64_t>(1, std::min(L_max, ix->dv.N));
+    const bool use_graph = ix->graph && !ix->profile;
+    fbpq_index::GraphKey key{d_q, nq, lcap, max_cells, ix->ws_gen, d_ids, d_dists, k_max, P, ix->chunk,
+                             ix->pop_budget, ix->items, ix->block_min, ix->stats_dev};
+    if (use_graph && ix->gexec && ix->gkey == key) {
+        HCK(ix, hipGraphLaunch(ix->gexec, st));
+        ++ix->graph_replays;
+    } else {
+        int64_t unused = 0;
+        TRY(run_round(ix, d_q, nq, nq, nullptr, P, max_cells, lcap, (const int64_t *)dL, (const int32_t *)dk, k_max,
+                      d_ids, d_dists, st, (int32_t *)dfail, nullptr, &unused, true));
+    }
+    HCK(ix, launch_copy_i32((const int32_t *)dfail, d_pending, st));
+    HCK(ix, hipMemcpyAsync(ix->async_count, dfail, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HCK(ix, hipEventRecord(ix->async_ev, st));
+    ix->async = fbpq_index::AsyncState{d_q, nq, P, max_cells, lcap, k_max, d_ids, d_dists, st};
+    ix->async_open = true;
+    return FBPQ_OK;
+}
+
+int fbpq_search_device_finish(fbpq_index *ix)
+{
+    TRY(check_handle(ix));
+    return async_finish(ix);
 }
 
 int fbpq_search_device_noalloc(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,

@@ -73,6 +73,10 @@ hipError_t launch_tables(const DevIndex &ix, float *CR1, float *CR2, float *nR, 
                          float *nC2, hipStream_t st);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+// Device budgets L[n], k[n] into Lo, ko clamped to [1, L_max], [1, k_max]; *nclamped counts the changed entries.
+hipError_t launch_sanitize(const int64_t *L, const int32_t *k, int64_t n, int64_t L_max, int32_t k_max, int64_t *Lo,
+                           int32_t *ko, int32_t *nclamped, hipStream_t st);
+hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, hipStream_t st);  // *dst = *src on the stream
 
 hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, uint8_t *b,
                               hipStream_t st);

@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         float b0[16], b1[16];
         float n0, n1;
         float(*mn)[kCT / 16] = smin[threadIdx.x >> 6];
-        auto tile = [&](const float (&bv)[16], float nc, int col, int t) __attribute__((always_inline)) {
+        auto tile = [&](const float (&bv)[16], float nc, int col) __attribute__((always_inline)) {
             floatx4 acc[kQT];
 #pragma unroll
             for (int a = 0; a < kQT; ++a) acc[a] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -205,19 +205,8 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
 #pragma unroll
             for (int a = 0; a < kQT; ++a)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float key = (nq4[a][r] + nc) - 2.f * acc[a][r];
-                    stg[(16 * a + 4 * lk + r) * kStgLd + col + li] = key;
-                    if (kmin) {
-                        // the tile's 16 columns of this row sit in the 16 lanes of its lane group
-                        float m = key;
-                        m = fminf(m, __shfl_xor(m, 1));
-                        m = fminf(m, __shfl_xor(m, 2));
-                        m = fminf(m, __shfl_xor(m, 4));
-                        m = fminf(m, __shfl_xor(m, 8));
-                        if (li == 0) mn[16 * a + 4 * lk + r][t] = m;
-                    }
-                }
+                for (int r = 0; r < 4; ++r)
+                    stg[(16 * a + 4 * lk + r) * kStgLd + col + li] = (nq4[a][r] + nc) - 2.f * acc[a][r];
         };
         // LDS executes a wavefront's instructions in issue order: the staged
         // keys are visible to the other lanes once the writes have completed
@@ -228,13 +217,25 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
             __builtin_amdgcn_wave_barrier();
             __asm__ __volatile__("" ::: "memory");
         };
+        // Block minima: a lane holds four consecutive keys of a row, four lanes
+        // (a DPP quad) one block of 16; the quad's first lane stages its block
+        // minimum for the chunk's write-out.
         auto flush = [&](int c0) __attribute__((always_inline)) {
             lds_order();
+            const int grp = (c0 - cb) / 64;  // 64-centroid group of the chunk
 #pragma unroll
             for (int i = 0; i < 16 * kQT / 4; ++i) {
                 const int row = 4 * i + (lane >> 4), col = 4 * (lane & 15);
                 const float4 v = *reinterpret_cast<const float4 *>(stg + row * kStgLd + col);
                 *reinterpret_cast<float4 *>(kout + row * ldq + c0 + col) = v;
+                if (kmin) {
+                    float m = fminf(fminf(v.x, v.y), fminf(v.z, v.w));
+                    m = fminf(m, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0xb1, 0xf, 0xf,
+                                                                            false)));  // quad lanes xor 1
+                    m = fminf(m, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x4e, 0xf, 0xf,
+                                                                            false)));  // quad lanes xor 2
+                    if ((lane & 3) == 0) mn[row][4 * grp + ((lane & 15) >> 2)] = m;
+                }
             }
             lds_order();
         };
@@ -252,8 +253,8 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
                     n1 = nC[c0 + 16 + li];
                 }
             }
-            if (t & 1) tile(b1, n1, 16 * (t & 3), t);
-            else tile(b0, n0, 16 * (t & 3), t);
+            if (t & 1) tile(b1, n1, 16 * (t & 3));
+            else tile(b0, n0, 16 * (t & 3));
             if ((t & 3) == 3) flush(c0 - 48);
         }
         if (kmin) {

@@ -130,6 +130,41 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st)
     return hipGetLastError();
 }
 
+// Per-query budgets given on the device: copies L and k into the search's own
+// arrays, clamped into [1, L_max] and [1, k_max], and counts the entries that
+// were out of range in *nclamped.
+__global__ void k_sanitize(const int64_t *__restrict__ L, const int32_t *__restrict__ k, int64_t n, int64_t L_max,
+                           int32_t k_max, int64_t *__restrict__ Lo, int32_t *__restrict__ ko,
+                           int32_t *__restrict__ nclamped)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t l = L[i];
+    const int32_t kk = k[i];
+    const int64_t lc = l < 1 ? 1 : (l > L_max ? L_max : l);
+    const int32_t kc = kk < 1 ? 1 : (kk > k_max ? k_max : kk);
+    Lo[i] = lc;
+    ko[i] = kc;
+    if (lc != l || kc != kk) atomicAdd(nclamped, 1);
+}
+
+hipError_t launch_sanitize(const int64_t *L, const int32_t *k, int64_t n, int64_t L_max, int32_t k_max, int64_t *Lo,
+                           int32_t *ko, int32_t *nclamped, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sanitize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, L, k, n, L_max, k_max, Lo,
+                       ko, nclamped);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_i32(const int32_t *__restrict__ src, int32_t *__restrict__ dst) { *dst = *src; }
+
+hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy_i32, dim3(1), dim3(1), 0, st, src, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, uint8_t *b,
                               hipStream_t st)
 {

@@ -31,6 +31,7 @@ FBPQ_K_MAX = 1024
 
 EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbpq_build_tables",
            "fbpq_search", "fbpq_search_uneven", "fbpq_search_device", "fbpq_search_device_noalloc",
+           "fbpq_search_device_async", "fbpq_search_device_finish",
            "fbpq_debug_visit",
            "fbpq_debug_dists", "fbpq_debug_tables", "fbpq_debug_rank", "fbpq_info",
            "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_stats_read", "fbpq_autotune",
@@ -86,6 +87,8 @@ def _load():
         "fbpq_search_uneven": ([P, P, i64, P, P, i32, P, P], ctypes.c_int),
         "fbpq_search_device": ([P, P, i64, P, P, i32, P, P, P], ctypes.c_int),
         "fbpq_search_device_noalloc": ([P, P, i64, P, P, i32, P, P, P], ctypes.c_int),
+        "fbpq_search_device_async": ([P, P, i64, P, P, i64, i32, P, P, P, P], ctypes.c_int),
+        "fbpq_search_device_finish": ([P], ctypes.c_int),
         "fbpq_debug_visit": ([P, P, i64, i64, P, i64, P, P, i64, P], ctypes.c_int),
         "fbpq_debug_dists": ([P, P, i64, i64, P, P, i64, P], ctypes.c_int),
         "fbpq_debug_tables": ([P, P, P, P, P, P], ctypes.c_int),
@@ -270,6 +273,29 @@ def fbpq_search_device(h, d_q, L: np.ndarray, k: np.ndarray, k_max: int, d_ids, 
     _check(lib.fbpq_search_device(h, ctypes.c_void_p(d_q.data_ptr()), nq, _p(L), _p(k), int(k_max),
                                   ctypes.c_void_p(d_ids.data_ptr()), ctypes.c_void_p(d_dists.data_ptr()),
                                   st))
+
+
+def fbpq_search_device_async(h, d_q, d_L, d_k, L_max: int, k_max: int, d_ids, d_dists, d_pending,
+                             stream=None) -> None:
+    """Queues a search without waiting: every array a contiguous torch tensor on
+    the index's GPU (d_L int64 [nq], d_k int32 [nq], d_pending int32 [2])."""
+    nq = d_q.shape[0]
+    for t in (d_q, d_L, d_k, d_ids, d_dists, d_pending):
+        assert t.is_contiguous()
+    st = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+    v = ctypes.c_void_p
+    _check(lib.fbpq_search_device_async(h, v(d_q.data_ptr()), nq, v(d_L.data_ptr()), v(d_k.data_ptr()), int(L_max),
+                                        int(k_max), v(d_ids.data_ptr()), v(d_dists.data_ptr()),
+                                        v(d_pending.data_ptr()), st))
+
+
+def fbpq_search_device_finish(h) -> int:
+    """Runs the deeper rounds of the last asynchronous search, if it has any;
+    returns FBPQ_OK or FBPQ_E_CAPACITY (rows it could not serve are (-2, NaN))."""
+    rc = lib.fbpq_search_device_finish(h)
+    if rc not in (FBPQ_OK, FBPQ_E_CAPACITY):
+        _check(rc)
+    return rc
 
 
 def fbpq_search_device_noalloc(h, d_q, L: np.ndarray, k: np.ndarray, k_max: int, d_ids, d_dists,

@@ -1019,3 +1019,68 @@ def test_capacity_rows_contract(fb, sparse_t8192):
     ok = ~failed
     o_ids, o_d, _, _ = oracle.search(ix, Q[ok], L, k)
     assert_topk(ix, Q[ok], k, g_ids[ok], g_d[ok], o_ids, o_d)
+
+
+def _dev_search(fb, h, Q, L, k, kmax, Lmax=None, async_=False):
+    import torch
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream()
+    nq = Q.shape[0]
+    dq = torch.from_numpy(np.ascontiguousarray(Q, np.float32)).to(dev)
+    ids = torch.full((nq, kmax), -7, dtype=torch.int64, device=dev)
+    d = torch.full((nq, kmax), -7.0, dtype=torch.float32, device=dev)
+    if not async_:
+        fb.fbpq_search_device(h, dq, L, k, kmax, ids, d, st)
+        torch.cuda.synchronize()
+        return ids.cpu().numpy(), d.cpu().numpy()
+    pend = torch.full((2,), -1, dtype=torch.int32, device=dev)
+    dL = torch.from_numpy(np.ascontiguousarray(L, np.int64)).to(dev)
+    dk = torch.from_numpy(np.ascontiguousarray(k, np.int32)).to(dev)
+    fb.fbpq_search_device_async(h, dq, dL, dk, Lmax, kmax, ids, d, pend, st)
+    return ids, d, pend, (dq, dL, dk)
+
+
+def test_async_entry_equals_blocking(fb, gmm_small):
+    """Device budgets, no wait: the same rows as the blocking device entry, bit
+    for bit; out-of-range budgets are clamped and counted."""
+    import torch
+    ix, Q = gmm_small
+    nq, kmax, Lmax = Q.shape[0], 20, 20000
+    rng = np.random.default_rng(12)
+    L = rng.integers(1, Lmax + 1, nq).astype(np.int64)
+    k = rng.integers(1, kmax + 1, nq).astype(np.int32)
+    L[3], L[5], k[7] = 0, 50000, 30
+    log("async device entry: N=1e5 T=64, 100 queries, 3 budgets out of range")
+    h = _open(fb, ix)
+    r_ids, r_d = _dev_search(fb, h, Q, np.clip(L, 1, Lmax), np.clip(k, 1, kmax), kmax)
+    ids, d, pend, keep = _dev_search(fb, h, Q, L, k, kmax, Lmax, async_=True)
+    torch.cuda.synchronize()
+    p = pend.cpu().numpy()
+    assert p[0] == 0 and p[1] == 3
+    assert fb.fbpq_search_device_finish(h) == fb.FBPQ_OK
+    assert np.array_equal(ids.cpu().numpy(), r_ids)
+    assert np.array_equal(d.cpu().numpy().view(np.uint32), r_d.view(np.uint32))
+    fb.fbpq_free_index(h)
+
+
+def test_async_entry_deeper_rounds(fb, sparse_t8192):
+    """A first round that leaves queries for deeper traversal: d_pending says
+    how many, and finish (or the next search) completes them on the stream."""
+    import torch
+    ix, Q = sparse_t8192
+    L, k = np.full(8, 50, np.int64), np.full(8, 10, np.int32)
+    log("async device entry with deeper rounds: T=8192, L=50")
+    h = _open(fb, ix)
+    r_ids, r_d = _dev_search(fb, h, Q, L, k, 10)
+    for implicit in (False, True):
+        ids, d, pend, keep = _dev_search(fb, h, Q, L, k, 10, 50, async_=True)
+        torch.cuda.synchronize()
+        assert pend.cpu().numpy()[0] > 0
+        if implicit:
+            _dev_search(fb, h, Q[:1], L[:1], k[:1], 10)  # the next search finishes the previous one first
+        else:
+            assert fb.fbpq_search_device_finish(h) == fb.FBPQ_OK
+        torch.cuda.synchronize()
+        assert np.array_equal(ids.cpu().numpy(), r_ids)
+        assert np.array_equal(d.cpu().numpy().view(np.uint32), r_d.view(np.uint32))
+    fb.fbpq_free_index(h)
