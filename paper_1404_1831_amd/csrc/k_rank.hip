@@ -1070,17 +1070,29 @@ __global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) 
             return;
         }
         lds_order();
-        // ... then read four blocks (16 keys each) per step
-        for (int b0 = 0; b0 < nb; b0 += 4) {
-            const int bi = b0 + (lane >> 4);
-            const int c = bi < nb ? blk[bi] * 16 + (lane & 15) : T;
-            const bool sv = c < T && kg[c] <= thr;
-            const uint64_t bm = __ballot(sv);
-            if (sv) {
-                const int w = n + __popcll(bm & below);
-                if (w < kWaveS) sidx[w] = c;
+        // ... then read them, four blocks (16 keys each) per step and kBlkU
+        // steps' loads in flight at once
+        constexpr int kBlkU = 8;
+        for (int b0 = 0; b0 < nb; b0 += 4 * kBlkU) {
+            int cc[kBlkU];
+            float kv[kBlkU];
+#pragma unroll
+            for (int u = 0; u < kBlkU; ++u) {
+                const int bi = b0 + 4 * u + (lane >> 4);
+                cc[u] = bi < nb ? blk[bi] * 16 + (lane & 15) : T;
             }
-            n += __popcll(bm);
+#pragma unroll
+            for (int u = 0; u < kBlkU; ++u) kv[u] = cc[u] < T ? kg[cc[u]] : __builtin_huge_valf();
+#pragma unroll
+            for (int u = 0; u < kBlkU; ++u) {
+                const bool sv = cc[u] < T && kv[u] <= thr;
+                const uint64_t bm = __ballot(sv);
+                if (sv) {
+                    const int w = n + __popcll(bm & below);
+                    if (w < kWaveS) sidx[w] = cc[u];
+                }
+                n += __popcll(bm);
+            }
         }
     } else {
         for (int ch = 0; ch < nch; ++ch) {
