@@ -234,10 +234,11 @@ int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int
  * of a half list than min(T, prefix_cap) ends with its row (-2, NaN) and the
  * search returns FBPQ_E_CAPACITY, the other rows being complete), "max_cells"
  * (initial per-query visited-cell capacity), "chunk"
- * (candidates per scan chunk), "block_min" (0/1, default 1: the first
- * layer's key kernel also writes the smallest key of each block of 16
- * centroids, and the prefix select draws its samples from them and reads only
- * the blocks that can hold survivors; same prefixes either way), "items" (0/1: use the cell scan for
+ * (candidates per scan chunk), "block_min" (0 off, 1 on, 2 = default: on
+ * when T >= 8192; the first layer's key kernel also writes the smallest key
+ * of each block of 16 centroids, and the prefix select draws its samples from
+ * them and reads only the blocks that can hold survivors; same prefixes
+ * either way), "items" (0/1: use the cell scan for
  * queries whose visited cells hold many points; 0 sends every query to the
  * two-pass scan), "profile" (0/1: time kernel launches with HIP events,
  * read with fbpq_profile_read), "profile_mask" (bit s set: stage s is timed

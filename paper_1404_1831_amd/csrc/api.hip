@@ -113,7 +113,7 @@ struct fbpq_index {
     int64_t max_cells = 4096;
     int32_t chunk = 8192;
     bool items = true;
-    bool block_min = true;  // the wave prefix select samples the key kernel's block minima
+    int32_t block_min = 2;  // the wave prefix select samples the key kernel's block minima: 0 off, 1 on, 2 when T >= 8192
     int32_t pop_budget = 512;  // cells popped one at a time before the threshold kernel takes over
     // per floor(log2(min(L, N))): the prefix length at which retried queries of
     // that budget last succeeded; retry rounds start there instead of at 4P
@@ -132,7 +132,8 @@ struct fbpq_index {
         int64_t *d_ids;
         float *d_d;
         int32_t k_max, P, chunk, pop_budget;
-        bool items, block_min;
+        bool items;
+        int32_t block_min;
         unsigned long long *stats;
         bool operator==(const GraphKey &o) const
         {
@@ -647,7 +648,9 @@ int first_layer(fbpq_index *ix, const float *d_q, int64_t nslots, const int32_t 
     TRY(ws_get(ix, W_KEYS, sizeof(float) * nslots * 2 * dv.T, &keys));
     const bool pwave = prefix_wave_ok(dv, P);
     void *kmin = nullptr;  // block minima: the wave select reads only the blocks that can hold survivors
-    if (pwave && ix->block_min && prefix_blocks_ok(dv, P))
+    // (at T >= 8192 the minima save more reading than they cost the key kernel)
+    const bool bmin = ix->block_min == 1 || (ix->block_min == 2 && dv.T >= 8192);
+    if (pwave && bmin && prefix_blocks_ok(dv, P))
         TRY(ws_get(ix, W_KMIN, sizeof(float) * nslots * 2 * (size_t)((dv.T + 15) / 16), &kmin));
     HCK(ix, timed(ix, FBPQ_STAGE_HALF_KEYS, st, [&] { return launch_half_approx(dv, d_q, d_qlist, nslots, (float *)keys, (float *)kmin, st); }));
     if (pwave)
@@ -1600,7 +1603,8 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
         if (value < 64 || value > ((int64_t)1 << 26)) return fail(FBPQ_E_INVALID, "max_cells out of range");
         ix->max_cells = value;
     } else if (!strcmp(key, "block_min")) {
-        ix->block_min = value != 0;
+        if (value < 0 || value > 2) return fail(FBPQ_E_INVALID, "block_min must be 0, 1 or 2");
+        ix->block_min = (int32_t)value;
     } else if (!strcmp(key, "items")) {
         ix->items = value != 0;
     } else if (!strcmp(key, "profile")) {
