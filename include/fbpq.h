@@ -238,7 +238,10 @@ int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int
  * when T >= 8192; the first layer's key kernel also writes the smallest key
  * of each block of 16 centroids, and the prefix select draws its samples from
  * them and reads only the blocks that can hold survivors; same prefixes
- * either way), "items" (0/1: use the cell scan for
+ * either way), "persist" (0/1: the cell scan as a persistent kernel over a
+ * device queue of (query, cell range) work items of at least "tile"
+ * candidates, 64..2^30, default 8192, largest queries first, in workgroups of
+ * "pwaves" (2, 4 or 8) wavefronts; same distances and results), "items" (0/1: use the cell scan for
  * queries whose visited cells hold many points; 0 sends every query to the
  * two-pass scan), "profile" (0/1: time kernel launches with HIP events,
  * read with fbpq_profile_read), "profile_mask" (bit s set: stage s is timed
@@ -355,15 +358,29 @@ void fbpq_server_destroy(fbpq_server *s);
 
 /* Autotuner. Times fbpq_search_device on the caller's batch (device queries
  * d_q [nq][D], per-query host L and k, device results as in
- * fbpq_search_device, on hip_stream) under each candidate setting of the
- * options "prefix" (64, 128, 256, 512, capped at T) and "items" (1, 0): one
- * warm search, then `reps` searches timed with HIP events, median kept. The
- * fastest setting stays set on the handle; chosen[0] = prefix, chosen[1] =
- * items, chosen[2] = its median microseconds per search. Synchronizes the
+ * fbpq_search_device, on hip_stream): one warm search, then `reps` searches
+ * timed with HIP events, median kept, for each candidate setting, in two
+ * stages: the options "prefix" (64, 128, 256, 512, capped at T) x "items"
+ * (1, 0); then, if the cell scan won, "persist" 1 with "tile" (2048, 8192,
+ * 32768, 2^30 candidates per work item) x "pwaves" (2, 4, 8 wavefronts per
+ * workgroup, where the kernel has that shape) against the per-query launch.
+ * The fastest setting stays set on the handle. chosen [6]: prefix, items,
+ * median microseconds per search, persist, tile, pwaves. Synchronizes the
  * stream. Profiling and graph replay are off while it runs. Errors: INVALID,
  * STATE, DEVICE, CAPACITY, OOM (then the handle keeps its previous options). */
 int fbpq_autotune(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
                   int32_t k_max, int64_t *d_ids, float *d_dists, void *hip_stream, int32_t reps, int64_t *chosen);
+
+/* The same with a cache: cache_path names a file of JSON lines, one record
+ * per tuned setting, keyed by the index geometry (D, T, M, N, local
+ * codebooks), the batch (floor(log2(nq)), floor(log2 of the mean min(L, N)),
+ * floor(log2(k_max))) and the device (architecture name and compute unit
+ * count). A key present in the file is applied without timing anything
+ * (*from_cache = 1); otherwise the batch is tuned as fbpq_autotune does and a
+ * record is appended (*from_cache = 0). Errors: as fbpq_autotune, IO. */
+int fbpq_autotune_cached(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
+                         int32_t k_max, int64_t *d_ids, float *d_dists, void *hip_stream, int32_t reps,
+                         const char *cache_path, int64_t *chosen, int32_t *from_cache);
 
 /* Path counters, accumulated on the device while option "stats" is 1 (setting
  * it to 1 clears them). fbpq_stats_read copies min(n, FBPQ_NUM_STATS) of them

@@ -65,9 +65,9 @@ struct fbpq_index {
     uint32_t *ids = nullptr;
     float *CR1 = nullptr, *CR2 = nullptr, *nR = nullptr, *nC1 = nullptr, *nC2 = nullptr;
     size_t base_bytes = 0, table_bytes = 0;
-    // workspace, grown on demand: slots [0, 40) for the first round of a
-    // search (the round a graph captures), [40, 80) for its retry rounds
-    DevBuf ws[80];
+    // workspace, grown on demand: slots [0, 48) for the first round of a
+    // search (the round a graph captures), [48, 96) for its retry rounds
+    DevBuf ws[96];
     int ws_base = 0;
     void *pinned = nullptr;
     size_t pinned_cap = 0;
@@ -76,8 +76,8 @@ struct fbpq_index {
     struct Arena {
         unsigned char *base = nullptr;  // this device's scratch array (device address)
         size_t cap = 0, used = 0;
-        void *slot[80] = {};
-        size_t bytes[80] = {};
+        void *slot[96] = {};
+        size_t bytes[96] = {};
     } arena;
     bool use_arena = false;
     std::vector<char> host_stage;
@@ -113,6 +113,9 @@ struct fbpq_index {
     int64_t max_cells = 4096;
     int32_t chunk = 8192;
     bool items = true;
+    bool persist = false;   // cell scan as a persistent kernel over a device work queue
+    int32_t tile = 8192;    // candidates per work item of the persistent scan
+    int32_t pwaves = 4;     // wavefronts per workgroup of the persistent scan
     int32_t block_min = 2;  // the wave prefix select samples the key kernel's block minima: 0 off, 1 on, 2 when T >= 8192
     int32_t pop_budget = 512;  // cells popped one at a time before the threshold kernel takes over
     // per floor(log2(min(L, N))): the prefix length at which retried queries of
@@ -134,13 +137,16 @@ struct fbpq_index {
         int32_t k_max, P, chunk, pop_budget;
         bool items;
         int32_t block_min;
+        bool persist;
+        int32_t tile, pwaves;
         unsigned long long *stats;
         bool operator==(const GraphKey &o) const
         {
             return d_q == o.d_q && nq == o.nq && lcap == o.lcap && max_cells == o.max_cells &&
                    ws_gen == o.ws_gen && d_ids == o.d_ids && d_d == o.d_d && k_max == o.k_max && P == o.P &&
                    chunk == o.chunk && pop_budget == o.pop_budget && items == o.items &&
-                   block_min == o.block_min && stats == o.stats;
+                   block_min == o.block_min && persist == o.persist && tile == o.tile && pwaves == o.pwaves &&
+                   stats == o.stats;
         }
     } gkey{};
     int64_t graph_replays = 0;
@@ -152,9 +158,10 @@ enum WsSlot {
     W_Q, W_KEYS, W_LKEY, W_LIDX, W_HDR, W_W, W_ROWNE, W_ROWCAND, W_COLNE, W_COLTOT, W_NECS,
     W_NECNT, W_NEBEG, W_NECST, W_CMCELL, W_CMPRE, W_L, W_K, W_QLIST, W_FAIL, W_IDS, W_D,
     W_DBGAB, W_DBGTAKE, W_DBGBEG, W_DBGPOS, W_DBGD, W_SPLIT, W_NESLOT, W_SLOTIJ, W_COUNTER,
-    W_LQ, W_ITEMN, W_PSTAT, W_SELDONE, W_QROT, W_PSORT, W_BIG, W_LAYSCR, W_KMIN, W_NSLOTS
+    W_LQ, W_ITEMN, W_PSTAT, W_SELDONE, W_QROT, W_PSORT, W_BIG, W_LAYSCR, W_KMIN, W_PITEMS, W_PCTL,
+    W_PQNIT, W_PQDONE, W_NSLOTS
 };
-constexpr int kWsSet = 40;  // slots per workspace set
+constexpr int kWsSet = 48;  // slots per workspace set
 static_assert(W_NSLOTS <= kWsSet, "workspace slots");
 
 #define HCK(ix, expr)                                                                           \
@@ -799,7 +806,22 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         ia.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
         if (!dv.local && !dv.od)  // local codebooks and the O(D) scan do not use LQ
             HCK(ix, timed(ix, FBPQ_STAGE_LQ, st, [&] { return launch_items_prep(ia, st); }));
-        if (ix->items) HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_scan(ia, st); }));
+        if (ix->items && ix->persist) {
+            PersistArgs pa{};
+            void *pit, *pctl, *pqn, *pqd;
+            TRY(ws_get(ix, W_PITEMS, sizeof(int32_t) * 3 * (size_t)persist_items_cap(nslots, dstride, ix->tile), &pit));
+            TRY(ws_get(ix, W_PCTL, sizeof(int32_t) * 66, &pctl));
+            TRY(ws_get(ix, W_PQNIT, sizeof(int32_t) * nslots, &pqn));
+            TRY(ws_get(ix, W_PQDONE, sizeof(int32_t) * nslots, &pqd));
+            pa.items = (int32_t *)pit;
+            pa.ctl = (int32_t *)pctl;
+            pa.qnit = (int32_t *)pqn;
+            pa.qdone = (int32_t *)pqd;
+            pa.tile = ix->tile;
+            HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_persist(ia, pa, ix->pwaves, st); }));
+        } else if (ix->items) {
+            HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_scan(ia, st); }));
+        }
         ScanArgs sa{};
         sa.ix = dv;
         sa.q = d_q;
@@ -1006,7 +1028,7 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     // same, else run it eagerly (and capture it for the next call)
     const bool use_graph = ix->graph && !dbg && !ix->profile && !ix->use_arena;
     fbpq_index::GraphKey key{d_q, nq, lcap, max_cells, ix->ws_gen, d_ids, d_d, k_max, P, ix->chunk, ix->pop_budget,
-                             ix->items, ix->block_min, ix->stats_dev};
+                             ix->items, ix->block_min, ix->persist, ix->tile, ix->pwaves, ix->stats_dev};
     if (use_graph && ix->gexec && ix->gkey == key) {
         HCK(ix, hipGraphLaunch(ix->gexec, st));
         ++ix->graph_replays;
@@ -1247,6 +1269,9 @@ int lane_create(fbpq_index *src, fbpq_index **out)
     ix->chunk = src->chunk;
     ix->items = src->items;
     ix->block_min = src->block_min;
+    ix->persist = src->persist;
+    ix->tile = src->tile;
+    ix->pwaves = src->pwaves;
     ix->pop_budget = src->pop_budget;
     *out = ix;
     return FBPQ_OK;
@@ -1419,7 +1444,8 @@ int fbpq_search_device_async(fbpq_index *ix, const float *d_q, int64_t nq, const
     const int64_t lcap = std::max<int64_t>(1, std::min(L_max, ix->dv.N));
     const bool use_graph = ix->graph && !ix->profile;
     fbpq_index::GraphKey key{d_q, nq, lcap, max_cells, ix->ws_gen, d_ids, d_dists, k_max, P, ix->chunk,
-                             ix->pop_budget, ix->items, ix->block_min, ix->stats_dev};
+                             ix->pop_budget, ix->items, ix->block_min, ix->persist, ix->tile, ix->pwaves,
+                             ix->stats_dev};
     if (use_graph && ix->gexec && ix->gkey == key) {
         HCK(ix, hipGraphLaunch(ix->gexec, st));
         ++ix->graph_replays;
@@ -1452,7 +1478,7 @@ int fbpq_search_device_noalloc(fbpq_index *ix, const float *d_q, int64_t nq, con
         ~ArenaOff() { ix->use_arena = false; }
     } arena_off{ix};
     ix->arena.used = 0;
-    for (int i = 0; i < 80; ++i) {
+    for (int i = 0; i < 96; ++i) {
         ix->arena.slot[i] = nullptr;
         ix->arena.bytes[i] = 0;
     }
@@ -1602,6 +1628,14 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
     } else if (!strcmp(key, "max_cells")) {
         if (value < 64 || value > ((int64_t)1 << 26)) return fail(FBPQ_E_INVALID, "max_cells out of range");
         ix->max_cells = value;
+    } else if (!strcmp(key, "persist")) {
+        ix->persist = value != 0;
+    } else if (!strcmp(key, "tile")) {
+        if (value < 64 || value > ((int64_t)1 << 30)) return fail(FBPQ_E_INVALID, "tile out of [64, 2^30]");
+        ix->tile = (int32_t)value;
+    } else if (!strcmp(key, "pwaves")) {
+        if (value != 2 && value != 4 && value != 8) return fail(FBPQ_E_INVALID, "pwaves must be 2, 4 or 8");
+        ix->pwaves = (int32_t)value;
     } else if (!strcmp(key, "block_min")) {
         if (value < 0 || value > 2) return fail(FBPQ_E_INVALID, "block_min must be 0, 1 or 2");
         ix->block_min = (int32_t)value;
@@ -1667,64 +1701,200 @@ int fbpq_profile_read(fbpq_index *ix, int32_t stage, int32_t reset, double *ms, 
     return FBPQ_OK;
 }
 
+// Times one setting: a warm search, then `reps` timed with HIP events; the median.
+static int tune_time(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k, int32_t k_max,
+                     int64_t *d_ids, float *d_dists, hipStream_t st, int32_t reps, hipEvent_t e0, hipEvent_t e1,
+                     double *ms_out)
+{
+    int rc = search_impl(ix, d_q, nq, L, k, k_max, d_ids, d_dists, st, nullptr);  // warm: workspace, retries
+    if (rc) return rc;
+    std::vector<float> t(reps);
+    for (int r = 0; r < reps; ++r) {
+        if (hipEventRecord(e0, st) != hipSuccess) return fail(FBPQ_E_DEVICE, "event record failed");
+        rc = search_impl(ix, d_q, nq, L, k, k_max, d_ids, d_dists, st, nullptr);
+        if (rc) return rc;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t[r], e0, e1) != hipSuccess)
+            return fail(FBPQ_E_DEVICE, "event timing failed");
+    }
+    std::sort(t.begin(), t.end());
+    *ms_out = t[t.size() / 2];
+    return FBPQ_OK;
+}
+
+struct TuneChoice {
+    int32_t prefix, items, persist, tile, pwaves;
+    double ms;
+};
+
+static void tune_apply(fbpq_index *ix, const TuneChoice &c)
+{
+    ix->prefix = c.prefix;
+    ix->items = c.items != 0;
+    ix->persist = c.persist != 0;
+    ix->tile = c.tile;
+    ix->pwaves = c.pwaves;
+}
+
+// Coordinate search: first the sorted-prefix length and the scan form, then
+// (cell scan only) the persistent scan's tile and wavefronts per workgroup
+// against the per-query launch.
+static int tune_run(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k, int32_t k_max,
+                    int64_t *d_ids, float *d_dists, hipStream_t st, int32_t reps, TuneChoice *best)
+{
+    const int32_t T = ix->dv.T;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HCK(ix, hipEventCreate(&e0));
+    HCK(ix, hipEventCreate(&e1));
+    int rc = FBPQ_OK;
+    TuneChoice b{std::min<int32_t>(T, kMaxPrefix), 1, 0, ix->tile, ix->pwaves, -1.0};
+    auto consider = [&](const TuneChoice &c) {
+        if (rc) return;
+        tune_apply(ix, c);
+        double ms = 0.0;
+        rc = tune_time(ix, d_q, nq, L, k, k_max, d_ids, d_dists, st, reps, e0, e1, &ms);
+        if (!rc && (b.ms < 0 || ms < b.ms)) {
+            b = c;
+            b.ms = ms;
+        }
+    };
+    bool any = false;
+    for (int32_t p : {64, 128, 256, 512})
+        if (p <= std::min<int32_t>(T, kMaxPrefix)) {
+            any = true;
+            consider({p, 1, 0, ix->tile, ix->pwaves, 0.0});
+            consider({p, 0, 0, ix->tile, ix->pwaves, 0.0});
+        }
+    if (!any) consider(b);
+    if (!rc && b.items) {
+        const int mh = ix->dv.M / 2;
+        for (int32_t tile : {2048, 8192, 32768, 1 << 30})
+            for (int32_t w : {2, 4, 8}) {
+                if ((w == 2 && mh > 4) || (w == 8 && mh < 2)) continue;  // the shapes the kernel is built for
+                consider({b.prefix, 1, 1, tile, w, 0.0});
+            }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *best = b;
+    return FBPQ_OK;
+}
+
+static void tune_out(const TuneChoice &c, int64_t *chosen)
+{
+    chosen[0] = c.prefix;
+    chosen[1] = c.items;
+    chosen[2] = (int64_t)(c.ms * 1000.0);  // microseconds per search of the batch
+    chosen[3] = c.persist;
+    chosen[4] = c.tile;
+    chosen[5] = c.pwaves;
+}
+
 int fbpq_autotune(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
                   int32_t k_max, int64_t *d_ids, float *d_dists, void *hip_stream, int32_t reps, int64_t *chosen)
 {
     TRY(check_handle(ix));
     if (reps < 1 || reps > 100 || !chosen) return fail(FBPQ_E_INVALID, "bad autotune arguments");
-    hipStream_t st = (hipStream_t)hip_stream;
     const bool prof0 = ix->profile, graph0 = ix->graph;
+    const TuneChoice keep{ix->prefix, ix->items ? 1 : 0, ix->persist ? 1 : 0, ix->tile, ix->pwaves, 0.0};
     ix->profile = false;
     ix->graph = false;
-    const int32_t T = ix->dv.T;
-    struct Cand {
-        int32_t prefix;
-        bool items;
-    };
-    std::vector<Cand> cands;
-    for (int32_t p : {64, 128, 256, 512})
-        if (p <= std::min<int32_t>(T, kMaxPrefix)) {
-            cands.push_back({p, true});
-            cands.push_back({p, false});
-        }
-    if (cands.empty()) cands.push_back({std::min<int32_t>(T, kMaxPrefix), true});
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HCK(ix, hipEventCreate(&e0));
-    HCK(ix, hipEventCreate(&e1));
-    double best = -1.0;
-    Cand bestc = cands[0];
-    int rc = FBPQ_OK;
-    for (const Cand &c : cands) {
-        ix->prefix = c.prefix;
-        ix->items = c.items;
-        rc = search_impl(ix, d_q, nq, L, k, k_max, d_ids, d_dists, st, nullptr);  // warm: workspace, retries
-        if (rc) break;
-        std::vector<float> t(reps);
-        for (int r = 0; r < reps && !rc; ++r) {
-            if (hipEventRecord(e0, st) != hipSuccess) rc = fail(FBPQ_E_DEVICE, "event record failed");
-            if (!rc) rc = search_impl(ix, d_q, nq, L, k, k_max, d_ids, d_dists, st, nullptr);
-            if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                        hipEventElapsedTime(&t[r], e0, e1) != hipSuccess))
-                rc = fail(FBPQ_E_DEVICE, "event timing failed");
-        }
-        if (rc) break;
-        std::sort(t.begin(), t.end());
-        const double med = t[t.size() / 2];
-        if (best < 0 || med < best) {
-            best = med;
-            bestc = c;
-        }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    ix->prefix = bestc.prefix;
-    ix->items = bestc.items;
+    TuneChoice best{};
+    const int rc = tune_run(ix, d_q, nq, L, k, k_max, d_ids, d_dists, (hipStream_t)hip_stream, reps, &best);
     ix->profile = prof0;
     ix->graph = graph0;
-    if (rc) return rc;
-    chosen[0] = bestc.prefix;
-    chosen[1] = bestc.items ? 1 : 0;
-    chosen[2] = (int64_t)(best * 1000.0);  // microseconds per search of the batch
+    if (rc) {
+        tune_apply(ix, keep);
+        return rc;
+    }
+    tune_apply(ix, best);
+    tune_out(best, chosen);
+    return FBPQ_OK;
+}
+
+// The tuning cache key: geometry, batch size class, budget classes (log2 of
+// the mean min(L, N) and of k_max) and the device (architecture and compute
+// unit count).
+static int tune_key(fbpq_index *ix, int64_t nq, const int64_t *L, int32_t k_max, std::string *key)
+{
+    double sum = 0.0;
+    for (int64_t i = 0; i < nq; ++i) sum += (double)std::min(L[i], ix->dv.N);
+    const int64_t mean = nq ? (int64_t)(sum / (double)nq) : 1;
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, ix->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FBPQ_E_DEVICE, "cannot read the device properties");
+    }
+    char buf[512];
+    snprintf(buf, sizeof buf, "D=%d T=%d M=%d N=%lld nq2=%d L2=%d k2=%d local=%d dev=%s/%d", ix->dv.D, ix->dv.T,
+             ix->dv.M, (long long)ix->dv.N, 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(1, nq)),
+             63 - __builtin_clzll((unsigned long long)std::max<int64_t>(1, mean)),
+             31 - __builtin_clz((unsigned)std::max(1, k_max)), ix->dv.local, prop.gcnArchName,
+             prop.multiProcessorCount);
+    *key = buf;
+    return FBPQ_OK;
+}
+
+static std::mutex g_tune_mu;
+
+// One JSON object per line: {"key": "...", "prefix": P, "items": I,
+// "persist": S, "tile": W, "pwaves": V, "us": U}. The last record of a key wins.
+static bool tune_lookup(const char *path, const std::string &key, TuneChoice *c)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[1024];
+    const std::string want = "\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof line, f)) {
+        if (!strstr(line, want.c_str())) continue;
+        const char *p = strstr(line, "\"prefix\":");
+        TuneChoice t{};
+        long long us = 0;
+        if (p && sscanf(p, "\"prefix\": %d, \"items\": %d, \"persist\": %d, \"tile\": %d, \"pwaves\": %d, \"us\": %lld",
+                        &t.prefix, &t.items, &t.persist, &t.tile, &t.pwaves, &us) == 6) {
+            t.ms = (double)us / 1000.0;
+            *c = t;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+int fbpq_autotune_cached(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, const int32_t *k,
+                         int32_t k_max, int64_t *d_ids, float *d_dists, void *hip_stream, int32_t reps,
+                         const char *cache_path, int64_t *chosen, int32_t *from_cache)
+{
+    TRY(check_handle(ix));
+    if (!cache_path || !from_cache || !chosen || !L || nq < 1) return fail(FBPQ_E_INVALID, "bad autotune arguments");
+    std::string key;
+    TRY(tune_key(ix, nq, L, k_max, &key));
+    TuneChoice c{};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (tune_lookup(cache_path, key, &c)) {
+            const bool ok = c.prefix >= 1 && c.prefix <= kMaxPrefix && c.tile >= 64 &&
+                            (c.pwaves == 2 || c.pwaves == 4 || c.pwaves == 8);
+            if (ok) {
+                tune_apply(ix, c);
+                tune_out(c, chosen);
+                *from_cache = 1;
+                return FBPQ_OK;
+            }
+        }
+    }
+    TRY(fbpq_autotune(ix, d_q, nq, L, k, k_max, d_ids, d_dists, hip_stream, reps, chosen));
+    *from_cache = 0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = fopen(cache_path, "a");
+    if (!f) return fail(FBPQ_E_IO, "cannot append to %s", cache_path);
+    fprintf(f, "{\"key\": \"%s\", \"prefix\": %lld, \"items\": %lld, \"persist\": %lld, \"tile\": %lld, \"pwaves\": %lld, "
+               "\"us\": %lld}\n",
+            key.c_str(), (long long)chosen[0], (long long)chosen[1], (long long)chosen[3], (long long)chosen[4],
+            (long long)chosen[5], (long long)chosen[2]);
+    fclose(f);
     return FBPQ_OK;
 }
 

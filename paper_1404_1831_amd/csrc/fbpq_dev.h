@@ -237,6 +237,20 @@ struct ItemArgs {
 hipError_t launch_items_prep(const ItemArgs &a, hipStream_t st);   // LQ tables
 hipError_t launch_items_scan(const ItemArgs &a, hipStream_t st);   // query-major cell scan
 hipError_t launch_items_merge(const ItemArgs &a, hipStream_t st);  // per-query top-k
+
+// Persistent form of the cell scan: a device queue of (query, cell range)
+// items of at least `tile` candidates, largest queries first, taken by
+// resident workgroups of `waves` wavefronts; the workgroup finishing a
+// query's last item selects its top-k (else k_select_dist does).
+struct PersistArgs {
+    int32_t *items;  // [cap][3]: slot, first cell, end cell
+    int32_t *ctl;    // [2 + 2 * 32]: queue head, item count, per-class counts and cursors
+    int32_t *qnit;   // [slot] items of the query
+    int32_t *qdone;  // [slot] items finished
+    int32_t tile;
+};
+int64_t persist_items_cap(int64_t nslots, int64_t lcap, int32_t tile);
+hipError_t launch_items_persist(const ItemArgs &a, const PersistArgs &p, int waves, hipStream_t st);
 int items_wcap(int k_max);
 size_t select_dist_lds(int k_max);
 

@@ -643,6 +643,337 @@ hipError_t launch_items_scan(const ItemArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---- persistent form: a device work queue of (query, cell range) items ------
+// A batch with budgets of very different sizes keeps every compute unit busy
+// to the end when its scoring work is dealt out in items of bounded size,
+// largest queries first, to workgroups that stay resident and take the next
+// item as soon as they finish one. Items are built on the device after the
+// layout: each query's nonempty cells are cut, in row-major order, into runs
+// of at least `tile` candidates (the last run of a query may be shorter), and
+// the items are ordered by the query's candidate count in power-of-two classes,
+// largest class first. A workgroup scores an item's cells exactly as the
+// per-query cell scan does (same tables, same FP32 order: the same distances);
+// the workgroup that finishes a query's last item selects its top-k from the
+// distance row.
+constexpr int kPClasses = 32;  // power-of-two classes of candidate counts
+
+// ctl: [0] queue head, [1] items, [2, 2 + kPClasses) items per class,
+// [2 + kPClasses, 2 + 2 kPClasses) fill cursors per class
+__global__ void k_pitems_count(ItemArgs a, PersistArgs p)
+{
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= a.nslots) return;
+    const TravHdr h = a.hdr[slot];
+    int nit = 0;
+    if (h.status == kStOk && h.n_items != 0) {
+        const int32_t *cnt = a.ne_cnt + slot * a.max_cells;
+        int64_t acc = 0;
+        for (int e = 0; e < h.nne; ++e) {
+            acc += cnt[e];
+            if (acc >= p.tile || e == h.nne - 1) {
+                ++nit;
+                acc = 0;
+            }
+        }
+        const int c = 63 - __clzll((unsigned long long)(h.ncand > 0 ? h.ncand : 1));
+        atomicAdd(&p.ctl[2 + c], nit);
+        a.sel_done[slot] = 0;  // set again by the fused selection when it completes
+        if (a.stats) {
+            atomicAdd(&a.stats[kStatCellScan], 1ull);
+            atomicAdd(&a.stats[kStatCandCell], (unsigned long long)h.ncand);
+        }
+    }
+    p.qnit[slot] = nit;
+    p.qdone[slot] = 0;
+}
+
+__global__ void k_pitems_fill(ItemArgs a, PersistArgs p)
+{
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot == 0) {
+        int tot = 0;
+        for (int c = 0; c < kPClasses; ++c) tot += p.ctl[2 + c];
+        p.ctl[1] = tot;
+    }
+    if (slot >= a.nslots) return;
+    const int nit = p.qnit[slot];
+    if (nit == 0) return;
+    const TravHdr h = a.hdr[slot];
+    const int c = 63 - __clzll((unsigned long long)(h.ncand > 0 ? h.ncand : 1));
+    int base = 0;
+    for (int c2 = kPClasses - 1; c2 > c; --c2) base += p.ctl[2 + c2];  // larger classes first
+    int pos = base + atomicAdd(&p.ctl[2 + kPClasses + c], nit);
+    const int32_t *cnt = a.ne_cnt + slot * a.max_cells;
+    int64_t acc = 0;
+    int e0 = 0;
+    for (int e = 0; e < h.nne; ++e) {
+        acc += cnt[e];
+        if (acc >= p.tile || e == h.nne - 1) {
+            p.items[3 * pos] = (int32_t)slot;
+            p.items[3 * pos + 1] = e0;
+            p.items[3 * pos + 2] = e + 1;
+            ++pos;
+            e0 = e + 1;
+            acc = 0;
+        }
+    }
+}
+
+template <int MH, int NT>
+__global__ __launch_bounds__(NT) void k_score_persist(ItemArgs a, PersistArgs p)
+{
+    constexpr int LW = MH * kKc;   // floats of one half table
+    constexpr int PT = LW / NT;    // table floats per thread
+    constexpr int CPT = kItem / NT;  // candidates per thread of a block of kItem
+    using CodeT = typename CodeU<MH>::T;
+    static_assert(PT >= 1 && LW % NT == 0, "table split");
+    __shared__ __align__(16) float lut1[LW];
+    __shared__ __align__(16) float lut2[LW];
+    __shared__ uint64_t s_win[kFWin];
+    __shared__ uint32_t s_wtau[NT / 64];
+    __shared__ uint32_t s_tau;
+    __shared__ int s_nwin, s_item, s_last;
+    const int tid = threadIdx.x, lane = tid & 63;
+    int64_t cur_slot = -1;
+    float lql[PT], lqh[PT];
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&p.ctl[0], 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= p.ctl[1]) break;  // every workgroup reaches this: the queue only grows
+        const int64_t slot = p.items[3 * item];
+        const int e0 = p.items[3 * item + 1], e1 = p.items[3 * item + 2];
+        const TravHdr h = a.hdr[slot];
+        const int64_t mc = a.max_cells;
+        const int32_t *g_cs = a.ne_cs + slot * mc, *g_cnt = a.ne_cnt + slot * mc;
+        const int32_t *g_sl = a.ne_slot + slot * mc;
+        const int64_t *g_beg = a.ne_beg + slot * mc;
+        const float *g_cst = a.ne_cst + slot * mc;
+        const int32_t *sij = a.slot_ij + slot * 2 * a.P;
+        if (slot != cur_slot) {
+            const float *lqg = a.lq + slot * 2 * LW;
+#pragma unroll
+            for (int u = 0; u < PT; ++u) {
+                lql[u] = lqg[tid + NT * u];
+                lqh[u] = lqg[LW + tid + NT * u];
+            }
+            cur_slot = slot;
+        }
+        float *dst = a.dist + slot * a.lcap;
+        int cur_rs = -1;
+        for (int e = e0; e < e1; ++e) {
+            const int sl = g_sl[e];
+            const int64_t p0 = g_beg[e];
+            const int n = g_cnt[e], t0 = g_cs[e], rs = sl & 0xffff;
+            const int ci = sij[sl & 0xffff], cj = sij[sl >> 16];
+            const float cst = g_cst[e];
+            CodeT ca[CPT], cb[CPT];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int o = tid + NT * j;
+                if (o < n) {
+                    ca[j] = load_c<MH>(a.ix.codesA, p0 + o);
+                    cb[j] = load_c<MH>(a.ix.codesB, p0 + o);
+                }
+            }
+            const bool newrow = rs != cur_rs;
+            float c1[PT], c2[PT];
+            const float *cr2 = a.ix.CR2 + (int64_t)cj * LW;
+#pragma unroll
+            for (int u = 0; u < PT; ++u) c2[u] = cr2[tid + NT * u];
+            if (newrow) {
+                const float *cr1 = a.ix.CR1 + (int64_t)ci * LW;
+#pragma unroll
+                for (int u = 0; u < PT; ++u) c1[u] = cr1[tid + NT * u];
+            }
+            __syncthreads();  // the previous cell's lookups are done
+#pragma unroll
+            for (int u = 0; u < PT; ++u) lut2[tid + NT * u] = lqh[u] + c2[u];
+            if (newrow) {
+#pragma unroll
+                for (int u = 0; u < PT; ++u) lut1[tid + NT * u] = lql[u] + c1[u];
+            }
+            cur_rs = rs;
+            __syncthreads();
+            for (int o0 = 0; o0 < n; o0 += kItem) {
+                if (o0 > 0) {
+#pragma unroll
+                    for (int j = 0; j < CPT; ++j) {
+                        const int o = o0 + tid + NT * j;
+                        if (o < n) {
+                            ca[j] = load_c<MH>(a.ix.codesA, p0 + o);
+                            cb[j] = load_c<MH>(a.ix.codesB, p0 + o);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) {
+                    const int o = o0 + tid + NT * j;
+                    if (o < n) {
+                        const float d = cst + lsum<MH>(lut1, ca[j]) + lsum<MH>(lut2, cb[j]);
+                        dst[t0 + o] = d;
+                        if (a.dbg_pos) {
+                            a.dbg_pos[slot * a.dbg_cap + t0 + o] = p0 + o;
+                            a.dbg_d[slot * a.dbg_cap + t0 + o] = d;
+                        }
+                    }
+                }
+            }
+        }
+        // the workgroup that completes a query's last item selects its top-k
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) s_last = atomicAdd(&p.qdone[slot], 1) == p.qnit[slot] - 1;
+        __syncthreads();
+        if (!s_last) continue;
+        __threadfence();
+        const int64_t qs = a.qlist ? a.qlist[slot] : slot;
+        const int kq = a.k[qs];
+        const int64_t ncand = h.ncand;
+        if (kq > NT) continue;  // left to k_select_dist (sel_done stays 0)
+        // per-thread minima of the distance row are samples of distinct
+        // candidates: each wavefront's ceil(kq / waves)-th smallest, the
+        // largest over the wavefronts, bounds the kq-th smallest distance
+        float smin = __builtin_huge_valf();
+        bool any = false;
+        for (int64_t t = tid; t < ncand; t += NT) {
+            const float d = dst[t];
+            smin = d < smin ? d : smin;
+            any = true;
+        }
+        if (tid == 0) s_nwin = 0;
+        {
+            const uint32_t u = any ? fkey(smin) : 0xffffffffu;
+            const int kw = (kq + NT / 64 - 1) / (NT / 64);
+            uint32_t pre = 0;
+            int need = kw;
+            for (int b = 31; b >= 0; --b) {
+                const uint32_t hm = b == 31 ? 0u : (0xffffffffu << (b + 1));
+                const int cnt = __popcll(__ballot(((u & hm) == pre) && !((u >> b) & 1u)));
+                if (cnt < need) {
+                    pre |= 1u << b;
+                    need -= cnt;
+                }
+            }
+            if (lane == 0) s_wtau[tid >> 6] = pre;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t m = 0;
+            for (int w = 0; w < NT / 64; ++w) m = s_wtau[w] > m ? s_wtau[w] : m;
+            s_tau = ncand <= kq ? 0xffffffffu : m;
+        }
+        __syncthreads();
+        const uint32_t tau = s_tau;
+        if (tau == 0xffffffffu && ncand > kq) continue;  // fewer than kq samples
+        for (int64_t t = tid; t - tid < ncand; t += NT) {
+            const bool pred = t < ncand && fkey(dst[t < ncand ? t : 0]) <= tau;
+            const uint64_t m = __ballot(pred);
+            if (m) {
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&s_nwin, (int)__popcll(m));
+                base = __shfl(base, 0);
+                if (pred) {
+                    const int wi = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+                    if (wi < kFWin) s_win[wi] = ((uint64_t)fkey(dst[t]) << 32) | (uint32_t)t;
+                }
+            }
+        }
+        __syncthreads();
+        const int nwin = s_nwin;
+        if (nwin > kFWin) continue;  // many equal distances: left to k_select_dist
+        const int nne = h.nne;
+        for (int i = tid; i < nwin; i += NT) {
+            const uint64_t x = s_win[i];
+            const int64_t t = (uint32_t)x;
+            int lo = 0, hi = nne - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (g_cs[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            s_win[i] = (x & 0xffffffff00000000ull) | a.ix.ids[g_beg[lo] + (t - g_cs[lo])];
+        }
+        __syncthreads();
+        int64_t *oid = a.out_ids + qs * a.k_max;
+        float *od = a.out_d + qs * a.k_max;
+        const int nk = nwin < kq ? nwin : kq;
+        for (int i = tid; i < nwin; i += NT) {
+            const uint64_t x = s_win[i];
+            int rank = 0;
+            for (int j = 0; j < nwin; ++j) rank += s_win[j] < x;
+            if (rank < nk) {
+                oid[rank] = (int64_t)(uint32_t)x;
+                od[rank] = unfkey((uint32_t)(x >> 32));
+            }
+        }
+        for (int r = nk + tid; r < a.k_max; r += NT) {
+            oid[r] = -1;
+            od[r] = __builtin_huge_valf();
+        }
+        if (tid == 0) {
+            a.sel_done[slot] = 1;
+            if (a.stats) atomicAdd(&a.stats[kStatFused], 1ull);
+        }
+        __syncthreads();  // s_win is reused by the next item
+    }
+}
+
+int64_t persist_items_cap(int64_t nslots, int64_t lcap, int32_t tile)
+{
+    return nslots * (lcap / (tile > 0 ? tile : 1) + 1);
+}
+
+hipError_t launch_items_persist(const ItemArgs &a, const PersistArgs &p, int waves, hipStream_t st)
+{
+    if (a.nslots == 0) return hipSuccess;
+    if (p.tile < 1) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_i32(p.ctl, 0, 2 + 2 * kPClasses, st);
+    if (e != hipSuccess) return e;
+    const dim3 gs((unsigned)((a.nslots + 255) / 256)), bs(256);
+    hipLaunchKernelGGL(k_pitems_count, gs, bs, 0, st, a, p);
+    hipLaunchKernelGGL(k_pitems_fill, gs, bs, 0, st, a, p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // one workgroup per resident slot of the device (more only exit at once)
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess)
+        ncu = 256;
+    auto go = [&](auto kern, int nt) {
+        int per = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, nt, 0) != hipSuccess || per < 1) per = 1;
+        const int64_t cap = persist_items_cap(a.nslots, a.lcap, p.tile);
+        int64_t grid = (int64_t)ncu * per;
+        grid = grid < cap ? grid : cap;
+        hipLaunchKernelGGL(kern, dim3((unsigned)(grid > 1 ? grid : 1)), dim3(nt), 0, st, a, p);
+    };
+    // waves per workgroup: 2 only where the codes of 16 candidates per thread
+    // fit in registers (M <= 8), 8 where a table has at least 512 entries
+    switch (a.ix.M / 2) {
+    case 1: go(k_score_persist<1, 256>, 256); break;
+    case 2:
+        if (waves == 2) go(k_score_persist<2, 128>, 128);
+        else if (waves == 8) go(k_score_persist<2, 512>, 512);
+        else go(k_score_persist<2, 256>, 256);
+        break;
+    case 4:
+        if (waves == 2) go(k_score_persist<4, 128>, 128);
+        else if (waves == 8) go(k_score_persist<4, 512>, 512);
+        else go(k_score_persist<4, 256>, 256);
+        break;
+    case 8:
+        if (waves == 8) go(k_score_persist<8, 512>, 512);
+        else go(k_score_persist<8, 256>, 256);
+        break;
+    case 16:
+        if (waves == 8) go(k_score_persist<16, 512>, 512);
+        else go(k_score_persist<16, 256>, 256);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_items_merge(const ItemArgs &a, hipStream_t st)
 {
     if (a.nslots == 0) return hipSuccess;

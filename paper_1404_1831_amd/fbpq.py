@@ -35,6 +35,7 @@ EXPORTS = ("fbpq_index_create", "fbpq_load_index", "fbpq_index_file_check", "fbp
            "fbpq_debug_visit",
            "fbpq_debug_dists", "fbpq_debug_tables", "fbpq_debug_rank", "fbpq_info",
            "fbpq_table_bytes", "fbpq_set_option", "fbpq_profile_read", "fbpq_stats_read", "fbpq_autotune",
+           "fbpq_autotune_cached",
            "fbpq_free_index", "fbpq_last_error", "fbpq_server_create", "fbpq_server_create2",
            "fbpq_server_submit", "fbpq_server_cancel", "fbpq_server_poll", "fbpq_server_counts",
            "fbpq_server_stats", "fbpq_server_first_error", "fbpq_server_destroy", "fbpq_probe_lds_gather")
@@ -99,6 +100,7 @@ def _load():
         "fbpq_profile_read": ([P, i32, i32, P, P], ctypes.c_int),
         "fbpq_stats_read": ([P, P, i32, i32], ctypes.c_int),
         "fbpq_autotune": ([P, P, i64, P, P, i32, P, P, P, i32, P], ctypes.c_int),
+        "fbpq_autotune_cached": ([P, P, i64, P, P, i32, P, P, P, i32, ctypes.c_char_p, P, P], ctypes.c_int),
         "fbpq_free_index": ([P], None),
         "fbpq_server_create": ([P, i32, i32, i32, P], ctypes.c_int),
         "fbpq_server_create2": ([P, P, P], ctypes.c_int),
@@ -202,16 +204,39 @@ def fbpq_stats_read(h, reset: bool = False) -> dict:
     return dict(zip(STATS, out.tolist()))
 
 
+def _tune_dict(out) -> dict:
+    return {"prefix": int(out[0]), "items": int(out[1]), "us_per_search": int(out[2]), "persist": int(out[3]),
+            "tile": int(out[4]), "pwaves": int(out[5])}
+
+
 def fbpq_autotune(h, d_q, L, k, k_max: int, d_ids, d_dists, stream, reps: int = 3) -> dict:
-    """Tune "prefix" and "items" on a device batch (torch tensors); returns the choice."""
+    """Tune the first layer, the scan form and the persistent scan's shape on a
+    device batch (torch tensors); returns the choice."""
     nq = d_q.shape[0]
     L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, np.int64), (nq,)))
     k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
-    out = np.zeros(3, np.int64)
+    out = np.zeros(6, np.int64)
     _check(lib.fbpq_autotune(h, ctypes.c_void_p(d_q.data_ptr()), nq, _p(L), _p(k), int(k_max),
                              ctypes.c_void_p(d_ids.data_ptr()), ctypes.c_void_p(d_dists.data_ptr()),
                              ctypes.c_void_p(stream.cuda_stream), int(reps), _p(out)))
-    return {"prefix": int(out[0]), "items": int(out[1]), "us_per_search": int(out[2])}
+    return _tune_dict(out)
+
+
+def fbpq_autotune_cached(h, d_q, L, k, k_max: int, d_ids, d_dists, stream, cache_path: str, reps: int = 3) -> dict:
+    """fbpq_autotune through a JSON-lines cache file; the dict says whether the
+    choice came from the cache."""
+    nq = d_q.shape[0]
+    L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, np.int64), (nq,)))
+    k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
+    out = np.zeros(6, np.int64)
+    hit = ctypes.c_int32()
+    _check(lib.fbpq_autotune_cached(h, ctypes.c_void_p(d_q.data_ptr()), nq, _p(L), _p(k), int(k_max),
+                                    ctypes.c_void_p(d_ids.data_ptr()), ctypes.c_void_p(d_dists.data_ptr()),
+                                    ctypes.c_void_p(stream.cuda_stream), int(reps), cache_path.encode(), _p(out),
+                                    ctypes.byref(hit)))
+    d = _tune_dict(out)
+    d["from_cache"] = bool(hit.value)
+    return d
 
 
 def fbpq_free_index(h) -> None:

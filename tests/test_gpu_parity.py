@@ -1084,3 +1084,65 @@ def test_async_entry_deeper_rounds(fb, sparse_t8192):
         assert np.array_equal(ids.cpu().numpy(), r_ids)
         assert np.array_equal(d.cpu().numpy().view(np.uint32), r_d.view(np.uint32))
     fb.fbpq_free_index(h)
+
+
+@pytest.fixture(scope="module")
+def gmm_dense():
+    # 4e5 points in T = 64 per half: dense cells (the cell scan's queries)
+    means = synth.gmm_means(0)
+    base = synth.sample_points(400000, means, 1)
+    ix = synth.build_index(base, 64, 8, train_n=20000)
+    Q = synth.make_queries(300, means, 2)
+    return ix, Q
+
+
+def test_persistent_scan_bitexact(fb, gmm_dense):
+    """Every tile size and workgroup shape of the persistent scan gives the
+    per-query scan's rows bit for bit, on a batch of uneven budgets."""
+    ix, Q = gmm_dense
+    nq, kmax = Q.shape[0], 100
+    L, k = synth.draw_L_k(nq, 3, 100, 100000, (1, 10, 100))
+    log("persistent scan: N=4e5 T=64 M=8, 300 queries, L log-uniform in [1e2, 1e5], k in {1, 10, 100}")
+    h = _open(fb, ix, stats=1)
+    r_ids, r_d = _dev_search(fb, h, Q, L, k, kmax)
+    assert fb.fbpq_stats_read(h, reset=True)["cell_scan"] > 0
+    for tile in (64, 2048, 8192, 1 << 30):
+        for w in (2, 4, 8):
+            fb.fbpq_set_option(h, "persist", 1)
+            fb.fbpq_set_option(h, "tile", tile)
+            fb.fbpq_set_option(h, "pwaves", w)
+            ids, d = _dev_search(fb, h, Q, L, k, kmax)
+            assert np.array_equal(ids, r_ids), (tile, w)
+            assert np.array_equal(d.view(np.uint32), r_d.view(np.uint32)), (tile, w)
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q[:60], L[:60], k[:60], kmax=kmax)
+    assert_topk(ix, Q[:60], k[:60], r_ids[:60], r_d[:60], o_ids, o_d)
+
+
+def test_autotune_cache(fb, gmm_dense, tmp_path):
+    import torch
+    ix, Q = gmm_dense
+    dev = torch.device("cuda:0")
+    nq, kmax = Q.shape[0], 100
+    L, k = synth.draw_L_k(nq, 3, 100, 100000, (1, 10, 100))
+    log("autotune with a cache: N=4e5 T=64 M=8, 300 queries")
+    cache = str(tmp_path / "tune.jsonl")
+    d_q = torch.from_numpy(Q).to(dev).contiguous()
+    d_ids = torch.empty(nq, kmax, dtype=torch.int64, device=dev)
+    d_d = torch.empty(nq, kmax, dtype=torch.float32, device=dev)
+    st = torch.cuda.current_stream(dev)
+    h = _open(fb, ix)
+    first = fb.fbpq_autotune_cached(h, d_q, L, k, kmax, d_ids, d_d, st, cache, reps=2)
+    fb.fbpq_free_index(h)
+    h = _open(fb, ix)
+    second = fb.fbpq_autotune_cached(h, d_q, L, k, kmax, d_ids, d_d, st, cache, reps=2)
+    log(f"  tuned {first}, then {second}")
+    assert not first["from_cache"] and second["from_cache"]
+    for key in ("prefix", "items", "persist", "tile", "pwaves"):
+        assert first[key] == second[key]
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and '"key": "D=128 T=64 M=8' in lines[0]
+    ids, d = _dev_search(fb, h, Q, L, k, kmax)  # the tuned setting is on the handle
+    fb.fbpq_free_index(h)
+    o_ids, o_d, _, _ = oracle.search(ix, Q[:60], L[:60], k[:60], kmax=kmax)
+    assert_topk(ix, Q[:60], k[:60], ids[:60], d[:60], o_ids, o_d)
