@@ -234,7 +234,11 @@ int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int
  * of a half list than min(T, prefix_cap) ends with its row (-2, NaN) and the
  * search returns FBPQ_E_CAPACITY, the other rows being complete), "max_cells"
  * (initial per-query visited-cell capacity), "chunk"
- * (candidates per scan chunk), "block_min" (0 off, 1 on, 2 = default: on
+ * (candidates per scan chunk), "hint_first" (0/1, default 1: with graph
+ * replay off, a batch whose queries' budget classes (floor(log2(min(L, N))))
+ * all needed deeper traversal rounds before starts its first round at the
+ * prefix length and cell capacity those rounds reached; same results),
+ * "block_min" (0 off, 1 on, 2 = default: on
  * when T >= 8192; the first layer's key kernel also writes the smallest key
  * of each block of 16 centroids, and the prefix select draws its samples from
  * them and reads only the blocks that can hold survivors; same prefixes

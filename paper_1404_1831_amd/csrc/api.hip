@@ -113,6 +113,7 @@ struct fbpq_index {
     int64_t max_cells = 4096;
     int32_t chunk = 8192;
     bool items = true;
+    bool hint_first = true;  // without graph replay: a batch whose budget classes all retried before starts deeper
     bool persist = false;   // cell scan as a persistent kernel over a device work queue
     int32_t tile = 8192;    // candidates per work item of the persistent scan
     int32_t pwaves = 4;     // wavefronts per workgroup of the persistent scan
@@ -1020,6 +1021,32 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     P = std::min<int32_t>(P, kMaxPrefix);
     int64_t max_cells = std::max<int64_t>(ix->max_cells, 64);
     const int64_t lcap = std::max<int64_t>(1, std::min(Lmax, ix->dv.N));
+    if (ix->hint_first && !ix->graph) {
+        // every query's budget class has needed a deeper traversal before (a
+        // served batch holds one class): start there instead of retrying
+        int32_t ph = INT32_MAX;
+        int64_t ch = INT64_MAX;
+        for (int64_t i = 0; i < nq && ph > 0; ++i) {
+            const int b = 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(1, std::min(L[i], ix->dv.N)));
+            ph = std::min(ph, ix->p_hint[b]);
+            ch = std::min(ch, ix->c_hint[b]);
+        }
+        if (ph > 0) {
+            int32_t pmax = 0;
+            int64_t cmax = 0;
+            for (int64_t i = 0; i < nq; ++i) {
+                const int b = 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(1, std::min(L[i], ix->dv.N)));
+                pmax = std::max(pmax, ix->p_hint[b]);
+                cmax = std::max(cmax, ix->c_hint[b]);
+            }
+            const int32_t pc = std::min<int32_t>(std::min<int32_t>(T, kMaxPrefix), std::max<int32_t>(P, ix->prefix_cap));
+            P = std::max(P, std::min(pmax, pc));
+            int64_t c = max_cells;
+            while (c < cmax && c < ((int64_t)1 << 26)) c *= 2;
+            max_cells = c;
+        }
+        (void)ch;
+    }
     int64_t nslots = nq;
     const int32_t *qlist = nullptr;
     int64_t nfail = 0;
@@ -1270,6 +1297,7 @@ int lane_create(fbpq_index *src, fbpq_index **out)
     ix->items = src->items;
     ix->block_min = src->block_min;
     ix->persist = src->persist;
+    ix->hint_first = src->hint_first;
     ix->tile = src->tile;
     ix->pwaves = src->pwaves;
     ix->pop_budget = src->pop_budget;
@@ -1628,6 +1656,8 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
     } else if (!strcmp(key, "max_cells")) {
         if (value < 64 || value > ((int64_t)1 << 26)) return fail(FBPQ_E_INVALID, "max_cells out of range");
         ix->max_cells = value;
+    } else if (!strcmp(key, "hint_first")) {
+        ix->hint_first = value != 0;
     } else if (!strcmp(key, "persist")) {
         ix->persist = value != 0;
     } else if (!strcmp(key, "tile")) {

@@ -659,50 +659,75 @@ constexpr int kPClasses = 32;  // power-of-two classes of candidate counts
 
 // ctl: [0] queue head, [1] items, [2, 2 + kPClasses) items per class,
 // [2 + kPClasses, 2 + 2 kPClasses) fill cursors per class
-__global__ void k_pitems_count(ItemArgs a, PersistArgs p)
+// Counts and positions are aggregated per workgroup in LDS, then one global
+// atomic per class and workgroup: a batch whose queries share one class would
+// otherwise serialize on a single counter.
+__global__ __launch_bounds__(256) void k_pitems_count(ItemArgs a, PersistArgs p)
 {
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= a.nslots) return;
-    const TravHdr h = a.hdr[slot];
-    int nit = 0;
-    if (h.status == kStOk && h.n_items != 0) {
-        const int32_t *cnt = a.ne_cnt + slot * a.max_cells;
-        int64_t acc = 0;
-        for (int e = 0; e < h.nne; ++e) {
-            acc += cnt[e];
-            if (acc >= p.tile || e == h.nne - 1) {
-                ++nit;
-                acc = 0;
+    __shared__ int cls[kPClasses];
+    const int tid = threadIdx.x;
+    if (tid < kPClasses) cls[tid] = 0;
+    __syncthreads();
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + tid;
+    if (slot < a.nslots) {
+        const TravHdr h = a.hdr[slot];
+        int nit = 0;
+        if (h.status == kStOk && h.n_items != 0) {
+            const int32_t *cnt = a.ne_cnt + slot * a.max_cells;
+            int64_t acc = 0;
+            for (int e = 0; e < h.nne; ++e) {
+                acc += cnt[e];
+                if (acc >= p.tile || e == h.nne - 1) {
+                    ++nit;
+                    acc = 0;
+                }
+            }
+            const int c = 63 - __clzll((unsigned long long)(h.ncand > 0 ? h.ncand : 1));
+            atomicAdd(&cls[c], nit);
+            a.sel_done[slot] = 0;  // set again by the fused selection when it completes
+            if (a.stats) {
+                atomicAdd(&a.stats[kStatCellScan], 1ull);
+                atomicAdd(&a.stats[kStatCandCell], (unsigned long long)h.ncand);
             }
         }
-        const int c = 63 - __clzll((unsigned long long)(h.ncand > 0 ? h.ncand : 1));
-        atomicAdd(&p.ctl[2 + c], nit);
-        a.sel_done[slot] = 0;  // set again by the fused selection when it completes
-        if (a.stats) {
-            atomicAdd(&a.stats[kStatCellScan], 1ull);
-            atomicAdd(&a.stats[kStatCandCell], (unsigned long long)h.ncand);
-        }
+        p.qnit[slot] = nit;
+        p.qdone[slot] = 0;
     }
-    p.qnit[slot] = nit;
-    p.qdone[slot] = 0;
+    __syncthreads();
+    if (tid < kPClasses && cls[tid]) atomicAdd(&p.ctl[2 + tid], cls[tid]);
 }
 
-__global__ void k_pitems_fill(ItemArgs a, PersistArgs p)
+__global__ __launch_bounds__(256) void k_pitems_fill(ItemArgs a, PersistArgs p)
 {
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot == 0) {
+    __shared__ int cls[kPClasses], bbase[kPClasses];
+    const int tid = threadIdx.x;
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + tid;
+    if (blockIdx.x == 0 && tid == 0) {
         int tot = 0;
         for (int c = 0; c < kPClasses; ++c) tot += p.ctl[2 + c];
         p.ctl[1] = tot;
     }
-    if (slot >= a.nslots) return;
-    const int nit = p.qnit[slot];
+    if (tid < kPClasses) cls[tid] = 0;
+    __syncthreads();
+    int nit = 0, c = 0, mine = 0;
+    TravHdr h{};
+    if (slot < a.nslots) {
+        nit = p.qnit[slot];
+        if (nit) {
+            h = a.hdr[slot];
+            c = 63 - __clzll((unsigned long long)(h.ncand > 0 ? h.ncand : 1));
+            mine = atomicAdd(&cls[c], nit);  // this query's place among the workgroup's items of its class
+        }
+    }
+    __syncthreads();
+    if (tid < kPClasses) {
+        int base = 0;
+        for (int c2 = kPClasses - 1; c2 > tid; --c2) base += p.ctl[2 + c2];  // larger classes first
+        bbase[tid] = cls[tid] ? base + atomicAdd(&p.ctl[2 + kPClasses + tid], cls[tid]) : 0;
+    }
+    __syncthreads();
     if (nit == 0) return;
-    const TravHdr h = a.hdr[slot];
-    const int c = 63 - __clzll((unsigned long long)(h.ncand > 0 ? h.ncand : 1));
-    int base = 0;
-    for (int c2 = kPClasses - 1; c2 > c; --c2) base += p.ctl[2 + c2];  // larger classes first
-    int pos = base + atomicAdd(&p.ctl[2 + kPClasses + c], nit);
+    int pos = bbase[c] + mine;
     const int32_t *cnt = a.ne_cnt + slot * a.max_cells;
     int64_t acc = 0;
     int e0 = 0;
@@ -720,7 +745,8 @@ __global__ void k_pitems_fill(ItemArgs a, PersistArgs p)
 }
 
 template <int MH, int NT>
-__global__ __launch_bounds__(NT) void k_score_persist(ItemArgs a, PersistArgs p)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(QWAVES))) void k_score_persist(ItemArgs a,
+                                                                                                 PersistArgs p)
 {
     constexpr int LW = MH * kKc;   // floats of one half table
     constexpr int PT = LW / NT;    // table floats per thread
@@ -729,20 +755,40 @@ __global__ __launch_bounds__(NT) void k_score_persist(ItemArgs a, PersistArgs p)
     static_assert(PT >= 1 && LW % NT == 0, "table split");
     __shared__ __align__(16) float lut1[LW];
     __shared__ __align__(16) float lut2[LW];
+    __shared__ int64_t m_p0[kMetaLds];
+    __shared__ int32_t m_n[kMetaLds], m_t0[kMetaLds], m_rs[kMetaLds], m_i[kMetaLds], m_j[kMetaLds];
+    __shared__ float m_cst[kMetaLds];
     __shared__ uint64_t s_win[kFWin];
     __shared__ uint32_t s_wtau[NT / 64];
     __shared__ uint32_t s_tau;
     __shared__ int s_nwin, s_item, s_last;
+    __shared__ int4 s_desc;  // the item's slot, first cell, end cell
     const int tid = threadIdx.x, lane = tid & 63;
     int64_t cur_slot = -1;
     float lql[PT], lqh[PT];
+    const int nitems = p.ctl[1];
+    // thread 0 takes the next item (and reads its description) while the
+    // workgroup works on the current one
+    int next = 0;
+    int4 ndesc{0, 0, 0, 0};
+    if (tid == 0) {
+        next = atomicAdd(&p.ctl[0], 1);
+        if (next < nitems) ndesc = int4{p.items[3 * next], p.items[3 * next + 1], p.items[3 * next + 2], 0};
+    }
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(&p.ctl[0], 1);
+        if (tid == 0) {
+            s_item = next;
+            s_desc = ndesc;
+        }
         __syncthreads();
         const int item = s_item;
-        if (item >= p.ctl[1]) break;  // every workgroup reaches this: the queue only grows
-        const int64_t slot = p.items[3 * item];
-        const int e0 = p.items[3 * item + 1], e1 = p.items[3 * item + 2];
+        if (item >= nitems) break;  // every workgroup reaches this: the queue only grows
+        const int64_t slot = s_desc.x;
+        const int e0 = s_desc.y, e1 = s_desc.z;
+        if (tid == 0) {
+            next = atomicAdd(&p.ctl[0], 1);
+            if (next < nitems) ndesc = int4{p.items[3 * next], p.items[3 * next + 1], p.items[3 * next + 2], 0};
+        }
         const TravHdr h = a.hdr[slot];
         const int64_t mc = a.max_cells;
         const int32_t *g_cs = a.ne_cs + slot * mc, *g_cnt = a.ne_cnt + slot * mc;
@@ -760,13 +806,44 @@ __global__ __launch_bounds__(NT) void k_score_persist(ItemArgs a, PersistArgs p)
             cur_slot = slot;
         }
         float *dst = a.dist + slot * a.lcap;
+        float smin = __builtin_huge_valf();  // this thread's smallest distance of the item
+        bool scored = false;
         int cur_rs = -1;
+        // the item's first kMetaLds cells: their values in LDS, loaded at once
+        for (int e = e0 + tid; e < e1 && e < e0 + kMetaLds; e += NT) {
+            const int sl = g_sl[e], m = e - e0;
+            m_p0[m] = g_beg[e];
+            m_n[m] = g_cnt[e];
+            m_t0[m] = g_cs[e];
+            m_rs[m] = sl & 0xffff;
+            m_i[m] = sij[sl & 0xffff];
+            m_j[m] = sij[sl >> 16];
+            m_cst[m] = g_cst[e];
+        }
+        __syncthreads();
         for (int e = e0; e < e1; ++e) {
-            const int sl = g_sl[e];
-            const int64_t p0 = g_beg[e];
-            const int n = g_cnt[e], t0 = g_cs[e], rs = sl & 0xffff;
-            const int ci = sij[sl & 0xffff], cj = sij[sl >> 16];
-            const float cst = g_cst[e];
+            int64_t p0;
+            int n, t0, rs, ci, cj;
+            float cst;
+            if (e - e0 < kMetaLds) {
+                const int m = e - e0;
+                p0 = m_p0[m];
+                n = m_n[m];
+                t0 = m_t0[m];
+                rs = m_rs[m];
+                ci = m_i[m];
+                cj = m_j[m];
+                cst = m_cst[m];
+            } else {
+                const int sl = g_sl[e];
+                p0 = g_beg[e];
+                n = g_cnt[e];
+                t0 = g_cs[e];
+                rs = sl & 0xffff;
+                ci = sij[sl & 0xffff];
+                cj = sij[sl >> 16];
+                cst = g_cst[e];
+            }
             CodeT ca[CPT], cb[CPT];
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
@@ -812,6 +889,8 @@ __global__ __launch_bounds__(NT) void k_score_persist(ItemArgs a, PersistArgs p)
                     if (o < n) {
                         const float d = cst + lsum<MH>(lut1, ca[j]) + lsum<MH>(lut2, cb[j]);
                         dst[t0 + o] = d;
+                        smin = d < smin ? d : smin;
+                        scored = true;
                         if (a.dbg_pos) {
                             a.dbg_pos[slot * a.dbg_cap + t0 + o] = p0 + o;
                             a.dbg_d[slot * a.dbg_cap + t0 + o] = d;
@@ -820,27 +899,38 @@ __global__ __launch_bounds__(NT) void k_score_persist(ItemArgs a, PersistArgs p)
                 }
             }
         }
-        // the workgroup that completes a query's last item selects its top-k
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) s_last = atomicAdd(&p.qdone[slot], 1) == p.qnit[slot] - 1;
-        __syncthreads();
-        if (!s_last) continue;
-        __threadfence();
+        // A query of one item is selected by the workgroup that scored it, from
+        // its own per-thread minima. Otherwise the workgroup that completes the
+        // query's last item does it (device-wide fences order the other
+        // workgroups' distance stores before its reads) and takes the minima
+        // from the distance row.
+        const bool single = p.qnit[slot] == 1;
+        if (!single) {
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) s_last = atomicAdd(&p.qdone[slot], 1) == p.qnit[slot] - 1;
+            __syncthreads();
+            if (!s_last) continue;
+            __threadfence();
+        }
         const int64_t qs = a.qlist ? a.qlist[slot] : slot;
         const int kq = a.k[qs];
         const int64_t ncand = h.ncand;
         if (kq > NT) continue;  // left to k_select_dist (sel_done stays 0)
-        // per-thread minima of the distance row are samples of distinct
-        // candidates: each wavefront's ceil(kq / waves)-th smallest, the
-        // largest over the wavefronts, bounds the kq-th smallest distance
-        float smin = __builtin_huge_valf();
-        bool any = false;
-        for (int64_t t = tid; t < ncand; t += NT) {
-            const float d = dst[t];
-            smin = d < smin ? d : smin;
-            any = true;
+        // per-thread minima are samples of distinct candidates: each
+        // wavefront's ceil(kq / waves)-th smallest, the largest over the
+        // wavefronts, bounds the kq-th smallest distance
+        bool any = scored;
+        if (!single) {
+            smin = __builtin_huge_valf();
+            any = false;
+            for (int64_t t = tid; t < ncand; t += NT) {
+                const float d = dst[t];
+                smin = d < smin ? d : smin;
+                any = true;
+            }
         }
+        __syncthreads();  // every thread's distance stores, before the read-back
         if (tid == 0) s_nwin = 0;
         {
             const uint32_t u = any ? fkey(smin) : 0xffffffffu;
@@ -866,16 +956,28 @@ __global__ __launch_bounds__(NT) void k_score_persist(ItemArgs a, PersistArgs p)
         __syncthreads();
         const uint32_t tau = s_tau;
         if (tau == 0xffffffffu && ncand > kq) continue;  // fewer than kq samples
-        for (int64_t t = tid; t - tid < ncand; t += NT) {
-            const bool pred = t < ncand && fkey(dst[t < ncand ? t : 0]) <= tau;
-            const uint64_t m = __ballot(pred);
-            if (m) {
-                int base = 0;
-                if (lane == 0) base = atomicAdd(&s_nwin, (int)__popcll(m));
-                base = __shfl(base, 0);
-                if (pred) {
-                    const int wi = base + (int)__popcll(m & ((1ull << lane) - 1ull));
-                    if (wi < kFWin) s_win[wi] = ((uint64_t)fkey(dst[t]) << 32) | (uint32_t)t;
+        constexpr int kFB = 24;  // distances per thread loaded before they are tested
+        for (int64_t b0 = 0; b0 < ncand; b0 += (int64_t)NT * kFB) {
+            float dv[kFB];
+#pragma unroll
+            for (int j = 0; j < kFB; ++j) {
+                const int64_t t = b0 + tid + (int64_t)NT * j;
+                dv[j] = t < ncand ? dst[t] : 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < kFB; ++j) {
+                const int64_t t = b0 + tid + (int64_t)NT * j;
+                const uint32_t key = fkey(dv[j]);
+                const bool pred = t < ncand && key <= tau;
+                const uint64_t m = __ballot(pred);
+                if (m) {
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(&s_nwin, (int)__popcll(m));
+                    base = __shfl(base, 0);
+                    if (pred) {
+                        const int wi = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+                        if (wi < kFWin) s_win[wi] = ((uint64_t)key << 32) | (uint32_t)t;
+                    }
                 }
             }
         }
@@ -883,16 +985,29 @@ __global__ __launch_bounds__(NT) void k_score_persist(ItemArgs a, PersistArgs p)
         const int nwin = s_nwin;
         if (nwin > kFWin) continue;  // many equal distances: left to k_select_dist
         const int nne = h.nne;
+        // a query whose cells are all in this workgroup's LDS resolves ids there
+        const bool meta = single && e0 == 0 && e1 == nne && nne <= kMetaLds;
         for (int i = tid; i < nwin; i += NT) {
             const uint64_t x = s_win[i];
             const int64_t t = (uint32_t)x;
             int lo = 0, hi = nne - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (g_cs[mid] <= t) lo = mid;
-                else hi = mid - 1;
+            int64_t pos;
+            if (meta) {
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (m_t0[mid] <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                pos = m_p0[lo] + (t - m_t0[lo]);
+            } else {
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (g_cs[mid] <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                pos = g_beg[lo] + (t - g_cs[lo]);
             }
-            s_win[i] = (x & 0xffffffff00000000ull) | a.ix.ids[g_beg[lo] + (t - g_cs[lo])];
+            s_win[i] = (x & 0xffffffff00000000ull) | a.ix.ids[pos];
         }
         __syncthreads();
         int64_t *oid = a.out_ids + qs * a.k_max;
@@ -940,8 +1055,9 @@ hipError_t launch_items_persist(const ItemArgs &a, const PersistArgs &p, int wav
                                                  hipSuccess)
         ncu = 256;
     auto go = [&](auto kern, int nt) {
-        int per = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, nt, 0) != hipSuccess || per < 1) per = 1;
+        // at least as many workgroups as the device can hold at once (more
+        // wait, then find the queue empty and leave)
+        const int per = 16;
         const int64_t cap = persist_items_cap(a.nslots, a.lcap, p.tile);
         int64_t grid = (int64_t)ncu * per;
         grid = grid < cap ? grid : cap;
