@@ -62,6 +62,8 @@ def _load():
         lib.orc_search_local.restype = ctypes.c_int
         lib.orc_point_dist_local.argtypes = [ctypes.c_int] * 4 + [P, P, P, P, P, i32, i32, P]
         lib.orc_point_dist_local.restype = ctypes.c_double
+        lib.orc_point_dists.argtypes = [ctypes.c_int] * 4 + [i64] + [P] * 7 + [P, i64, P, P]
+        lib.orc_point_dists.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -138,6 +140,26 @@ def point_dist(ix, q: np.ndarray, i: int, j: int, code: np.ndarray) -> float:
     R = np.ascontiguousarray(ix.R, np.float32)
     return _load().orc_point_dist(ix.D, ix.T, ix.M, ix.Kc, _p(C1), _p(C2), _p(R), _p(q),
                                   int(i), int(j), _p(code))
+
+
+def point_dists(ix, q: np.ndarray, pos: np.ndarray) -> np.ndarray:
+    """FP64 distances from q, given in the index's (rotated, if any) space, to
+    the stored points at storage positions pos, by explicit reconstruction
+    (through the local codebooks when the index has them)."""
+    q = np.ascontiguousarray(q, np.float32)
+    pos = np.ascontiguousarray(pos, np.int64)
+    local = getattr(ix, "QL", None) is not None
+    arrs = [np.ascontiguousarray(ix.C1, np.float32), np.ascontiguousarray(ix.C2, np.float32),
+            np.ascontiguousarray(ix.R, np.float32),
+            np.ascontiguousarray(ix.QL, np.float32) if local else None,
+            np.ascontiguousarray(ix.SL, np.float32) if local else None,
+            np.ascontiguousarray(ix.offsets, np.int64), np.ascontiguousarray(ix.codes, np.uint8)]
+    out = np.empty(pos.size, np.float64)
+    ptrs = [(_p(a) if a is not None else None) for a in arrs]
+    rc = _load().orc_point_dists(ix.D, ix.T, ix.M, ix.Kc, ix.N, *ptrs, _p(q), pos.size, _p(pos), _p(out))
+    if rc != 0:
+        raise ValueError("storage position out of range")
+    return out
 
 
 def point_dist_local(ix, q: np.ndarray, i: int, j: int, code: np.ndarray) -> float:

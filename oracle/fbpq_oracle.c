@@ -306,6 +306,29 @@ double orc_point_dist_local(int D, int T, int M, int Kc, const float *C1, const 
     return orc_dist(D, M, Kc, C1, C2, NULL, QL, SL, q, i, j, code);
 }
 
+/* FP64 distances (O(D) reconstruction, equation approximation; with QL and
+ * SL the local codebooks of equation residual) from q, in the index's space,
+ * to the stored points at storage positions pos[0..n): each point's cell is
+ * found in the offsets. Returns 0, or -1 for a position outside [0, N). */
+int orc_point_dists(int D, int T, int M, int Kc, int64_t N, const float *C1, const float *C2, const float *R,
+                    const float *QL, const float *SL, const int64_t *offsets, const uint8_t *codes,
+                    const float *q, int64_t n, const int64_t *pos, double *out)
+{
+    const int64_t C = (int64_t)T * T;
+    for (int64_t e = 0; e < n; ++e) {
+        const int64_t p = pos[e];
+        if (p < 0 || p >= N) return -1;
+        int64_t lo = 0, hi = C - 1; /* the last cell c with offsets[c] <= p */
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (offsets[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        out[e] = orc_dist(D, M, Kc, C1, C2, R, QL, SL, q, (int32_t)(lo / T), (int32_t)(lo % T), codes + p * M);
+    }
+    return 0;
+}
+
 /* Second step (Section 2.3.3): rerank the candidates by increasing distance,
  * ties by id, and keep the first k. */
 static void orc_rerank(const orc_ix *ix, orc_work *w, const float *q, int64_t ncand,

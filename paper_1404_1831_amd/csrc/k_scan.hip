@@ -18,6 +18,7 @@
 // an LDS array of partial sums, rows then columns, with each row's and
 // column's folded table built once. It keeps the k smallest (distance, id)
 // with select_k after every chunk of candidates.
+#include "codes.h"
 #include "fbpq_dev.h"
 #include "select_k.h"
 
@@ -34,49 +35,9 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t v)
 }
 
 template <int MH>
-struct CodeT;
-template <> struct CodeT<1> { using T = uint8_t; };
-template <> struct CodeT<2> { using T = uint16_t; };
-template <> struct CodeT<4> { using T = uint32_t; };
-template <> struct CodeT<8> { using T = uint2; };
-template <> struct CodeT<16> { using T = uint4; };
-
-template <int MH>
-__device__ __forceinline__ typename CodeT<MH>::T load_code(const uint8_t *__restrict__ codes, int64_t p)
-{
-    return *reinterpret_cast<const typename CodeT<MH>::T *>(codes + p * MH);
-}
-
-template <int MH>
-__device__ __forceinline__ float lut_sum_c(const float *lut, typename CodeT<MH>::T c)
-{
-    float s = 0.f;
-    if constexpr (MH == 1) {
-        s = lut[c];
-    } else if constexpr (MH == 2) {
-        s = lut[c & 255] + lut[kKc + (c >> 8)];
-    } else if constexpr (MH == 4) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s += lut[k * kKc + ((c >> (8 * k)) & 255)];
-    } else if constexpr (MH == 8) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s += lut[k * kKc + ((c.x >> (8 * k)) & 255)];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s += lut[(k + 4) * kKc + ((c.y >> (8 * k)) & 255)];
-    } else {
-        const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) s += lut[(q * 4 + k) * kKc + ((cw[q] >> (8 * k)) & 255)];
-    }
-    return s;
-}
-
-template <int MH>
 __device__ __forceinline__ float lut_sum(const float *lut, const uint8_t *__restrict__ codes, int64_t p)
 {
-    return lut_sum_c<MH>(lut, load_code<MH>(codes, p));
+    return lsum<MH>(lut, load_c<MH>(codes, p));
 }
 
 // last index x in [lo, hi) with v[x] <= t (v ascending over the range, v[lo] <= t)
@@ -482,7 +443,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
         __builtin_amdgcn_wave_barrier();
     };
     // O(D): sum over the half's subspaces of ||(q - c)|k - R_k(b_k)||^2
-    auto od_sum = [&](typename CodeT<MH>::T code) __attribute__((always_inline)) {
+    auto od_sum = [&](typename CodeU<MH>::T code) __attribute__((always_inline)) {
         uint8_t bytes[MH];
         __builtin_memcpy(bytes, &code, MH);
         float acc = 0.f;
@@ -610,7 +571,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
                     ccst = t_cst[xb + lane];
                 }
                 for (int64_t t0 = rs; t0 < re; t0 += 64 * kWideU) {
-                    typename CodeT<MH>::T cv[kWideU];
+                    typename CodeU<MH>::T cv[kWideU];
                     float cst_[kWideU];
 #pragma unroll
                     for (int j = 0; j < kWideU; ++j) {
@@ -619,14 +580,14 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
                         const int32_t cso = __shfl(ccs, o);
                         const int64_t bego = __shfl(cbeg, o);
                         cst_[j] = __shfl(ccst, o);
-                        if (t < re) cv[j] = load_code<MH>(a.ix.codesA, bego + (t - cso));
+                        if (t < re) cv[j] = load_c<MH>(a.ix.codesA, bego + (t - cso));
                     }
 #pragma unroll
                     for (int j = 0; j < kWideU; ++j) {
                         const int64_t t = t0 + 64 * j + lane;
                         if (t < re)
                             dist[t] = OD ? (g == 0 ? 0.f : dist[t]) + od_sum(cv[j])
-                                         : lut_sum_c<MH>(lut, cv[j]) + cst_[j];
+                                         : lsum<MH>(lut, cv[j]) + cst_[j];
                     }
                 }
                 tk = tn;
@@ -654,8 +615,8 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
                 const float csto = __shfl(cst, owner);
                 const int64_t t = t0 + lane;
                 if (t < re) {
-                    const auto code = load_code<MH>(a.ix.codesA, bego + (t - cso));
-                    dist[t] = OD ? (g == 0 ? 0.f : dist[t]) + od_sum(code) : lut_sum_c<MH>(lut, code) + csto;
+                    const auto code = load_c<MH>(a.ix.codesA, bego + (t - cso));
+                    dist[t] = OD ? (g == 0 ? 0.f : dist[t]) + od_sum(code) : lsum<MH>(lut, code) + csto;
                 }
                 // cell of candidate t0 + 64: that of lane 63's candidate, or the next
                 const int o63 = __shfl(owner, 63);
@@ -720,7 +681,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
                     cbeg = t_beg[e];
                 }
                 for (int u0 = us; u0 < ue; u0 += 64 * kWideU) {
-                    typename CodeT<MH>::T cv[kWideU];
+                    typename CodeU<MH>::T cv[kWideU];
                     int64_t tt[kWideU], pp[kWideU];
 #pragma unroll
                     for (int j = 0; j < kWideU; ++j) {
@@ -731,13 +692,13 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
                         const int64_t bego = __shfl(cbeg, o);
                         tt[j] = cso + (uu - preo);
                         pp[j] = bego + (uu - preo);
-                        if (uu < ue) cv[j] = load_code<MH>(a.ix.codesB, pp[j]);
+                        if (uu < ue) cv[j] = load_c<MH>(a.ix.codesB, pp[j]);
                     }
 #pragma unroll
                     for (int j = 0; j < kWideU; ++j) {
                         const int uu = u0 + 64 * j + lane;
                         if (uu < ue) {
-                            const float d = dist[tt[j]] + (OD ? od_sum(cv[j]) : lut_sum_c<MH>(lut, cv[j]));
+                            const float d = dist[tt[j]] + (OD ? od_sum(cv[j]) : lsum<MH>(lut, cv[j]));
                             dist[tt[j]] = d;
                             if (!last) continue;
                             keep(d, tt[j]);
@@ -775,8 +736,8 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
                 if (uu < ue) {
                     const int64_t t = cso + (uu - preo);
                     const int64_t p = bego + (t - cso);
-                    const auto code = load_code<MH>(a.ix.codesB, p);
-                    const float d = dist[t] + (OD ? od_sum(code) : lut_sum_c<MH>(lut, code));
+                    const auto code = load_c<MH>(a.ix.codesB, p);
+                    const float d = dist[t] + (OD ? od_sum(code) : lsum<MH>(lut, code));
                     dist[t] = d;
                     if (last) keep(d, t);
                     if (last && a.dbg_pos) {

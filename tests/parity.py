@@ -25,7 +25,8 @@ def log(msg: str) -> None:
 
 def recon(ix, pos: np.ndarray) -> np.ndarray:
     """FP64 reconstructions [len(pos), D] of stored points (equation
-    approximation; with local codebooks, equation residual of Section 3.2)."""
+    approximation; with local codebooks, equation residual of Section 3.2),
+    for the norm term of the tolerance."""
     cell = np.searchsorted(ix.offsets, pos, side="right") - 1
     i, j = cell // ix.T, cell % ix.T
     x = np.concatenate([ix.C1[i], ix.C2[j]], 1).astype(np.float64)
@@ -48,8 +49,10 @@ def tol(ix, q: np.ndarray, pos: np.ndarray, d64: np.ndarray) -> np.ndarray:
 
 
 def oracle_dists(ix, q: np.ndarray, pos: np.ndarray) -> np.ndarray:
-    x = recon(ix, pos)
-    return ((x - q.astype(np.float64)[None]) ** 2).sum(1)
+    """The oracle's FP64 distances (explicit reconstruction) from q, in the
+    index's space, to the stored points at positions pos."""
+    import oracle
+    return oracle.point_dists(ix, q, pos)
 
 
 def pos_of_ids(ix, ids: np.ndarray) -> np.ndarray:

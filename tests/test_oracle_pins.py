@@ -341,3 +341,20 @@ def test_random_rotation_is_orthogonal_and_seeded():
     assert np.abs(G - np.eye(128)).max() < 1e-5
     assert np.array_equal(R, synth.random_rotation(128, seed=23))
     assert not np.array_equal(R, synth.random_rotation(128, seed=24))
+
+
+def test_point_dists_lossless_and_consistent():
+    """Batch point distances: on a lossless index (codewords equal the
+    displacements) they are the exact squared distances to the stored points,
+    and they equal the one-point entry for every position."""
+    ix = synth.lossless_index(N=400, T=4, M=4, D=16, seed=7)
+    rng = np.random.default_rng(3)
+    q = rng.integers(0, 40, 16).astype(np.float32)
+    pos = np.arange(ix.N)
+    d = oracle.point_dists(ix, q, pos)
+    pts = ix.base[np.asarray(ix.ids, np.int64)].astype(np.float64)
+    assert np.array_equal(d, ((pts - q.astype(np.float64)) ** 2).sum(1))
+    for p in rng.integers(0, ix.N, 20):
+        cell = int(np.searchsorted(ix.offsets, p, side="right") - 1)
+        one = oracle.point_dist(ix, q, cell // ix.T, cell % ix.T, ix.codes[p])
+        assert one == d[p]
