@@ -406,7 +406,12 @@ int fbpq_autotune_cached(fbpq_index *ix, const float *d_q, int64_t nq, const int
 #define FBPQ_STAT_CAND_TWO_PASS 12  /* candidates scored by the two-pass scan in LDS */
 #define FBPQ_STAT_CAND_WIDE 13      /* candidates scored by the two-pass scan with sums in HBM
                                        (once per pass group with adc_od) */
-#define FBPQ_NUM_STATS 14
+#define FBPQ_STAT_FUSED_RESCAN 14   /* cell-scan queries scored again with streamed distances
+                                       because their candidate window overflowed */
+#define FBPQ_STAT_WIN_ADMITTED 15   /* candidates the running bound admitted to those windows */
+#define FBPQ_STAT_WIN_LOST 16       /* windows that overflowed during the scan (before the
+                                       final bound) */
+#define FBPQ_NUM_STATS 17
 int fbpq_stats_read(fbpq_index *ix, int64_t *out, int32_t n, int32_t reset);
 
 /* Device time per kernel stage, measured with HIP events recorded on the

@@ -25,27 +25,34 @@ __device__ __forceinline__ typename CodeU<MH>::T load_c(const uint8_t *__restric
 template <int MH>
 __device__ __forceinline__ float lsum(const float *lut, typename CodeU<MH>::T c)
 {
-    float s = 0.f;
+    // the running sum starts at the first lookup (0 + x = x for every
+    // nonzero x, and the tables hold no -0 that could matter to a sum)
     if constexpr (MH == 1) {
-        s = lut[c];
+        return lut[c];
     } else if constexpr (MH == 2) {
-        s = lut[c & 255] + lut[kKc + (c >> 8)];
+        return lut[c & 255] + lut[kKc + (c >> 8)];
     } else if constexpr (MH == 4) {
+        float s = lut[c & 255];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s += lut[k * kKc + ((c >> (8 * k)) & 255)];
+        for (int k = 1; k < 4; ++k) s += lut[k * kKc + ((c >> (8 * k)) & 255)];
+        return s;
     } else if constexpr (MH == 8) {
+        float s = lut[c.x & 255];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s += lut[k * kKc + ((c.x >> (8 * k)) & 255)];
+        for (int k = 1; k < 4; ++k) s += lut[k * kKc + ((c.x >> (8 * k)) & 255)];
 #pragma unroll
         for (int k = 0; k < 4; ++k) s += lut[(k + 4) * kKc + ((c.y >> (8 * k)) & 255)];
+        return s;
     } else {
         const uint32_t cw[4] = {c.x, c.y, c.z, c.w};
+        float s = lut[cw[0] & 255];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) s += lut[(q * 4 + k) * kKc + ((cw[q] >> (8 * k)) & 255)];
+            for (int k = 0; k < 4; ++k)
+                if (q > 0 || k > 0) s += lut[(q * 4 + k) * kKc + ((cw[q] >> (8 * k)) & 255)];
+        return s;
     }
-    return s;
 }
 
 }  // namespace fbpq

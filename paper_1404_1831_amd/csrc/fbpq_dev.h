@@ -42,7 +42,8 @@ struct TravHdr {
 constexpr int kStatCellScan = 0, kStatFused = 1, kStatTwoPass = 2, kStatPrefixWave = 3, kStatPrefixWG = 4;
 constexpr int kStatWide = 7, kStatWideBands = 8, kStatWideEvals = 9, kStatWideLoads = 10;
 constexpr int kStatCandCell = 11, kStatCandTwoPass = 12, kStatCandWide = 13;  // candidates each scan scored
-constexpr int kNumStatSlots = 16;
+constexpr int kStatFusedRescan = 14, kStatWinAdmitted = 15, kStatWinLost = 16;
+constexpr int kNumStatSlots = 20;
 
 // Candidate block of the cell scan: up to kItem candidates of one nonempty cell.
 constexpr int kItem = 2048;

@@ -12,10 +12,13 @@
 //                 row-major order: LQ sits in LDS, LUT1 is rebuilt only when
 //                 the row changes (the paper's per-row table reuse), LUT2 once
 //                 per cell; the cell's first block of codes is requested before
-//                 its table rows, and the FP32 distances stream to HBM;
-//                 A query whose k fits is then selected in the same workgroup;
+//                 its table rows. A query whose k fits the workgroup keeps only
+//                 the candidates under a running bound in an LDS window and is
+//                 selected there; the others stream their FP32 distances to HBM;
 //  k_select_dist  per query left over, the k smallest (distance, id) of its
 //                 distances.
+#include <type_traits>
+
 #include "codes.h"
 #include "fbpq_dev.h"
 #include "select_k.h"
@@ -117,36 +120,93 @@ __global__ __launch_bounds__(256) void k_lq(ItemArgs a)
 
 // Per-cell values staged in LDS for the first kMetaLds cells of a query.
 constexpr int kMetaLds = 64;
+// The windowed scan synchronises its wavefronts' bounds on the blocks that
+// start below this many candidates of the query.
+constexpr int kSyncBelow = 4096;
 constexpr int kFWin = 512;  // candidates the fused selection can rank
 #ifndef QWAVES
 #define QWAVES 4
 #endif
 
-template <int MH>
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Largest kw-th smallest key of a wavefront's 64 lanes, resolved on the top
+// (32 - LOW) bits and padded with ones below: at least kw of the keys lie at or
+// below the result. LOW = 0 gives the exact key (kw <= 64).
+template <int LOW>
+__device__ __forceinline__ uint32_t wave_kth(uint32_t u, int kw)
+{
+    uint32_t pre = 0;
+    int need = kw;
+#pragma unroll
+    for (int b = 31; b >= LOW; --b) {
+        const uint32_t hm = b == 31 ? 0u : (0xffffffffu << (b + 1));
+        const int cnt = __popcll(__ballot(((u & hm) == pre) && !((u >> b) & 1u)));
+        if (cnt < need) {
+            pre |= 1u << b;
+            need -= cnt;
+        }
+    }
+    return LOW == 0 ? pre : (pre | ((1u << LOW) - 1u));
+}
+
+// STREAM false: the windowed scan and selection of every query whose k fits
+// the workgroup; STREAM true (launched after it): the streamed scan of the
+// queries it left unselected (k above kNT, or an overflowed window).
+template <int MH, bool STREAM>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) void k_score_query(ItemArgs a)
 {
     constexpr int LW = MH * kKc;   // floats of one half table
     constexpr int PT = LW / kNT;   // table floats per thread
+    constexpr int WIN = MH >= 16 ? 512 : 1024;  // candidates the running bound admits
     using CodeT = typename CodeU<MH>::T;
-    __shared__ __align__(16) float lut1[LW];
-    __shared__ __align__(16) float lut2[LW];
+    // LUT1 then LUT2; after the scan, the survivors of the final bound
+    __shared__ __align__(16) float luts[2 * LW];
+    float *const lut1 = luts, *const lut2 = luts + LW;
     __shared__ int64_t m_p0[kMetaLds];
     __shared__ int32_t m_n[kMetaLds], m_t0[kMetaLds], m_rs[kMetaLds], m_i[kMetaLds], m_j[kMetaLds];
     __shared__ float m_cst[kMetaLds];
-    __shared__ uint64_t s_win[kFWin];
-    __shared__ uint32_t s_tau;
-    __shared__ int s_nwin;
+    __shared__ uint64_t s_win[WIN];
+    __shared__ uint32_t s_wb[kNT / 64];  // each wavefront's latest bound
+    __shared__ int s_nwin, s_nsv, s_lost, s_admit;
     const int slot = blockIdx.x;
     const TravHdr h = a.hdr[slot];
     if (h.status != kStOk || h.n_items == 0) return;
-    const int tid = threadIdx.x, lane = tid & 63;
-    if (tid == 0) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t qs = a.qlist ? a.qlist[slot] : slot;
+    const int kq = a.k[qs];
+    if constexpr (STREAM) {
+        if (a.sel_done[slot]) return;  // selected by the windowed scan
+    } else if (kq > kNT) {
+        if (tid == 0) {
+            a.sel_done[slot] = 0;
+            if (a.stats) {
+                atomicAdd(&a.stats[kStatCellScan], 1ull);
+                atomicAdd(&a.stats[kStatCandCell], (unsigned long long)h.ncand);
+            }
+        }
+        return;
+    }
+    if (tid == 0 && !STREAM) {
         a.sel_done[slot] = 0;
+        s_nwin = 0;
+        s_nsv = 0;
+        s_lost = 0;
+        s_admit = 0;
         if (a.stats) {
             atomicAdd(&a.stats[kStatCellScan], 1ull);
             atomicAdd(&a.stats[kStatCandCell], (unsigned long long)h.ncand);
         }
     }
+    if (tid < kNT / 64) s_wb[tid] = 0xffffffffu;
+    const int64_t ncand = h.ncand;
+    const int kw = (kq + kNT / 64 - 1) / (kNT / 64);
     const int64_t mc = a.max_cells;
     const int32_t *g_cs = a.ne_cs + slot * mc, *g_cnt = a.ne_cnt + slot * mc;
     const int32_t *g_sl = a.ne_slot + slot * mc;
@@ -154,16 +214,20 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
     const float *g_cst = a.ne_cst + slot * mc;
     const int32_t *sij = a.slot_ij + (int64_t)slot * 2 * a.P;
     const int nne = h.nne;
-    for (int e = tid; e < nne && e < kMetaLds; e += kNT) {
-        const int sl = g_sl[e];
-        m_p0[e] = g_beg[e];
-        m_n[e] = g_cnt[e];
-        m_t0[e] = g_cs[e];
-        m_rs[e] = sl & 0xffff;
-        m_i[e] = sij[sl & 0xffff];
-        m_j[e] = sij[sl >> 16];
-        m_cst[e] = g_cst[e];
-    }
+    // values of cells e0 .. e0 + kMetaLds - 1 into LDS (slot e mod kMetaLds)
+    auto stage_meta = [&](int e0) {
+        for (int e = e0 + tid; e < nne && e < e0 + kMetaLds; e += kNT) {
+            const int sl = g_sl[e], em = e & (kMetaLds - 1);
+            m_p0[em] = g_beg[e];
+            m_n[em] = g_cnt[e];
+            m_t0[em] = g_cs[e];
+            m_rs[em] = sl & 0xffff;
+            m_i[em] = sij[sl & 0xffff];
+            m_j[em] = sij[sl >> 16];
+            m_cst[em] = g_cst[e];
+        }
+    };
+    stage_meta(0);
     // each thread folds the same table positions for every cell: LQ in registers
     const float *lqg = a.lq + (int64_t)slot * 2 * LW;
     float lql[PT], lqh[PT];
@@ -176,153 +240,232 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
     float *dst = a.dist + (int64_t)slot * a.lcap;
     float smin = __builtin_huge_valf();  // this thread's smallest distance: a selection sample
     bool scored = false;
-    int cur_rs = -1;
-    for (int e = 0; e < nne; ++e) {
-        int64_t p0;
-        int n, t0, rs, ci, cj;
-        float cst;
-        if (e < kMetaLds) {
-            p0 = m_p0[e];
-            n = m_n[e];
-            t0 = m_t0[e];
-            rs = m_rs[e];
-            ci = m_i[e];
-            cj = m_j[e];
-            cst = m_cst[e];
-        } else {
-            const int sl = g_sl[e];
-            p0 = g_beg[e];
-            n = g_cnt[e];
-            t0 = g_cs[e];
-            rs = sl & 0xffff;
-            ci = sij[sl & 0xffff];
-            cj = sij[sl >> 16];
-            cst = g_cst[e];
-        }
-        CodeT ca[kCPT], cb[kCPT];
+
+    // One pass over the query's cells. Streamed (WINDOW false): every distance
+    // goes to HBM for k_select_dist. Windowed: each thread's minimum is a
+    // sample (the distance of a distinct candidate), so a value with kq
+    // samples at or below it bounds the kq-th smallest distance from above;
+    // after each block of codes every wavefront publishes the bound of its own
+    // samples (ceil(kq/4) of them), and the largest of the four published
+    // bounds admits a candidate into the LDS window. Samples only decrease, so
+    // a bound read before its wavefront's latest update is still a bound, and
+    // every candidate of the final kq smallest is admitted. A window past half
+    // full is compacted to the current bound at the next cell.
+    // the largest published wavefront bound
+    auto cur_bound = [&]() {
+        uint32_t tau = 0;
 #pragma unroll
-        for (int j = 0; j < kCPT; ++j) {
-            const int o = tid + kNT * j;
-            if (o < n) {
-                ca[j] = load_c<MH>(a.ix.codesA, p0 + o);
-                cb[j] = load_c<MH>(a.ix.codesB, p0 + o);
+        for (int w = 0; w < kNT / 64; ++w) {
+            const uint32_t b = __hip_atomic_load(&s_wb[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            tau = b > tau ? b : tau;
+        }
+        return tau;
+    };
+    // wavefront-wide append of the lanes whose pred holds (one LDS atomic)
+    auto append = [&](bool pred, uint64_t x, bool fresh) {
+        const uint64_t m = __ballot(pred);
+        if (m) {
+            int base = 0;
+            if (lane == 0) {
+                base = atomicAdd(&s_nwin, (int)__popcll(m));
+                if (fresh && a.stats) atomicAdd(&s_admit, (int)__popcll(m));
+            }
+            base = __shfl(base, 0);
+            if (pred) {
+                const int wi = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+                if (wi < WIN) s_win[wi] = x;
             }
         }
-        const bool newrow = rs != cur_rs;
-        float c1[PT], c2[PT];
-        const float *cr2 = a.ix.CR2 + (int64_t)cj * LW;
-#pragma unroll
-        for (int u = 0; u < PT; ++u) c2[u] = cr2[tid + kNT * u];
-        if (newrow) {
-            const float *cr1 = a.ix.CR1 + (int64_t)ci * LW;
-#pragma unroll
-            for (int u = 0; u < PT; ++u) c1[u] = cr1[tid + kNT * u];
-        }
-        __syncthreads();  // the previous cell's lookups are done
-#pragma unroll
-        for (int u = 0; u < PT; ++u) lut2[tid + kNT * u] = lqh[u] + c2[u];
-        if (newrow) {
-#pragma unroll
-            for (int u = 0; u < PT; ++u) lut1[tid + kNT * u] = lql[u] + c1[u];
-        }
-        cur_rs = rs;
-        __syncthreads();
-        for (int o0 = 0; o0 < n; o0 += kItem) {
-            if (o0 > 0) {
-#pragma unroll
-                for (int j = 0; j < kCPT; ++j) {
-                    const int o = o0 + tid + kNT * j;
-                    if (o < n) {
-                        ca[j] = load_c<MH>(a.ix.codesA, p0 + o);
-                        cb[j] = load_c<MH>(a.ix.codesB, p0 + o);
-                    }
-                }
+    };
+    auto scan = [&](auto window) {
+        constexpr bool WINDOW = decltype(window)::value;
+        int cur_rs = -1, last_upd = 0;
+        for (int e = 0; e < nne; ++e) {
+            const int em = e & (kMetaLds - 1);
+            if (em == 0 && e > 0) {
+                // the next kMetaLds cells' values: every thread read the
+                // previous ones before the last cell's barriers
+                stage_meta(e);
+                __syncthreads();
             }
+            // the cell's values are the same in every lane: scalar registers
+            const int64_t p0 = uni64(m_p0[em]);
+            const int n = uni(m_n[em]), t0 = uni(m_t0[em]), rs = uni(m_rs[em]), ci = uni(m_i[em]), cj = uni(m_j[em]);
+            const float cst = __int_as_float(uni(__float_as_int(m_cst[em])));
+            // candidate t0 + o goes to thread (t0 + o) mod kNT, so that every
+            // thread holds samples however small the cells are
+            const int rot = (tid - t0) & (kNT - 1);
+            const uint8_t *const ba = a.ix.codesA + p0 * MH, *const bb = a.ix.codesB + p0 * MH;
+            CodeT ca[kCPT], cb[kCPT];
 #pragma unroll
             for (int j = 0; j < kCPT; ++j) {
-                const int o = o0 + tid + kNT * j;
+                const int o = rot + kNT * j;
                 if (o < n) {
-                    const float d = cst + lsum<MH>(lut1, ca[j]) + lsum<MH>(lut2, cb[j]);
-                    dst[t0 + o] = d;
-                    smin = d < smin ? d : smin;
-                    scored = true;
+                    ca[j] = *reinterpret_cast<const CodeT *>(ba + (uint32_t)o * MH);
+                    cb[j] = *reinterpret_cast<const CodeT *>(bb + (uint32_t)o * MH);
+                }
+            }
+            const bool newrow = rs != cur_rs;
+            float c1[PT], c2[PT];
+            const float *cr2 = a.ix.CR2 + (int64_t)cj * LW;
+#pragma unroll
+            for (int u = 0; u < PT; ++u) c2[u] = cr2[tid + kNT * u];
+            if (newrow) {
+                const float *cr1 = a.ix.CR1 + (int64_t)ci * LW;
+#pragma unroll
+                for (int u = 0; u < PT; ++u) c1[u] = cr1[tid + kNT * u];
+            }
+            __syncthreads();  // the previous cell's lookups and appends are done
+            if constexpr (WINDOW) {
+                // a window past half full keeps only what the current bound admits
+                const int nw = s_nwin;
+                if (nw > WIN / 2) {
+                    const uint32_t tau = cur_bound();
+                    uint64_t keep[WIN / kNT];
+#pragma unroll
+                    for (int u = 0; u < WIN / kNT; ++u) {
+                        const int i = tid + kNT * u;
+                        keep[u] = i < nw && i < WIN ? s_win[i] : ~0ull;
+                    }
+                    __syncthreads();
+                    if (tid == 0) {
+                        if (nw > WIN) s_lost = 1;
+                        s_nwin = 0;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int u = 0; u < WIN / kNT; ++u) append((uint32_t)(keep[u] >> 32) <= tau && keep[u] != ~0ull, keep[u], false);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < PT; ++u) lut2[tid + kNT * u] = lqh[u] + c2[u];
+            if (newrow) {
+#pragma unroll
+                for (int u = 0; u < PT; ++u) lut1[tid + kNT * u] = lql[u] + c1[u];
+            }
+            cur_rs = rs;
+            __syncthreads();
+            for (int o0 = 0; o0 < n; o0 += kItem) {
+                if (o0 > 0) {
+#pragma unroll
+                    for (int j = 0; j < kCPT; ++j) {
+                        const int o = o0 + rot + kNT * j;
+                        if (o < n) {
+                            ca[j] = *reinterpret_cast<const CodeT *>(ba + (uint32_t)o * MH);
+                            cb[j] = *reinterpret_cast<const CodeT *>(bb + (uint32_t)o * MH);
+                        }
+                    }
+                }
+                if constexpr (!WINDOW) {
+                    // streamed: each distance stored as it is made
+#pragma unroll
+                    for (int j = 0; j < kCPT; ++j) {
+                        const int o = o0 + rot + kNT * j;
+                        if (o < n) {
+                            const float d = cst + lsum<MH>(lut1, ca[j]) + lsum<MH>(lut2, cb[j]);
+                            dst[t0 + o] = d;
+                            if (a.dbg_pos) {
+                                a.dbg_pos[(int64_t)slot * a.dbg_cap + t0 + o] = p0 + o;
+                                a.dbg_d[(int64_t)slot * a.dbg_cap + t0 + o] = d;
+                            }
+                        }
+                    }
+                } else {
+                    float dv[kCPT];
+#pragma unroll
+                    for (int j = 0; j < kCPT; ++j) {
+                        const int o = o0 + rot + kNT * j;
+                        if (o < n) {
+                            const float d = cst + lsum<MH>(lut1, ca[j]) + lsum<MH>(lut2, cb[j]);
+                            dv[j] = d;
+                            smin = d < smin ? d : smin;
+                            scored = true;
+                        }
+                    }
                     if (a.dbg_pos) {
-                        a.dbg_pos[(int64_t)slot * a.dbg_cap + t0 + o] = p0 + o;
-                        a.dbg_d[(int64_t)slot * a.dbg_cap + t0 + o] = d;
+#pragma unroll
+                        for (int j = 0; j < kCPT; ++j) {
+                            const int o = o0 + rot + kNT * j;
+                            if (o < n) {
+                                a.dbg_pos[(int64_t)slot * a.dbg_cap + t0 + o] = p0 + o;
+                                a.dbg_d[(int64_t)slot * a.dbg_cap + t0 + o] = dv[j];
+                            }
+                        }
+                    }
+                    // the bounds are taken again on every block of the first
+                    // kSyncBelow candidates, where they fall fastest (with every
+                    // wavefront's bound of the block awaited), then each time the
+                    // candidates seen have grown by a quarter since the last time
+                    const int seen = t0 + o0;
+                    if (seen < kSyncBelow || 4 * seen >= 5 * last_upd) {
+                        const uint32_t wb = wave_kth<16>(scored ? fkey(smin) : 0xffffffffu, kw);
+                        if (lane == 0) __hip_atomic_store(&s_wb[wave], wb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        last_upd = seen;
+                    }
+                    if (seen < kSyncBelow) __syncthreads();
+                    const uint32_t tau = cur_bound();
+#pragma unroll
+                    for (int j = 0; j < kCPT; ++j) {
+                        const int o = o0 + rot + kNT * j;
+                        const uint32_t key = fkey(dv[j]);
+                        append(o < n && key <= tau, ((uint64_t)key << 32) | (uint32_t)(t0 + o), true);
                     }
                 }
             }
         }
+    };
+
+    if constexpr (STREAM) {
+        scan(std::false_type{});
+        return;
+    } else {
+        scan(std::true_type{});
     }
 
-    // Fused selection of the kq smallest (distance, id). Per-thread minima are
-    // samples, each the distance of a distinct candidate, so any value with kq
-    // samples at or below it bounds the kq-th smallest distance. The distances
-    // are read back while they are still in the cache. Queries with kq above
-    // the thread count, too few samples or too many candidates at or below the
-    // bound are left to k_select_dist.
-    const int64_t qs = a.qlist ? a.qlist[slot] : slot;
-    const int kq = a.k[qs];
-    const int64_t ncand = h.ncand;
-    if (kq > kNT) return;
-    // Each wavefront finds the ceil(kq/4)-th smallest of its own 64 samples;
-    // the largest of the four has at least kq samples at or below it.
-    __shared__ uint32_t s_wtau[kNT / 64];
-    if (tid == 0) s_nwin = 0;
-    {
-        const uint32_t u = scored ? fkey(smin) : 0xffffffffu;
-        const int kw = (kq + kNT / 64 - 1) / (kNT / 64);
-        uint32_t pre = 0;
-        int need = kw;
-        for (int b = 31; b >= 0; --b) {
-            const uint32_t hm = b == 31 ? 0u : (0xffffffffu << (b + 1));
-            const int cnt = __popcll(__ballot(((u & hm) == pre) && !((u >> b) & 1u)));
-            if (cnt < need) {
-                pre |= 1u << b;
-                need -= cnt;
-            }
-        }
-        if (lane == 0) s_wtau[tid >> 6] = pre;
+    // Fused selection of the kq smallest (distance, id): the exact bound of
+    // the final samples keeps the window entries that can rank (all of them
+    // when there are at most kq candidates).
+    __syncthreads();  // every append and every table lookup is done
+    if (tid == 0 && a.stats) {
+        atomicAdd(&a.stats[kStatWinAdmitted], (unsigned long long)s_admit);
+        if (s_lost || s_nwin > WIN) atomicAdd(&a.stats[kStatWinLost], 1ull);
     }
-    __syncthreads();  // the wavefront bounds, and every thread's distance stores
-    if (tid == 0) {
-        uint32_t m = 0;
-        for (int w = 0; w < kNT / 64; ++w) m = s_wtau[w] > m ? s_wtau[w] : m;
-        s_tau = ncand <= kq ? 0xffffffffu : m;
+    const int nwin = s_lost ? WIN + 1 : s_nwin;
+    if (nwin <= WIN) {
+        const uint32_t wt = wave_kth<0>(scored ? fkey(smin) : 0xffffffffu, kw);
+        if (lane == 0) s_wb[wave] = wt;
     }
     __syncthreads();
-    const uint32_t tau = s_tau;
-    if (tau == 0xffffffffu && ncand > kq) return;  // fewer than kq samples
-    constexpr int kFB = 24;  // distances per thread loaded before they are tested
-    for (int64_t b0 = 0; b0 < ncand; b0 += kNT * kFB) {
-        float dv[kFB];
+    uint64_t *sv = reinterpret_cast<uint64_t *>(luts);  // LW survivors fit
+    if (nwin <= WIN) {
+        uint32_t tau = 0;
 #pragma unroll
-        for (int j = 0; j < kFB; ++j) {
-            const int64_t t = b0 + tid + kNT * j;
-            dv[j] = t < ncand ? dst[t] : 0.f;
-        }
-#pragma unroll
-        for (int j = 0; j < kFB; ++j) {
-            const int64_t t = b0 + tid + kNT * j;
-            const uint32_t key = fkey(dv[j]);
-            const bool pred = t < ncand && key <= tau;
+        for (int w = 0; w < kNT / 64; ++w) tau = s_wb[w] > tau ? s_wb[w] : tau;
+        if (ncand <= kq) tau = 0xffffffffu;
+        for (int i0 = 0; i0 < nwin; i0 += kNT) {
+            const int i = i0 + tid;
+            const uint64_t x = i < nwin ? s_win[i] : 0;
+            const bool pred = i < nwin && (uint32_t)(x >> 32) <= tau;
             const uint64_t m = __ballot(pred);
             if (m) {
                 int base = 0;
-                if (lane == 0) base = atomicAdd(&s_nwin, (int)__popcll(m));
+                if (lane == 0) base = atomicAdd(&s_nsv, (int)__popcll(m));
                 base = __shfl(base, 0);
-                if (pred) {
-                    const int wi = base + (int)__popcll(m & ((1ull << lane) - 1ull));
-                    if (wi < kFWin) s_win[wi] = ((uint64_t)key << 32) | (uint32_t)t;
-                }
+                const int si = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+                if (pred && si < LW) sv[si] = x;
             }
         }
     }
     __syncthreads();
-    const int nwin = s_nwin;
-    if (nwin > kFWin) return;
-    for (int i = tid; i < nwin; i += kNT) {
-        const uint64_t x = s_win[i];
+    const int nsv = s_nsv;
+    if (nwin > WIN || nsv > LW) {
+        // the window or the survivors overflowed (many candidates at the
+        // bound): the streamed scan scores this query again
+        if (tid == 0 && a.stats) atomicAdd(&a.stats[kStatFusedRescan], 1ull);
+        return;
+    }
+    for (int i = tid; i < nsv; i += kNT) {
+        const uint64_t x = sv[i];
         const int64_t t = (uint32_t)x;
         int lo = 0, hi = nne - 1;
         int64_t p;
@@ -341,16 +484,16 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(QWAVES))) v
             }
             p = g_beg[lo] + (t - g_cs[lo]);
         }
-        s_win[i] = (x & 0xffffffff00000000ull) | a.ix.ids[p];
+        sv[i] = (x & 0xffffffff00000000ull) | a.ix.ids[p];
     }
     __syncthreads();
     int64_t *oid = a.out_ids + qs * a.k_max;
     float *od = a.out_d + qs * a.k_max;
-    const int nk = nwin < kq ? nwin : kq;
-    for (int i = tid; i < nwin; i += kNT) {
-        const uint64_t x = s_win[i];
+    const int nk = nsv < kq ? nsv : kq;
+    for (int i = tid; i < nsv; i += kNT) {
+        const uint64_t x = sv[i];
         int rank = 0;
-        for (int j = 0; j < nwin; ++j) rank += s_win[j] < x;
+        for (int j = 0; j < nsv; ++j) rank += sv[j] < x;
         if (rank < nk) {
             oid[rank] = (int64_t)(uint32_t)x;
             od[rank] = unfkey((uint32_t)(x >> 32));
@@ -593,12 +736,16 @@ hipError_t launch_items_scan(const ItemArgs &a, hipStream_t st)
 {
     if (a.nslots == 0) return hipSuccess;
     const dim3 g((unsigned)a.nslots), b(kNT);
+    auto go = [&](auto win, auto str) {
+        hipLaunchKernelGGL(win, g, b, 0, st, a);
+        hipLaunchKernelGGL(str, g, b, 0, st, a);
+    };
     switch (a.ix.M / 2) {
-    case 1: hipLaunchKernelGGL(k_score_query<1>, g, b, 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_score_query<2>, g, b, 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_score_query<4>, g, b, 0, st, a); break;
-    case 8: hipLaunchKernelGGL(k_score_query<8>, g, b, 0, st, a); break;
-    case 16: hipLaunchKernelGGL(k_score_query<16>, g, b, 0, st, a); break;
+    case 1: go(k_score_query<1, false>, k_score_query<1, true>); break;
+    case 2: go(k_score_query<2, false>, k_score_query<2, true>); break;
+    case 4: go(k_score_query<4, false>, k_score_query<4, true>); break;
+    case 8: go(k_score_query<8, false>, k_score_query<8, true>); break;
+    case 16: go(k_score_query<16, false>, k_score_query<16, true>); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -44,7 +44,8 @@ STAGES = ("half_keys", "prefix", "prefix_fb", "traverse", "layout", "lq", "score
 SERVER_STATS = ("submitted", "completed", "failed", "timeout", "cancelled", "rejected", "batches", "batched",
                 "peak_reserved", "peak_batch_reserved", "budget", "lane_budget", "pending")
 STATS = ("cell_scan", "fused_topk", "two_pass", "prefix_wave", "prefix_wg", "retried", "graph_replays",
-         "wide", "wide_bands", "wide_evals", "wide_loads", "cand_cell_scan", "cand_two_pass", "cand_wide")
+         "wide", "wide_bands", "wide_evals", "wide_loads", "cand_cell_scan", "cand_two_pass", "cand_wide",
+         "fused_rescan", "win_admitted", "win_lost")
 
 
 class FbpqError(RuntimeError):

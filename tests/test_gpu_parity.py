@@ -757,11 +757,36 @@ def test_fused_topk_and_fallbacks(fb, const_codes, k):
     log(f"  counters {st}")
     assert st["cell_scan"] == Q.shape[0] and st["two_pass"] == 0
     if k > 256:
-        assert st["fused_topk"] == 0  # k above the sample count
-    elif const_codes:
-        assert st["fused_topk"] < Q.shape[0]  # a whole cell ties at the bound: window overflow
-    elif k <= 100:
-        assert st["fused_topk"] > 0  # (k near the sample count overflows the window: fallback)
+        assert st["fused_topk"] == 0 and st["fused_rescan"] == 0  # k above the sample count: streamed
+    else:
+        # every query is either selected in the scan or scored again, streamed
+        assert st["fused_topk"] + st["fused_rescan"] == Q.shape[0]
+        if const_codes:
+            assert st["fused_rescan"] > 0  # a whole cell ties at the bound: window overflow
+        elif k <= 100:
+            assert st["fused_topk"] > 0
+    o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
+    assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
+
+
+@pytest.mark.parametrize("k,L", [(256, 30000), (100, 60000), (1, 20000)])
+def test_window_compaction_and_bounds(fb, gmm_small, k, L):
+    # k = 256 gives each wavefront's bound its loosest form (the largest of its
+    # 64 samples), so the window passes half full and is compacted; long lists
+    # take the bounds at growing intervals. Every query is either selected in
+    # the scan or scored again, and the top-k equals the oracle's.
+    ix, Q = gmm_small
+    Q = Q[:24]
+    log(f"window: N=1e5 T=64 M=8 nq=24 L={L} k={k}")
+    h = _open(fb, ix, stats=1, items=1)
+    g_ids, g_d = fb.fbpq_search(h, Q, L, k)
+    st = fb.fbpq_stats_read(h)
+    fb.fbpq_free_index(h)
+    log(f"  counters {st}")
+    assert st["fused_topk"] + st["fused_rescan"] == st["cell_scan"] == Q.shape[0]
+    assert st["fused_topk"] > 0
+    if k == 256:
+        assert st["win_admitted"] > 512 * Q.shape[0]  # more than half a window per query
     o_ids, o_d, _, _ = oracle.search(ix, Q, L, k)
     assert_topk(ix, Q, k, g_ids, g_d, o_ids, o_d)
 
