@@ -55,4 +55,38 @@ __device__ __forceinline__ float lsum(const float *lut, typename CodeU<MH>::T c)
     }
 }
 
+// Byte k of a code word (k < MH).
+template <int MH>
+__device__ __forceinline__ uint32_t code_byte(typename CodeU<MH>::T c, int k)
+{
+    if constexpr (MH <= 4) {
+        return ((uint32_t)c >> (8 * k)) & 255u;
+    } else if constexpr (MH == 8) {
+        return ((k < 4 ? c.x : c.y) >> (8 * (k & 3))) & 255u;
+    } else {
+        const uint32_t w = k < 4 ? c.x : k < 8 ? c.y : k < 12 ? c.z : c.w;
+        return (w >> (8 * (k & 3))) & 255u;
+    }
+}
+
+// cst + lsum(lut1, ca) + lsum(lut2, cb), the same additions in the same
+// order, with all 2 * MH lookups issued before the first addition, so a
+// wavefront keeps them in flight together.
+template <int MH>
+__device__ __forceinline__ float dsum(const float *lut1, const float *lut2, typename CodeU<MH>::T ca,
+                                      typename CodeU<MH>::T cb, float cst)
+{
+    float v1[MH], v2[MH];
+#pragma unroll
+    for (int k = 0; k < MH; ++k) v1[k] = lut1[k * kKc + code_byte<MH>(ca, k)];
+#pragma unroll
+    for (int k = 0; k < MH; ++k) v2[k] = lut2[k * kKc + code_byte<MH>(cb, k)];
+    float s1 = v1[0], s2 = v2[0];
+#pragma unroll
+    for (int k = 1; k < MH; ++k) s1 += v1[k];
+#pragma unroll
+    for (int k = 1; k < MH; ++k) s2 += v2[k];
+    return cst + s1 + s2;
+}
+
 }  // namespace fbpq

@@ -1022,10 +1022,22 @@ __global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) 
         int bin = 0;
         uint32_t low = 0;
         if (lane == L) {
-            const uint32_t v[4] = {hb.x, hb.y, hb.z, hb.w};
+            // the first of the lane's four bins where the count reaches need
+            // (no indexed array: the dispatch needs no scratch memory)
             uint32_t c = exc;
             int j = 0;
-            while (j < 3 && c + v[j] < (uint32_t)need) c += v[j++];
+            if (c + hb.x < (uint32_t)need) {
+                c += hb.x;
+                j = 1;
+                if (c + hb.y < (uint32_t)need) {
+                    c += hb.y;
+                    j = 2;
+                    if (c + hb.z < (uint32_t)need) {
+                        c += hb.z;
+                        j = 3;
+                    }
+                }
+            }
             bin = 4 * L + j;
             low = c;
         }

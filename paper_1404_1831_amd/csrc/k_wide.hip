@@ -1013,9 +1013,10 @@ hipError_t launch_traverse_big(const TravArgs &a, int64_t nslots, hipStream_t st
 // ---- workgroup form of the row-major layout, for large visited sets ---------
 // Same outputs as the one-wavefront layout kernel (compacted nonempty cells in
 // row-major order, per-row and per-column starts, column lists, LUT slots),
-// with 1024 threads taking kLayE consecutive cells each per step, so that a
-// query with 10^5 visited cells needs about fifty dependent steps.
-constexpr int kLayNT = 1024;
+// with 512 threads taking kLayE consecutive cells each per step, so that a
+// query with 10^5 visited cells needs about fifty dependent steps (512
+// threads keep every value in registers: no scratch memory for the dispatch).
+constexpr int kLayNT = 512;
 constexpr int kLayE = 4;
 
 // exclusive prefix of x[0..n) in place (n <= kLayNT * per), returns the total
@@ -1089,7 +1090,7 @@ __global__ __launch_bounds__(kLayNT) void k_layout_wide(LayoutArgs args)
     __syncthreads();
 
     // cell of diagram position xi: row by binary search over rc, then column
-    auto cells = [&](int64_t x0, int *as, int *bs, int64_t *begs, int64_t *cnts) __attribute__((always_inline)) {
+    auto cells = [&](int64_t x0, int (&as)[E], int (&bs)[E], int64_t (&begs)[E], int64_t (&cnts)[E]) __attribute__((always_inline)) {
         int lo[E], hi[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
