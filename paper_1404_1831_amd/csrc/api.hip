@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -64,6 +65,9 @@ struct fbpq_index {
     uint8_t *codesA = nullptr, *codesB = nullptr;
     uint32_t *ids = nullptr;
     float *CR1 = nullptr, *CR2 = nullptr, *nR = nullptr, *nC1 = nullptr, *nC2 = nullptr;
+    _Float16 *Cs1 = nullptr, *Cs2 = nullptr;  // two-part FP16 half-centroids (D/2 = 64)
+    float csc1 = 1.f, csc2 = 1.f;
+    bool split_keys = true;  // option "split_keys": approximate keys from the FP16 parts
     size_t base_bytes = 0, table_bytes = 0;
     // workspace, grown on demand: slots [0, 48) for the first round of a
     // search (the round a graph captures), [48, 96) for its retry rounds
@@ -141,13 +145,14 @@ struct fbpq_index {
         bool persist;
         int32_t tile, pwaves;
         unsigned long long *stats;
+        bool split;
         bool operator==(const GraphKey &o) const
         {
             return d_q == o.d_q && nq == o.nq && lcap == o.lcap && max_cells == o.max_cells &&
                    ws_gen == o.ws_gen && d_ids == o.d_ids && d_d == o.d_d && k_max == o.k_max && P == o.P &&
                    chunk == o.chunk && pop_budget == o.pop_budget && items == o.items &&
                    block_min == o.block_min && persist == o.persist && tile == o.tile && pwaves == o.pwaves &&
-                   stats == o.stats;
+                   stats == o.stats && split == o.split;
         }
     } gkey{};
     int64_t graph_replays = 0;
@@ -362,7 +367,7 @@ void free_all(fbpq_index *ix)
     (void)hipSetDevice(ix->device);
     if (ix->stream) (void)hipStreamSynchronize(ix->stream);
     void *ps[] = {ix->C1, ix->C2, ix->R, ix->offsets, ix->codesA, ix->codesB, ix->ids,
-                  ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2, ix->QL, ix->SL, ix->Rot};
+                  ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2, ix->QL, ix->SL, ix->Rot, ix->Cs1, ix->Cs2};
     if (!ix->shared)
         for (void *p : ps)
             if (p) (void)hipFree(p);
@@ -470,6 +475,7 @@ int create_impl(const fbpq_index_desc *d, int device, fbpq_index **out)
     v.SL = ix->SL;
     v.Rot = ix->Rot;
     v.local = ix->QL ? 1 : 0;
+    v.ecoef = 1.25f * (d->D / 2 + 8);
     *out = ix;
     return FBPQ_OK;
 }
@@ -1055,7 +1061,8 @@ int search_impl(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t *L, 
     // same, else run it eagerly (and capture it for the next call)
     const bool use_graph = ix->graph && !dbg && !ix->profile && !ix->use_arena;
     fbpq_index::GraphKey key{d_q, nq, lcap, max_cells, ix->ws_gen, d_ids, d_d, k_max, P, ix->chunk, ix->pop_budget,
-                             ix->items, ix->block_min, ix->persist, ix->tile, ix->pwaves, ix->stats_dev};
+                             ix->items, ix->block_min, ix->persist, ix->tile, ix->pwaves, ix->stats_dev,
+                             ix->dv.Cs1 != nullptr};
     if (use_graph && ix->gexec && ix->gkey == key) {
         HCK(ix, hipGraphLaunch(ix->gexec, st));
         ++ix->graph_replays;
@@ -1291,6 +1298,11 @@ int lane_create(fbpq_index *src, fbpq_index **out)
     ix->nR = src->nR;
     ix->nC1 = src->nC1;
     ix->nC2 = src->nC2;
+    ix->Cs1 = src->Cs1;
+    ix->Cs2 = src->Cs2;
+    ix->csc1 = src->csc1;
+    ix->csc2 = src->csc2;
+    ix->split_keys = src->split_keys;
     ix->prefix = src->prefix;
     ix->max_cells = src->max_cells;
     ix->chunk = src->chunk;
@@ -1391,6 +1403,22 @@ int fbpq_load_index(const char *path, int device, fbpq_index **out)
     return create_impl(&d, device, out);
 }
 
+// Approximate keys from the split FP16 half-centroids (when built and
+// enabled) or from FP32 products, with the error coefficient that goes with
+// them: 1.25 (h + 8) for FP32 sums of h products; 1.25 (2.5 h + 17) for the
+// split form, whose sums run over 3 h exact products and drop terms below
+// 3 2^-22 |q| |c|.
+static void set_key_form(fbpq_index *ix)
+{
+    const int h = ix->dv.D / 2;
+    const bool split = ix->split_keys && ix->Cs1 && ix->Cs2;
+    ix->dv.Cs1 = split ? ix->Cs1 : nullptr;
+    ix->dv.Cs2 = split ? ix->Cs2 : nullptr;
+    ix->dv.csc1 = ix->csc1;
+    ix->dv.csc2 = ix->csc2;
+    ix->dv.ecoef = split ? 1.25f * (2.5f * h + 17.f) : 1.25f * (h + 8.f);
+}
+
 int fbpq_build_tables(fbpq_index *ix)
 {
     TRY(check_handle(ix));
@@ -1414,6 +1442,31 @@ int fbpq_build_tables(fbpq_index *ix)
         ix->dv.cmax1 = *std::max_element(n1.begin(), n1.end());
         ix->dv.cmax2 = *std::max_element(n2.begin(), n2.end());
     }
+    if (ix->dv.D / 2 == 64) {
+        // two-part FP16 half-centroids for the approximate keys, each half
+        // scaled by a power of two to a largest magnitude below 2^14
+        const int h = 64;
+        const size_t sb = sizeof(_Float16) * T * 2 * h;
+        if (hipMalloc(&ix->Cs1, sb) != hipSuccess || hipMalloc(&ix->Cs2, sb) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(FBPQ_E_OOM, "table allocation failed");
+        }
+        std::vector<float> c((size_t)T * h);
+        float *scs[2] = {&ix->csc1, &ix->csc2};
+        const float *src[2] = {ix->C1, ix->C2};
+        _Float16 *dst[2] = {ix->Cs1, ix->Cs2};
+        for (int half = 0; half < 2; ++half) {
+            HCK(ix, hipMemcpy(c.data(), src[half], sizeof(float) * c.size(), hipMemcpyDeviceToHost));
+            float mx = 0.f;
+            for (float x : c) mx = std::max(mx, std::fabs(x));
+            int ex = 0;
+            (void)std::frexp(mx, &ex);  // mx < 2^ex
+            *scs[half] = std::ldexp(1.f, 14 - ex);
+            HCK(ix, launch_split_centroids(src[half], T, h, *scs[half], dst[half], ix->stream));
+        }
+        HCK(ix, hipStreamSynchronize(ix->stream));
+    }
+    set_key_form(ix);
     ix->dv.CR1 = ix->CR1;
     ix->dv.CR2 = ix->CR2;
     ix->dv.nR = ix->nR;
@@ -1675,6 +1728,9 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
         ix->profile = value != 0;
     } else if (!strcmp(key, "profile_mask")) {
         ix->prof_mask = value;
+    } else if (!strcmp(key, "split_keys")) {
+        ix->split_keys = value != 0;
+        set_key_form(ix);
     } else if (!strcmp(key, "graph")) {
         ix->graph = value != 0;
         if (!ix->graph && ix->gexec) {

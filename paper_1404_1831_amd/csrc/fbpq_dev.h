@@ -67,6 +67,14 @@ struct DevIndex {
     const float *Rot;      // OPQ rotation [D][D] row-major, or null
     int32_t local;         // 1: local codebooks
     int32_t od;            // 1: candidates scored by explicit O(D) reconstruction (Multi-D-ADC baseline)
+    // Half-centroids scaled by csc (a power of two) and split into two FP16
+    // parts, hi = fp16(c csc) and lo = fp16(c csc - hi), row c at [c][2 D/2]
+    // (hi then lo); null when the approximate keys use FP32 products only.
+    const _Float16 *Cs1, *Cs2;
+    float csc1, csc2;
+    // e(q) = ecoef 2^-23 (||q_h|| + max ||c||)^2 bounds the error of every
+    // approximate key (FP32 products, or the split FP16 ones)
+    float ecoef;
 };
 
 // Launchers (each defined next to its kernel).
@@ -78,6 +86,9 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 hipError_t launch_sanitize(const int64_t *L, const int32_t *k, int64_t n, int64_t L_max, int32_t k_max, int64_t *Lo,
                            int32_t *ko, int32_t *nclamped, hipStream_t st);
 hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, hipStream_t st);  // *dst = *src on the stream
+
+// out[c][0, h) = fp16(C[c] scale), out[c][h, 2h) = fp16(C[c] scale - hi) for T rows of h floats
+hipError_t launch_split_centroids(const float *C, int64_t T, int h, float scale, _Float16 *out, hipStream_t st);
 
 hipError_t launch_split_codes(const uint8_t *src, int64_t n, int M, uint8_t *a, uint8_t *b,
                               hipStream_t st);

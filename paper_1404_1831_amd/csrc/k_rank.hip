@@ -23,6 +23,7 @@
 namespace fbpq {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
 // ---- OPQ: queries into the index's rotated space -----------------------------
 // q' = Rot q (optimized product quantization, Section 2.1). Coordinate a is
@@ -125,7 +126,9 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
                                                      const float *__restrict__ C2,
                                                      const float *__restrict__ nC1,
                                                      const float *__restrict__ nC2, int T, int nchunk,
-                                                     float *__restrict__ ka, float *__restrict__ kmin)
+                                                     float *__restrict__ ka, float *__restrict__ kmin,
+                                                     const _Float16 *__restrict__ Cs1,
+                                                     const _Float16 *__restrict__ Cs2, float csc1, float csc2)
 {
     // rows are slots 0..nq-1; slot s holds query qlist[s] (or s); ka is [slot][2][T]
     // and kmin (when set) [slot][2][ceil(T/16)]: the smallest key of each
@@ -184,6 +187,40 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         for (int a = 0; a < kQT; ++a)
 #pragma unroll
             for (int r = 0; r < 4; ++r) nq4[a][r] = __shfl(qn[a], 4 * lk + r);
+        const _Float16 *Cs = half ? Cs2 : Cs1;
+        // Split FP16 products (the index carries the two-part centroids): each
+        // query row is scaled by a power of two to a largest magnitude below
+        // 2^14 and split the same way, and <q, c> is taken as
+        // q_hi c_hi + q_hi c_lo + q_lo c_hi, the three on the FP16 matrix
+        // cores with FP32 sums (products of FP16 values are exact in FP32).
+        // The dropped q_lo c_lo and the split remainders are below
+        // 3 2^-22 |q| |c|, which the index's error coefficient covers.
+        half8 qs[kQT][2][2];  // [tile][hi, lo][coordinates 0-7, 8-15 of the lane's 16]
+        float inv4[kQT][4];   // 1 / (row scale x centroid scale) of each output row
+        if (Cs) {
+            const float csc = half ? csc2 : csc1;
+#pragma unroll
+            for (int a = 0; a < kQT; ++a) {
+                float mx = 0.f;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) mx = fmaxf(mx, fabsf(av[a][u]));
+                mx = fmaxf(mx, __shfl_xor(mx, 16));
+                mx = fmaxf(mx, __shfl_xor(mx, 32));
+                int ex;
+                (void)frexpf(mx, &ex);  // mx < 2^ex
+                const float sq = ldexpf(1.f, 14 - ex);
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const float x = av[a][u] * sq;
+                    const _Float16 hi = (_Float16)x;
+                    qs[a][0][u >> 3][u & 7] = hi;
+                    qs[a][1][u >> 3][u & 7] = (_Float16)(x - (float)hi);
+                }
+                const float inv = 1.f / (sq * csc);  // a power of two
+#pragma unroll
+                for (int r = 0; r < 4; ++r) inv4[a][r] = __shfl(inv, 4 * lk + r);
+            }
+        }
         // Centroid strips alternate between two register sets, a set loaded
         // one tile before its products. Four tiles (64 centroids) are staged
         // in this wavefront's LDS slot and written as 256-byte runs of each
@@ -191,8 +228,35 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         // pieces one tile holds per row.
         float *stg = stage[threadIdx.x >> 6];
         float b0[16], b1[16];
+        half8 h0[2][2], h1[2][2];  // split strips: [hi, lo][coordinates 0-7, 8-15]
         float n0, n1;
         float(*mn)[kCT / 16] = smin[threadIdx.x >> 6];
+        auto strip_split = [&](int c, half8 (&hv)[2][2]) __attribute__((always_inline)) {
+            const half8 *row = reinterpret_cast<const half8 *>(Cs + (int64_t)c * 2 * h + 16 * lk);
+            hv[0][0] = row[0];
+            hv[0][1] = row[1];
+            hv[1][0] = row[h / 8];
+            hv[1][1] = row[h / 8 + 1];
+        };
+        auto tile_split = [&](const half8 (&hv)[2][2], float nc, int col) __attribute__((always_inline)) {
+            floatx4 acc[kQT];
+#pragma unroll
+            for (int a = 0; a < kQT; ++a) acc[a] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int a = 0; a < kQT; ++a) {
+                    acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_f16(qs[a][0][p], hv[0][p], acc[a], 0, 0, 0);
+                    acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_f16(qs[a][0][p], hv[1][p], acc[a], 0, 0, 0);
+                    acc[a] = __builtin_amdgcn_mfma_f32_16x16x32_f16(qs[a][1][p], hv[0][p], acc[a], 0, 0, 0);
+                }
+#pragma unroll
+            for (int a = 0; a < kQT; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    stg[(16 * a + 4 * lk + r) * kStgLd + col + li] =
+                        (nq4[a][r] + nc) - 2.f * (acc[a][r] * inv4[a][r]);
+        };
         auto tile = [&](const float (&bv)[16], float nc, int col) __attribute__((always_inline)) {
             floatx4 acc[kQT];
 #pragma unroll
@@ -239,23 +303,44 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
             }
             lds_order();
         };
-        load_strip(C + (int64_t)(cb + li) * h, true, 16 * lk, h, true, b0);
-        n0 = nC[cb + li];
+        if (Cs) {
+            strip_split(cb + li, h0);
+            n0 = nC[cb + li];
 #pragma unroll
-        for (int t = 0; t < kCT / 16; ++t) {  // straight-line code: exact wait counts
-            const int c0 = cb + 16 * t;
-            if (t + 1 < kCT / 16) {
-                if (t & 1) {
-                    load_strip(C + (int64_t)(c0 + 16 + li) * h, true, 16 * lk, h, true, b0);
-                    n0 = nC[c0 + 16 + li];
-                } else {
-                    load_strip(C + (int64_t)(c0 + 16 + li) * h, true, 16 * lk, h, true, b1);
-                    n1 = nC[c0 + 16 + li];
+            for (int t = 0; t < kCT / 16; ++t) {  // straight-line code: exact wait counts
+                const int c0 = cb + 16 * t;
+                if (t + 1 < kCT / 16) {
+                    if (t & 1) {
+                        strip_split(c0 + 16 + li, h0);
+                        n0 = nC[c0 + 16 + li];
+                    } else {
+                        strip_split(c0 + 16 + li, h1);
+                        n1 = nC[c0 + 16 + li];
+                    }
                 }
+                if (t & 1) tile_split(h1, n1, 16 * (t & 3));
+                else tile_split(h0, n0, 16 * (t & 3));
+                if ((t & 3) == 3) flush(c0 - 48);
             }
-            if (t & 1) tile(b1, n1, 16 * (t & 3));
-            else tile(b0, n0, 16 * (t & 3));
-            if ((t & 3) == 3) flush(c0 - 48);
+        } else {
+            load_strip(C + (int64_t)(cb + li) * h, true, 16 * lk, h, true, b0);
+            n0 = nC[cb + li];
+#pragma unroll
+            for (int t = 0; t < kCT / 16; ++t) {  // straight-line code: exact wait counts
+                const int c0 = cb + 16 * t;
+                if (t + 1 < kCT / 16) {
+                    if (t & 1) {
+                        load_strip(C + (int64_t)(c0 + 16 + li) * h, true, 16 * lk, h, true, b0);
+                        n0 = nC[c0 + 16 + li];
+                    } else {
+                        load_strip(C + (int64_t)(c0 + 16 + li) * h, true, 16 * lk, h, true, b1);
+                        n1 = nC[c0 + 16 + li];
+                    }
+                }
+                if (t & 1) tile(b1, n1, 16 * (t & 3));
+                else tile(b0, n0, 16 * (t & 3));
+                if ((t & 3) == 3) flush(c0 - 48);
+            }
         }
         if (kmin) {
             // 16 block minima per row of the chunk: 64 contiguous bytes of each row
@@ -322,10 +407,10 @@ hipError_t launch_half_approx(const DevIndex &ix, const float *q, const int32_t 
     const dim3 grid((unsigned)((waves + 3) / 4));
     if (ix.D / 2 <= 64)
         hipLaunchKernelGGL(k_half_approx<true>, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2,
-                           ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin);
+                           ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin, ix.Cs1, ix.Cs2, ix.csc1, ix.csc2);
     else
         hipLaunchKernelGGL(k_half_approx<false>, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2,
-                           ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin);
+                           ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin, nullptr, nullptr, 1.f, 1.f);
     return hipGetLastError();
 }
 
@@ -504,7 +589,7 @@ constexpr int kApproxLds = 16384;
 
 __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     const float *__restrict__ kapprox, const float *__restrict__ Q, int D,
-    const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, int T,
+    const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, float ecoef, int T,
     const int32_t *qlist, int P, int S, int stage_ka, double *__restrict__ lkey, int32_t *__restrict__ lidx,
     const int32_t *__restrict__ pstat, unsigned long long *stats, unsigned char *__restrict__ gsort)
 {
@@ -541,12 +626,13 @@ __global__ __launch_bounds__(kSelThreads) void k_select_prefix(
     __syncthreads();
     const float *kv = lds_ka ? kal : kg;
 
-    // error bound of the approximate keys (any summation order, FP32)
+    // error bound of the approximate keys (any summation order; the split
+    // FP16 products too, through the index's coefficient)
     double qn = 0.0;  // each wave sums ||q_half||^2 on its own (any order suits a bound)
     for (int t = tid & 63; t < h; t += 64) qn += (double)qh[t] * (double)qh[t];
     for (int o = 32; o > 0; o >>= 1) qn += __shfl_xor(qn, o);
     const double rn = sqrt(qn) + sqrt((double)cmax) * (1.0 + 1e-6);
-    const float err = (float)(1.25 * (h + 8) * 0x1.0p-23 * rn * rn) + 1e-30f;
+    const float err = (float)(ecoef * 0x1.0p-23 * rn * rn) + 1e-30f;
 
     bool done = false;
     double *ok = lkey + ((int64_t)slot * 2 + half) * P;
@@ -912,7 +998,7 @@ constexpr int kBlkCap = 512;  // blocks a wavefront reads for survivors
 template <int SPL, bool BLK>
 __global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_prefix_wave(
     const float *__restrict__ kapprox, const float *__restrict__ kmin, const float *__restrict__ Q, int D,
-    const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, int T,
+    const float *__restrict__ C1, const float *__restrict__ C2, float cmax1, float cmax2, float ecoef, int T,
     const int32_t *qlist, int64_t nslots, int P, double *__restrict__ lkey, int32_t *__restrict__ lidx,
     int32_t *__restrict__ pstat, unsigned long long *stats)
 {
@@ -1048,7 +1134,8 @@ __global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) 
         need -= (int)low;
         lds_order();  // the reads are done before the next clear
     }
-    // error bound of the approximate keys (any summation order, FP32)
+    // error bound of the approximate keys (any summation order; the split
+    // FP16 products too, through the index's coefficient)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1056,7 +1143,7 @@ __global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) 
     for (int t = lane; t < h; t += 64) qn += (double)qh[t] * (double)qh[t];
     for (int o = 32; o > 0; o >>= 1) qn += __shfl_xor(qn, o);
     const double rn = sqrt(qn) + sqrt((double)cmax) * (1.0 + 1e-6);
-    const float err = (float)(1.25 * (h + 8) * 0x1.0p-23 * rn * rn) + 1e-30f;
+    const float err = (float)(ecoef * 0x1.0p-23 * rn * rn) + 1e-30f;
     const float thr = unokey(pre) + 2.f * err;
 
     // survivors (ka <= thr), compacted with ballots
@@ -1194,7 +1281,7 @@ hipError_t launch_prefix_wave(const DevIndex &ix, const float *q, const float *k
     const int64_t pairs = nslots * 2;
     const dim3 g((unsigned)((pairs + kWPB - 1) / kWPB)), b(kWPB * 64);
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, g, b, lds, st, ka, kmin, q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist,
+        hipLaunchKernelGGL(kern, g, b, lds, st, ka, kmin, q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.ecoef, ix.T, qlist,
                            nslots, P, lkey, lidx, pstat, stats);
     };
     if (blk) {
@@ -1227,7 +1314,7 @@ hipError_t launch_prefix_block(const DevIndex &ix, const float *q, const float *
     const size_t lds = select_lds_bytes(ix.D, ix.T, S, stage, !glob);
     if (lds > kSelLdsMax) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_select_prefix, dim3((unsigned)nslots, 2), dim3(kSelThreads), lds, st, ka,
-                       q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.T, qlist, P, S, stage ? 1 : 0, lkey, lidx,
+                       q, ix.D, ix.C1, ix.C2, ix.cmax1, ix.cmax2, ix.ecoef, ix.T, qlist, P, S, stage ? 1 : 0, lkey, lidx,
                        pstat, stats, glob ? gsort : nullptr);
     return hipGetLastError();
 }

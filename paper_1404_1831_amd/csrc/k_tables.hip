@@ -76,6 +76,29 @@ __global__ void k_local_table(const float *__restrict__ C, const float *__restri
     CQ[e] = (float)(nn + 2.0 * cr);
 }
 
+// Two-part FP16 form of the half-centroids for the approximate keys: the
+// scaled value x = c scale (a power of two, exact) is hi + lo + r with
+// hi = fp16(x), lo = fp16(x - hi) (the difference is exact in FP32) and
+// |r| <= 2^-22 |x| when lo is normal.
+__global__ void k_split_centroids(const float *__restrict__ C, int64_t n, int h, float scale, _Float16 *__restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int64_t c = e / h, t = e - c * h;
+    const float x = C[e] * scale;
+    const _Float16 hi = (_Float16)x;
+    out[c * 2 * h + t] = hi;
+    out[c * 2 * h + h + t] = (_Float16)(x - (float)hi);
+}
+
+hipError_t launch_split_centroids(const float *C, int64_t T, int h, float scale, _Float16 *out, hipStream_t st)
+{
+    const int64_t n = T * h;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_centroids, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, C, n, h, scale, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_tables(const DevIndex &ix, float *CR1, float *CR2, float *nR, float *nC1,
                          float *nC2, hipStream_t st)
 {

@@ -366,6 +366,31 @@ def test_rank_prefix_wave_bitexact(fb, gmm_wide, T, P):
         assert np.array_equal(keys[r, 0], d1[u[:P]]) and np.array_equal(keys[r, 1], d2[v[:P]]), r
 
 
+@pytest.mark.parametrize("scale,shift", [(1.0, 0.0), (1e-4, -0.0128), (300.0, -38400.0)])
+@pytest.mark.parametrize("split", [1, 0])
+def test_split_keys_prefix_bitexact(fb, gmm_wide, scale, shift, split):
+    # The approximate keys from two-part FP16 half-centroids (split = 1) or FP32
+    # products (split = 0), on data whose magnitudes span small values, the
+    # SIFT-like range and values beyond the FP16 range (each side scaled by a
+    # power of two on the device), with negative coordinates: the FP64
+    # prefixes equal the oracle's bit for bit either way.
+    import dataclasses
+    idxs, Q = gmm_wide
+    ix = idxs[4096]
+    ixs = dataclasses.replace(ix, C1=(ix.C1 * scale + shift).astype(np.float32),
+                              C2=(ix.C2 * scale + shift).astype(np.float32))
+    Qs = (Q * scale + shift).astype(np.float32)
+    P = 128
+    log(f"split keys: T=4096 P={P} scale={scale} shift={shift} split={split}")
+    h = _open(fb, ixs, split_keys=split)
+    keys, idx = fb.fbpq_debug_rank(h, Qs, P)
+    fb.fbpq_free_index(h)
+    for r in range(Qs.shape[0]):
+        d1, d2, u, v = oracle.rank_lists(ixs, Qs[r])
+        assert np.array_equal(idx[r, 0], u[:P]) and np.array_equal(idx[r, 1], v[:P]), r
+        assert np.array_equal(keys[r, 0], d1[u[:P]]) and np.array_equal(keys[r, 1], d2[v[:P]]), r
+
+
 def test_search_T1000_visit_and_topk(fb, gmm_wide):
     idxs, Q = gmm_wide
     ix = idxs[1000]
