@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 FP32_MFMA_TFLOPS = 157.3
+FP16_MFMA_TFLOPS = 2500.0  # dense
 
 WORKLOADS = {
     "batched": dict(N=10_000_000, T=4096, M=16, nq=10_000, L=10_000, k=100),
@@ -65,14 +66,16 @@ def host_facts() -> dict:
     return {"nproc": os.cpu_count(), "affinity_cores": aff, "cpu_model": model}
 
 
-def roofline_models(ix, nq: int, k_max: int, ncand: int, cand: dict) -> dict:
+def roofline_models(ix, nq: int, k_max: int, ncand: int, cand: dict, split_keys: bool = True) -> dict:
     """Algorithmic work per launch of the kernels a roofline is reported for.
 
     score, scan_wide, scan2: M code bytes per candidate the kernel scores (the
                scan's HBM stream; candidates per kernel from the path counters)
     select:    the 4-byte distance of every candidate, plus k (id, distance) results per query
     prefix:    the 4-byte approximate key of every (query, half, centroid), plus P (key, index) outputs
-    half_keys: 2 (D/2) FLOP per (query, half, centroid) on the FP32 matrix cores
+    half_keys: 2 (D/2) FLOP per (query, half, centroid): on the FP32 matrix
+               cores, or three times that on the FP16 ones in the split form
+               (D/2 = 64 and split_keys)
     """
     P = 128
     csrc = os.path.join(ROOT, "paper_1404_1831_amd", "csrc")
@@ -88,10 +91,30 @@ def roofline_models(ix, nq: int, k_max: int, ncand: int, cand: dict) -> dict:
                        what="distance and result bytes", source=os.path.join(csrc, "k_items.hip")),
         "prefix": dict(gbs, kernel="k_prefix_wave", amount=nq * 2 * ix.T * 4 + nq * 2 * P * 12,
                        what="approximate-key and prefix bytes", source=os.path.join(csrc, "k_rank.hip")),
-        "half_keys": dict(bound="mfma", peak=FP32_MFMA_TFLOPS, unit="TFLOP/s", scale=1e12, kernel="k_half_approx",
-                          amount=nq * 2 * ix.T * (ix.D // 2) * 2, what="FP32 matrix-core FLOP",
-                          source=os.path.join(csrc, "k_rank.hip")),
+        "half_keys": (dict(bound="mfma", peak=FP16_MFMA_TFLOPS, unit="TFLOP/s", scale=1e12, kernel="k_half_approx",
+                           amount=3 * nq * 2 * ix.T * (ix.D // 2) * 2,
+                           what="FP16 matrix-core FLOP (three products of the split form)",
+                           source=os.path.join(csrc, "k_rank.hip"))
+                      if split_keys and ix.D // 2 == 64 else
+                      dict(bound="mfma", peak=FP32_MFMA_TFLOPS, unit="TFLOP/s", scale=1e12, kernel="k_half_approx",
+                           amount=nq * 2 * ix.T * (ix.D // 2) * 2, what="FP32 matrix-core FLOP",
+                           source=os.path.join(csrc, "k_rank.hip"))),
     }
+
+
+def scan_roof(model: dict, ms: float, peaks: dict):
+    """The scan roof of a code-scanning kernel as the survey defines it: the
+    larger of its code bytes at the HBM peak and its table lookups (one 4-byte
+    LDS read per code byte, the tables folded) at the measured LDS gather rate,
+    and the fraction roof / measured time."""
+    if not ms or model.get("what") != "code bytes" or not peaks.get("lds_gather_lookups_per_s"):
+        return None
+    hbm_ms = model["amount"] / (HBM_PEAK_GBPS * 1e9) * 1e3
+    lds_ms = model["amount"] / peaks["lds_gather_lookups_per_s"] * 1e3
+    roof = max(hbm_ms, lds_ms)
+    return {"kernel": model["kernel"], "hbm_ms": hbm_ms, "lds_ms": lds_ms, "roof_ms": roof, "measured_ms": ms,
+            "frac": roof / ms, "lds_rate_lookups_per_s": peaks["lds_gather_lookups_per_s"],
+            "definition": "max(code bytes / 8 TB/s, lookups / measured LDS gather rate) / kernel time"}
 
 
 def traffic_from_profile(kernel: str, source: str, workload: str):
@@ -447,7 +470,8 @@ def run_batch(args, w) -> int:
     per = max(1, args.profile_steps)
     cand = {"score": stats.get("cand_cell_scan", ncand * per) // per,
             "scan_wide": stats.get("cand_wide", 0) // per, "scan2": stats.get("cand_two_pass", 0) // per}
-    models = roofline_models(ix, nq, k, ncand, cand)
+    split = not any(kv.replace(" ", "") == "split_keys=0" for kv in args.option)
+    models = roofline_models(ix, nq, k, ncand, cand, split)
 
     def total(s):
         p = prof[s]
@@ -591,6 +615,9 @@ def run_batch(args, w) -> int:
     if hasattr(fbpq, "fbpq_probe_lds_gather"):
         peaks["lds_gather_lookups_per_s"] = fbpq.fbpq_probe_lds_gather(0)
     log(f"measured peaks: {peaks}")
+    sroof = scan_roof(model, dom_ms, peaks)
+    if sroof:
+        log(f"scan roof: {sroof}")
 
     if args.calibrate_copy_mib > 0:
         nel = args.calibrate_copy_mib * (1 << 20) // 4
@@ -636,6 +663,7 @@ def run_batch(args, w) -> int:
         "served_same_index": served,
         "scan_GBps": scan_GBps,
         "measured_peaks": peaks,
+        "scan_roof": sroof,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
