@@ -259,8 +259,14 @@ int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int
  * rounding, the same distances; a baseline for comparison), "graph" (0/1: the first traversal round of a search
  * is captured once into a HIP graph and replayed on later searches with the
  * same queries buffer, result buffers, nq, k_max, min(L, N) and options;
- * retry rounds and profiled or debug searches run eagerly). Errors: INVALID,
- * DEVICE. */
+ * retry rounds and profiled or debug searches run eagerly), "split_keys"
+ * (0/1, default 1: at D/2 = 64 the first layer's approximate keys come from
+ * two-part FP16 half-centroids on the FP16 matrix cores, with the error
+ * bound of that form; 0 uses FP32 products; the same prefixes either way),
+ * "inject_device_error" (n >= 1, for tests of error handling: the n-th
+ * checked HIP call after this one reports a failure instead of being made,
+ * which poisons the handle like a real device error; 0 clears it).
+ * Errors: INVALID, DEVICE. */
 int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value);
 
 /* Kernel stages timed by the library's profiler (one kernel each, except

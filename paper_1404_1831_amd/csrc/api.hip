@@ -53,6 +53,7 @@ struct fbpq_index {
     int device = 0;
     bool shared = false;  // a serving lane: index arrays belong to another handle
     bool poisoned = false;
+    int64_t inject_after = 0;  // option "inject_device_error": countdown to a reported failure
     bool tables = false;
     DevIndex dv{};
     hipStream_t stream = nullptr;
@@ -170,9 +171,11 @@ enum WsSlot {
 constexpr int kWsSet = 48;  // slots per workspace set
 static_assert(W_NSLOTS <= kWsSet, "workspace slots");
 
+// a failure injected by the option "inject_device_error" (tests of error handling)
+#define HCK_INJECTED(ix) ((ix)->inject_after > 0 && --(ix)->inject_after == 0)
 #define HCK(ix, expr)                                                                           \
     do {                                                                                        \
-        hipError_t e_ = (expr);                                                                 \
+        hipError_t e_ = HCK_INJECTED(ix) ? hipErrorLaunchFailure : (expr);                       \
         if (e_ != hipSuccess) {                                                                 \
             (ix)->poisoned = true;                                                              \
             return fail(FBPQ_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
@@ -1682,6 +1685,7 @@ int fbpq_debug_rank(fbpq_index *ix, const float *q, int64_t nq, int32_t P, doubl
 int fbpq_info(const fbpq_index *ix, fbpq_info_t *out)
 {
     if (!ix || !out) return fail(FBPQ_E_INVALID, "null argument");
+    if (ix->poisoned) return fail(FBPQ_E_DEVICE, "index handle poisoned by an earlier device error");
     memset(out, 0, sizeof *out);
     out->D = ix->dv.D;
     out->T = ix->dv.T;
@@ -1700,6 +1704,7 @@ int fbpq_info(const fbpq_index *ix, fbpq_info_t *out)
 int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
 {
     if (!ix || !key) return fail(FBPQ_E_INVALID, "null argument");
+    if (ix->poisoned) return fail(FBPQ_E_DEVICE, "index handle poisoned by an earlier device error");
     if (!strcmp(key, "prefix")) {
         if (value < 1 || value > kMaxPrefix) return fail(FBPQ_E_INVALID, "prefix out of [1, %d]", kMaxPrefix);
         ix->prefix = (int32_t)value;
@@ -1728,6 +1733,9 @@ int fbpq_set_option(fbpq_index *ix, const char *key, int64_t value)
         ix->profile = value != 0;
     } else if (!strcmp(key, "profile_mask")) {
         ix->prof_mask = value;
+    } else if (!strcmp(key, "inject_device_error")) {
+        if (value < 0) return fail(FBPQ_E_INVALID, "inject_device_error < 0");
+        ix->inject_after = value;
     } else if (!strcmp(key, "split_keys")) {
         ix->split_keys = value != 0;
         set_key_form(ix);
@@ -1778,6 +1786,7 @@ int fbpq_profile_read(fbpq_index *ix, int32_t stage, int32_t reset, double *ms, 
 {
     if (!ix || stage < 0 || stage >= FBPQ_NUM_STAGES || !ms || !launches)
         return fail(FBPQ_E_INVALID, "bad arguments");
+    if (ix->poisoned) return fail(FBPQ_E_DEVICE, "index handle poisoned by an earlier device error");
     *ms = ix->prof_ms[stage];
     *launches = ix->prof_n[stage];
     if (reset) {

@@ -318,6 +318,41 @@ def test_load_index_file_matches_create(fb, gmm_small, tmp_path):
     assert info.tables_ready == 1 and info.table_bytes == 64 * 8 * 256 * 4
 
 
+@pytest.mark.parametrize("nth", [1, 4, 12])
+def test_device_error_poisons_handle(fb, gmm_small, nth):
+    # A failed HIP call (reported on the host in place of the nth checked call
+    # after the option is set; no kernel misbehaves) ends that search with
+    # FBPQ_E_DEVICE and poisons the handle: every later call refuses with the
+    # same code, the handle still frees, and a fresh handle on the same index
+    # gives the results of before.
+    ix, Q = gmm_small
+    h = _open(fb, ix)
+    ids0, d0 = fb.fbpq_search(h, Q[:8], 2000, 10)
+    fb.fbpq_set_option(h, "inject_device_error", nth)
+    failed = None
+    for _ in range(nth):  # each search makes at least one checked call
+        try:
+            fb.fbpq_search(h, Q[:8], 2000, 10)
+        except fb.FbpqError as ex:
+            failed = ex
+            break
+    assert failed is not None and failed.code == fb.FBPQ_E_DEVICE
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_search(h, Q[:8], 2000, 10)
+    assert e.value.code == fb.FBPQ_E_DEVICE
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_set_option(h, "prefix", 64)
+    assert e.value.code == fb.FBPQ_E_DEVICE
+    with pytest.raises(fb.FbpqError) as e:
+        fb.fbpq_info(h)
+    assert e.value.code == fb.FBPQ_E_DEVICE
+    fb.fbpq_free_index(h)
+    h = _open(fb, ix)
+    ids1, d1 = fb.fbpq_search(h, Q[:8], 2000, 10)
+    fb.fbpq_free_index(h)
+    assert np.array_equal(ids0, ids1) and np.array_equal(d0, d1)
+
+
 def test_errors(fb, gmm_small):
     ix, Q = gmm_small
     h = fb.fbpq_index_create(ix, 0)
