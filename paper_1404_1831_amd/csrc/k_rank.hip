@@ -118,8 +118,9 @@ __device__ __forceinline__ void load_strip(const float *__restrict__ row, bool o
     }
 }
 
-// ONE: D/2 <= 64, so the query rows are loaded once and stay in registers
-template <bool ONE>
+// ONE: D/2 <= 64, so the query rows are loaded once and stay in registers.
+// SPLIT: full tiles at D/2 = 64 take the split FP16 products (Cs1/Cs2 set).
+template <bool ONE, bool SPLIT>
 __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q, int64_t nq, int D,
                                                      const int32_t *__restrict__ qlist,
                                                      const float *__restrict__ C1,
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         for (int a = 0; a < kQT; ++a)
 #pragma unroll
             for (int r = 0; r < 4; ++r) nq4[a][r] = __shfl(qn[a], 4 * lk + r);
-        const _Float16 *Cs = half ? Cs2 : Cs1;
+        const _Float16 *Cs = SPLIT ? (half ? Cs2 : Cs1) : nullptr;
         // Split FP16 products (the index carries the two-part centroids): each
         // query row is scaled by a power of two to a largest magnitude below
         // 2^14 and split the same way, and <q, c> is taken as
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         // 3 2^-22 |q| |c|, which the index's error coefficient covers.
         half8 qs[kQT][2][2];  // [tile][hi, lo][coordinates 0-7, 8-15 of the lane's 16]
         float inv4[kQT][4];   // 1 / (row scale x centroid scale) of each output row
-        if (Cs) {
+        if constexpr (SPLIT) {
             const float csc = half ? csc2 : csc1;
 #pragma unroll
             for (int a = 0; a < kQT; ++a) {
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
             }
             lds_order();
         };
-        if (Cs) {
+        if constexpr (SPLIT) {
             strip_split(cb + li, h0);
             n0 = nC[cb + li];
 #pragma unroll
@@ -405,12 +406,15 @@ hipError_t launch_half_approx(const DevIndex &ix, const float *q, const int32_t 
     const int nchunk = (ix.T + kCT - 1) / kCT;
     const int64_t waves = 2 * ((nslots + 16 * kQT - 1) / (16 * kQT)) * nchunk;
     const dim3 grid((unsigned)((waves + 3) / 4));
-    if (ix.D / 2 <= 64)
-        hipLaunchKernelGGL(k_half_approx<true>, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2,
-                           ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin, ix.Cs1, ix.Cs2, ix.csc1, ix.csc2);
+    if (ix.D / 2 <= 64 && ix.Cs1 && ix.Cs2)
+        hipLaunchKernelGGL((k_half_approx<true, true>), grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1,
+                           ix.C2, ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin, ix.Cs1, ix.Cs2, ix.csc1, ix.csc2);
+    else if (ix.D / 2 <= 64)
+        hipLaunchKernelGGL((k_half_approx<true, false>), grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1,
+                           ix.C2, ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin, nullptr, nullptr, 1.f, 1.f);
     else
-        hipLaunchKernelGGL(k_half_approx<false>, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2,
-                           ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin, nullptr, nullptr, 1.f, 1.f);
+        hipLaunchKernelGGL((k_half_approx<false, false>), grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1,
+                           ix.C2, ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin, nullptr, nullptr, 1.f, 1.f);
     return hipGetLastError();
 }
 
