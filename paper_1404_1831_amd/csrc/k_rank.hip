@@ -86,7 +86,8 @@ hipError_t launch_rotate(const float *q, int64_t nq, int D, const float *Rot, fl
 
 // ---- step 1: approximate keys on the matrix cores ---------------------------
 // A wavefront owns kQT tiles of 16 rows (query halves of one half) and a chunk
-// of kCT centroids, which it takes 16 at a time. The dot product runs over the
+// of CT centroids (256, or 512 when that still gives the chip enough
+// wavefronts), which it takes 16 at a time. The dot product runs over the
 // D/2 coordinates in slabs of 64; inside a slab, coordinate 16k + s feeds step
 // s of v_mfma_f32_16x16x4f32 from lane i + 16k (A: row i) and lane j + 16k
 // (B: centroid j), so each lane reads 16 consecutive floats of its own row and
@@ -96,7 +97,7 @@ hipError_t launch_rotate(const float *q, int64_t nq, int D, const float *Rot, fl
 // 64 bytes of each output row, so the keys of four tiles are staged in LDS and
 // written as 256-byte runs: the key array is the kernel's dominant traffic.
 constexpr int kQT = 2;    // 16-row query tiles per wavefront
-constexpr int kCT = 256;  // centroids per wavefront (a multiple of 64)
+constexpr int kCT = 256;  // centroids per wavefront (a multiple of 64), or 2 kCT
 constexpr int kStgLd = 68;  // LDS row stride of the staged keys (floats): 64 keys + 4
 
 // v[s] = row[t + s] for t + s < h, 0 beyond h or when the row is absent
@@ -120,7 +121,7 @@ __device__ __forceinline__ void load_strip(const float *__restrict__ row, bool o
 
 // ONE: D/2 <= 64, so the query rows are loaded once and stay in registers.
 // SPLIT: full tiles at D/2 = 64 take the split FP16 products (Cs1/Cs2 set).
-template <bool ONE, bool SPLIT>
+template <bool ONE, bool SPLIT, int CT>
 __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q, int64_t nq, int D,
                                                      const int32_t *__restrict__ qlist,
                                                      const float *__restrict__ C1,
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
     // and kmin (when set) [slot][2][ceil(T/16)]: the smallest key of each
     // block of 16 consecutive centroids, one per 16x16 tile column group
     __shared__ __align__(16) float stage[4][16 * kQT * kStgLd];  // per wavefront: 16 kQT rows x 64 keys
-    __shared__ __align__(16) float smin[4][16 * kQT][kCT / 16];  // per wavefront: block minima of its chunk
+    __shared__ __align__(16) float smin[4][16 * kQT][CT / 16];  // per wavefront: block minima of its chunk
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     // the wavefront index, in a scalar register so that everything derived from
     // it (and every branch on it) is uniform
@@ -176,9 +177,9 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         p += __shfl_xor(p, 32);
         qn[a] = p;
     }
-    const int cb = chunk * kCT, ce = min(T, cb + kCT);
+    const int cb = chunk * CT, ce = min(T, cb + CT);
     float *kout = ka + (s0 * 2 + half) * (int64_t)T;  // row s0 + q of this half at kout[2 q T]
-    if (ONE && vec && h == 64 && s0 + 16 * kQT <= nq && ce - cb == kCT) {
+    if (ONE && vec && h == 64 && s0 + 16 * kQT <= nq && ce - cb == CT) {
         // every row and centroid present: the next centroid strip is loaded
         // before this tile's products, and the stores are unconditional, so
         // waiting for the strip does not wait for the stores
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         float b0[16], b1[16];
         half8 h0[2][2], h1[2][2];  // split strips: [hi, lo][coordinates 0-7, 8-15]
         float n0, n1;
-        float(*mn)[kCT / 16] = smin[threadIdx.x >> 6];
+        float(*mn)[CT / 16] = smin[threadIdx.x >> 6];
         auto strip_split = [&](int c, half8 (&hv)[2][2]) __attribute__((always_inline)) {
             const half8 *row = reinterpret_cast<const half8 *>(Cs + (int64_t)c * 2 * h + 16 * lk);
             hv[0][0] = row[0];
@@ -305,31 +306,40 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
             lds_order();
         };
         if constexpr (SPLIT) {
+            // strips loaded two tiles ahead, in three register sets
+            half8 h2[2][2];
+            float n2;
             strip_split(cb + li, h0);
             n0 = nC[cb + li];
+            strip_split(cb + 16 + li, h1);
+            n1 = nC[cb + 16 + li];
 #pragma unroll
-            for (int t = 0; t < kCT / 16; ++t) {  // straight-line code: exact wait counts
+            for (int t = 0; t < CT / 16; ++t) {  // straight-line code: exact wait counts
                 const int c0 = cb + 16 * t;
-                if (t + 1 < kCT / 16) {
-                    if (t & 1) {
-                        strip_split(c0 + 16 + li, h0);
-                        n0 = nC[c0 + 16 + li];
+                if (t + 2 < CT / 16) {
+                    if (t % 3 == 0) {
+                        strip_split(c0 + 32 + li, h2);
+                        n2 = nC[c0 + 32 + li];
+                    } else if (t % 3 == 1) {
+                        strip_split(c0 + 32 + li, h0);
+                        n0 = nC[c0 + 32 + li];
                     } else {
-                        strip_split(c0 + 16 + li, h1);
-                        n1 = nC[c0 + 16 + li];
+                        strip_split(c0 + 32 + li, h1);
+                        n1 = nC[c0 + 32 + li];
                     }
                 }
-                if (t & 1) tile_split(h1, n1, 16 * (t & 3));
-                else tile_split(h0, n0, 16 * (t & 3));
+                if (t % 3 == 0) tile_split(h0, n0, 16 * (t & 3));
+                else if (t % 3 == 1) tile_split(h1, n1, 16 * (t & 3));
+                else tile_split(h2, n2, 16 * (t & 3));
                 if ((t & 3) == 3) flush(c0 - 48);
             }
         } else {
             load_strip(C + (int64_t)(cb + li) * h, true, 16 * lk, h, true, b0);
             n0 = nC[cb + li];
 #pragma unroll
-            for (int t = 0; t < kCT / 16; ++t) {  // straight-line code: exact wait counts
+            for (int t = 0; t < CT / 16; ++t) {  // straight-line code: exact wait counts
                 const int c0 = cb + 16 * t;
-                if (t + 1 < kCT / 16) {
+                if (t + 1 < CT / 16) {
                     if (t & 1) {
                         load_strip(C + (int64_t)(c0 + 16 + li) * h, true, 16 * lk, h, true, b0);
                         n0 = nC[c0 + 16 + li];
@@ -344,12 +354,13 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
             }
         }
         if (kmin) {
-            // 16 block minima per row of the chunk: 64 contiguous bytes of each row
+            // CT / 16 block minima per row of the chunk: contiguous in each row
             const int64_t G = (T + 15) / 16;
             float *mout = kmin + (s0 * 2 + half) * G + cb / 16;
+            constexpr int NP = CT / 64;  // 16-byte parts per row
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int row = (lane >> 2) + 16 * i, part = lane & 3;
+            for (int e0 = 0; e0 < 16 * kQT * NP; e0 += 64) {
+                const int e = e0 + lane, row = e / NP, part = e - row * NP;
                 const float4 v = *reinterpret_cast<const float4 *>(&mn[row][4 * part]);
                 *reinterpret_cast<float4 *>(mout + row * 2 * G + 4 * part) = v;
             }
@@ -403,18 +414,26 @@ hipError_t launch_half_approx(const DevIndex &ix, const float *q, const int32_t 
                               float *ka, float *kmin, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
-    const int nchunk = (ix.T + kCT - 1) / kCT;
-    const int64_t waves = 2 * ((nslots + 16 * kQT - 1) / (16 * kQT)) * nchunk;
+    // wider chunks when the batch still gives at least 16384 wavefronts
+    // (16 per SIMD): fewer query loads and splits per key
+    const int64_t rows2 = 2 * ((nslots + 16 * kQT - 1) / (16 * kQT));
+    const bool wide = rows2 * ((ix.T + 2 * kCT - 1) / (2 * kCT)) >= 16384;
+    const int ct = wide ? 2 * kCT : kCT;
+    const int nchunk = (ix.T + ct - 1) / ct;
+    const int64_t waves = rows2 * nchunk;
     const dim3 grid((unsigned)((waves + 3) / 4));
-    if (ix.D / 2 <= 64 && ix.Cs1 && ix.Cs2)
-        hipLaunchKernelGGL((k_half_approx<true, true>), grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1,
-                           ix.C2, ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin, ix.Cs1, ix.Cs2, ix.csc1, ix.csc2);
-    else if (ix.D / 2 <= 64)
-        hipLaunchKernelGGL((k_half_approx<true, false>), grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1,
-                           ix.C2, ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin, nullptr, nullptr, 1.f, 1.f);
+    const bool one = ix.D / 2 <= 64, split = one && ix.Cs1 && ix.Cs2;
+    auto go = [&](auto kern, const _Float16 *c1, const _Float16 *c2) {
+        hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2, ix.nC1, ix.nC2, ix.T,
+                           nchunk, ka, kmin, c1, c2, ix.csc1, ix.csc2);
+    };
+    if (split)
+        wide ? go(k_half_approx<true, true, 2 * kCT>, ix.Cs1, ix.Cs2) : go(k_half_approx<true, true, kCT>, ix.Cs1, ix.Cs2);
+    else if (one)
+        wide ? go(k_half_approx<true, false, 2 * kCT>, nullptr, nullptr) : go(k_half_approx<true, false, kCT>, nullptr, nullptr);
     else
-        hipLaunchKernelGGL((k_half_approx<false, false>), grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1,
-                           ix.C2, ix.nC1, ix.nC2, ix.T, nchunk, ka, kmin, nullptr, nullptr, 1.f, 1.f);
+        wide ? go(k_half_approx<false, false, 2 * kCT>, nullptr, nullptr)
+             : go(k_half_approx<false, false, kCT>, nullptr, nullptr);
     return hipGetLastError();
 }
 
