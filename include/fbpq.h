@@ -239,7 +239,7 @@ int fbpq_table_bytes(int64_t T, int64_t M, int64_t Kc, int64_t *table_bytes, int
  * all needed deeper traversal rounds before starts its first round at the
  * prefix length and cell capacity those rounds reached; same results),
  * "block_min" (0 off, 1 on, 2 = default: on
- * when T >= 8192; the first layer's key kernel also writes the smallest key
+ * when T >= 4096; the first layer's key kernel also writes the smallest key
  * of each block of 16 centroids, and the prefix select draws its samples from
  * them and reads only the blocks that can hold survivors; same prefixes
  * either way), "persist" (0/1: the cell scan as a persistent kernel over a

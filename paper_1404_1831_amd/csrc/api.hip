@@ -122,7 +122,7 @@ struct fbpq_index {
     bool persist = false;   // cell scan as a persistent kernel over a device work queue
     int32_t tile = 8192;    // candidates per work item of the persistent scan
     int32_t pwaves = 4;     // wavefronts per workgroup of the persistent scan
-    int32_t block_min = 2;  // the wave prefix select samples the key kernel's block minima: 0 off, 1 on, 2 when T >= 8192
+    int32_t block_min = 2;  // the wave prefix select samples the key kernel's block minima: 0 off, 1 on, 2 when T >= 4096
     int32_t pop_budget = 512;  // cells popped one at a time before the threshold kernel takes over
     // per floor(log2(min(L, N))): the prefix length at which retried queries of
     // that budget last succeeded; retry rounds start there instead of at 4P
@@ -665,8 +665,8 @@ int first_layer(fbpq_index *ix, const float *d_q, int64_t nslots, const int32_t 
     TRY(ws_get(ix, W_KEYS, sizeof(float) * nslots * 2 * dv.T, &keys));
     const bool pwave = prefix_wave_ok(dv, P);
     void *kmin = nullptr;  // block minima: the wave select reads only the blocks that can hold survivors
-    // (at T >= 8192 the minima save more reading than they cost the key kernel)
-    const bool bmin = ix->block_min == 1 || (ix->block_min == 2 && dv.T >= 8192);
+    // (from T = 4096 on the minima save more reading than they cost the key kernel)
+    const bool bmin = ix->block_min == 1 || (ix->block_min == 2 && dv.T >= 4096);
     if (pwave && bmin && prefix_blocks_ok(dv, P))
         TRY(ws_get(ix, W_KMIN, sizeof(float) * nslots * 2 * (size_t)((dv.T + 15) / 16), &kmin));
     HCK(ix, timed(ix, FBPQ_STAGE_HALF_KEYS, st, [&] { return launch_half_approx(dv, d_q, d_qlist, nslots, (float *)keys, (float *)kmin, st); }));
