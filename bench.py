@@ -351,6 +351,8 @@ def main() -> int:
                     help="autotuner cache (JSON lines); '' to keep the library defaults")
     ap.add_argument("--option", action="append", default=[],
                     help="library option key=value set on the search handle (repeatable)")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="batched workload: skip the uneven-batch leg (N=1e8, T=16384, per-query L and k)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (read once, written once), "
                          "the reference dispatch for scaling HBM traffic counters")
@@ -371,11 +373,29 @@ def main() -> int:
         return run_local(args, w)
     if args.workload == "gist":
         return run_gist(args, w)
-    return run_batch(args, w)
+    out = run_batch(args, w)
+    if args.workload == "batched" and not args.no_uneven:
+        # the uneven-batch configuration in the same run, with its own
+        # roofline, oracle sample and recall (no served, O(D) or plain legs)
+        import copy
+        import gc
+        gc.collect()
+        a2 = copy.copy(args)
+        a2.workload, a2.nq, a2.plain_queries, a2.adc_steps, a2.served_rates = "uneven", None, 0, 0, ""
+        a2.recall_queries = min(args.recall_queries, 500)
+        a2.cpu_seconds = min(args.cpu_seconds, 8.0)
+        a2.calibrate_copy_mib = 0
+        u = run_batch(a2, dict(WORKLOADS["uneven"]))
+        out["uneven_workload"] = {key: u[key] for key in (
+            "value", "unit", "ms_per_step", "p50_ms", "p99_ms", "step_ms", "config", "kernels", "path_counters",
+            "recall", "autotune", "graph_replay", "scan_roof", "roofline", "cpu_baseline")}
+    print(json.dumps(out))
+    return 0
 
 
-def run_batch(args, w) -> int:
-    """One batch searched as a whole (batched, uneven and plain workloads)."""
+def run_batch(args, w) -> dict:
+    """One batch searched as a whole (batched, uneven and plain workloads);
+    returns the result line."""
     import torch
 
     import synth
@@ -667,8 +687,7 @@ def run_batch(args, w) -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out))
-    return 0
+    return out
 
 
 def run_local(args, w) -> int:
