@@ -85,20 +85,26 @@ hipError_t launch_rotate(const float *q, int64_t nq, int D, const float *Rot, fl
 }
 
 // ---- step 1: approximate keys on the matrix cores ---------------------------
-// A wavefront owns kQT tiles of 16 rows (query halves of one half) and a chunk
-// of CT centroids (256, or 512 when that still gives the chip enough
-// wavefronts), which it takes 16 at a time. The dot product runs over the
-// D/2 coordinates in slabs of 64; inside a slab, coordinate 16k + s feeds step
-// s of v_mfma_f32_16x16x4f32 from lane i + 16k (A: row i) and lane j + 16k
-// (B: centroid j), so each lane reads 16 consecutive floats of its own row and
-// the operands need no LDS. The instruction leaves D[4*(lane/16) + r][lane % 16]
-// in accumulator r. The summation order differs from a plain loop, which the
-// error bound of step 2 allows (it holds for any order). One tile holds only
-// 64 bytes of each output row, so the keys of four tiles are staged in LDS and
-// written as 256-byte runs: the key array is the kernel's dominant traffic.
+// A workgroup takes a chunk of CT centroids of one half (256, or 512 when that
+// still gives the chip enough wavefronts) for four groups of 16 kQT rows
+// (query halves), one group per wavefront, which takes the chunk 16 centroids
+// at a time. Workgroup b takes chunk b mod nchunk, so with a chunk count that
+// is a multiple of the 8 XCDs each XCD's L2 serves a fixed eighth of the
+// centroids. In the FP32 form the dot product runs over the D/2 coordinates in
+// slabs of 64; inside a slab, coordinate 16k + s feeds step s of
+// v_mfma_f32_16x16x4f32 from lane i + 16k (A: row i) and lane j + 16k (B:
+// centroid j), so each lane reads 16 consecutive floats of its own row. The
+// instruction leaves D[4*(lane/16) + r][lane % 16] in accumulator r. The
+// summation order differs from a plain loop, which the error bound of step 2
+// allows (it holds for any order). One tile holds only 64 bytes of each output
+// row, so the keys of kFT tiles are staged in LDS and written as 128-byte runs
+// of each row.
 constexpr int kQT = 2;    // 16-row query tiles per wavefront
-constexpr int kCT = 256;  // centroids per wavefront (a multiple of 64), or 2 kCT
-constexpr int kStgLd = 68;  // LDS row stride of the staged keys (floats): 64 keys + 4
+constexpr int kCT = 256;  // centroids per workgroup (a multiple of 64), or 2 kCT
+constexpr int kFT = 2;    // tiles staged per key write-out
+constexpr int kStgLd = 16 * kFT + 4;  // LDS row stride of the staged keys (floats)
+constexpr int kPF = 4;    // shared centroid strips in flight per thread
+static_assert(kPF < kCT / 16, "the prefetch ring is filled from the chunk's first strips");
 
 // v[s] = row[t + s] for t + s < h, 0 beyond h or when the row is absent
 __device__ __forceinline__ void load_strip(const float *__restrict__ row, bool ok, int t, int h, bool vec,
@@ -135,20 +141,30 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
     // rows are slots 0..nq-1; slot s holds query qlist[s] (or s); ka is [slot][2][T]
     // and kmin (when set) [slot][2][ceil(T/16)]: the smallest key of each
     // block of 16 consecutive centroids, one per 16x16 tile column group
-    __shared__ __align__(16) float stage[4][16 * kQT * kStgLd];  // per wavefront: 16 kQT rows x 64 keys
+    __shared__ __align__(16) float stage[4][16 * kQT * kStgLd];  // per wavefront: 16 kQT rows x 16 kFT keys
     __shared__ __align__(16) float smin[4][16 * kQT][CT / 16];  // per wavefront: block minima of its chunk
+    __shared__ __align__(16) half8 sstrip[2][256];  // shared split strips, piece-major (see below)
+    __shared__ float snc[CT];                         // ||c||^2 of the chunk (shared form)
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     // the wavefront index, in a scalar register so that everything derived from
     // it (and every branch on it) is uniform
-    const int64_t w = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t ngrp = (nq + 16 * kQT - 1) / (16 * kQT);
-    const int64_t g = w / nchunk;
-    if (g >= 2 * ngrp) return;  // no barriers below: a wavefront may leave alone
-    const int chunk = (int)(w - g * nchunk);
-    const int half = (int)(g / ngrp);
-    const int64_t s0 = (g - half * ngrp) * 16 * kQT;
+    const int64_t ngq = (ngrp + 3) / 4;  // groups of four row groups per half
+    const int chunk = (int)(blockIdx.x % (unsigned)nchunk);
+    const int64_t rest = blockIdx.x / (unsigned)nchunk;
+    if (rest >= 2 * ngq) return;  // the whole workgroup
+    const int half = (int)(rest / ngq);
+    const int64_t quad = rest - (int64_t)half * ngq;
+    const int64_t s0 = (quad * 4 + wv) * 16 * kQT;
     const int h = D / 2;
     const bool vec = ((h | D) & 3) == 0;
+    const int cb = chunk * CT, ce = min(T, cb + CT);
+    // The four wavefronts share the split centroid strips through LDS (with
+    // barriers) when all four row groups and the chunk are full; every other
+    // wavefront runs alone and may leave here.
+    const bool shared = SPLIT && ONE && vec && h == 64 && (quad * 4 + 4) * 16 * kQT <= nq && ce - cb == CT;
+    if (!shared && s0 >= nq) return;
     const float *C = half ? C2 : C1;
     const float *nC = half ? nC2 : nC1;
     const float *qrow[kQT];
@@ -177,19 +193,16 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         p += __shfl_xor(p, 32);
         qn[a] = p;
     }
-    const int cb = chunk * CT, ce = min(T, cb + CT);
     float *kout = ka + (s0 * 2 + half) * (int64_t)T;  // row s0 + q of this half at kout[2 q T]
     if (ONE && vec && h == 64 && s0 + 16 * kQT <= nq && ce - cb == CT) {
-        // every row and centroid present: the next centroid strip is loaded
-        // before this tile's products, and the stores are unconditional, so
-        // waiting for the strip does not wait for the stores
+        // every row and centroid present: the stores are unconditional, so
+        // waiting for a prefetched centroid strip does not wait for them
         const int64_t ldq = 2 * (int64_t)T;
         float nq4[kQT][4];
 #pragma unroll
         for (int a = 0; a < kQT; ++a)
 #pragma unroll
             for (int r = 0; r < 4; ++r) nq4[a][r] = __shfl(qn[a], 4 * lk + r);
-        const _Float16 *Cs = SPLIT ? (half ? Cs2 : Cs1) : nullptr;
         // Split FP16 products (the index carries the two-part centroids): each
         // query row is scaled by a power of two to a largest magnitude below
         // 2^14 and split the same way, and <q, c> is taken as
@@ -199,7 +212,7 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         // 3 2^-22 |q| |c|, which the index's error coefficient covers.
         half8 qs[kQT][2][2];  // [tile][hi, lo][coordinates 0-7, 8-15 of the lane's 16]
         float inv4[kQT][4];   // 1 / (row scale x centroid scale) of each output row
-        if constexpr (SPLIT) {
+        if (SPLIT && shared) {
             const float csc = half ? csc2 : csc1;
 #pragma unroll
             for (int a = 0; a < kQT; ++a) {
@@ -223,23 +236,8 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
                 for (int r = 0; r < 4; ++r) inv4[a][r] = __shfl(inv, 4 * lk + r);
             }
         }
-        // Centroid strips alternate between two register sets, a set loaded
-        // one tile before its products. Four tiles (64 centroids) are staged
-        // in this wavefront's LDS slot and written as 256-byte runs of each
-        // row, 16 bytes per lane: whole cache lines instead of the 64-byte
-        // pieces one tile holds per row.
-        float *stg = stage[threadIdx.x >> 6];
-        float b0[16], b1[16];
-        half8 h0[2][2], h1[2][2];  // split strips: [hi, lo][coordinates 0-7, 8-15]
-        float n0, n1;
-        float(*mn)[CT / 16] = smin[threadIdx.x >> 6];
-        auto strip_split = [&](int c, half8 (&hv)[2][2]) __attribute__((always_inline)) {
-            const half8 *row = reinterpret_cast<const half8 *>(Cs + (int64_t)c * 2 * h + 16 * lk);
-            hv[0][0] = row[0];
-            hv[0][1] = row[1];
-            hv[1][0] = row[h / 8];
-            hv[1][1] = row[h / 8 + 1];
-        };
+        float *stg = stage[wv];
+        float(*mn)[CT / 16] = smin[wv];
         auto tile_split = [&](const half8 (&hv)[2][2], float nc, int col) __attribute__((always_inline)) {
             floatx4 acc[kQT];
 #pragma unroll
@@ -279,6 +277,7 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         // (lgkmcnt 0, vector memory counters untouched); the empty asm keeps
         // the compiler from moving LDS accesses across
         auto lds_order = [&]() __attribute__((always_inline)) {
+            __asm__ __volatile__("" ::: "memory");
             __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0) only
             __builtin_amdgcn_wave_barrier();
             __asm__ __volatile__("" ::: "memory");
@@ -286,12 +285,13 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         // Block minima: a lane holds four consecutive keys of a row, four lanes
         // (a DPP quad) one block of 16; the quad's first lane stages its block
         // minimum for the chunk's write-out.
-        auto flush = [&](int c0) __attribute__((always_inline)) {
+        auto flush = [&](int c0) __attribute__((always_inline)) {  // c0: first centroid of the staged tiles
             lds_order();
-            const int grp = (c0 - cb) / 64;  // 64-centroid group of the chunk
+            constexpr int LPR = 4 * kFT;   // lanes per row, 16 bytes each
+            constexpr int RPI = 64 / LPR;  // rows per instruction
 #pragma unroll
-            for (int i = 0; i < 16 * kQT / 4; ++i) {
-                const int row = 4 * i + (lane >> 4), col = 4 * (lane & 15);
+            for (int i = 0; i < 16 * kQT / RPI; ++i) {
+                const int row = RPI * i + lane / LPR, col = 4 * (lane % LPR);
                 const float4 v = *reinterpret_cast<const float4 *>(stg + row * kStgLd + col);
                 *reinterpret_cast<float4 *>(kout + row * ldq + c0 + col) = v;
                 if (kmin) {
@@ -300,40 +300,60 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
                                                                             false)));  // quad lanes xor 1
                     m = fminf(m, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x4e, 0xf, 0xf,
                                                                             false)));  // quad lanes xor 2
-                    if ((lane & 3) == 0) mn[row][4 * grp + ((lane & 15) >> 2)] = m;
+                    if ((lane & 3) == 0) mn[row][(c0 - cb) / 16 + (lane % LPR) / 4] = m;
                 }
             }
             lds_order();
         };
-        if constexpr (SPLIT) {
-            // strips loaded two tiles ahead, in three register sets
-            half8 h2[2][2];
-            float n2;
-            strip_split(cb + li, h0);
-            n0 = nC[cb + li];
-            strip_split(cb + 16 + li, h1);
-            n1 = nC[cb + 16 + li];
+        if (SPLIT && shared) {
+            // The workgroup's four wavefronts score the same chunk for their own
+            // rows, so each 16-centroid strip (16 rows of 64 hi then 64 lo FP16
+            // values, sixteen 16-byte pieces per row) is fetched once per
+            // workgroup: thread p loads piece p / 16 of centroid p % 16 kPF
+            // strips ahead into a register and stores it at slot p of a
+            // double-buffered LDS strip, piece-major, from which a lane reads
+            // its four pieces (the hi and lo parts of its 16 coordinates) with
+            // 16 lanes on 16 consecutive pieces. One barrier per tile (the LDS
+            // counter only, no memory fence) keeps the prefetches in flight and
+            // orders the slot writes against the reads of the tile before.
+            constexpr int NT = CT / 16;
+            const int p = threadIdx.x;
+            const half8 *src = reinterpret_cast<const half8 *>((half ? Cs2 : Cs1) + (int64_t)(cb + (p & 15)) * 2 * h) + (p >> 4);
+            constexpr int64_t kStripV = 16 * 16;  // half8 values per strip
+            auto lds_barrier = [&]() __attribute__((always_inline)) {
+                __asm__ __volatile__("" ::: "memory");
+                __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0) only
+                __asm__ __volatile__("" ::: "memory");
+                __builtin_amdgcn_s_barrier();
+                __asm__ __volatile__("" ::: "memory");
+            };
+            half8 pre[kPF];
 #pragma unroll
-            for (int t = 0; t < CT / 16; ++t) {  // straight-line code: exact wait counts
+            for (int i = 0; i < kPF; ++i) pre[i] = src[i * kStripV];
+            for (int e = p; e < CT; e += 256) snc[e] = nC[cb + e];
+            sstrip[0][p] = pre[0];
+            pre[0] = src[kPF * kStripV];  // strip i is held in pre[i % kPF]
+            lds_barrier();
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {  // straight-line code: exact wait counts
                 const int c0 = cb + 16 * t;
-                if (t + 2 < CT / 16) {
-                    if (t % 3 == 0) {
-                        strip_split(c0 + 32 + li, h2);
-                        n2 = nC[c0 + 32 + li];
-                    } else if (t % 3 == 1) {
-                        strip_split(c0 + 32 + li, h0);
-                        n0 = nC[c0 + 32 + li];
-                    } else {
-                        strip_split(c0 + 32 + li, h1);
-                        n1 = nC[c0 + 32 + li];
-                    }
-                }
-                if (t % 3 == 0) tile_split(h0, n0, 16 * (t & 3));
-                else if (t % 3 == 1) tile_split(h1, n1, 16 * (t & 3));
-                else tile_split(h2, n2, 16 * (t & 3));
-                if ((t & 3) == 3) flush(c0 - 48);
+                if (t + 1 < NT) sstrip[(t + 1) & 1][p] = pre[(t + 1) % kPF];
+                if (t + 1 + kPF < NT) pre[(t + 1) % kPF] = src[(t + 1 + kPF) * kStripV];
+                const half8 *S = sstrip[t & 1];
+                half8 hv[2][2];
+                hv[0][0] = S[(2 * lk) * 16 + li];
+                hv[0][1] = S[(2 * lk + 1) * 16 + li];
+                hv[1][0] = S[(8 + 2 * lk) * 16 + li];
+                hv[1][1] = S[(9 + 2 * lk) * 16 + li];
+                tile_split(hv, snc[16 * t + li], 16 * (t % kFT));
+                if (t % kFT == kFT - 1) flush(c0 - 16 * (kFT - 1));
+                lds_barrier();
             }
         } else {
+            // FP32 products; the next centroid strip is loaded before this
+            // tile's products, alternating between two register sets
+            float b0[16], b1[16];
+            float n0, n1;
             load_strip(C + (int64_t)(cb + li) * h, true, 16 * lk, h, true, b0);
             n0 = nC[cb + li];
 #pragma unroll
@@ -348,9 +368,9 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
                         n1 = nC[c0 + 16 + li];
                     }
                 }
-                if (t & 1) tile(b1, n1, 16 * (t & 3));
-                else tile(b0, n0, 16 * (t & 3));
-                if ((t & 3) == 3) flush(c0 - 48);
+                if (t & 1) tile(b1, n1, 16 * (t % kFT));
+                else tile(b0, n0, 16 * (t % kFT));
+                if (t % kFT == kFT - 1) flush(c0 - 16 * (kFT - 1));
             }
         }
         if (kmin) {
@@ -420,8 +440,8 @@ hipError_t launch_half_approx(const DevIndex &ix, const float *q, const int32_t 
     const bool wide = rows2 * ((ix.T + 2 * kCT - 1) / (2 * kCT)) >= 16384;
     const int ct = wide ? 2 * kCT : kCT;
     const int nchunk = (ix.T + ct - 1) / ct;
-    const int64_t waves = rows2 * nchunk;
-    const dim3 grid((unsigned)((waves + 3) / 4));
+    const int64_t ngq = (rows2 / 2 + 3) / 4;  // groups of four 16 kQT-row groups per half
+    const dim3 grid((unsigned)(nchunk * 2 * ngq));
     const bool one = ix.D / 2 <= 64, split = one && ix.Cs1 && ix.Cs2;
     auto go = [&](auto kern, const _Float16 *c1, const _Float16 *c2) {
         hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, q, nslots, ix.D, qlist, ix.C1, ix.C2, ix.nC1, ix.nC2, ix.T,

@@ -426,6 +426,35 @@ def test_split_keys_prefix_bitexact(fb, gmm_wide, scale, shift, split):
         assert np.array_equal(keys[r, 0], d1[u[:P]]) and np.array_equal(keys[r, 1], d2[v[:P]]), r
 
 
+@pytest.mark.parametrize("nq", [300, 32800])
+@pytest.mark.parametrize("split", [1, 0])
+def test_rank_prefix_full_workgroups(fb, gmm_wide, nq, split):
+    # Batches of at least 128 queries fill whole workgroups of four 32-row
+    # groups, which in the split form share each 16-centroid strip through LDS
+    # (the 40-query batches above never fill one). 300 queries also leave a
+    # workgroup with one full and one partial row group; 32,800 queries take
+    # the 512-centroid chunks and leave one full row group alone. The FP64
+    # prefixes equal the oracle's bit for bit on every row checked, and most
+    # rows take the wavefront select (wrong approximate keys push rows off it).
+    idxs, _ = gmm_wide
+    ix = idxs[4096]
+    Q = synth.make_queries(nq, synth.gmm_means(0), 5)
+    P = 64
+    log(f"rank prefix, full workgroups: T=4096 nq={nq} P={P} split={split}")
+    h = _open(fb, ix, split_keys=split, stats=1)
+    keys, idx = fb.fbpq_debug_rank(h, Q, P)
+    st = fb.fbpq_stats_read(h)
+    fb.fbpq_free_index(h)
+    log(f"  counters {st}")
+    assert st["prefix_wave"] + st["prefix_wg"] == 2 * nq
+    assert st["prefix_wave"] > nq
+    rows = range(nq) if nq <= 300 else sorted(set(range(0, nq, 211)) | set(range(nq - 40, nq)))
+    for r in rows:
+        d1, d2, u, v = oracle.rank_lists(ix, Q[r])
+        assert np.array_equal(idx[r, 0], u[:P]) and np.array_equal(idx[r, 1], v[:P]), r
+        assert np.array_equal(keys[r, 0], d1[u[:P]]) and np.array_equal(keys[r, 1], d2[v[:P]]), r
+
+
 def test_search_T1000_visit_and_topk(fb, gmm_wide):
     idxs, Q = gmm_wide
     ix = idxs[1000]
