@@ -194,7 +194,10 @@ __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q
         qn[a] = p;
     }
     float *kout = ka + (s0 * 2 + half) * (int64_t)T;  // row s0 + q of this half at kout[2 q T]
-    if (ONE && vec && h == 64 && s0 + 16 * kQT <= nq && ce - cb == CT) {
+    // With 256-centroid chunks, full row groups outside a shared workgroup (at
+    // most three per half) take the general loop below: without the register
+    // form of the FP32 tiles the split kernel fits four wavefronts per SIMD.
+    if (ONE && vec && h == 64 && s0 + 16 * kQT <= nq && ce - cb == CT && (shared || !SPLIT || CT != kCT)) {
         // every row and centroid present: the stores are unconditional, so
         // waiting for a prefetched centroid strip does not wait for them
         const int64_t ldq = 2 * (int64_t)T;
@@ -1118,7 +1121,7 @@ __global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) 
     uint32_t u[SPL];
 #pragma unroll
     for (int q = 0; q < SPL; ++q) u[q] = okey(smp[q]);
-    // The P-th smallest sample key, one byte at a time from the top: a 256-bin
+    // The P-th smallest sample key, one byte at a time from its top three: a 256-bin
     // histogram of the samples that match the bytes found so far, a scan over
     // the lanes (four bins each), and the bin where the running count reaches
     // the rank still needed. LDS executes a wavefront's instructions in issue
@@ -1131,7 +1134,7 @@ __global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) 
     };
     uint32_t pre = 0, hm = 0;
     int need = P;  // at most the 64 SPL samples, so a bin always reaches it
-    for (int sh = 24; sh >= 0; sh -= 8) {
+    for (int sh = 24; sh >= 8; sh -= 8) {
         reinterpret_cast<uint4 *>(hist)[lane] = uint4{0u, 0u, 0u, 0u};
         lds_order();
 #pragma unroll
@@ -1177,6 +1180,10 @@ __global__ __launch_bounds__(kWPB * 64) __attribute__((amdgpu_waves_per_eu(4))) 
         need -= (int)low;
         lds_order();  // the reads are done before the next clear
     }
+    // The largest key with those three bytes bounds the P-th smallest sample
+    // from above (any value whose top 24 bits match is at most it); a bucket
+    // that holds +inf keeps +inf, the rest of it being NaN patterns.
+    pre = (pre >> 8) == 0xFF8000u ? 0xFF800000u : (pre | 0xFFu);
     // error bound of the approximate keys (any summation order; the split
     // FP16 products too, through the index's coefficient)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
