@@ -56,15 +56,18 @@ __global__ __launch_bounds__(256) void k_lq(ItemArgs a)
     __shared__ int nsel;
     const int D = a.ix.D, M = a.ix.M, ds = DS > 0 ? DS : D / M;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        int n = 0;
-        for (int i = 0; i < kLqQ; ++i) {
-            const int64_t slot = (int64_t)blockIdx.x * kLqQ + i;
-            if (slot >= a.nslots) break;
+    if (tid < 64) {
+        // the group's headers read by kLqQ lanes at once, the selected slots
+        // listed in ascending order
+        const int64_t slot = (int64_t)blockIdx.x * kLqQ + tid;
+        bool sel = false;
+        if (tid < kLqQ && slot < a.nslots) {
             const TravHdr h = a.hdr[slot];
-            if (h.status == kStOk && (h.n_items != 0 || h.gscan)) slots[n++] = slot;
+            sel = h.status == kStOk && (h.n_items != 0 || h.gscan);
         }
-        nsel = n;
+        const uint64_t m = __ballot(sel);
+        if (sel) slots[__popcll(m & ((1ull << tid) - 1ull))] = slot;
+        if (tid == 0) nsel = __popcll(m);
     }
     __syncthreads();
     const int n = nsel;
