@@ -126,7 +126,8 @@ __device__ __forceinline__ void load_strip(const float *__restrict__ row, bool o
 }
 
 // ONE: D/2 <= 64, so the query rows are loaded once and stay in registers.
-// SPLIT: full tiles at D/2 = 64 take the split FP16 products (Cs1/Cs2 set).
+// SPLIT: at D/2 = 64, workgroups whose four row groups and chunk are full take
+// the split FP16 products (Cs1/Cs2 set); other row groups the FP32 ones.
 template <bool ONE, bool SPLIT, int CT>
 __global__ __launch_bounds__(256) void k_half_approx(const float *__restrict__ Q, int64_t nq, int D,
                                                      const int32_t *__restrict__ qlist,
