@@ -426,21 +426,22 @@ def test_split_keys_prefix_bitexact(fb, gmm_wide, scale, shift, split):
         assert np.array_equal(keys[r, 0], d1[u[:P]]) and np.array_equal(keys[r, 1], d2[v[:P]]), r
 
 
-@pytest.mark.parametrize("nq", [300, 32800])
+@pytest.mark.parametrize("nq,T", [(300, 4096), (32800, 4096), (300, 1000)])
 @pytest.mark.parametrize("split", [1, 0])
-def test_rank_prefix_full_workgroups(fb, gmm_wide, nq, split):
+def test_rank_prefix_full_workgroups(fb, gmm_wide, nq, T, split):
     # Batches of at least 128 queries fill whole workgroups of four 32-row
     # groups, which in the split form share each 16-centroid strip through LDS
     # (the 40-query batches above never fill one). 300 queries also leave a
     # workgroup with one full and one partial row group; 32,800 queries take
-    # the 512-centroid chunks and leave one full row group alone. The FP64
+    # the 512-centroid chunks and leave one full row group alone; at T = 1000
+    # the last chunk of every row is partial and takes the general loop. The FP64
     # prefixes equal the oracle's bit for bit on every row checked, and most
     # rows take the wavefront select (wrong approximate keys push rows off it).
     idxs, _ = gmm_wide
-    ix = idxs[4096]
+    ix = idxs[T]
     Q = synth.make_queries(nq, synth.gmm_means(0), 5)
     P = 64
-    log(f"rank prefix, full workgroups: T=4096 nq={nq} P={P} split={split}")
+    log(f"rank prefix, full workgroups: T={T} nq={nq} P={P} split={split}")
     h = _open(fb, ix, split_keys=split, stats=1)
     keys, idx = fb.fbpq_debug_rank(h, Q, P)
     st = fb.fbpq_stats_read(h)
