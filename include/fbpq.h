@@ -370,8 +370,9 @@ void fbpq_server_destroy(fbpq_server *s);
  * d_q [nq][D], per-query host L and k, device results as in
  * fbpq_search_device, on hip_stream): one warm search, then `reps` searches
  * timed with HIP events, median kept, for each candidate setting, in two
- * stages: the options "prefix" (64, 128, 256, 512, capped at T) x "items"
- * (1, 0); then, if the cell scan won, "persist" 1 with "tile" (2048, 8192,
+ * stages: the options "prefix" (16, 32, 64, 128, 256, 512, capped at T) x "items"
+ * (1, 0), each timed in two round-robin passes with its faster median kept;
+ * then, if the cell scan won, "persist" 1 with "tile" (2048, 8192,
  * 32768, 2^30 candidates per work item) x "pwaves" (2, 4, 8 wavefronts per
  * workgroup, where the kernel has that shape) against the per-query launch.
  * The fastest setting stays set on the handle. chosen [6]: prefix, items,

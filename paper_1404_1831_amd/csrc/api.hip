@@ -1822,8 +1822,12 @@ struct TuneChoice {
     double ms;
 };
 
+// A candidate starts from no learned budget-class hints: hints left by an
+// earlier candidate's retries would start every later one at that depth.
 static void tune_apply(fbpq_index *ix, const TuneChoice &c)
 {
+    std::fill(std::begin(ix->p_hint), std::end(ix->p_hint), 0);
+    std::fill(std::begin(ix->c_hint), std::end(ix->c_hint), 0);
     ix->prefix = c.prefix;
     ix->items = c.items != 0;
     ix->persist = c.persist != 0;
@@ -1853,14 +1857,26 @@ static int tune_run(fbpq_index *ix, const float *d_q, int64_t nq, const int64_t 
             b.ms = ms;
         }
     };
-    bool any = false;
-    for (int32_t p : {64, 128, 256, 512})
+    // Stage 1 times every (prefix, scan form) twice, round robin, and keeps
+    // each one's faster median: the first candidates of a single pass would
+    // run while the clocks still rise after the caller's own work.
+    std::vector<TuneChoice> c1;
+    for (int32_t p : {16, 32, 64, 128, 256, 512})  // short prefixes retry the queries they do not cover
         if (p <= std::min<int32_t>(T, kMaxPrefix)) {
-            any = true;
-            consider({p, 1, 0, ix->tile, ix->pwaves, 0.0});
-            consider({p, 0, 0, ix->tile, ix->pwaves, 0.0});
+            c1.push_back({p, 1, 0, ix->tile, ix->pwaves, -1.0});
+            c1.push_back({p, 0, 0, ix->tile, ix->pwaves, -1.0});
         }
-    if (!any) consider(b);
+    for (int pass = 0; pass < 2 && !rc; ++pass)
+        for (TuneChoice &c : c1) {
+            if (rc) break;
+            tune_apply(ix, c);
+            double ms = 0.0;
+            rc = tune_time(ix, d_q, nq, L, k, k_max, d_ids, d_dists, st, reps, e0, e1, &ms);
+            if (!rc && (c.ms < 0 || ms < c.ms)) c.ms = ms;
+        }
+    for (const TuneChoice &c : c1)
+        if (!rc && (b.ms < 0 || c.ms < b.ms)) b = c;
+    if (c1.empty()) consider(b);
     if (!rc && b.items) {
         const int mh = ix->dv.M / 2;
         for (int32_t tile : {2048, 8192, 32768, 1 << 30})
