@@ -501,6 +501,11 @@ def run_batch(args, w) -> dict:
     fbpq.fbpq_set_option(h, "profile_mask", 1 << fbpq.STAGES.index(dom))
 
     step_ms = []
+    # no interpreter garbage collection inside the timed steps: a collection
+    # pause between two launches idles the stream and lengthens that step
+    import gc
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
@@ -510,6 +515,7 @@ def run_batch(args, w) -> dict:
         step_ms.append((time.perf_counter() - a) * 1e3)
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t_start
+    gc.enable()
     log(f"timed {args.steps} steps in {total_s:.3f}s: " + ", ".join(f"{x:.3f}" for x in step_ms) + " ms")
     dom_ms, dom_n = fbpq.fbpq_profile_read(h, fbpq.STAGES.index(dom), reset=True)
     fbpq.fbpq_set_option(h, "profile", 0)
