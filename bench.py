@@ -325,7 +325,7 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="batched", choices=sorted(WORKLOADS))
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -426,14 +426,6 @@ def run_batch(args, w) -> dict:
     log(f"index built in {time.time() - t0:.1f}s: N={ix.N} T={ix.T} M={ix.M} "
         f"nonempty cells={int((np.diff(ix.offsets) > 0).sum())}; {lk_desc}")
 
-    # exact nearest neighbours of the first queries (brute force on the GPU), for Recall@10
-    nr = min(nq, args.recall_queries)
-    a = time.perf_counter()
-    nn = exact_nn(base, Q[:nr]) if nr > 0 else None
-    log(f"exact nearest neighbours of {nr} queries in {time.perf_counter() - a:.1f}s")
-    del base
-    torch.cuda.empty_cache()
-
     h = fbpq.fbpq_index_create(ix, 0)
     fbpq.fbpq_build_tables(h)
     for kv in args.option:
@@ -457,11 +449,6 @@ def run_batch(args, w) -> dict:
     for kv in args.option:  # explicit options override the tuned ones
         key, val = kv.split("=")
         fbpq.fbpq_set_option(h, key, int(val))
-
-    for i in range(args.warmup):
-        search()
-        log(f"warmup {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
 
     # path counters (untimed steps of their own: their atomics would slow the kernels)
     fbpq.fbpq_set_option(h, "stats", 1)
@@ -500,12 +487,20 @@ def run_batch(args, w) -> dict:
     dom = max(models, key=total)
     fbpq.fbpq_set_option(h, "profile_mask", 1 << fbpq.STAGES.index(dom))
 
-    step_ms = []
-    # no interpreter garbage collection inside the timed steps: a collection
-    # pause between two launches idles the stream and lengthens that step
+    # no interpreter garbage collection from here to the end of the timed
+    # steps: a collection pause between two launches idles the stream
     import gc
     gc.collect()
     gc.disable()
+    # the warmup steps right before the timed ones, in their configuration
+    # (the clocks fall while the host reads the counters and profiles)
+    for i in range(args.warmup):
+        search()
+        torch.cuda.synchronize()
+    log(f"{args.warmup} warmup steps done")
+    fbpq.fbpq_profile_read(h, fbpq.STAGES.index(dom), reset=True)
+
+    step_ms = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
@@ -562,6 +557,16 @@ def run_batch(args, w) -> dict:
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - a
     log(f"plain per-query launches: {npl} queries in {plain_s:.3f}s")
+
+    # exact nearest neighbours of the first queries (brute force on the GPU),
+    # for Recall@10: after the timed legs, so that neither this work nor the
+    # release of its buffers and of the base points comes just before them
+    nr = min(nq, args.recall_queries)
+    a = time.perf_counter()
+    nn = exact_nn(base, Q[:nr]) if nr > 0 else None
+    log(f"exact nearest neighbours of {nr} queries in {time.perf_counter() - a:.1f}s")
+    del base
+    torch.cuda.empty_cache()
 
     ms_per_step = total_s * 1e3 / args.steps
     qps = nq / (ms_per_step / 1e3)
