@@ -58,6 +58,10 @@ struct fbpq_index {
     DevIndex dv{};
     hipStream_t stream = nullptr;
     hipStream_t cur = nullptr;  // stream of the search in progress (workspace growth is ordered on it)
+    // second stream: the query tables of a round run on it beside the first
+    // layer and the traversal, forked and joined through two events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // owned device allocations
     float *C1 = nullptr, *C2 = nullptr, *R = nullptr;
     float *QL = nullptr, *SL = nullptr;  // local codebooks (HBPQ), or null
@@ -369,6 +373,7 @@ void free_all(fbpq_index *ix)
     if (!ix) return;
     (void)hipSetDevice(ix->device);
     if (ix->stream) (void)hipStreamSynchronize(ix->stream);
+    if (ix->side) (void)hipStreamSynchronize(ix->side);
     void *ps[] = {ix->C1, ix->C2, ix->R, ix->offsets, ix->codesA, ix->codesB, ix->ids,
                   ix->CR1, ix->CR2, ix->nR, ix->nC1, ix->nC2, ix->QL, ix->SL, ix->Rot, ix->Cs1, ix->Cs2};
     if (!ix->shared)
@@ -386,8 +391,29 @@ void free_all(fbpq_index *ix)
     }
     for (auto e : ix->ev_pool) (void)hipEventDestroy(e);
     if (ix->gexec) (void)hipGraphExecDestroy(ix->gexec);
+    if (ix->side) {
+        (void)hipStreamSynchronize(ix->side);
+        (void)hipStreamDestroy(ix->side);
+    }
+    if (ix->ev_fork) (void)hipEventDestroy(ix->ev_fork);
+    if (ix->ev_join) (void)hipEventDestroy(ix->ev_join);
     if (ix->stream) (void)hipStreamDestroy(ix->stream);
     delete ix;
+}
+
+// The side stream and its two events (default priority); without them the
+// query tables run on the search stream.
+static void side_init(fbpq_index *ix)
+{
+    if (hipStreamCreateWithFlags(&ix->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ix->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ix->ev_join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ix->side) (void)hipStreamDestroy(ix->side);
+        if (ix->ev_fork) (void)hipEventDestroy(ix->ev_fork);
+        ix->side = nullptr;
+        ix->ev_fork = ix->ev_join = nullptr;
+    }
 }
 
 int create_impl(const fbpq_index_desc *d, int device, fbpq_index **out)
@@ -415,6 +441,7 @@ int create_impl(const fbpq_index_desc *d, int device, fbpq_index **out)
             delete ix;
             return rc;
         }
+        side_init(ix);
         ix->arena.base = (unsigned char *)sp;
         ix->arena.cap = kScratchBytes;
     }
@@ -720,6 +747,26 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
     }
     HCK(ix, launch_fill_i32(d_fail, 0, 1, st));
     TRY(first_layer(ix, d_q, nslots, d_qlist, P, (double *)lkey, (int32_t *)lidx, st));
+    // The query tables depend on the queries only: on the side stream they run
+    // beside the traversal (forked after the first layer, which fills the chip), for every slot (the two-pass
+    // scans, which do not read them, serve few queries), joined before the scans.
+    const bool lq_need = !dv.local && !dv.od && !(dbg && dbg->visit);  // local and O(D) scans do not use LQ
+    const bool lq_side = lq_need && ix->side && ix->ev_fork && ix->ev_join;
+    void *lq = nullptr;
+    if (lq_need) TRY(ws_get(ix, W_LQ, sizeof(float) * nslots * dv.M * FBPQ_KC, &lq));
+    if (lq_side) {
+        ItemArgs iq{};
+        iq.ix = dv;
+        iq.q = d_q;
+        iq.qlist = d_qlist;
+        iq.nslots = nslots;
+        iq.hdr = nullptr;  // every slot
+        iq.lq = (float *)lq;
+        HCK(ix, hipEventRecord(ix->ev_fork, st));
+        HCK(ix, hipStreamWaitEvent(ix->side, ix->ev_fork, 0));
+        HCK(ix, timed(ix, FBPQ_STAGE_LQ, ix->side, [&] { return launch_items_prep(iq, ix->side); }));
+        HCK(ix, hipEventRecord(ix->ev_join, ix->side));
+    }
     TravArgs ta{};
     ta.ix = dv;
     ta.lkey = (const double *)lkey;
@@ -782,9 +829,8 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         // query tables and per-candidate distance rows: the cell scan and the
         // wide two-pass scan write the rows, the distance select reads them
         const int wcap = items_wcap(k_max);
-        void *lq, *dist, *seldone;
+        void *dist, *seldone;
         TRY(ws_get(ix, W_SELDONE, sizeof(int32_t) * nslots, &seldone));
-        TRY(ws_get(ix, W_LQ, sizeof(float) * nslots * dv.M * FBPQ_KC, &lq));
         const int64_t dstride = (lcap + 63) & ~(int64_t)63;  // 256-byte aligned distance rows
         TRY(ws_get(ix, W_ITEMN, sizeof(float) * nslots * dstride, &dist));
         ItemArgs ia{};
@@ -814,7 +860,9 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         ia.dbg_pos = (int64_t *)dpos;
         ia.dbg_d = (float *)ddd;
         ia.dbg_cap = dbg && dbg->dists ? dbg->dcap : 0;
-        if (!dv.local && !dv.od)  // local codebooks and the O(D) scan do not use LQ
+        if (lq_side)
+            HCK(ix, hipStreamWaitEvent(st, ix->ev_join, 0));
+        else if (lq_need)
             HCK(ix, timed(ix, FBPQ_STAGE_LQ, st, [&] { return launch_items_prep(ia, st); }));
         if (ix->items && ix->persist) {
             PersistArgs pa{};
@@ -1282,6 +1330,7 @@ int lane_create(fbpq_index *src, fbpq_index **out)
         delete ix;
         return fail(FBPQ_E_DEVICE, "cannot create a stream on device %d", src->device);
     }
+    side_init(ix);
     ix->tables = true;
     ix->arena.base = src->arena.base;
     ix->arena.cap = src->arena.cap;

@@ -62,8 +62,12 @@ __global__ __launch_bounds__(256) void k_lq(ItemArgs a)
         const int64_t slot = (int64_t)blockIdx.x * kLqQ + tid;
         bool sel = false;
         if (tid < kLqQ && slot < a.nslots) {
-            const TravHdr h = a.hdr[slot];
-            sel = h.status == kStOk && (h.n_items != 0 || h.gscan);
+            if (a.hdr) {
+                const TravHdr h = a.hdr[slot];
+                sel = h.status == kStOk && (h.n_items != 0 || h.gscan);
+            } else {
+                sel = true;  // every slot (launched before the traversal)
+            }
         }
         const uint64_t m = __ballot(sel);
         if (sel) slots[__popcll(m & ((1ull << tid) - 1ull))] = slot;
