@@ -62,6 +62,7 @@ struct fbpq_index {
     // layer and the traversal, forked and joined through two events
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;  // the two-pass scans beside the cell scan
     // owned device allocations
     float *C1 = nullptr, *C2 = nullptr, *R = nullptr;
     float *QL = nullptr, *SL = nullptr;  // local codebooks (HBPQ), or null
@@ -397,22 +398,27 @@ void free_all(fbpq_index *ix)
     }
     if (ix->ev_fork) (void)hipEventDestroy(ix->ev_fork);
     if (ix->ev_join) (void)hipEventDestroy(ix->ev_join);
+    if (ix->ev_fork2) (void)hipEventDestroy(ix->ev_fork2);
+    if (ix->ev_join2) (void)hipEventDestroy(ix->ev_join2);
     if (ix->stream) (void)hipStreamDestroy(ix->stream);
     delete ix;
 }
 
-// The side stream and its two events (default priority); without them the
-// query tables run on the search stream.
+// The side stream and its events (default priority); without them the query
+// tables and the two-pass scans run on the search stream.
 static void side_init(fbpq_index *ix)
 {
     if (hipStreamCreateWithFlags(&ix->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ix->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ix->ev_join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ix->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ix->ev_fork2, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ix->ev_join2, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         if (ix->side) (void)hipStreamDestroy(ix->side);
-        if (ix->ev_fork) (void)hipEventDestroy(ix->ev_fork);
+        for (hipEvent_t e : {ix->ev_fork, ix->ev_join, ix->ev_fork2, ix->ev_join2})
+            if (e) (void)hipEventDestroy(e);
         ix->side = nullptr;
-        ix->ev_fork = ix->ev_join = nullptr;
+        ix->ev_fork = ix->ev_join = ix->ev_fork2 = ix->ev_join2 = nullptr;
     }
 }
 
@@ -864,22 +870,6 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
             HCK(ix, hipStreamWaitEvent(st, ix->ev_join, 0));
         else if (lq_need)
             HCK(ix, timed(ix, FBPQ_STAGE_LQ, st, [&] { return launch_items_prep(ia, st); }));
-        if (ix->items && ix->persist) {
-            PersistArgs pa{};
-            void *pit, *pctl, *pqn, *pqd;
-            TRY(ws_get(ix, W_PITEMS, sizeof(int32_t) * 3 * (size_t)persist_items_cap(nslots, dstride, ix->tile), &pit));
-            TRY(ws_get(ix, W_PCTL, sizeof(int32_t) * 66, &pctl));
-            TRY(ws_get(ix, W_PQNIT, sizeof(int32_t) * nslots, &pqn));
-            TRY(ws_get(ix, W_PQDONE, sizeof(int32_t) * nslots, &pqd));
-            pa.items = (int32_t *)pit;
-            pa.ctl = (int32_t *)pctl;
-            pa.qnit = (int32_t *)pqn;
-            pa.qdone = (int32_t *)pqd;
-            pa.tile = ix->tile;
-            HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_persist(ia, pa, ix->pwaves, st); }));
-        } else if (ix->items) {
-            HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_scan(ia, st); }));
-        }
         ScanArgs sa{};
         sa.ix = dv;
         sa.q = d_q;
@@ -915,9 +905,37 @@ int run_round(fbpq_index *ix, const float *d_q, int64_t nq, int64_t nslots, cons
         sa.lq = (const float *)lq;
         sa.dist = (float *)dist;
         sa.lcap = dstride;
+        // the two-pass scans serve other slots than the cell scan, the wide scan
+        // and the distance select: on the side stream they run beside them
+        const bool s2_side = lq_side && ix->ev_fork2 && ix->ev_join2;
+        if (s2_side) {
+            HCK(ix, hipEventRecord(ix->ev_fork2, st));
+            HCK(ix, hipStreamWaitEvent(ix->side, ix->ev_fork2, 0));
+            HCK(ix, timed(ix, FBPQ_STAGE_SCAN2, ix->side, [&] { return launch_scan(sa, nslots, ix->side); }));
+            HCK(ix, hipEventRecord(ix->ev_join2, ix->side));
+        }
+        if (ix->items && ix->persist) {
+            PersistArgs pa{};
+            void *pit, *pctl, *pqn, *pqd;
+            TRY(ws_get(ix, W_PITEMS, sizeof(int32_t) * 3 * (size_t)persist_items_cap(nslots, dstride, ix->tile), &pit));
+            TRY(ws_get(ix, W_PCTL, sizeof(int32_t) * 66, &pctl));
+            TRY(ws_get(ix, W_PQNIT, sizeof(int32_t) * nslots, &pqn));
+            TRY(ws_get(ix, W_PQDONE, sizeof(int32_t) * nslots, &pqd));
+            pa.items = (int32_t *)pit;
+            pa.ctl = (int32_t *)pctl;
+            pa.qnit = (int32_t *)pqn;
+            pa.qdone = (int32_t *)pqd;
+            pa.tile = ix->tile;
+            HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_persist(ia, pa, ix->pwaves, st); }));
+        } else if (ix->items) {
+            HCK(ix, timed(ix, FBPQ_STAGE_SCORE, st, [&] { return launch_items_scan(ia, st); }));
+        }
         HCK(ix, timed(ix, FBPQ_STAGE_SCAN_WIDE, st, [&] { return launch_scan_wide(sa, nslots, st); }));
         HCK(ix, timed(ix, FBPQ_STAGE_SELECT, st, [&] { return launch_items_merge(ia, st); }));
-        HCK(ix, timed(ix, FBPQ_STAGE_SCAN2, st, [&] { return launch_scan(sa, nslots, st); }));
+        if (s2_side)
+            HCK(ix, hipStreamWaitEvent(st, ix->ev_join2, 0));
+        else
+            HCK(ix, timed(ix, FBPQ_STAGE_SCAN2, st, [&] { return launch_scan(sa, nslots, st); }));
     }
     if (launch_only) return FBPQ_OK;
     // how many slots need another round
