@@ -293,7 +293,9 @@ __host__ __device__ constexpr int64_t wide_region_floats(int D, int group = MH)
     return MODE == kWideOD ? (int64_t)group * kKc * (D / (2 * MH)) + (int64_t)wide_waves<MH, MODE>() * (D / 2)
                            : (int64_t)wide_regions<MH, MODE>() * MH * kKc;
 }
-constexpr int kWideRanks = 4097;  // task prefix entries (ranks up to 4096, plus the total)
+// task prefix entries: one per rank of the longer half list (at most P) plus the
+// total, so P + 1 of them; sized at launch from the prefix length
+__host__ __device__ constexpr int64_t wide_ranks(int P) { return (int64_t)P + 1; }
 constexpr int kWideU = 4;         // 64-candidate chunks a wavefront has in flight
 constexpr int kWideKeep = 6;      // (distance, candidate) pairs each lane keeps for the selection
 constexpr int kWideWin = 512;     // candidates the fused selection can rank
@@ -311,7 +313,7 @@ __device__ __forceinline__ int lane_owner(int32_t v, int n, int32_t x)
     return lo;
 }
 
-// exclusive prefix of x[0..n) in place, n <= kWideRanks; every thread calls it
+// exclusive prefix of x[0..n) in place, n <= wide_ranks(P); every thread calls it
 template <int NT>
 __device__ void wide_scan(int *x, int n, int *wtot)
 {
@@ -348,7 +350,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
     constexpr int NT = 64 * NW;
     constexpr int TL = MH * kKc;  // floats of one folded half table
     // the regions (wide_regions of them: folded tables, or the O(D) codebooks and
-    // q - c), then the task prefix [kWideRanks], then q [D]
+    // q - c), then the task prefix [wide_ranks(P)], then q [D]
     extern __shared__ __align__(16) float wlut[];
     __shared__ int wtot[NW];
     const int slot = blockIdx.x;
@@ -393,7 +395,7 @@ __global__ __launch_bounds__((64 * wide_waves<MH, MODE>())) void k_scan_wide(Sca
     const float *cbh = wlut;  // O(D): codebooks of subspaces [k0, k1) of the pass (LDS or memory)
     int k0 = 0, k1 = MH;
     float *qcw = wlut + (int64_t)og * kKc * (a.ix.D / (2 * MH)) + wv * (a.ix.D / 2);  // O(D): q - c
-    float *qs = reinterpret_cast<float *>(tpre + kWideRanks);
+    float *qs = reinterpret_cast<float *>(tpre + wide_ranks(a.P));
     const int P = a.P;
     const int D = a.ix.D, ds = D / (2 * MH);
     const int64_t mc = a.max_cells;
@@ -928,24 +930,39 @@ hipError_t launch_scan(const ScanArgs &a, int64_t nslots, hipStream_t st)
     return launch_scan2<false>(a, nslots, st);
 }
 
+// LDS a workgroup of `kernel` holds before its dynamic part (its __shared__
+// arrays); a dispatch asks for that plus the dynamic bytes, within 160 KiB
+static size_t static_lds(const void *kernel)
+{
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, kernel) != hipSuccess) {
+        (void)hipGetLastError();
+        return 16 * 1024;  // unknown: keep a wide margin
+    }
+    return fa.sharedSizeBytes;
+}
+
 hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
     const dim3 g((unsigned)nslots);
-    const size_t extra = (size_t)kWideRanks * sizeof(int) + (size_t)a.ix.D * sizeof(float);
+    // rows (pass 1) and columns (pass 2) of a diagram are at most P each
+    const size_t extra = (size_t)wide_ranks(a.P) * sizeof(int) + (size_t)a.ix.D * sizeof(float);
     const int mode = a.ix.od ? kWideOD : (a.ix.local ? kWideLocal : kWideFbpq);
 #define FBPQ_WIDE_MODE(MH, MODE)                                                                  \
     {                                                                                             \
         constexpr int nt = 64 * wide_waves<MH, MODE>();                                           \
+        static const size_t budget =                                                              \
+            160 * 1024 - static_lds(reinterpret_cast<const void *>(&k_scan_wide<MH, MODE>));      \
         ScanArgs b = a;                                                                           \
         b.od_group = MH; /* O(D): the most subspaces whose codebooks fit in LDS at once */        \
         while (b.od_group > 0 &&                                                                  \
                (size_t)wide_region_floats<MH, MODE>(a.ix.D, b.od_group) * sizeof(float) + extra > \
-                   160 * 1024)                                                                    \
+                   budget)                                                                        \
             --b.od_group;                                                                         \
         const size_t lds =                                                                        \
             (size_t)wide_region_floats<MH, MODE>(a.ix.D, b.od_group) * sizeof(float) + extra;     \
-        if (lds > 160 * 1024) return hipErrorInvalidValue;                                       \
+        if (lds > budget) return hipErrorInvalidValue;                                            \
         hipLaunchKernelGGL((k_scan_wide<MH, MODE>), g, dim3(nt), lds, st, b);                     \
     }
 #define FBPQ_WIDE_CASE(MH)                                                                        \

@@ -1261,3 +1261,44 @@ def test_autotune_cache(fb, gmm_dense, tmp_path):
     fb.fbpq_free_index(h)
     o_ids, o_d, _, _ = oracle.search(ix, Q[:60], L[:60], k[:60], kmax=kmax)
     assert_topk(ix, Q[:60], k[:60], ids[:60], d[:60], o_ids, o_d)
+
+
+def test_wide_scan_long_prefix(fb):
+    """Far queries on a sparse Zipf-sized index (1e9 points over 16384^2 cells,
+    M=8) at L = 1e5: the visited diagram spans more than 4096 rows or columns
+    with about one point per cell, so the query takes the two-pass wide scan
+    after the long-prefix traversal. Every candidate's distance and the top-k
+    against the oracle (this case once scored from stale memory)."""
+    import torch
+
+    log("wide scan, long prefix: Zipf index N=1e9 T=16384 M=8, two far queries, L=100000")
+    ix = synth.zipf_index(1_000_000_000, 16384, 8, device="cuda:0")
+    torch.cuda.empty_cache()
+    Q = synth.make_queries(160000, synth.gmm_means(0), 2)[[58183, 114151]]
+    L, k = 100000, 10
+    h = _open(fb, ix)
+    try:
+        o_ids, o_d, _, _ = oracle.search(ix, Q, np.full(2, L, np.int64), k)
+        for r in range(2):
+            cells, _ = oracle.visit(ix, Q[r], L, 1 << 20)
+            rows = np.unique(cells[:, 0] // ix.T).size
+            cols = np.unique(cells[:, 0] % ix.T).size
+            log(f"query {r}: {len(cells)} cells, {rows} rows, {cols} columns")
+            assert max(rows, cols) > 4096 and L < 128 * len(cells)
+            (dp, dd), = fb.fbpq_debug_dists(h, Q[r:r + 1], L, L)
+            assert dp.size == L
+            od = oracle_dists(ix, Q[r], dp)
+            bad = np.abs(dd.astype(np.float64) - od) > tol(ix, Q[r], dp, od)
+            assert not bad.any(), f"query {r}: {int(bad.sum())} of {L} candidate distances off"
+        g_ids, g_d = fb.fbpq_search_uneven(h, Q, np.full(2, L, np.int64), np.full(2, k, np.int32), k)
+        for r in range(2):
+            q = Q[r].astype(np.float64)
+            # the distance tolerance of tests/parity.py with |x| bounded by |q| + sqrt(d)
+            t = 1e-4 * o_d[r] + 1e-6 * (q @ q + (np.sqrt(q @ q) + np.sqrt(np.maximum(o_d[r], 0))) ** 2)
+            assert np.all(np.abs(g_d[r].astype(np.float64) - o_d[r]) <= t)
+            firm = o_d[r] < o_d[r][k - 1] - 2 * t[k - 1]
+            assert set(o_ids[r][firm].tolist()) <= set(g_ids[r].tolist())
+    finally:
+        fb.fbpq_free_index(h)
+        del ix
+        torch.cuda.empty_cache()
