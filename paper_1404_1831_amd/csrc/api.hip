@@ -451,6 +451,7 @@ int create_impl(const fbpq_index_desc *d, int device, fbpq_index **out)
         ix->arena.base = (unsigned char *)sp;
         ix->arena.cap = kScratchBytes;
     }
+    scan_wide_prepare((int)d->M);  // kernel attributes read here, never inside a graph capture
     const int64_t T = d->T, h = d->D / 2, C = T * T, N = d->N, M = d->M;
     rc = upload(ix, &ix->C1, d->C1, sizeof(float) * T * h);
     if (!rc) rc = upload(ix, &ix->C2, d->C2, sizeof(float) * T * h);

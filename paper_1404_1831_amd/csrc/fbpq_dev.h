@@ -216,6 +216,8 @@ struct ScanArgs {
 };
 hipError_t launch_scan(const ScanArgs &a, int64_t nslots, hipStream_t st);
 hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st);
+// reads the static LDS of every k_scan_wide form for M subspaces (once per process)
+void scan_wide_prepare(int M);
 
 size_t scan_lds_bytes(int D, int M, int chunk, int k_max, int P);
 constexpr int kScanCellsLds = 256;  // nonempty cells whose tables the scan keeps in LDS

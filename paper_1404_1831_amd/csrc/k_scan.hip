@@ -942,6 +942,33 @@ static size_t static_lds(const void *kernel)
     return fa.sharedSizeBytes;
 }
 
+// LDS left for the dynamic part of a k_scan_wide<MH, MODE> workgroup
+template <int MH, int MODE>
+static size_t wide_budget()
+{
+    static const size_t b = 160 * 1024 - static_lds(reinterpret_cast<const void *>(&k_scan_wide<MH, MODE>));
+    return b;
+}
+
+void scan_wide_prepare(int M)
+{
+    switch (M / 2) {
+#define FBPQ_WIDE_PREP(MH)                    \
+    case MH:                                  \
+        (void)wide_budget<MH, kWideFbpq>();   \
+        (void)wide_budget<MH, kWideLocal>();  \
+        (void)wide_budget<MH, kWideOD>();     \
+        break;
+        FBPQ_WIDE_PREP(1)
+        FBPQ_WIDE_PREP(2)
+        FBPQ_WIDE_PREP(4)
+        FBPQ_WIDE_PREP(8)
+        FBPQ_WIDE_PREP(16)
+#undef FBPQ_WIDE_PREP
+    default: break;
+    }
+}
+
 hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st)
 {
     if (nslots == 0) return hipSuccess;
@@ -952,8 +979,7 @@ hipError_t launch_scan_wide(const ScanArgs &a, int64_t nslots, hipStream_t st)
 #define FBPQ_WIDE_MODE(MH, MODE)                                                                  \
     {                                                                                             \
         constexpr int nt = 64 * wide_waves<MH, MODE>();                                           \
-        static const size_t budget =                                                              \
-            160 * 1024 - static_lds(reinterpret_cast<const void *>(&k_scan_wide<MH, MODE>));      \
+        const size_t budget = wide_budget<MH, MODE>();                                            \
         ScanArgs b = a;                                                                           \
         b.od_group = MH; /* O(D): the most subspaces whose codebooks fit in LDS at once */        \
         while (b.od_group > 0 &&                                                                  \
